@@ -1,0 +1,174 @@
+"""FP64 CPU oracle for space-time kernel density estimation (arXiv 1705.09366).
+
+TEST INFRASTRUCTURE.  Only the tests, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  It shares no code
+with the GPU library and never calls it.
+
+Contents
+--------
+* :func:`pbsym`   -- Alg. PB-SYM (Sec. 3.2) in FP64, plain C with OpenMP slabs.
+* :func:`vb_voxels` -- Alg. VB (Sec. 2.2) in FP64 at chosen voxels, plain C.
+* :func:`vb_grid_numpy` -- Alg. VB over a whole (tiny) grid, written a second
+  time in numpy so that the brute-force check does not share code with the C
+  loops.
+* :func:`point_sums` -- per-point in-grid kernel sums and support counts.
+
+Kernels follow the Epanechnikov reading of the garbled kernel formulas of
+Sec. 2.1: ks(u,v) = (2/pi)(1-u^2-v^2) on the open unit disc,
+kt(w) = (3/4)(1-w^2) on |w| <= 1.
+"""
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("gx", ctypes.c_int64), ("gy", ctypes.c_int64), ("gt", ctypes.c_int64),
+                ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("t0", ctypes.c_double),
+                ("sres", ctypes.c_double), ("tres", ctypes.c_double),
+                ("hs", ctypes.c_double), ("ht", ctypes.c_double)]
+
+
+@dataclass(frozen=True)
+class Grid:
+    """Discretised domain (Sec. 2.1): gx x gy x gt voxels of sres x sres x tres
+    with voxel (0,0,0) cornered at (x0, y0, t0), and bandwidths hs, ht."""
+    gx: int
+    gy: int
+    gt: int
+    hs: float
+    ht: float
+    sres: float = 1.0
+    tres: float = 1.0
+    x0: float = 0.0
+    y0: float = 0.0
+    t0: float = 0.0
+
+    def _c(self):
+        return _Grid(self.gx, self.gy, self.gt, self.x0, self.y0, self.t0,
+                     self.sres, self.tres, self.hs, self.ht)
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        path = _build.LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+            _build.build()
+        lib = ctypes.CDLL(path)
+        P = ctypes.POINTER
+        lib.oracle_pbsym.argtypes = [P(_Grid), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                     P(ctypes.c_int64), ctypes.c_int]
+        lib.oracle_vb_voxels.argtypes = [P(_Grid), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                         ctypes.c_int64, ctypes.c_void_p, ctypes.c_int]
+        lib.oracle_point_sums.argtypes = [P(_Grid), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_int]
+        for f in (lib.oracle_pbsym, lib.oracle_vb_voxels, lib.oracle_point_sums):
+            f.restype = ctypes.c_int
+        _LIB = lib
+    return _LIB
+
+
+def _threads(nthreads):
+    if nthreads is None or nthreads < 1:
+        return max(1, len(os.sched_getaffinity(0)))
+    return int(nthreads)
+
+
+def _points(xyt):
+    a = np.ascontiguousarray(xyt, dtype=np.float64)
+    if a.ndim != 2 or a.shape[1] != 3:
+        raise ValueError("points must be an (n, 3) array of (x, y, t)")
+    return a
+
+
+def pbsym(xyt, grid: Grid, nthreads=None):
+    """Alg. PB-SYM in FP64.  Returns (density[gx, gy, gt] float64, evals)."""
+    pts = _points(xyt)
+    out = np.empty((grid.gx, grid.gy, grid.gt), dtype=np.float64)
+    ev = ctypes.c_int64(0)
+    rc = _lib().oracle_pbsym(ctypes.byref(grid._c()), pts.ctypes.data, pts.shape[0],
+                             out.ctypes.data, ctypes.byref(ev), _threads(nthreads))
+    if rc != 0:
+        raise ValueError(f"oracle_pbsym failed ({rc})")
+    return out, int(ev.value)
+
+
+def vb_voxels(xyt, grid: Grid, voxels, nthreads=None):
+    """Alg. VB evaluated at the (m, 3) integer voxel list ``voxels``."""
+    pts = _points(xyt)
+    vox = np.ascontiguousarray(voxels, dtype=np.int64).reshape(-1, 3)
+    out = np.empty(vox.shape[0], dtype=np.float64)
+    rc = _lib().oracle_vb_voxels(ctypes.byref(grid._c()), pts.ctypes.data, pts.shape[0],
+                                 vox.ctypes.data, vox.shape[0], out.ctypes.data,
+                                 _threads(nthreads))
+    if rc != 0:
+        raise ValueError(f"oracle_vb_voxels failed ({rc})")
+    return out
+
+
+def point_sums(xyt, grid: Grid, nthreads=None):
+    """Per point: (Ss, St, cs, ct) -- in-grid sums of ks and kt and the numbers
+    of in-grid columns and rows inside the support."""
+    pts = _points(xyt)
+    n = pts.shape[0]
+    Ss = np.empty(n, np.float64)
+    St = np.empty(n, np.float64)
+    cs = np.empty(n, np.int64)
+    ct = np.empty(n, np.int64)
+    rc = _lib().oracle_point_sums(ctypes.byref(grid._c()), pts.ctypes.data, n, Ss.ctypes.data,
+                                  St.ctypes.data, cs.ctypes.data, ct.ctypes.data,
+                                  _threads(nthreads))
+    if rc != 0:
+        raise ValueError(f"oracle_point_sums failed ({rc})")
+    return Ss, St, cs, ct
+
+
+def exact_mass(xyt, grid: Grid, nthreads=None):
+    """Total density times voxel volume implied by the per-point sums:
+    sum_i Ss(i) St(i) / (n hs^2 ht) * sres^2 tres (exact up to rounding
+    because grid clipping is a box and the kernel is separable)."""
+    Ss, St, _, _ = point_sums(xyt, grid, nthreads)
+    n = Ss.shape[0]
+    return float(np.sum(Ss * St) / (n * grid.hs ** 2 * grid.ht) * grid.sres ** 2 * grid.tres)
+
+
+def exact_evals(xyt, grid: Grid, nthreads=None):
+    """Exact number of in-grid (voxel, point) pairs inside both supports."""
+    _, _, cs, ct = point_sums(xyt, grid, nthreads)
+    return int(np.sum(cs * ct))
+
+
+def vb_grid_numpy(xyt, grid: Grid):
+    """Alg. VB over the whole grid, vectorised over points with numpy.  For
+    tiny grids only (it holds a points x voxels-row temporary)."""
+    pts = _points(xyt)
+    fin = np.all(np.isfinite(pts), axis=1)
+    n = pts.shape[0]
+    p = pts[fin]
+    out = np.zeros((grid.gx, grid.gy, grid.gt), dtype=np.float64)
+    xs = grid.x0 + (np.arange(grid.gx) + 0.5) * grid.sres
+    ys = grid.y0 + (np.arange(grid.gy) + 0.5) * grid.sres
+    ts = grid.t0 + (np.arange(grid.gt) + 0.5) * grid.tres
+    for X, x in enumerate(xs):
+        for Y, y in enumerate(ys):
+            d = np.sqrt((p[:, 0] - x) ** 2 + (p[:, 1] - y) ** 2)
+            ins = d < grid.hs
+            if not np.any(ins):
+                continue
+            q = p[ins]
+            u = (x - q[:, 0]) / grid.hs
+            v = (y - q[:, 1]) / grid.hs
+            ksv = (2.0 / np.pi) * (1.0 - u * u - v * v)
+            dt = ts[None, :] - q[:, 2][:, None]
+            w = dt / grid.ht
+            ktv = np.where(np.abs(dt) <= grid.ht, 0.75 * (1.0 - w * w), 0.0)
+            out[X, Y, :] = np.sum(ksv[:, None] * ktv, axis=0)
+    return out / (n * grid.hs ** 2 * grid.ht)

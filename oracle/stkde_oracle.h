@@ -1,0 +1,47 @@
+/*
+ * stkde_oracle.h -- interface of the FP64 CPU oracle (test infrastructure).
+ *
+ * Only the tests, the smoke check and the CPU-baseline leg of the benchmark
+ * use this.  It is deliberately separate from the library's public header:
+ * the oracle and the GPU path share no declarations.
+ *
+ * All arrays are host memory.  xyt holds n points as (x, y, t) triples in
+ * domain units, row-major.  Grids are FP64, indexed [X][Y][T], T fastest.
+ * Functions return 0 on success and a negative value on invalid arguments
+ * (-1) or allocation failure (-2).
+ */
+#ifndef STKDE_ORACLE_H
+#define STKDE_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int64_t gx, gy, gt;    /* grid size in voxels (Sec. 2.1: G_x, G_y, G_t) */
+    double x0, y0, t0;     /* domain coordinate of the corner of voxel (0,0,0) */
+    double sres, tres;     /* voxel size in space and time */
+    double hs, ht;         /* spatial and temporal bandwidths, domain units */
+} oracle_grid;
+
+/* Alg. PB-SYM (Sec. 3.2) in FP64.  grid: gx*gy*gt doubles, overwritten.
+ * evals_out (optional): number of (voxel, point) pairs that pass both
+ * support tests. */
+int oracle_pbsym(const oracle_grid* g, const double* xyt, int64_t n, double* grid,
+                 int64_t* evals_out, int nthreads);
+
+/* Alg. VB (Sec. 2.2) evaluated at m voxels vox[3*j .. 3*j+2] = (X, Y, T). */
+int oracle_vb_voxels(const oracle_grid* g, const double* xyt, int64_t n, const int64_t* vox,
+                     int64_t m, double* out, int nthreads);
+
+/* Per-point in-grid kernel sums and support counts (any pointer may be NULL):
+ * Ss = sum over in-grid columns of ks, St = sum over in-grid rows of kt,
+ * cs / ct = the numbers of those columns / rows. */
+int oracle_point_sums(const oracle_grid* g, const double* xyt, int64_t n, double* Ss, double* St,
+                      int64_t* cs, int64_t* ct, int nthreads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
