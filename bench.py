@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Benchmark of the space-time kernel density hot path on one MI355X.
+
+One step = one full density estimate of the workload through the C ABI
+(stkde_compute: FP64 transform and binning, stable radix sort, per-point
+tables, gather/accumulate, single FP32 store of every voxel, fused FP64 grid
+mass), with the points already resident in HBM.
+
+Default workload: 1,000,000 clustered events (64-component Gaussian mixture
+in space, 8 seasonal bumps plus 20 % uniform background in time) on a
+1024 x 1024 x 256 grid (1 GiB FP32), hs = 10, ht = 7 voxels -- a synthetic
+stand-in shaped like the paper's social-media workload (Sec. 6.1; no dataset
+is available here).
+
+Prints ONE JSON line:
+  value            kernel evaluations per second = exact in-grid
+                   (voxel, point) pairs inside both supports / step time
+  roofline         the gather kernel (dominant): algorithmic bytes (grid
+                   written once + points read once) / its average duration,
+                   timed with HIP events on the stream it runs on
+  cpu_baseline     the FP64 CPU oracle on a bounded sample of the same
+                   workload, on this host's cores
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = ("clustered-1M", "clustered-200k-hs50", "uniform-10k")
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _instance(name):
+    import workloads
+    if name == "clustered-1M":
+        return workloads.config1()
+    if name == "clustered-200k-hs50":
+        return workloads.config2()
+    if name == "uniform-10k":
+        return workloads.config0()
+    raise SystemExit(f"unknown workload {name}; choose from {WORKLOADS}")
+
+
+def _cpu_threads():
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return n
+
+
+def _traffic_from_profile(kernel_src_hash):
+    """HBM bytes per launch of the gather kernel from a committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "gather_clustered1M_pmc.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    if rec.get("gather_src_sha256") != kernel_src_hash:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(inst, gpu_plan_fn, budget_s=20.0):
+    """Time the FP64 oracle on a bounded sample (the first k events of the
+    workload on the full grid), growing k until the run takes a few seconds
+    or covers the whole workload.  Also returns the GPU's max error against
+    the oracle on that same sample."""
+    import numpy as np
+    import oracle
+    g = oracle.Grid(gx=inst.gx, gy=inst.gy, gt=inst.gt, hs=inst.hs, ht=inst.ht,
+                    sres=inst.sres, tres=inst.tres, x0=inst.x0, y0=inst.y0, t0=inst.t0)
+    n = inst.points.shape[0]
+    th = _cpu_threads()
+    k = max(1, n // 64)
+    while True:
+        t0 = time.perf_counter()
+        ref, evals = oracle.pbsym(inst.points[:k], g, nthreads=th)
+        dt = time.perf_counter() - t0
+        _log(f"cpu oracle: {k} points, {evals} evals, {dt:.2f} s on {th} threads")
+        if k >= n or dt * min(4, n / k) > budget_s:
+            break
+        k = min(n, k * 4)
+    gpu = gpu_plan_fn(inst.points[:k]).astype(np.float64)
+    err = float(np.max(np.abs(gpu - ref)) / max(np.max(np.abs(ref)), 1e-300))
+    del ref
+    sample = (f"first {k} of {n} events of the workload on the full {inst.gx}x{inst.gy}x{inst.gt} "
+              f"grid (FP64 grid zeroing + PB-SYM accumulation, IO excluded)")
+    return {"value": evals / dt, "unit": "evals/s", "cores": th, "kind": "oracle",
+            "sample": sample, "seconds": round(dt, 3), "evals": int(evals)}, err
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="clustered-1M", choices=WORKLOADS)
+    ap.add_argument("--plain", action="store_true", help="plain FP32 accumulation (no Kahan)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU sharding of the output slabs "
+              "is a design (see the sharding section of the design notes), not an implemented "
+              "path. Run with --gpus 1.", file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1705_09366_amd as m
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    m.lib()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    inst = _instance(args.workload)
+    n = inst.points.shape[0]
+    kahan = not args.plain
+    flags = m.FLAG_MASS | (m.FLAG_KAHAN if kahan else 0)
+    desc = m.Desc(gx=inst.gx, gy=inst.gy, gt=inst.gt, hs=inst.hs, ht=inst.ht, sres=inst.sres,
+                  tres=inst.tres, x0=inst.x0, y0=inst.y0, t0=inst.t0, flags=flags)
+    plan = m.Plan(desc)
+    pts = torch.from_numpy(inst.points).to(dev)
+    out = torch.empty((inst.gx, inst.gy, inst.gt), dtype=torch.float32, device=dev)
+    stats = torch.zeros(8, dtype=torch.float64, device=dev)
+    ws = plan.workspace(n, dev)
+    stream = torch.cuda.current_stream(dev)
+    _log(f"workload {inst.name}: n={n}, grid {inst.gx}x{inst.gy}x{inst.gt}, "
+         f"workspace {ws.numel() / 2**20:.1f} MiB, kahan={kahan}")
+
+    # exact evaluation count (once, outside the timed region)
+    chk = m.Plan(m.Desc(**{**desc.__dict__, "flags": m.FLAG_POINT_STATS | m.FLAG_MASS}))
+    cstats = torch.zeros(8, dtype=torch.float64, device=dev)
+    chk.compute_into(pts, out, stats=cstats, workspace=ws)
+    torch.cuda.synchronize()
+    cs = cstats.cpu().numpy()
+    evals = int(cs[2])
+    chk.close()
+    _log(f"evals {evals}, point mass {cs[1]:.9f}, grid mass {cs[0]:.9f}")
+
+    for _ in range(args.warmup):
+        plan.compute_into(pts, out, stats=stats, workspace=ws)
+    torch.cuda.synchronize()
+    _log(f"warmup {args.warmup} done")
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        plan.compute_into(pts, out, stats=stats, workspace=ws)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    step_ms = sorted(a.elapsed_time(b) for a, b in ev)
+    _log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step wall, median event {step_ms[len(step_ms) // 2]:.3f} ms")
+    st = stats.cpu().numpy()
+
+    # stage timing: binning and the gather kernel alone (accumulate without
+    # stats is exactly one launch of the gather kernel), on the same stream
+    reps = max(5, args.steps)
+    bev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    gev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for k in range(reps):
+        bev[k][0].record(stream)
+        plan.bin(pts, ws)
+        bev[k][1].record(stream)
+        gev[k][0].record(stream)
+        plan.accumulate(n, out, ws)
+        gev[k][1].record(stream)
+    torch.cuda.synchronize()
+    bin_ms = sum(a.elapsed_time(b) for a, b in bev) / reps
+    gather_ms = sum(a.elapsed_time(b) for a, b in gev) / reps
+    _log(f"stage times: bin {bin_ms:.3f} ms, gather {gather_ms:.3f} ms")
+
+    grid_bytes = inst.gx * inst.gy * inst.gt * 4
+    alg_bytes = grid_bytes + n * 24
+    achieved = alg_bytes / (gather_ms * 1e-3) / 1e9
+    src = open(os.path.join(ROOT, "paper_1705_09366_amd", "csrc", "gather.hip"), "rb").read()
+    traffic = _traffic_from_profile(hashlib.sha256(src).hexdigest())
+
+    value = evals / (ms_per_step * 1e-3)
+    rec = {
+        "metric": "voxel-point kernel evals/s",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": inst.name, "n": n, "grid": [inst.gx, inst.gy, inst.gt],
+                   "hs": inst.hs, "ht": inst.ht, "accumulation": "kahan" if kahan else "plain",
+                   "evals": evals},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "stage_ms": {"bin": bin_ms, "gather": gather_ms},
+        "mass": {"grid": float(st[0]), "points": float(cs[1])},
+    }
+
+    if not args.no_cpu_baseline:
+        def gpu_sample(p):
+            sp = m.Plan(m.Desc(**{**desc.__dict__, "flags": flags & ~m.FLAG_MASS}))
+            o = sp(torch.from_numpy(np.ascontiguousarray(p)).to(dev))
+            torch.cuda.synchronize()
+            r = o.cpu().numpy()
+            sp.close()
+            return r
+        cb, err = cpu_baseline(inst, gpu_sample, args.cpu_budget)
+        rec["cpu_baseline"] = cb
+        rec["max_rel_err_vs_oracle"] = err
+        _log(f"gpu vs oracle on the cpu sample: max rel err {err:.3e}")
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

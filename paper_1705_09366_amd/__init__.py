@@ -1,0 +1,252 @@
+"""Python binding of the gfx950 space-time kernel density library.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libstkde.so`` behind the C ABI of ``include/stkde.h``.  PyTorch
+supplies device memory and the stream.  There is no CPU fallback: if the
+library is missing, importing :func:`lib` raises.
+
+The estimator (Sec. 2.1 of Saule et al., arXiv 1705.09366) is
+
+    f[X][Y][T] = 1/(n hs^2 ht) sum_i ks(u, v) kt(w)
+
+with Epanechnikov kernels ks = (2/pi)(1 - u^2 - v^2) on the unit disc and
+kt = (3/4)(1 - w^2) on [-1, 1], evaluated at voxel centres; it is computed
+by the point-based, symmetry-exploiting PB-SYM method (Sec. 3.2) organised
+as an atomic-free gather over output tiles.
+"""
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libstkde.so")
+
+STKDE_OK = 0
+STKDE_ERR_INVALID_ARG = -1
+STKDE_ERR_TOO_LARGE = -2
+STKDE_ERR_WORKSPACE = -3
+STKDE_ERR_HIP = -4
+STKDE_ERR_UNSUPPORTED = -5
+
+FLAG_KAHAN = 1
+FLAG_MASS = 4
+FLAG_POINT_STATS = 8
+
+EXPORTED = ("stkde_plan", "stkde_plan_destroy", "stkde_workspace_bytes", "stkde_compute",
+            "stkde_bin", "stkde_accumulate", "stkde_status_string", "stkde_version")
+
+
+class StkdeError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [("gx", ctypes.c_int64), ("gy", ctypes.c_int64), ("gt", ctypes.c_int64),
+                ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("t0", ctypes.c_double),
+                ("sres", ctypes.c_double), ("tres", ctypes.c_double),
+                ("hs", ctypes.c_double), ("ht", ctypes.c_double), ("flags", ctypes.c_uint32)]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("tile_t", ctypes.c_int32), ("cell_xy", ctypes.c_int32),
+                ("cell_t", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_LIB = None
+
+
+def lib():
+    """Load libstkde.so (built in-tree by ``build.py``); raise if absent."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_1705_09366_amd/build.py "
+                              "(or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        L.stkde_plan.argtypes = [P(_Desc), P(_Tuning), P(ctypes.c_void_p)]
+        L.stkde_plan_destroy.argtypes = [ctypes.c_void_p]
+        L.stkde_workspace_bytes.argtypes = [ctypes.c_void_p, ctypes.c_int64, P(ctypes.c_size_t)]
+        L.stkde_compute.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                    ctypes.c_void_p, ctypes.c_void_p]
+        L.stkde_bin.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                ctypes.c_size_t, ctypes.c_void_p]
+        L.stkde_accumulate.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                       ctypes.c_void_p]
+        for f in (L.stkde_plan, L.stkde_plan_destroy, L.stkde_workspace_bytes, L.stkde_compute,
+                  L.stkde_bin, L.stkde_accumulate):
+            f.restype = ctypes.c_int
+        L.stkde_status_string.argtypes = [ctypes.c_int]
+        L.stkde_status_string.restype = ctypes.c_char_p
+        L.stkde_version.restype = ctypes.c_int32
+        _LIB = L
+    return _LIB
+
+
+def status_string(status: int) -> str:
+    return lib().stkde_status_string(int(status)).decode()
+
+
+@dataclass(frozen=True)
+class Desc:
+    """Problem description (Sec. 2.1, Table "Notations"): a gx x gy x gt
+    grid of sres x sres x tres voxels cornered at (x0, y0, t0), bandwidths
+    hs, ht in domain units."""
+    gx: int
+    gy: int
+    gt: int
+    hs: float
+    ht: float
+    sres: float = 1.0
+    tres: float = 1.0
+    x0: float = 0.0
+    y0: float = 0.0
+    t0: float = 0.0
+    flags: int = 0
+
+    def _c(self):
+        return _Desc(self.gx, self.gy, self.gt, self.x0, self.y0, self.t0, self.sres, self.tres,
+                     self.hs, self.ht, self.flags)
+
+
+@dataclass(frozen=True)
+class Tuning:
+    tile_t: int = 0
+    cell_xy: int = 0
+    cell_t: int = 0
+
+    def _c(self):
+        return _Tuning(self.tile_t, self.cell_xy, self.cell_t, 0)
+
+
+class Plan:
+    """A plan for one grid and bandwidth pair: ``Plan(desc)(points)`` returns
+    the FP32 density grid as a [gx, gy, gt] CUDA tensor."""
+
+    def __init__(self, desc: Desc, tuning: Optional[Tuning] = None):
+        self.desc = desc
+        self.tuning = tuning
+        h = ctypes.c_void_p()
+        st = lib().stkde_plan(ctypes.byref(desc._c()),
+                              ctypes.byref(tuning._c()) if tuning is not None else None,
+                              ctypes.byref(h))
+        if st != STKDE_OK:
+            raise StkdeError(st, "stkde_plan")
+        self._h = h
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().stkde_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def workspace_bytes(self, n: int) -> int:
+        b = ctypes.c_size_t(0)
+        st = lib().stkde_workspace_bytes(self._h, int(n), ctypes.byref(b))
+        if st != STKDE_OK:
+            raise StkdeError(st, "stkde_workspace_bytes")
+        return int(b.value)
+
+    def workspace(self, n: int, device=None):
+        """A cached uint8 workspace tensor large enough for n points."""
+        import torch
+        need = self.workspace_bytes(n)
+        dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        if self._ws is None or self._ws.numel() < need or self._ws.device != dev:
+            self._ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+        return self._ws
+
+    def compute_into(self, points, out, stats=None, workspace=None, stream=None):
+        """Enqueue the computation on ``stream`` (default: torch's current
+        stream).  points: [n, 3] float64 CUDA tensor; out: float32 CUDA tensor
+        with gx*gy*gt elements; stats: optional float64 CUDA tensor of 8."""
+        import torch
+        n = int(points.shape[0])
+        if points.dtype != torch.float64 or not points.is_cuda or points.dim() != 2 or points.shape[1] != 3:
+            raise ValueError("points must be a [n, 3] float64 CUDA tensor")
+        if not points.is_contiguous():
+            raise ValueError("points must be contiguous")
+        d = self.desc
+        if out.dtype != torch.float32 or not out.is_cuda or out.numel() != d.gx * d.gy * d.gt \
+                or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 CUDA tensor of gx*gy*gt elements")
+        if stats is not None and (stats.dtype != torch.float64 or stats.numel() < 8 or not stats.is_cuda):
+            raise ValueError("stats must be a float64 CUDA tensor of 8 elements")
+        ws = workspace if workspace is not None else self.workspace(n, points.device)
+        base = ws.data_ptr()
+        off = (-base) % 256
+        if stream is None:
+            stream = torch.cuda.current_stream(points.device)
+        st = lib().stkde_compute(self._h, ctypes.c_void_p(points.data_ptr()), n,
+                                 ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(base + off),
+                                 ctypes.c_size_t(ws.numel() - off),
+                                 ctypes.c_void_p(stats.data_ptr()) if stats is not None else None,
+                                 ctypes.c_void_p(stream.cuda_stream))
+        if st != STKDE_OK:
+            raise StkdeError(st, "stkde_compute")
+        return out
+
+    def _ws_args(self, ws):
+        base = ws.data_ptr()
+        off = (-base) % 256
+        return ctypes.c_void_p(base + off), ctypes.c_size_t(ws.numel() - off)
+
+    def bin(self, points, workspace, stream=None):
+        """Stage 1 (stkde_bin): bin the [n, 3] float64 points into workspace."""
+        import torch
+        if points.dtype != torch.float64 or not points.is_cuda or points.dim() != 2 \
+                or points.shape[1] != 3 or not points.is_contiguous():
+            raise ValueError("points must be a contiguous [n, 3] float64 CUDA tensor")
+        if stream is None:
+            stream = torch.cuda.current_stream(points.device)
+        p, nb = self._ws_args(workspace)
+        st = lib().stkde_bin(self._h, ctypes.c_void_p(points.data_ptr()), int(points.shape[0]), p, nb,
+                             ctypes.c_void_p(stream.cuda_stream))
+        if st != STKDE_OK:
+            raise StkdeError(st, "stkde_bin")
+
+    def accumulate(self, n, out, workspace, stats=None, stream=None):
+        """Stage 2 (stkde_accumulate): gather and store the grid from a
+        workspace that :meth:`bin` filled for the same n."""
+        import torch
+        d = self.desc
+        if out.dtype != torch.float32 or not out.is_cuda or out.numel() != d.gx * d.gy * d.gt \
+                or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 CUDA tensor of gx*gy*gt elements")
+        if stats is not None and (stats.dtype != torch.float64 or stats.numel() < 8 or not stats.is_cuda):
+            raise ValueError("stats must be a float64 CUDA tensor of 8 elements")
+        if stream is None:
+            stream = torch.cuda.current_stream(out.device)
+        p, nb = self._ws_args(workspace)
+        st = lib().stkde_accumulate(self._h, int(n), ctypes.c_void_p(out.data_ptr()), p, nb,
+                                    ctypes.c_void_p(stats.data_ptr()) if stats is not None else None,
+                                    ctypes.c_void_p(stream.cuda_stream))
+        if st != STKDE_OK:
+            raise StkdeError(st, "stkde_accumulate")
+        return out
+
+    def __call__(self, points, stats=None):
+        import torch
+        d = self.desc
+        out = torch.empty((d.gx, d.gy, d.gt), dtype=torch.float32, device=points.device)
+        return self.compute_into(points, out, stats=stats)
+
+
+def compute(points, desc: Desc, tuning: Optional[Tuning] = None, stats=None):
+    """One-shot convenience: plan, compute, return the [gx, gy, gt] grid."""
+    return Plan(desc, tuning)(points, stats=stats)

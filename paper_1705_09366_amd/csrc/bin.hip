@@ -1,0 +1,343 @@
+// bin.hip -- binning of points into space-time bins on the device.
+//
+// Stages (all deterministic; atomics appear only in integer counters whose
+// final values do not depend on order):
+//   1. transform: FP64 point -> voxel coordinates, support footprint clipped
+//      to the grid, bin key.  Points whose footprint misses the grid, and
+//      points with a non-finite coordinate, get the key `ncell`, which sorts
+//      after every bin and is never visited.
+//   2. stable LSD radix sort of (key, index) with 8-bit digits, 1-3 passes.
+//      This is the device form of the per-subdomain point lists that the
+//      paper's domain decompositions build on the host (Sec. 4.2, Sec. 5.1).
+//   3. bin offsets: cell_start[c] = first sorted position with key >= c.
+//   4. records: per sorted point, the 32-byte PointRec and the time-kernel
+//      table kt(T) = 1 - w^2, w = (T + 1/2 - tr)/tv, over its window in rows
+//      aligned to multiples of 4 (the temporal invariant of PB-SYM, Sec. 3.2,
+//      computed once per point in FP64 and rounded once to FP32).
+#include "stkde_internal.h"
+
+namespace stkde {
+namespace {
+
+struct Footprint {
+    double xr, yr, tr;
+    int32_t xlo, xhi, ylo, yhi, tlo, thi;
+    int32_t fx, fy, ft;  // floor of the voxel coordinate, clamped to [-1, G]
+    bool finite, inside;
+};
+
+__device__ inline int32_t clamp_i(int32_t v, int32_t lo, int32_t hi) {
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+__device__ inline int32_t floordiv(int32_t a, int32_t b) {
+    int32_t q = a / b;
+    return (a % b != 0 && (a < 0)) ? q - 1 : q;
+}
+
+// Voxel-space footprint of one point.  Column X is inside the disc when
+// |X + 1/2 - xr| < hv; row T is inside the window when |T + 1/2 - tr| <= tv.
+// The integer ranges below are those sets up to rows where the kernel value
+// is zero to rounding, clipped to the grid.
+__device__ inline Footprint footprint(const Geometry& g, double x, double y, double t) {
+    Footprint f;
+    f.finite = isfinite(x) && isfinite(y) && isfinite(t);
+    f.inside = false;
+    f.xr = (x - g.x0) / g.sres;
+    f.yr = (y - g.y0) / g.sres;
+    f.tr = (t - g.t0) / g.tres;
+    f.xlo = f.xhi = f.ylo = f.yhi = f.tlo = f.thi = 0;
+    f.fx = f.fy = f.ft = 0;
+    if (!f.finite) return f;
+    // reject far-away points before any conversion to integers
+    if (f.xr + g.hv < -1.0 || f.xr - g.hv > (double)g.gx + 1.0) return f;
+    if (f.yr + g.hv < -1.0 || f.yr - g.hv > (double)g.gy + 1.0) return f;
+    if (f.tr + g.tv < -1.0 || f.tr - g.tv > (double)g.gt + 1.0) return f;
+    const double xlo = floor(f.xr - g.hv - 0.5) + 1.0, xhi = ceil(f.xr + g.hv - 0.5) - 1.0;
+    const double ylo = floor(f.yr - g.hv - 0.5) + 1.0, yhi = ceil(f.yr + g.hv - 0.5) - 1.0;
+    const double tlo = ceil(f.tr - g.tv - 0.5), thi = floor(f.tr + g.tv - 0.5);
+    f.xlo = (int32_t)fmax(xlo, 0.0);
+    f.xhi = (int32_t)fmin(xhi, (double)(g.gx - 1));
+    f.ylo = (int32_t)fmax(ylo, 0.0);
+    f.yhi = (int32_t)fmin(yhi, (double)(g.gy - 1));
+    f.tlo = (int32_t)fmax(tlo, 0.0);
+    f.thi = (int32_t)fmin(thi, (double)(g.gt - 1));
+    f.inside = f.xlo <= f.xhi && f.ylo <= f.yhi && f.tlo <= f.thi;
+    f.fx = (int32_t)fmin(fmax(floor(f.xr), -1.0), (double)g.gx);
+    f.fy = (int32_t)fmin(fmax(floor(f.yr), -1.0), (double)g.gy);
+    f.ft = (int32_t)fmin(fmax(floor(f.tr), -1.0), (double)g.gt);
+    return f;
+}
+
+__device__ inline uint32_t bin_key(const Geometry& g, const Footprint& f) {
+    const int32_t cx = clamp_i(floordiv(f.fx, g.cxy), 0, g.ncx - 1);
+    const int32_t cy = clamp_i(floordiv(f.fy, g.cxy), 0, g.ncy - 1);
+    const int32_t ct = clamp_i(floordiv(f.ft, g.ct), 0, g.nct - 1);
+    return (uint32_t)((ct * g.ncy + cy) * g.ncx + cx);
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0ull;
+}
+
+__global__ __launch_bounds__(kThreads) void k_transform(Geometry g, const double* __restrict__ xyt,
+                                                        int32_t n, uint32_t* __restrict__ keys,
+                                                        uint32_t* __restrict__ vals,
+                                                        unsigned long long* __restrict__ counters) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    bool nonfinite = false, culled = false;
+    if (i < n) {
+        const Footprint f = footprint(g, xyt[3 * (size_t)i], xyt[3 * (size_t)i + 1],
+                                      xyt[3 * (size_t)i + 2]);
+        uint32_t key = (uint32_t)g.ncell;
+        if (!f.finite) nonfinite = true;
+        else if (!f.inside) culled = true;
+        else key = bin_key(g, f);
+        keys[i] = key;
+        vals[i] = (uint32_t)i;
+    }
+    const unsigned long long mnf = __ballot(nonfinite), mcu = __ballot(culled);
+    if ((threadIdx.x & 63) == 0) {
+        if (mnf) atomicAdd(&counters[0], (unsigned long long)__popcll(mnf));
+        if (mcu) atomicAdd(&counters[1], (unsigned long long)__popcll(mcu));
+    }
+}
+
+// ---- stable LSD radix sort, 8-bit digits --------------------------------
+
+// Per-block digit histogram.  hist is digit-major: hist[d * nblk + b].
+__global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
+                                                         int32_t n, int shift,
+                                                         uint32_t* __restrict__ hist,
+                                                         int32_t nblk) {
+    __shared__ uint32_t cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int32_t base = blockIdx.x * kSortTile;
+#pragma unroll 4
+    for (int it = 0; it < kSortItems; ++it) {
+        const int32_t i = base + it * kThreads + threadIdx.x;
+        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Exclusive scan of hist (count entries) in place, by one workgroup of 1024
+// threads walking the array in order with a running carry.
+__global__ __launch_bounds__(1024) void k_scan_exclusive(uint32_t* __restrict__ a, int32_t count) {
+    __shared__ uint32_t wsum[16];
+    __shared__ uint32_t carry_s;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (tid == 0) carry_s = 0;
+    __syncthreads();
+    for (int32_t base = 0; base < count; base += 1024 * 4) {
+        uint32_t v[4], s = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int32_t i = base + tid * 4 + k;
+            v[k] = i < count ? a[i] : 0u;
+            s += v[k];
+        }
+        // inclusive scan of s across the wave
+        uint32_t inc = s;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t o = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += o;
+        }
+        if (lane == 63) wsum[wv] = inc;
+        __syncthreads();
+        uint32_t wpre = 0, total = 0;
+        for (int k = 0; k < 16; ++k) {
+            const uint32_t ws = wsum[k];
+            if (k < wv) wpre += ws;
+            total += ws;
+        }
+        const uint32_t carry = carry_s;
+        uint32_t run = carry + wpre + inc - s;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int32_t i = base + tid * 4 + k;
+            if (i < count) a[i] = run;
+            run += v[k];
+        }
+        __syncthreads();
+        if (tid == 0) carry_s = carry + total;
+        __syncthreads();
+    }
+}
+
+// Stable scatter.  Keys of a block are processed in index order: round r
+// covers indices base + r*256 + [0, 256), waves in order, lanes in order.
+// The rank of a key among equal digits is (keys of that digit in earlier
+// rounds) + (in earlier waves of this round) + (in earlier lanes).
+__global__ __launch_bounds__(kThreads) void k_radix_scatter(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, int32_t n, int shift,
+    const uint32_t* __restrict__ hist, int32_t nblk, uint32_t* __restrict__ kout,
+    uint32_t* __restrict__ vout) {
+    __shared__ uint32_t off[256];
+    __shared__ uint32_t wcnt[kWaves][256];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    off[tid] = hist[tid * nblk + blockIdx.x];
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    const int32_t base = blockIdx.x * kSortTile;
+    const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int r = 0; r < kSortItems; ++r) {
+        const int32_t i = base + r * kThreads + tid;
+        const bool valid = i < n;
+        uint32_t key = 0, val = 0, d = 0;
+        if (valid) {
+            key = kin[i];
+            val = vin[i];
+            d = (key >> shift) & 255u;
+        }
+        unsigned long long peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const unsigned long long bb = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? bb : ~bb;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+        if (valid && rank == 0) wcnt[wv][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = off[d] + rank;
+            for (int w = 0; w < wv; ++w) pos += wcnt[w][d];
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        {
+            uint32_t add = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) {
+                add += wcnt[w][tid];
+                wcnt[w][tid] = 0;
+            }
+            off[tid] += add;
+        }
+        __syncthreads();
+    }
+}
+
+// cell_start[c] = lower_bound(sorted keys, c) for c in [0, ncell].
+__global__ void k_cell_start(const uint32_t* __restrict__ keys, int32_t n, int32_t ncell,
+                             uint32_t* __restrict__ cell_start) {
+    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > ncell) return;
+    int32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (keys[mid] < (uint32_t)c) lo = mid + 1;
+        else hi = mid;
+    }
+    cell_start[c] = (uint32_t)lo;
+}
+
+__global__ __launch_bounds__(kThreads) void k_records(Geometry g, const double* __restrict__ xyt,
+                                                      const uint32_t* __restrict__ vals,
+                                                      const uint32_t* __restrict__ cell_start,
+                                                      int32_t n, PointRec* __restrict__ recs,
+                                                      float* __restrict__ kt) {
+    const int64_t s = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (s >= n) return;
+    const int64_t nvalid = (int64_t)cell_start[g.ncell];
+    if (s >= nvalid) return;
+    const uint32_t i = vals[s];
+    const Footprint f = footprint(g, xyt[3 * (size_t)i], xyt[3 * (size_t)i + 1],
+                                  xyt[3 * (size_t)i + 2]);
+    PointRec r;
+    r.xh = (float)f.xr;
+    r.xl = (float)(f.xr - (double)r.xh);
+    r.yh = (float)f.yr;
+    r.yl = (float)(f.yr - (double)r.yh);
+    r.xb = (uint32_t)f.xlo | ((uint32_t)f.xhi << 16);
+    r.yb = (uint32_t)f.ylo | ((uint32_t)f.yhi << 16);
+    // The window spans at most g.wrows rows in exact arithmetic; the clamp
+    // keeps the table reads of the gather inside the row even if rounding
+    // of the bounds ever said otherwise.
+    const int32_t thi = min(f.thi, f.tlo + g.wrows - 1);
+    r.tlo = f.tlo;
+    r.thi = thi;
+    recs[s] = r;
+    const int32_t tb = f.tlo & ~(kChunk - 1);
+    float4* row = reinterpret_cast<float4*>(kt + (size_t)s * g.ktw);
+    for (int k = 0; k < g.ktw; k += 4) {
+        float v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int32_t T = tb + k + q;
+            const double w = ((double)T + 0.5 - f.tr) / g.tv;
+            v[q] = (T >= f.tlo && T <= thi && fabs(w) <= 1.0) ? (float)(1.0 - w * w) : 0.0f;
+        }
+        row[k >> 2] = make_float4(v[0], v[1], v[2], v[3]);
+    }
+}
+
+inline int bits_for(uint32_t v) {
+    int b = 0;
+    while (b < 32 && (v >> b) != 0u) ++b;
+    return b;
+}
+
+}  // namespace
+
+Workspace layout_workspace(const Geometry& g, int64_t n) {
+    Workspace w{};
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    size_t o = 0;
+    const size_t nn = (size_t)n;
+    w.nblk_sort = (int32_t)((n + kSortTile - 1) / kSortTile);
+    w.nblk_pts = (int32_t)((n + kStatBlock - 1) / kStatBlock);
+    w.keys0 = o; o = al(o + nn * 4);
+    w.vals0 = o; o = al(o + nn * 4);
+    w.keys1 = o; o = al(o + nn * 4);
+    w.vals1 = o; o = al(o + nn * 4);
+    w.hist = o; o = al(o + (size_t)256 * w.nblk_sort * 4);
+    w.cell_start = o; o = al(o + ((size_t)g.ncell + 1) * 4);
+    w.recs = o; o = al(o + nn * sizeof(PointRec));
+    w.kt = o; o = al(o + nn * (size_t)g.ktw * 4);
+    w.tile_part = o; o = al(o + (size_t)g.ntiles * kWaves * 8);
+    w.pt_part = o; o = al(o + (size_t)w.nblk_pts * 4 * 8);
+    w.counters = o; o = al(o + 4 * 8);
+    w.total = o;
+    return w;
+}
+
+hipError_t launch_bin(const Geometry& g, const double* d_xyt, int32_t n, uint8_t* ws,
+                      const Workspace& w, hipStream_t s) {
+    uint32_t* k0 = reinterpret_cast<uint32_t*>(ws + w.keys0);
+    uint32_t* v0 = reinterpret_cast<uint32_t*>(ws + w.vals0);
+    uint32_t* k1 = reinterpret_cast<uint32_t*>(ws + w.keys1);
+    uint32_t* v1 = reinterpret_cast<uint32_t*>(ws + w.vals1);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(ws + w.hist);
+    uint32_t* cs = reinterpret_cast<uint32_t*>(ws + w.cell_start);
+    unsigned long long* ctr = reinterpret_cast<unsigned long long*>(ws + w.counters);
+    const int nb = (n + kThreads - 1) / kThreads;
+
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ctr, 4);
+    hipLaunchKernelGGL(k_transform, dim3(nb), dim3(kThreads), 0, s, g, d_xyt, n, k0, v0, ctr);
+
+    const int bits = bits_for((uint32_t)g.ncell);
+    const int passes = bits <= 8 ? 1 : (bits + 7) / 8;
+    for (int p = 0; p < passes; ++p) {
+        hipLaunchKernelGGL(k_radix_hist, dim3(w.nblk_sort), dim3(kThreads), 0, s, k0, n, 8 * p,
+                           hist, w.nblk_sort);
+        hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, s, hist, 256 * w.nblk_sort);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(w.nblk_sort), dim3(kThreads), 0, s, k0, v0, n,
+                           8 * p, hist, w.nblk_sort, k1, v1);
+        std::swap(k0, k1);
+        std::swap(v0, v1);
+    }
+    const int nc = (g.ncell + 1 + kThreads - 1) / kThreads;
+    hipLaunchKernelGGL(k_cell_start, dim3(nc), dim3(kThreads), 0, s, k0, n, g.ncell, cs);
+    hipLaunchKernelGGL(k_records, dim3(nb), dim3(kThreads), 0, s, g, d_xyt, v0, cs, n,
+                       reinterpret_cast<PointRec*>(ws + w.recs), reinterpret_cast<float*>(ws + w.kt));
+    return hipGetLastError();
+}
+
+}  // namespace stkde

@@ -1,0 +1,150 @@
+// stats.hip -- per-point FP64 checks of a computed grid (not on the hot path).
+//
+// Because clipping a cylinder to the grid is a box and the kernel is a
+// product of a spatial and a temporal factor (the separability PB-SYM
+// exploits, Sec. 3.2), the mass point i deposits on the grid is
+// Ss(i) * St(i) / (n hs^2 ht), with Ss(i) the sum of ks over its in-grid
+// columns and St(i) the sum of kt over its in-grid rows, and the number of
+// (voxel, point) pairs it is evaluated on is cs(i) * ct(i).  This kernel
+// evaluates those sums in FP64 with the support tests of Alg. VB / PB-SYM
+// written in domain units (spatial distance < hs via a square root, time
+// distance <= ht), in the same precision and the same form as the CPU
+// reference, so that the integer counts agree exactly.
+#include "stkde_internal.h"
+
+namespace stkde {
+namespace {
+
+__device__ inline bool clip_rng(double v, double h, int32_t lo, int32_t hi, int32_t* a, int32_t* b) {
+    const double da = v - h, db = v + h;
+    if (db < (double)lo || da > (double)(hi - 1)) return false;
+    *a = da < (double)lo ? lo : (int32_t)da;
+    *b = db > (double)(hi - 1) ? hi - 1 : (int32_t)db;
+    return *a <= *b;
+}
+
+__global__ __launch_bounds__(kStatBlock) void k_point_stats(Geometry g, const double* __restrict__ xyt,
+                                                            int32_t n, double* __restrict__ part) {
+#pragma clang fp contract(off)
+    __shared__ double sm[kStatBlock];
+    __shared__ double se[kStatBlock];
+    const int32_t i = blockIdx.x * kStatBlock + threadIdx.x;
+    double mass = 0.0, evals = 0.0;
+    if (i < n) {
+        const double xi = xyt[3 * (size_t)i], yi = xyt[3 * (size_t)i + 1], ti = xyt[3 * (size_t)i + 2];
+        if (isfinite(xi) && isfinite(yi) && isfinite(ti)) {
+            const double Xi = floor((xi - g.x0) / g.sres);
+            const double Yi = floor((yi - g.y0) / g.sres);
+            const double Ti = floor((ti - g.t0) / g.tres);
+            int32_t xa, xb, ya, yb, ta, tb;
+            double ss = 0.0, st = 0.0;
+            long long cs = 0, ct = 0;
+            if (clip_rng(Xi, g.Hs_d, 0, g.gx, &xa, &xb) && clip_rng(Yi, g.Hs_d, 0, g.gy, &ya, &yb)) {
+                for (int32_t X = xa; X <= xb; ++X) {
+                    const double x = g.x0 + ((double)X + 0.5) * g.sres;
+                    for (int32_t Y = ya; Y <= yb; ++Y) {
+                        const double y = g.y0 + ((double)Y + 0.5) * g.sres;
+                        const double d = sqrt((xi - x) * (xi - x) + (yi - y) * (yi - y));
+                        if (d < g.hs) {
+                            const double u = (x - xi) / g.hs, v = (y - yi) / g.hs;
+                            ss += (2.0 / 3.14159265358979323846) * (1.0 - u * u - v * v);
+                            ++cs;
+                        }
+                    }
+                }
+            }
+            if (clip_rng(Ti, g.Ht_d, 0, g.gt, &ta, &tb)) {
+                for (int32_t T = ta; T <= tb; ++T) {
+                    const double t = g.t0 + ((double)T + 0.5) * g.tres;
+                    if (fabs(ti - t) <= g.ht) {
+                        const double w = (t - ti) / g.ht;
+                        st += 0.75 * (1.0 - w * w);
+                        ++ct;
+                    }
+                }
+            }
+            mass = ss * st;
+            evals = (double)(cs * ct);
+        }
+    }
+    sm[threadIdx.x] = mass;
+    se[threadIdx.x] = evals;
+    __syncthreads();
+    for (int w = kStatBlock / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sm[threadIdx.x] += sm[threadIdx.x + w];
+            se[threadIdx.x] += se[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[4 * (size_t)blockIdx.x + 0] = sm[0];
+        part[4 * (size_t)blockIdx.x + 1] = se[0];
+        part[4 * (size_t)blockIdx.x + 2] = 0.0;
+        part[4 * (size_t)blockIdx.x + 3] = 0.0;
+    }
+}
+
+// d_stats[1] = sum of mass partials / (n hs^2 ht) * sres^2 tres;
+// d_stats[2] = sum of evaluation counts (exact below 2^53).
+__global__ __launch_bounds__(1024) void k_stats_final(const double* __restrict__ part, int32_t nblk,
+                                                      double scale, double* __restrict__ stats) {
+    __shared__ double sm[1024];
+    __shared__ double se[1024];
+    double a = 0.0, b = 0.0;
+    for (int32_t k = threadIdx.x; k < nblk; k += 1024) {
+        a += part[4 * (size_t)k];
+        b += part[4 * (size_t)k + 1];
+    }
+    sm[threadIdx.x] = a;
+    se[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 512; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sm[threadIdx.x] += sm[threadIdx.x + w];
+            se[threadIdx.x] += se[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        stats[1] = sm[0] * scale;
+        stats[2] = se[0];
+    }
+}
+
+// d_stats[3], [4] from the binning counters; [5..7] = 0; [0..2] = 0 unless
+// another stage fills them afterwards.
+__global__ void k_stats_counters(const unsigned long long* __restrict__ ctr, double* __restrict__ stats) {
+    if (threadIdx.x == 0) {
+        stats[0] = 0.0;
+        stats[1] = 0.0;
+        stats[2] = 0.0;
+        stats[3] = (double)ctr[0];
+        stats[4] = (double)ctr[1];
+        stats[5] = 0.0;
+        stats[6] = 0.0;
+        stats[7] = 0.0;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_stats(const Geometry& g, const double* d_xyt, int32_t n, bool point_stats,
+                        double* d_stats, uint8_t* ws, const Workspace& w, hipStream_t s) {
+    hipLaunchKernelGGL(k_stats_counters, dim3(1), dim3(64), 0, s,
+                       reinterpret_cast<const unsigned long long*>(ws + w.counters), d_stats);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !point_stats) return e;
+    return launch_point_stats(g, d_xyt, n, d_stats, ws, w, s);
+}
+
+hipError_t launch_point_stats(const Geometry& g, const double* d_xyt, int32_t n, double* d_stats,
+                              uint8_t* ws, const Workspace& w, hipStream_t s) {
+    double* part = reinterpret_cast<double*>(ws + w.pt_part);
+    hipLaunchKernelGGL(k_point_stats, dim3(w.nblk_pts), dim3(kStatBlock), 0, s, g, d_xyt, n, part);
+    const double scale = g.sres * g.sres * g.tres / ((double)n * g.hs * g.hs * g.ht);
+    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(1024), 0, s, part, w.nblk_pts, scale, d_stats);
+    return hipGetLastError();
+}
+
+}  // namespace stkde

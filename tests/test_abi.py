@@ -1,0 +1,112 @@
+"""Host-side checks of the C ABI that run without a GPU: the library loads,
+exports every entry point declared in include/stkde.h, and rejects invalid
+arguments on the host before anything is enqueued."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "stkde.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(stkde_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_1705_09366_amd as m
+    if not os.path.exists(m.LIB_PATH):
+        pytest.fail("libstkde.so is not built (run __graft_entry__.build())")
+    return m
+
+
+def test_exports_every_declared_symbol(L):
+    lib = L.lib()
+    decl = _declared_symbols()
+    assert "stkde_compute" in decl and "stkde_plan" in decl
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert set(decl) == set(L.EXPORTED)
+
+
+def test_status_strings_and_version(L):
+    assert L.status_string(0) == "ok"
+    assert "workspace" in L.status_string(L.STKDE_ERR_WORKSPACE)
+    assert L.lib().stkde_version() >= 100
+
+
+def _plan_status(L, **kw):
+    base = dict(gx=16, gy=16, gt=16, hs=2.0, ht=2.0)
+    base.update(kw)
+    d = L.Desc(**base)
+    h = ctypes.c_void_p()
+    st = L.lib().stkde_plan(ctypes.byref(d._c()), None, ctypes.byref(h))
+    if st == 0:
+        L.lib().stkde_plan_destroy(h)
+    return st
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(), 0),
+    (dict(gx=0), -1), (dict(gy=-3), -1), (dict(gt=0), -1),
+    (dict(gx=70000), -2),
+    (dict(hs=0.0), -1), (dict(ht=-1.0), -1), (dict(hs=float("nan")), -1),
+    (dict(sres=0.0), -1), (dict(tres=float("inf")), -1),
+    (dict(x0=float("nan")), -1),
+    (dict(flags=1 << 10), -1),
+    (dict(hs=1e12), -2),
+])
+def test_plan_validation(L, kw, expect):
+    assert _plan_status(L, **kw) == expect
+
+
+def test_tuning_validation(L):
+    d = L.Desc(gx=16, gy=16, gt=16, hs=2.0, ht=2.0)
+    for bad in (L.Tuning(tile_t=8), L.Tuning(cell_xy=12), L.Tuning(cell_t=2), L.Tuning(cell_xy=512)):
+        with pytest.raises(L.StkdeError):
+            L.Plan(d, bad)
+    L.Plan(d, L.Tuning(tile_t=16, cell_xy=32, cell_t=8)).close()
+
+
+def test_workspace_bytes_monotone(L):
+    p = L.Plan(L.Desc(gx=100, gy=90, gt=70, hs=5.0, ht=4.0))
+    a, b = p.workspace_bytes(1000), p.workspace_bytes(100000)
+    assert 0 < a < b
+    with pytest.raises(L.StkdeError):
+        p.workspace_bytes(0)
+
+
+def test_compute_rejects_before_launch(L):
+    """Every one of these fails host-side validation, so no HIP call is made
+    and the test is safe without a GPU."""
+    lib = L.lib()
+    p = L.Plan(L.Desc(gx=32, gy=32, gt=32, hs=3.0, ht=3.0))
+    need = p.workspace_bytes(10)
+    fake = ctypes.c_void_p(0x10000)
+    h = p.handle
+    assert lib.stkde_compute(None, fake, 10, fake, fake, need, None, None) == -1
+    assert lib.stkde_compute(h, None, 10, fake, fake, need, None, None) == -1
+    assert lib.stkde_compute(h, fake, 10, None, fake, need, None, None) == -1
+    assert lib.stkde_compute(h, fake, 0, fake, fake, need, None, None) == -1
+    assert lib.stkde_compute(h, fake, 1 << 31, fake, fake, need, None, None) == -2
+    assert lib.stkde_compute(h, fake, 10, fake, None, need, None, None) == -3
+    assert lib.stkde_compute(h, fake, 10, fake, fake, need - 1, None, None) == -3
+    assert lib.stkde_compute(h, fake, 10, fake, ctypes.c_void_p(0x10010), need, None, None) == -3
+
+
+def test_oracle_and_library_share_no_code():
+    """The oracle and the GPU path are independent: neither source tree
+    includes or imports the other."""
+    for dp, _, files in os.walk(os.path.join(ROOT, "paper_1705_09366_amd")):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                s = open(os.path.join(dp, f)).read()
+                assert "oracle" not in s.lower().replace("oracles", ""), os.path.join(dp, f)
+    for f in os.listdir(os.path.join(ROOT, "oracle")):
+        if f.endswith((".py", ".c", ".h")):
+            s = open(os.path.join(ROOT, "oracle", f)).read()
+            assert "paper_1705_09366_amd" not in s and "stkde.h" not in s, f
