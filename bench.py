@@ -111,6 +111,9 @@ def main():
     ap.add_argument("--plain", action="store_true", help="plain FP32 accumulation (no Kahan)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--tile-t", type=int, default=0, help="tuning: time rows per tile (16/32)")
+    ap.add_argument("--cell-xy", type=int, default=0, help="tuning: bin edge in x, y")
+    ap.add_argument("--cell-t", type=int, default=0, help="tuning: bin edge in t")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -136,7 +139,9 @@ def main():
     flags = m.FLAG_MASS | (m.FLAG_KAHAN if kahan else 0)
     desc = m.Desc(gx=inst.gx, gy=inst.gy, gt=inst.gt, hs=inst.hs, ht=inst.ht, sres=inst.sres,
                   tres=inst.tres, x0=inst.x0, y0=inst.y0, t0=inst.t0, flags=flags)
-    plan = m.Plan(desc)
+    tuning = m.Tuning(args.tile_t, args.cell_xy, args.cell_t) \
+        if (args.tile_t or args.cell_xy or args.cell_t) else None
+    plan = m.Plan(desc, tuning)
     pts = torch.from_numpy(inst.points).to(dev)
     out = torch.empty((inst.gx, inst.gy, inst.gt), dtype=torch.float32, device=dev)
     stats = torch.zeros(8, dtype=torch.float64, device=dev)
@@ -146,7 +151,7 @@ def main():
          f"workspace {ws.numel() / 2**20:.1f} MiB, kahan={kahan}")
 
     # exact evaluation count (once, outside the timed region)
-    chk = m.Plan(m.Desc(**{**desc.__dict__, "flags": m.FLAG_POINT_STATS | m.FLAG_MASS}))
+    chk = m.Plan(m.Desc(**{**desc.__dict__, "flags": m.FLAG_POINT_STATS | m.FLAG_MASS}), tuning)
     cstats = torch.zeros(8, dtype=torch.float64, device=dev)
     chk.compute_into(pts, out, stats=cstats, workspace=ws)
     torch.cuda.synchronize()
@@ -214,7 +219,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": inst.name, "n": n, "grid": [inst.gx, inst.gy, inst.gt],
                    "hs": inst.hs, "ht": inst.ht, "accumulation": "kahan" if kahan else "plain",
-                   "evals": evals},
+                   "evals": evals,
+                   "tuning": [args.tile_t, args.cell_xy, args.cell_t] if tuning else "default"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "stage_ms": {"bin": bin_ms, "gather": gather_ms},
@@ -223,7 +229,7 @@ def main():
 
     if not args.no_cpu_baseline:
         def gpu_sample(p):
-            sp = m.Plan(m.Desc(**{**desc.__dict__, "flags": flags & ~m.FLAG_MASS}))
+            sp = m.Plan(m.Desc(**{**desc.__dict__, "flags": flags & ~m.FLAG_MASS}), tuning)
             o = sp(torch.from_numpy(np.ascontiguousarray(p)).to(dev))
             torch.cuda.synchronize()
             r = o.cpu().numpy()

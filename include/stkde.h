@@ -77,14 +77,16 @@ typedef struct {
     uint32_t flags;     /* STKDE_FLAG_* */
 } stkde_desc;
 
-/* Optional tuning of one plan (tile shape, points per pass).  Zero fields
- * mean "library default".  tile_t must be 0, 16 or 32; cell_xy a multiple
- * of 8 in [8, 256]; cell_t a multiple of 4 in [4, 256]. */
+/* Optional tuning of one plan.  Zero fields mean "library default".
+ * tile_t must be 0, 16 or 32; cell_xy and cell_t in [4, 256].  The plan may
+ * enlarge the bins beyond these values when a tile would otherwise read
+ * more bin rows than the gather supports.  Tuning changes the summation
+ * order, so results differ between tunings in the last bits. */
 typedef struct {
-    int32_t tile_t;   /* voxel rows in time held per lane (registers) */
+    int32_t tile_t;   /* voxel rows in time per output tile (16 or 32) */
     int32_t cell_xy;  /* bin edge in x and y, voxels */
     int32_t cell_t;   /* bin edge in t, voxels */
-    int32_t reserved;
+    int32_t reserved; /* must be 0 */
 } stkde_tuning;
 
 typedef struct stkde_plan_s* stkde_plan_t;

@@ -57,9 +57,9 @@ stkde_status stkde_plan(const stkde_desc* d, const stkde_tuning* tun, stkde_plan
     int32_t tile_t = 0, cell_xy = 0, cell_t = 0;
     if (tun) {
         if (tun->tile_t != 0 && tun->tile_t != 16 && tun->tile_t != 32) return STKDE_ERR_INVALID_ARG;
-        if (tun->cell_xy != 0 && (tun->cell_xy < 8 || tun->cell_xy > 256 || tun->cell_xy % 8))
+        if (tun->cell_xy != 0 && (tun->cell_xy < 4 || tun->cell_xy > 256))
             return STKDE_ERR_INVALID_ARG;
-        if (tun->cell_t != 0 && (tun->cell_t < 4 || tun->cell_t > 256 || tun->cell_t % 4))
+        if (tun->cell_t != 0 && (tun->cell_t < 4 || tun->cell_t > 256))
             return STKDE_ERR_INVALID_ARG;
         tile_t = tun->tile_t;
         cell_xy = tun->cell_xy;
@@ -90,22 +90,32 @@ stkde_status stkde_plan(const stkde_desc* d, const stkde_tuning* tun, stkde_plan
     g.Hs_d = ceil(g.hv);
     g.Ht_d = ceil(g.tv);
     g.inv_hv2 = (float)(1.0 / (g.hv * g.hv));
-    g.inv_tv = (float)(1.0 / g.tv);
+    g.inv_tv2 = (float)(1.0 / (g.tv * g.tv));
 
-    g.tile_t = tile_t ? tile_t : (d->gt >= 24 ? 32 : 16);
-    g.cxy = cell_xy ? cell_xy : 16;
-    g.ct = cell_t ? cell_t : 16;
+    g.tile_t = tile_t ? tile_t : 32;
+    // Bins about as wide as the bandwidth (the paper's bandwidth-sized
+    // blocks of points, Sec. 4.2 and Sec. 5.1): a tile then reads a few bin
+    // rows, and few of the candidates it reads miss it.
+    g.cxy = cell_xy ? cell_xy : (int32_t)fmin(256.0, fmax(16.0, 8.0 * ceil(g.Hs / 8.0)));
+    g.ct = cell_t ? cell_t : (int32_t)fmin(256.0, fmax(8.0, 4.0 * ceil(g.Ht / 4.0)));
+    // most bins an interval of L voxels can touch when bins are c wide
+    auto span = [](int64_t L, int64_t c) { return (L - 1) / c + 2; };
     for (;;) {
         g.ncx = ceil_div(d->gx, g.cxy);
         g.ncy = ceil_div(d->gy, g.cxy);
         g.nct = ceil_div(d->gt, g.ct);
         const int64_t nc = (int64_t)g.ncx * g.ncy * g.nct;
-        if (nc <= kMaxCells) {
+        const int64_t ny = span(stkde::kTileXY + 2 * (int64_t)g.Hs + 2, g.cxy);
+        const int64_t nt = span(g.tile_t + 2 * (int64_t)g.Ht + 2, g.ct);
+        const int64_t ry = ny < g.ncy ? ny : g.ncy, rt = nt < g.nct ? nt : g.nct;
+        if (nc <= kMaxCells && ry * rt <= stkde::kMaxRanges) {
             g.ncell = (int32_t)nc;
+            g.max_ranges = (int32_t)(ry * rt);
             break;
         }
-        if (g.cxy < 4096) g.cxy *= 2;
-        if (g.ct < 4096) g.ct *= 2;
+        // grow the dimension that contributes more bin rows
+        if ((ry >= rt && g.cxy < 65536) || g.ct >= 65536) g.cxy *= 2;
+        else g.ct *= 2;
     }
     g.ntx = ceil_div(d->gx, stkde::kTileXY);
     g.nty = ceil_div(d->gy, stkde::kTileXY);
@@ -113,11 +123,6 @@ stkde_status stkde_plan(const stkde_desc* d, const stkde_tuning* tun, stkde_plan
     const int64_t nt = (int64_t)g.ntx * g.nty * g.ntt;
     if (nt > 0x7fffffffLL) return STKDE_ERR_TOO_LARGE;
     g.ntiles = (int32_t)nt;
-    // rows of one point's time-kernel table: the clipped window plus the
-    // alignment of its first row down to a multiple of 4
-    const int32_t wrows = (int32_t)fmin(2.0 * g.Ht + 1.0, (double)d->gt);
-    g.wrows = wrows;
-    g.ktw = ((wrows + 3) + 3) & ~3;
 
     stkde_plan_s* p = new (std::nothrow) stkde_plan_s;
     if (!p) return STKDE_ERR_TOO_LARGE;

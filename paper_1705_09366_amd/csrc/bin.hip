@@ -10,10 +10,8 @@
 //      This is the device form of the per-subdomain point lists that the
 //      paper's domain decompositions build on the host (Sec. 4.2, Sec. 5.1).
 //   3. bin offsets: cell_start[c] = first sorted position with key >= c.
-//   4. records: per sorted point, the 32-byte PointRec and the time-kernel
-//      table kt(T) = 1 - w^2, w = (T + 1/2 - tr)/tv, over its window in rows
-//      aligned to multiples of 4 (the temporal invariant of PB-SYM, Sec. 3.2,
-//      computed once per point in FP64 and rounded once to FP32).
+//   4. records: per sorted point, the 32-byte PointRec (voxel-space
+//      coordinates as FP32 head + FP16 tail, and the clipped footprint box).
 #include "stkde_internal.h"
 
 namespace stkde {
@@ -238,11 +236,16 @@ __global__ void k_cell_start(const uint32_t* __restrict__ keys, int32_t n, int32
     cell_start[c] = (uint32_t)lo;
 }
 
+// FP16 bit pattern of the tail v - head (|tail| <= half an FP32 ulp of v).
+__device__ inline uint32_t pack_tail(double v, float head) {
+    const _Float16 h = (_Float16)(float)(v - (double)head);
+    return (uint32_t)__builtin_bit_cast(uint16_t, h);
+}
+
 __global__ __launch_bounds__(kThreads) void k_records(Geometry g, const double* __restrict__ xyt,
                                                       const uint32_t* __restrict__ vals,
                                                       const uint32_t* __restrict__ cell_start,
-                                                      int32_t n, PointRec* __restrict__ recs,
-                                                      float* __restrict__ kt) {
+                                                      int32_t n, PointRec* __restrict__ recs) {
     const int64_t s = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (s >= n) return;
     const int64_t nvalid = (int64_t)cell_start[g.ncell];
@@ -252,30 +255,14 @@ __global__ __launch_bounds__(kThreads) void k_records(Geometry g, const double* 
                                   xyt[3 * (size_t)i + 2]);
     PointRec r;
     r.xh = (float)f.xr;
-    r.xl = (float)(f.xr - (double)r.xh);
     r.yh = (float)f.yr;
-    r.yl = (float)(f.yr - (double)r.yh);
+    r.th = (float)f.tr;
     r.xb = (uint32_t)f.xlo | ((uint32_t)f.xhi << 16);
     r.yb = (uint32_t)f.ylo | ((uint32_t)f.yhi << 16);
-    // The window spans at most g.wrows rows in exact arithmetic; the clamp
-    // keeps the table reads of the gather inside the row even if rounding
-    // of the bounds ever said otherwise.
-    const int32_t thi = min(f.thi, f.tlo + g.wrows - 1);
-    r.tlo = f.tlo;
-    r.thi = thi;
+    r.tb = (uint32_t)f.tlo | ((uint32_t)f.thi << 16);
+    r.xl_yl = pack_tail(f.xr, r.xh) | (pack_tail(f.yr, r.yh) << 16);
+    r.tl = pack_tail(f.tr, r.th);
     recs[s] = r;
-    const int32_t tb = f.tlo & ~(kChunk - 1);
-    float4* row = reinterpret_cast<float4*>(kt + (size_t)s * g.ktw);
-    for (int k = 0; k < g.ktw; k += 4) {
-        float v[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int32_t T = tb + k + q;
-            const double w = ((double)T + 0.5 - f.tr) / g.tv;
-            v[q] = (T >= f.tlo && T <= thi && fabs(w) <= 1.0) ? (float)(1.0 - w * w) : 0.0f;
-        }
-        row[k >> 2] = make_float4(v[0], v[1], v[2], v[3]);
-    }
 }
 
 inline int bits_for(uint32_t v) {
@@ -300,7 +287,6 @@ Workspace layout_workspace(const Geometry& g, int64_t n) {
     w.hist = o; o = al(o + (size_t)256 * w.nblk_sort * 4);
     w.cell_start = o; o = al(o + ((size_t)g.ncell + 1) * 4);
     w.recs = o; o = al(o + nn * sizeof(PointRec));
-    w.kt = o; o = al(o + nn * (size_t)g.ktw * 4);
     w.tile_part = o; o = al(o + (size_t)g.ntiles * kWaves * 8);
     w.pt_part = o; o = al(o + (size_t)w.nblk_pts * 4 * 8);
     w.counters = o; o = al(o + 4 * 8);
@@ -336,7 +322,7 @@ hipError_t launch_bin(const Geometry& g, const double* d_xyt, int32_t n, uint8_t
     const int nc = (g.ncell + 1 + kThreads - 1) / kThreads;
     hipLaunchKernelGGL(k_cell_start, dim3(nc), dim3(kThreads), 0, s, k0, n, g.ncell, cs);
     hipLaunchKernelGGL(k_records, dim3(nb), dim3(kThreads), 0, s, g, d_xyt, v0, cs, n,
-                       reinterpret_cast<PointRec*>(ws + w.recs), reinterpret_cast<float*>(ws + w.kt));
+                       reinterpret_cast<PointRec*>(ws + w.recs));
     return hipGetLastError();
 }
 

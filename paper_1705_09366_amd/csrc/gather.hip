@@ -1,50 +1,64 @@
-// gather.hip -- the density accumulation of PB-SYM (Sec. 3.2), as an
-// atomic-free gather over output tiles.
+// gather.hip -- the density accumulation of PB-SYM (Sec. 3.2) as an
+// atomic-free gather over output tiles, on the FP32 matrix cores.
 //
 // PB-SYM adds, for every point, the outer product of a spatial table
-// Ks[X][Y] and a temporal table Kt[T] into the grid.  Here every voxel is
-// owned by exactly one lane, which sums the contributions of all points
-// whose cylinder covers it, in a fixed order (bins in order, points in
-// sorted order within a bin), and stores the result once:
+// Ks[X][Y] and a temporal table Kt[T] into the grid.  Restricted to one tile
+// of the grid this is a rank-k update
 //
-//  * a workgroup owns a 16 x 16 x TT tile; each of its four waves owns an
-//    8 x 8 patch of columns; each lane owns one column (X, Y) and holds its
-//    TT rows of the tile in registers;
-//  * a wave walks the bins that can hold points reaching its patch, tests 64
-//    candidates at a time (one per lane) against the patch, and then
-//    visits the hits one by one with wave-uniform (scalar) loads;
-//  * per visit the lane evaluates the spatial factor of its column,
-//    ks = max(0, 1 - (dx^2 + dy^2)/hv^2), once (the Ks table entry), and
-//    accumulates ks * kt(T) over the rows of the point's window that fall in
-//    the tile, 4 rows per table chunk (the Kt table entries come from the
-//    point's precomputed table as scalar operands);
-//  * the normalisation (2/pi)(3/4)/(n hs^2 ht) is applied once at the store.
+//     out[T][XY] += sum_p Kt[T][p] * Ks[p][XY]
 //
-// There is no zeroing pass and no read-modify-write of the grid: each voxel
-// is written exactly once (the initialisation cost the paper measures,
-// Sec. 6.2, disappears into the store).
+// over the k points whose cylinder meets the tile, i.e. a dense contraction
+// over points, which maps onto v_mfma_f32_16x16x4f32 (16 rows x 16 columns,
+// 4 points per instruction).  Every voxel is owned by exactly one lane of
+// one workgroup, which sums all contributions in a fixed order (bins in
+// order, points in sorted order within a bin, four at a time) and stores the
+// result once; there is no zeroing pass and no read-modify-write of the
+// grid.
+//
+// Per workgroup (256 threads) and 16 x 16 x TT tile:
+//   setup   the bin rows (t, y) whose bins can hold points reaching the tile
+//           become a list of candidate ranges in LDS;
+//   stage   256 candidates at a time: one per thread, test the point's
+//           clipped footprint box against the tile, compact the survivors;
+//   tables  for every survivor the separable pieces of its Ks table,
+//           AX[x] = 1 - dx^2/hv^2 and BY[y] = dy^2/hv^2 (Ks = max(0, AX - BY),
+//           the Epanechnikov disc), and its Kt table 1 - dt^2/tv^2 over the
+//           tile rows, laid out as matrix-core operands; plus, per group of 4
+//           survivors, which 4 x 4 column groups and 16-row blocks the group
+//           touches (a disc-versus-group test, so blocks outside every disc
+//           are skipped);
+//   mma     each wave owns an 8 x 8 quadrant (four 4 x 4 column groups) x
+//           TT/16 row blocks of accumulators and issues one matrix-core
+//           instruction per touched block and group;
+//   store   each lane writes 4 consecutive rows of one column per block,
+//           scaled by the normalisation (2/pi)(3/4)/(n hs^2 ht).
+// With compensated accumulation each staged batch accumulates into a fresh
+// pass accumulator that is then added into (sum, compensation) by Kahan's
+// rule; within a pass the sum is plain FP32.
 #include "stkde_internal.h"
 
 namespace stkde {
 namespace {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kCap = kThreads;  // survivors per staged batch (one candidate per thread)
+
 struct GatherArgs {
     const uint32_t* cell_start;
     const PointRec* recs;
-    const float* kt;
     float* out;
     double* tile_part;
     int32_t gx, gy, gt;
     int32_t Hs, Ht;
     int32_t cxy, ct, ncx, ncy, nct;
     int32_t ntx, nty, ntiles;
-    int32_t ktw;
-    float inv_hv2;
+    float hv, inv_hv2, inv_tv2;
     float cnorm;
 };
 
 __device__ inline int32_t floordiv_d(int32_t a, int32_t b) {
-    int32_t q = a / b;
+    const int32_t q = a / b;
     return (a % b != 0 && a < 0) ? q - 1 : q;
 }
 
@@ -52,142 +66,268 @@ __device__ inline int32_t clampi(int32_t v, int32_t lo, int32_t hi) {
     return v < lo ? lo : (v > hi ? hi : v);
 }
 
-template <int TT>
-__device__ inline void kahan_fold(float (&acc)[TT], float (&comp)[TT], float (&pass)[TT]) {
+__device__ inline float half_lo(uint32_t v) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(v & 0xffffu));
+}
+
+__device__ inline float half_hi(uint32_t v) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(v >> 16));
+}
+
+// Bank-spread index of the separable spatial tables: survivors s and s + 2
+// of a group would share banks with a plain stride of 16 floats.
+__device__ inline int sidx(int s, int c) { return s * 16 + (c ^ (((s >> 1) & 1) << 3)); }
+
+template <int NB>
+__device__ inline void kahan_fold(f32x4 (&acc)[4][NB], f32x4 (&comp)[4][NB], f32x4 (&pass)[4][NB]) {
 #pragma unroll
-    for (int r = 0; r < TT; ++r) {
-        const float y = __fsub_rn(pass[r], comp[r]);
-        const float t = __fadd_rn(acc[r], y);
-        comp[r] = __fsub_rn(__fsub_rn(t, acc[r]), y);
-        acc[r] = t;
-        pass[r] = 0.0f;
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float y = __fsub_rn(pass[q][b][e], comp[q][b][e]);
+                const float t = __fadd_rn(acc[q][b][e], y);
+                comp[q][b][e] = __fsub_rn(__fsub_rn(t, acc[q][b][e]), y);
+                acc[q][b][e] = t;
+                pass[q][b][e] = 0.0f;
+            }
+        }
     }
 }
 
 template <int TT, bool KAHAN, bool MASS>
-__global__ __launch_bounds__(kThreads) void k_gather(GatherArgs a) {
-    constexpr int NCH = TT / kChunk;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+__global__ __launch_bounds__(kThreads, 2) void k_gather(GatherArgs a) {
+    constexpr int NB = TT / 16;           // 16-row blocks per tile
+    constexpr int NE = 16 + 16 + TT + 16; // table entries per survivor
+    __shared__ float sAX[kCap * 16];
+    __shared__ float sBY[kCap * 16];
+    __shared__ float sAT[kCap * TT];
+    __shared__ float sC[kCap * 6];
+    __shared__ uint32_t sRowBits[kCap];
+    __shared__ uint32_t sGM[kCap / 4];
+    __shared__ int32_t sRB[kMaxRanges];
+    __shared__ int32_t sRP[kMaxRanges + 1];
+    __shared__ int32_t sWC[kWaves];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
     // Tiles are dealt to the 8 XCDs in contiguous ranges (workgroup i runs on
-    // XCD i mod 8), so neighbouring tiles, which read the same bins, share
-    // an L2.
+    // XCD i mod 8) so that neighbouring tiles, which read the same bins,
+    // share an L2.
     const int32_t bid = blockIdx.x;
     const int32_t per = a.ntiles >> 3, rem = a.ntiles & 7;
-    const int32_t xcd = bid & 7, slot = bid >> 3;
-    const int32_t tile = xcd * per + min(xcd, rem) + slot;
+    const int32_t xcd = bid & 7, slot_in_xcd = bid >> 3;
+    const int32_t tile = xcd * per + min(xcd, rem) + slot_in_xcd;
     const int32_t tx = tile % a.ntx;
     const int32_t rest = tile / a.ntx;
     const int32_t ty = rest % a.nty;
     const int32_t tt = rest / a.nty;
+    const int32_t X0 = tx * kTileXY, Y0 = ty * kTileXY, T0 = tt * TT;
 
-    const int32_t PX0 = tx * kTileXY + (wave & 1) * kPatch;
-    const int32_t PY0 = ty * kTileXY + (wave >> 1) * kPatch;
-    const int32_t T0 = tt * TT;
-    const int32_t X = PX0 + (lane & 7), Y = PY0 + (lane >> 3);
-    const float Xc = (float)X + 0.5f, Yc = (float)Y + 0.5f;
+    // ---- setup: candidate ranges ------------------------------------------
+    // A point reaches column X only if floor(xr) lies in [X - Hs, X + Hs]; one
+    // voxel of margin absorbs rounding of the footprint bounds.
+    const int32_t cx0 = clampi(floordiv_d(X0 - a.Hs - 1, a.cxy), 0, a.ncx - 1);
+    const int32_t cx1 = clampi(floordiv_d(X0 + kTileXY - 1 + a.Hs + 1, a.cxy), 0, a.ncx - 1);
+    const int32_t cy0 = clampi(floordiv_d(Y0 - a.Hs - 1, a.cxy), 0, a.ncy - 1);
+    const int32_t cy1 = clampi(floordiv_d(Y0 + kTileXY - 1 + a.Hs + 1, a.cxy), 0, a.ncy - 1);
+    const int32_t ct0 = clampi(floordiv_d(T0 - a.Ht - 1, a.ct), 0, a.nct - 1);
+    const int32_t ct1 = clampi(floordiv_d(T0 + TT - 1 + a.Ht + 1, a.ct), 0, a.nct - 1);
+    const int32_t nyr = cy1 - cy0 + 1;
+    const int32_t nranges = nyr * (ct1 - ct0 + 1);  // <= kMaxRanges (the plan guarantees it)
+    if (wave == 0) {
+        int32_t beg = 0, len = 0;
+        if (lane < nranges) {
+            const int32_t cz = ct0 + lane / nyr, cy = cy0 + lane % nyr;
+            const int32_t row = (cz * a.ncy + cy) * a.ncx;
+            beg = (int32_t)a.cell_start[row + cx0];
+            len = (int32_t)a.cell_start[row + cx1 + 1] - beg;
+        }
+        int32_t inc = len;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int32_t o = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += o;
+        }
+        if (lane < nranges) {
+            sRB[lane] = beg;
+            sRP[lane] = inc - len;
+        }
+        if (lane == nranges - 1) sRP[nranges] = inc;
+    }
+    __syncthreads();
+    const int32_t total = sRP[nranges];
 
-    float acc[TT];
-    float comp[KAHAN ? TT : 1];
-    float pass[KAHAN ? TT : 1];
+    // ---- accumulators ------------------------------------------------------
+    f32x4 acc[4][NB];
+    f32x4 comp[4][KAHAN ? NB : 1];
+    f32x4 pass[4][KAHAN ? NB : 1];
 #pragma unroll
-    for (int r = 0; r < TT; ++r) acc[r] = 0.0f;
-    if constexpr (KAHAN) {
+    for (int q = 0; q < 4; ++q) {
 #pragma unroll
-        for (int r = 0; r < TT; ++r) {
-            comp[r] = 0.0f;
-            pass[r] = 0.0f;
+        for (int b = 0; b < NB; ++b) {
+            acc[q][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+            if constexpr (KAHAN) {
+                comp[q][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+                pass[q][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+            }
         }
     }
+    // this wave's four column groups (gx, gy) in the tile's 4 x 4 grid of groups
+    const int gqx = 2 * (wave & 1), gqy = 2 * (wave >> 1);
 
-    if (PX0 < a.gx && PY0 < a.gy) {
-        // Bins that can hold a point reaching this patch: a point reaches
-        // column X only if floor(xr) lies in [X - Hs, X + Hs]; one voxel of
-        // margin absorbs rounding of the footprint bounds.
-        const int32_t PX1 = PX0 + kPatch - 1, PY1 = PY0 + kPatch - 1, T1 = T0 + TT - 1;
-        const int32_t cx0 = clampi(floordiv_d(PX0 - a.Hs - 1, a.cxy), 0, a.ncx - 1);
-        const int32_t cx1 = clampi(floordiv_d(PX1 + a.Hs + 1, a.cxy), 0, a.ncx - 1);
-        const int32_t cy0 = clampi(floordiv_d(PY0 - a.Hs - 1, a.cxy), 0, a.ncy - 1);
-        const int32_t cy1 = clampi(floordiv_d(PY1 + a.Hs + 1, a.cxy), 0, a.ncy - 1);
-        const int32_t ct0 = clampi(floordiv_d(T0 - a.Ht - 1, a.ct), 0, a.nct - 1);
-        const int32_t ct1 = clampi(floordiv_d(T1 + a.Ht + 1, a.ct), 0, a.nct - 1);
-
-        for (int32_t cz = ct0; cz <= ct1; ++cz) {
-            for (int32_t cy = cy0; cy <= cy1; ++cy) {
-                const int32_t row = (cz * a.ncy + cy) * a.ncx;
-                const int32_t beg = (int32_t)a.cell_start[row + cx0];
-                const int32_t end = (int32_t)a.cell_start[row + cx1 + 1];
-                for (int32_t base = beg; base < end; base += 64) {
-                    const int32_t j = base + lane;
-                    bool hit = false;
-                    if (j < end) {
-                        const uint4 q = reinterpret_cast<const uint4*>(a.recs + j)[1];
-                        const int32_t xlo = (int32_t)(q.x & 0xffffu), xhi = (int32_t)(q.x >> 16);
-                        const int32_t ylo = (int32_t)(q.y & 0xffffu), yhi = (int32_t)(q.y >> 16);
-                        const int32_t tlo = (int32_t)q.z, thi = (int32_t)q.w;
-                        hit = xlo <= PX1 && xhi >= PX0 && ylo <= PY1 && yhi >= PY0 && tlo <= T1 &&
-                              thi >= T0;
-                    }
-                    unsigned long long m = __ballot(hit);
-                    if (m == 0ull) continue;
-                    while (m) {
-                        const int b = __builtin_ctzll(m);
-                        m &= m - 1ull;
-                        const int32_t p = base + b;
-                        const PointRec r = a.recs[p];
-                        const float dx = (Xc - r.xh) - r.xl;
-                        const float dy = (Yc - r.yh) - r.yl;
-                        const float ks = fmaxf(0.0f, fmaf(-(dx * dx + dy * dy), a.inv_hv2, 1.0f));
-                        // chunks of 4 rows of this tile inside [tlo, thi]
-                        const int32_t c0 = max(0, (r.tlo - T0) >> 2);
-                        const int32_t c1 = min(NCH - 1, (r.thi - T0) >> 2);
-                        const float* ktp = a.kt + (size_t)p * a.ktw - (r.tlo & ~3) + T0;
+    for (int32_t bb = 0; bb < total; bb += kCap) {
+        // ---- stage: test one candidate per thread, compact survivors -------
+        const int32_t c = bb + tid;
+        bool surv = false;
+        PointRec r{};
+        int32_t tlo = 0, thi = 0;
+        if (c < total) {
+            int32_t lo = 0, hi = nranges - 1;  // last range with sRP <= c
+            while (lo < hi) {
+                const int32_t mid = (lo + hi + 1) >> 1;
+                if (sRP[mid] <= c) lo = mid;
+                else hi = mid - 1;
+            }
+            const int32_t p = sRB[lo] + (c - sRP[lo]);
+            r = a.recs[p];
+            const int32_t xlo = (int32_t)(r.xb & 0xffffu), xhi = (int32_t)(r.xb >> 16);
+            const int32_t ylo = (int32_t)(r.yb & 0xffffu), yhi = (int32_t)(r.yb >> 16);
+            tlo = (int32_t)(r.tb & 0xffffu);
+            thi = (int32_t)(r.tb >> 16);
+            surv = xlo <= X0 + kTileXY - 1 && xhi >= X0 && ylo <= Y0 + kTileXY - 1 && yhi >= Y0 &&
+                   tlo <= T0 + TT - 1 && thi >= T0;
+        }
+        const unsigned long long m = __ballot(surv);
+        const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+        if (lane == 0) sWC[wave] = __popcll(m);
+        __syncthreads();
+        int32_t off = 0, nsurv = 0;
 #pragma unroll
-                        for (int c = 0; c < NCH; ++c) {
-                            if (c >= c0 && c <= c1) {
-                                const float4 k4 = *reinterpret_cast<const float4*>(ktp + 4 * c);
-                                if constexpr (KAHAN) {
-                                    pass[4 * c + 0] = fmaf(ks, k4.x, pass[4 * c + 0]);
-                                    pass[4 * c + 1] = fmaf(ks, k4.y, pass[4 * c + 1]);
-                                    pass[4 * c + 2] = fmaf(ks, k4.z, pass[4 * c + 2]);
-                                    pass[4 * c + 3] = fmaf(ks, k4.w, pass[4 * c + 3]);
-                                } else {
-                                    acc[4 * c + 0] = fmaf(ks, k4.x, acc[4 * c + 0]);
-                                    acc[4 * c + 1] = fmaf(ks, k4.y, acc[4 * c + 1]);
-                                    acc[4 * c + 2] = fmaf(ks, k4.z, acc[4 * c + 2]);
-                                    acc[4 * c + 3] = fmaf(ks, k4.w, acc[4 * c + 3]);
-                                }
-                            }
-                        }
+        for (int w = 0; w < kWaves; ++w) {
+            const int32_t cw = sWC[w];
+            off += (w < wave) ? cw : 0;
+            nsurv += cw;
+        }
+        if (surv) {
+            const int s = off + __popcll(m & lt);
+            sC[s * 6 + 0] = r.xh - (float)X0;  // exact for the offsets that reach the tile
+            sC[s * 6 + 1] = half_lo(r.xl_yl);
+            sC[s * 6 + 2] = r.yh - (float)Y0;
+            sC[s * 6 + 3] = half_hi(r.xl_yl);
+            sC[s * 6 + 4] = r.th - (float)T0;
+            sC[s * 6 + 5] = half_lo(r.tl);
+            const int32_t b0 = max(0, (tlo - T0) >> 4), b1 = min(NB - 1, (thi - T0) >> 4);
+            sRowBits[s] = ((1u << (b1 + 1)) - 1u) & ~((1u << b0) - 1u);
+        }
+        const int32_t ngroups = (nsurv + 3) >> 2;
+        if (tid < kCap / 4) sGM[tid] = 0u;
+        __syncthreads();
+
+        // ---- tables ---------------------------------------------------------
+        const int32_t nent = ngroups * 4 * NE;
+        for (int32_t e = tid; e < nent; e += kThreads) {
+            const int s = e / NE, q = e - s * NE;
+            const bool valid = s < nsurv;
+            if (q < 16) {
+                float v = 0.0f;
+                if (valid) {
+                    const float dx = ((float)q + 0.5f - sC[s * 6 + 0]) - sC[s * 6 + 1];
+                    v = fmaf(-dx * dx, a.inv_hv2, 1.0f);
+                }
+                sAX[sidx(s, q)] = v;
+            } else if (q < 32) {
+                float v = 0.0f;
+                if (valid) {
+                    const float dy = ((float)(q - 16) + 0.5f - sC[s * 6 + 2]) - sC[s * 6 + 3];
+                    v = dy * dy * a.inv_hv2;
+                }
+                sBY[sidx(s, q - 16)] = v;
+            } else if (q < 32 + TT) {
+                const int row = q - 32;
+                float v = 0.0f;
+                if (valid) {
+                    const float dt = ((float)row + 0.5f - sC[s * 6 + 4]) - sC[s * 6 + 5];
+                    v = fmaxf(0.0f, fmaf(-dt * dt, a.inv_tv2, 1.0f));
+                }
+                sAT[(((s >> 2) * NB + (row >> 4)) << 6) + ((s & 3) << 4) + (row & 15)] = v;
+            } else if (valid) {
+                // does the disc reach any column centre of group g?
+                const int g = q - 32 - TT, gx = g & 3, gy = g >> 2;
+                const float px = sC[s * 6 + 0] + sC[s * 6 + 1];
+                const float py = sC[s * 6 + 2] + sC[s * 6 + 3];
+                const float nx = fminf(fmaxf(px, 4.0f * gx + 0.5f), 4.0f * gx + 3.5f);
+                const float ny = fminf(fmaxf(py, 4.0f * gy + 0.5f), 4.0f * gy + 3.5f);
+                const float d2 = (nx - px) * (nx - px) + (ny - py) * (ny - py);
+                if (d2 * a.inv_hv2 < 1.0f + 1e-3f) atomicOr(&sGM[s >> 2], sRowBits[s] << (g * NB));
+            }
+        }
+        __syncthreads();
+
+        // ---- matrix-core accumulation ---------------------------------------
+        for (int32_t grp = 0; grp < ngroups; ++grp) {
+            const uint32_t gm = __builtin_amdgcn_readfirstlane(sGM[grp]);
+            uint32_t mine[4];
+            uint32_t any = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int g = (gqy + (q >> 1)) * 4 + gqx + (q & 1);
+                mine[q] = (gm >> (g * NB)) & ((1u << NB) - 1u);
+                any |= mine[q];
+            }
+            if (any == 0) continue;
+            float av[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) av[b] = sAT[((grp * NB + b) << 6) + lane];
+            const int s = grp * 4 + (lane >> 4);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (mine[q] == 0) continue;
+                const int x = 4 * (gqx + (q & 1)) + (lane & 3);
+                const int y = 4 * (gqy + (q >> 1)) + ((lane >> 2) & 3);
+                const float ks = fmaxf(0.0f, sAX[sidx(s, x)] - sBY[sidx(s, y)]);
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    if (mine[q] & (1u << b)) {
+                        if constexpr (KAHAN)
+                            pass[q][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[b], ks, pass[q][b], 0, 0, 0);
+                        else
+                            acc[q][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[b], ks, acc[q][b], 0, 0, 0);
                     }
-                    if constexpr (KAHAN) kahan_fold<TT>(acc, comp, pass);
                 }
             }
         }
+        if constexpr (KAHAN) kahan_fold<NB>(acc, comp, pass);
+        __syncthreads();
     }
 
-    // Store the tile once, FP32, [X][Y][T] with T fastest.
+    // ---- store: lane holds rows 16b + 4(lane/16) + e of column (lane % 16)
+    // of each of its four column groups ---------------------------------------
     double msum = 0.0;
-    if (X < a.gx && Y < a.gy) {
-        float* o = a.out + ((size_t)X * a.gy + Y) * a.gt + T0;
-        float v[TT];
+    const bool vec = (a.gt & 3) == 0;
 #pragma unroll
-        for (int r = 0; r < TT; ++r) v[r] = acc[r] * a.cnorm;
-        if (T0 + TT <= a.gt && (a.gt & 3) == 0) {
+    for (int q = 0; q < 4; ++q) {
+        const int32_t X = X0 + 4 * (gqx + (q & 1)) + (lane & 3);
+        const int32_t Y = Y0 + 4 * (gqy + (q >> 1)) + ((lane >> 2) & 3);
+        if (X >= a.gx || Y >= a.gy) continue;
+        float* col = a.out + ((size_t)X * a.gy + Y) * a.gt;
 #pragma unroll
-            for (int r = 0; r < TT; r += 4)
-                *reinterpret_cast<float4*>(o + r) = make_float4(v[r], v[r + 1], v[r + 2], v[r + 3]);
-            if constexpr (MASS) {
+        for (int b = 0; b < NB; ++b) {
+            const int32_t T = T0 + 16 * b + 4 * (lane >> 4);
+            const f32x4 v = acc[q][b] * a.cnorm;
+            if (vec && T + 3 < a.gt) {
+                *reinterpret_cast<f32x4*>(col + T) = v;
+                if constexpr (MASS) msum += (double)v[0] + (double)v[1] + (double)v[2] + (double)v[3];
+            } else {
 #pragma unroll
-                for (int r = 0; r < TT; ++r) msum += (double)v[r];
-            }
-        } else {
-#pragma unroll
-            for (int r = 0; r < TT; ++r) {
-                if (T0 + r < a.gt) {
-                    o[r] = v[r];
-                    if constexpr (MASS) msum += (double)v[r];
+                for (int e = 0; e < 4; ++e) {
+                    if (T + e < a.gt) {
+                        col[T + e] = v[e];
+                        if constexpr (MASS) msum += (double)v[e];
+                    }
                 }
             }
         }
@@ -228,7 +368,6 @@ hipError_t launch_gather(const Geometry& g, float cnorm, bool kahan, bool mass, 
     GatherArgs ga;
     ga.cell_start = reinterpret_cast<const uint32_t*>(ws + w.cell_start);
     ga.recs = reinterpret_cast<const PointRec*>(ws + w.recs);
-    ga.kt = reinterpret_cast<const float*>(ws + w.kt);
     ga.out = d_out;
     ga.tile_part = reinterpret_cast<double*>(ws + w.tile_part);
     ga.gx = g.gx;
@@ -244,8 +383,9 @@ hipError_t launch_gather(const Geometry& g, float cnorm, bool kahan, bool mass, 
     ga.ntx = g.ntx;
     ga.nty = g.nty;
     ga.ntiles = g.ntiles;
-    ga.ktw = g.ktw;
+    ga.hv = (float)g.hv;
     ga.inv_hv2 = g.inv_hv2;
+    ga.inv_tv2 = g.inv_tv2;
     ga.cnorm = cnorm;
     if (g.tile_t == 16) {
         if (kahan) mass ? launch_one<16, true, true>(ga, s) : launch_one<16, true, false>(ga, s);
@@ -254,9 +394,7 @@ hipError_t launch_gather(const Geometry& g, float cnorm, bool kahan, bool mass, 
         if (kahan) mass ? launch_one<32, true, true>(ga, s) : launch_one<32, true, false>(ga, s);
         else mass ? launch_one<32, false, true>(ga, s) : launch_one<32, false, false>(ga, s);
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return hipSuccess;
+    return hipGetLastError();
 }
 
 hipError_t launch_mass_reduce(const Geometry& g, double* d_dst, uint8_t* ws, const Workspace& w,

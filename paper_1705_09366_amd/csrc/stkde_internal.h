@@ -12,27 +12,27 @@
 
 namespace stkde {
 
-// Lanes of a wave own an 8 x 8 patch of voxel columns (X, Y); four waves of
-// a 256-thread workgroup own a 16 x 16 tile; every lane holds TT time rows
-// of its column in registers.
+// A 256-thread workgroup owns a 16 x 16 x TT tile of voxels; each of its four
+// waves owns an 8 x 8 quadrant of columns, i.e. four 4 x 4 column groups,
+// times TT/16 blocks of 16 rows, as FP32 matrix-core accumulators.
 constexpr int kPatch = 8;
 constexpr int kTileXY = 16;
 constexpr int kWaves = 4;
 constexpr int kThreads = 256;
-// Kernel values in time are served in chunks of 4 rows aligned to global
-// row multiples of 4.
-constexpr int kChunk = 4;
+// Bin rows (t, y) a tile may read; the plan picks bin sizes to respect it.
+constexpr int kMaxRanges = 64;
 
-// Per-point record in sorted (binned) order, 32 bytes.  The spatial
-// coordinate is split into a float head and tail (x = xh + xl to ~2^-48
-// relative), so that differences against voxel centres, which are exact
-// in FP32, keep FP64-class accuracy where they matter (near the point).
+// Per-point record in sorted (binned) order, 32 bytes.  Each voxel-space
+// coordinate is split into an FP32 head and an FP16 tail (c = head + tail to
+// ~2^-35 relative), so that tile-local offsets keep FP64-class accuracy where
+// it matters (near the point) although every kernel below works in FP32.
 struct alignas(16) PointRec {
-    float xh, xl, yh, yl;
-    uint32_t xb;  // footprint columns: Xlo | Xhi << 16, clipped to the grid
-    uint32_t yb;  // footprint rows in y: Ylo | Yhi << 16
-    int32_t tlo;  // footprint time rows [tlo, thi], clipped to the grid
-    int32_t thi;
+    float xh, yh, th;
+    uint32_t xb;       // footprint columns in x: lo | hi << 16, clipped to the grid
+    uint32_t yb;       // footprint columns in y: lo | hi << 16
+    uint32_t tb;       // footprint rows in t: lo | hi << 16
+    uint32_t xl_yl;    // tails of x and y as two FP16 (x in the low half)
+    uint32_t tl;       // tail of t as FP16 in the low half
 };
 static_assert(sizeof(PointRec) == 32, "record layout");
 
@@ -47,8 +47,7 @@ struct Geometry {
     int32_t tile_t;           // time rows per lane (16 or 32)
     int32_t ntx, nty, ntt;    // tiles per axis
     int32_t ntiles;
-    int32_t ktw;              // floats per point in the time-kernel table (multiple of 4)
-    int32_t wrows;            // most rows a clipped time window can span
+    int32_t max_ranges;       // most (t, y) bin rows one tile reads
     double x0, y0, t0;
     double inv_sres, inv_tres;  // used as multipliers only where exact (see binning)
     double sres, tres;
@@ -56,7 +55,7 @@ struct Geometry {
     double Hs_d, Ht_d;        // ceil(hv), ceil(tv) uncapped (loop bounds of the statistics)
     double hs, ht;            // domain bandwidths
     float inv_hv2;            // 1/hv^2 (FP32)
-    float inv_tv;             // unused by the gather; kept for the tables
+    float inv_tv2;            // 1/tv^2 (FP32)
 };
 
 // Workspace carve-up (byte offsets from d_ws, each 256-byte aligned).
@@ -65,7 +64,6 @@ struct Workspace {
     size_t hist;         // radix digit counts, 256 * nblk_sort u32
     size_t cell_start;   // (ncell + 1) u32
     size_t recs;         // n PointRec
-    size_t kt;           // n * ktw float
     size_t tile_part;    // ntiles * kWaves double (grid mass partials)
     size_t pt_part;      // nblk_pts * 4 double (per-point statistics partials)
     size_t counters;     // 4 x u64 (non-finite, culled)
