@@ -18,23 +18,24 @@
 // Per workgroup (256 threads) and 16 x 16 x TT tile:
 //   setup   the bin rows (t, y) whose bins can hold points reaching the tile
 //           become a list of candidate ranges in LDS;
-//   stage   256 candidates at a time: one per thread, test the point's
-//           clipped footprint box against the tile, compact the survivors;
-//   tables  for every survivor the separable pieces of its Ks table,
-//           AX[x] = 1 - dx^2/hv^2 and BY[y] = dy^2/hv^2 (Ks = max(0, AX - BY),
-//           the Epanechnikov disc), and its Kt table 1 - dt^2/tv^2 over the
-//           tile rows, laid out as matrix-core operands; plus, per group of 4
-//           survivors, which 4 x 4 column groups and 16-row blocks the group
-//           touches (a disc-versus-group test, so blocks outside every disc
-//           are skipped);
+//   stage   256 candidates at a time, one per thread: test the point's
+//           clipped footprint box against the tile, append the survivors'
+//           tile-local coordinates to an LDS list, together with the set of
+//           4 x 4 column groups and 16-row blocks the survivor's cylinder
+//           touches (a disc-versus-group test); repeat until the list is
+//           nearly full or the candidates are exhausted;
 //   mma     each wave owns an 8 x 8 quadrant (four 4 x 4 column groups) x
-//           TT/16 row blocks of accumulators and issues one matrix-core
-//           instruction per touched block and group;
+//           TT/16 row blocks of accumulators.  For every group of 4
+//           survivors each lane builds its matrix-core operands in
+//           registers -- the Kt entry of one (point, row) and the Ks entry
+//           of one (point, column), Ks = max(0, 1 - (dx^2 + dy^2)/hv^2), the
+//           Epanechnikov disc, Kt = max(0, 1 - dt^2/tv^2) -- and issues one
+//           instruction per block the group touches;
 //   store   each lane writes 4 consecutive rows of one column per block,
 //           scaled by the normalisation (2/pi)(3/4)/(n hs^2 ht).
-// With compensated accumulation each staged batch accumulates into a fresh
-// pass accumulator that is then added into (sum, compensation) by Kahan's
-// rule; within a pass the sum is plain FP32.
+// With compensated accumulation each matrix-core phase accumulates into a
+// fresh pass accumulator that is then added into (sum, compensation) by
+// Kahan's rule; within a pass the sum is plain FP32.
 #include "stkde_internal.h"
 
 namespace stkde {
@@ -42,7 +43,7 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kCap = kThreads;  // survivors per staged batch (one candidate per thread)
+constexpr int kCap = 1024;  // survivors held in LDS between matrix-core phases
 
 struct GatherArgs {
     const uint32_t* cell_start;
@@ -74,10 +75,6 @@ __device__ inline float half_hi(uint32_t v) {
     return (float)__builtin_bit_cast(_Float16, (uint16_t)(v >> 16));
 }
 
-// Bank-spread index of the separable spatial tables: survivors s and s + 2
-// of a group would share banks with a plain stride of 16 floats.
-__device__ inline int sidx(int s, int c) { return s * 16 + (c ^ (((s >> 1) & 1) << 3)); }
-
 template <int NB>
 __device__ inline void kahan_fold(f32x4 (&acc)[4][NB], f32x4 (&comp)[4][NB], f32x4 (&pass)[4][NB]) {
 #pragma unroll
@@ -96,16 +93,35 @@ __device__ inline void kahan_fold(f32x4 (&acc)[4][NB], f32x4 (&comp)[4][NB], f32
     }
 }
 
+// Bit (g * NB + b) of the mask: the cylinder of a survivor at tile-local
+// (px, py) with rows [tlo, thi] (tile-local) reaches a column centre of
+// column group g and a row of block b.
+template <int NB>
+__device__ inline uint32_t touch_mask(float px, float py, int32_t tlo, int32_t thi, float inv_hv2) {
+    const int32_t b0 = max(0, tlo >> 4), b1 = min(NB - 1, thi >> 4);
+    const uint32_t rb = ((1u << (b1 + 1)) - 1u) & ~((1u << b0) - 1u);
+    float ex[4], ey[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float nx = fminf(fmaxf(px, 4.0f * k + 0.5f), 4.0f * k + 3.5f) - px;
+        const float ny = fminf(fmaxf(py, 4.0f * k + 0.5f), 4.0f * k + 3.5f) - py;
+        ex[k] = nx * nx * inv_hv2;
+        ey[k] = ny * ny * inv_hv2;
+    }
+    uint32_t m = 0;
+#pragma unroll
+    for (int g = 0; g < 16; ++g)
+        if (ex[g & 3] + ey[g >> 2] < 1.0f + 1e-3f) m |= rb << (g * NB);
+    return m;
+}
+
 template <int TT, bool KAHAN, bool MASS>
-__global__ __launch_bounds__(kThreads, 2) void k_gather(GatherArgs a) {
-    constexpr int NB = TT / 16;           // 16-row blocks per tile
-    constexpr int NE = 16 + 16 + TT + 16; // table entries per survivor
-    __shared__ float sAX[kCap * 16];
-    __shared__ float sBY[kCap * 16];
-    __shared__ float sAT[kCap * TT];
-    __shared__ float sC[kCap * 6];
-    __shared__ uint32_t sRowBits[kCap];
-    __shared__ uint32_t sGM[kCap / 4];
+__global__ __launch_bounds__(kThreads) void k_gather(GatherArgs a) {
+    constexpr int NB = TT / 16;  // 16-row blocks per tile
+    // survivor list: tile-local coordinates as (x head, x tail), (y head,
+    // y tail), (t head, t tail), and the touch mask
+    __shared__ float2 sX[kCap], sY[kCap], sT[kCap];
+    __shared__ __align__(16) uint32_t sM[kCap];
     __shared__ int32_t sRB[kMaxRanges];
     __shared__ int32_t sRP[kMaxRanges + 1];
     __shared__ int32_t sWC[kWaves];
@@ -178,98 +194,73 @@ __global__ __launch_bounds__(kThreads, 2) void k_gather(GatherArgs a) {
     }
     // this wave's four column groups (gx, gy) in the tile's 4 x 4 grid of groups
     const int gqx = 2 * (wave & 1), gqy = 2 * (wave >> 1);
+    const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    // lane roles in the matrix-core operands: point k of the group, row i of
+    // a block (Kt operand), column j of a group (Ks operand)
+    const int kq = lane >> 4, ri = lane & 15;
+    const float rowc = (float)ri + 0.5f;
 
-    for (int32_t bb = 0; bb < total; bb += kCap) {
-        // ---- stage: test one candidate per thread, compact survivors -------
-        const int32_t c = bb + tid;
-        bool surv = false;
-        PointRec r{};
-        int32_t tlo = 0, thi = 0;
-        if (c < total) {
-            int32_t lo = 0, hi = nranges - 1;  // last range with sRP <= c
-            while (lo < hi) {
-                const int32_t mid = (lo + hi + 1) >> 1;
-                if (sRP[mid] <= c) lo = mid;
-                else hi = mid - 1;
+    int32_t bb = 0;
+    while (bb < total) {
+        // ---- stage: fill the survivor list ---------------------------------
+        int32_t count = 0;
+        while (bb < total && count <= kCap - kThreads) {
+            const int32_t c = bb + tid;
+            bool surv = false;
+            PointRec r{};
+            if (c < total) {
+                int32_t lo = 0, hi = nranges - 1;  // last range with sRP <= c
+                while (lo < hi) {
+                    const int32_t mid = (lo + hi + 1) >> 1;
+                    if (sRP[mid] <= c) lo = mid;
+                    else hi = mid - 1;
+                }
+                r = a.recs[sRB[lo] + (c - sRP[lo])];
+                const int32_t xlo = (int32_t)(r.xb & 0xffffu), xhi = (int32_t)(r.xb >> 16);
+                const int32_t ylo = (int32_t)(r.yb & 0xffffu), yhi = (int32_t)(r.yb >> 16);
+                const int32_t tlo = (int32_t)(r.tb & 0xffffu), thi = (int32_t)(r.tb >> 16);
+                surv = xlo <= X0 + kTileXY - 1 && xhi >= X0 && ylo <= Y0 + kTileXY - 1 &&
+                       yhi >= Y0 && tlo <= T0 + TT - 1 && thi >= T0;
             }
-            const int32_t p = sRB[lo] + (c - sRP[lo]);
-            r = a.recs[p];
-            const int32_t xlo = (int32_t)(r.xb & 0xffffu), xhi = (int32_t)(r.xb >> 16);
-            const int32_t ylo = (int32_t)(r.yb & 0xffffu), yhi = (int32_t)(r.yb >> 16);
-            tlo = (int32_t)(r.tb & 0xffffu);
-            thi = (int32_t)(r.tb >> 16);
-            surv = xlo <= X0 + kTileXY - 1 && xhi >= X0 && ylo <= Y0 + kTileXY - 1 && yhi >= Y0 &&
-                   tlo <= T0 + TT - 1 && thi >= T0;
-        }
-        const unsigned long long m = __ballot(surv);
-        const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-        if (lane == 0) sWC[wave] = __popcll(m);
-        __syncthreads();
-        int32_t off = 0, nsurv = 0;
+            const unsigned long long m = __ballot(surv);
+            if (lane == 0) sWC[wave] = __popcll(m);
+            __syncthreads();
+            int32_t off = count, add = 0;
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) {
-            const int32_t cw = sWC[w];
-            off += (w < wave) ? cw : 0;
-            nsurv += cw;
-        }
-        if (surv) {
-            const int s = off + __popcll(m & lt);
-            sC[s * 6 + 0] = r.xh - (float)X0;  // exact for the offsets that reach the tile
-            sC[s * 6 + 1] = half_lo(r.xl_yl);
-            sC[s * 6 + 2] = r.yh - (float)Y0;
-            sC[s * 6 + 3] = half_hi(r.xl_yl);
-            sC[s * 6 + 4] = r.th - (float)T0;
-            sC[s * 6 + 5] = half_lo(r.tl);
-            const int32_t b0 = max(0, (tlo - T0) >> 4), b1 = min(NB - 1, (thi - T0) >> 4);
-            sRowBits[s] = ((1u << (b1 + 1)) - 1u) & ~((1u << b0) - 1u);
-        }
-        const int32_t ngroups = (nsurv + 3) >> 2;
-        if (tid < kCap / 4) sGM[tid] = 0u;
-        __syncthreads();
-
-        // ---- tables ---------------------------------------------------------
-        const int32_t nent = ngroups * 4 * NE;
-        for (int32_t e = tid; e < nent; e += kThreads) {
-            const int s = e / NE, q = e - s * NE;
-            const bool valid = s < nsurv;
-            if (q < 16) {
-                float v = 0.0f;
-                if (valid) {
-                    const float dx = ((float)q + 0.5f - sC[s * 6 + 0]) - sC[s * 6 + 1];
-                    v = fmaf(-dx * dx, a.inv_hv2, 1.0f);
-                }
-                sAX[sidx(s, q)] = v;
-            } else if (q < 32) {
-                float v = 0.0f;
-                if (valid) {
-                    const float dy = ((float)(q - 16) + 0.5f - sC[s * 6 + 2]) - sC[s * 6 + 3];
-                    v = dy * dy * a.inv_hv2;
-                }
-                sBY[sidx(s, q - 16)] = v;
-            } else if (q < 32 + TT) {
-                const int row = q - 32;
-                float v = 0.0f;
-                if (valid) {
-                    const float dt = ((float)row + 0.5f - sC[s * 6 + 4]) - sC[s * 6 + 5];
-                    v = fmaxf(0.0f, fmaf(-dt * dt, a.inv_tv2, 1.0f));
-                }
-                sAT[(((s >> 2) * NB + (row >> 4)) << 6) + ((s & 3) << 4) + (row & 15)] = v;
-            } else if (valid) {
-                // does the disc reach any column centre of group g?
-                const int g = q - 32 - TT, gx = g & 3, gy = g >> 2;
-                const float px = sC[s * 6 + 0] + sC[s * 6 + 1];
-                const float py = sC[s * 6 + 2] + sC[s * 6 + 3];
-                const float nx = fminf(fmaxf(px, 4.0f * gx + 0.5f), 4.0f * gx + 3.5f);
-                const float ny = fminf(fmaxf(py, 4.0f * gy + 0.5f), 4.0f * gy + 3.5f);
-                const float d2 = (nx - px) * (nx - px) + (ny - py) * (ny - py);
-                if (d2 * a.inv_hv2 < 1.0f + 1e-3f) atomicOr(&sGM[s >> 2], sRowBits[s] << (g * NB));
+            for (int w = 0; w < kWaves; ++w) {
+                const int32_t cw = sWC[w];
+                off += (w < wave) ? cw : 0;
+                add += cw;
             }
+            if (surv) {
+                const int s = off + __popcll(m & lt);
+                // head - origin is exact for the offsets that reach the tile
+                const float px = r.xh - (float)X0, py = r.yh - (float)Y0;
+                const float xl = half_lo(r.xl_yl), yl = half_hi(r.xl_yl);
+                sX[s] = make_float2(px, xl);
+                sY[s] = make_float2(py, yl);
+                sT[s] = make_float2(r.th - (float)T0, half_lo(r.tl));
+                sM[s] = touch_mask<NB>(px + xl, py + yl, (int32_t)(r.tb & 0xffffu) - T0,
+                                       (int32_t)(r.tb >> 16) - T0, a.inv_hv2);
+            }
+            count += add;
+            bb += kThreads;
+            __syncthreads();  // sWC is rewritten by the next round
+        }
+        // pad the last group with survivors that touch nothing
+        if (tid < ((4 - (count & 3)) & 3)) {
+            sM[count + tid] = 0u;
+            sX[count + tid] = make_float2(0.f, 0.f);
+            sY[count + tid] = make_float2(0.f, 0.f);
+            sT[count + tid] = make_float2(0.f, 0.f);
         }
         __syncthreads();
 
         // ---- matrix-core accumulation ---------------------------------------
+        const int32_t ngroups = (count + 3) >> 2;
         for (int32_t grp = 0; grp < ngroups; ++grp) {
-            const uint32_t gm = __builtin_amdgcn_readfirstlane(sGM[grp]);
+            const uint4 m4 = reinterpret_cast<const uint4*>(sM)[grp];
+            const uint32_t gm = __builtin_amdgcn_readfirstlane(m4.x | m4.y | m4.z | m4.w);
             uint32_t mine[4];
             uint32_t any = 0;
 #pragma unroll
@@ -279,16 +270,22 @@ __global__ __launch_bounds__(kThreads, 2) void k_gather(GatherArgs a) {
                 any |= mine[q];
             }
             if (any == 0) continue;
+            const int s = grp * 4 + kq;
+            const float2 cx = sX[s], cy = sY[s], ctt = sT[s];
             float av[NB];
 #pragma unroll
-            for (int b = 0; b < NB; ++b) av[b] = sAT[((grp * NB + b) << 6) + lane];
-            const int s = grp * 4 + (lane >> 4);
+            for (int b = 0; b < NB; ++b) {
+                const float dt = ((float)(16 * b) + rowc - ctt.x) - ctt.y;
+                av[b] = fmaxf(0.0f, fmaf(-dt * dt, a.inv_tv2, 1.0f));
+            }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 if (mine[q] == 0) continue;
-                const int x = 4 * (gqx + (q & 1)) + (lane & 3);
-                const int y = 4 * (gqy + (q >> 1)) + ((lane >> 2) & 3);
-                const float ks = fmaxf(0.0f, sAX[sidx(s, x)] - sBY[sidx(s, y)]);
+                const float xc = (float)(4 * (gqx + (q & 1)) + (lane & 3)) + 0.5f;
+                const float yc = (float)(4 * (gqy + (q >> 1)) + ((lane >> 2) & 3)) + 0.5f;
+                const float dx = (xc - cx.x) - cx.y;
+                const float dy = (yc - cy.x) - cy.y;
+                const float ks = fmaxf(0.0f, fmaf(-(dx * dx + dy * dy), a.inv_hv2, 1.0f));
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
                     if (mine[q] & (1u << b)) {
@@ -301,7 +298,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_gather(GatherArgs a) {
             }
         }
         if constexpr (KAHAN) kahan_fold<NB>(acc, comp, pass);
-        __syncthreads();
+        __syncthreads();  // the list is refilled next
     }
 
     // ---- store: lane holds rows 16b + 4(lane/16) + e of column (lane % 16)
