@@ -247,12 +247,13 @@ __global__ __launch_bounds__(kThreads) void k_gather(GatherArgs a) {
             bb += kThreads;
             __syncthreads();  // sWC is rewritten by the next round
         }
-        // pad the last group with survivors that touch nothing
+        // pad the last group with points far outside the tile, whose kernel
+        // values are exactly zero in every operand
         if (tid < ((4 - (count & 3)) & 3)) {
             sM[count + tid] = 0u;
-            sX[count + tid] = make_float2(0.f, 0.f);
-            sY[count + tid] = make_float2(0.f, 0.f);
-            sT[count + tid] = make_float2(0.f, 0.f);
+            sX[count + tid] = make_float2(-1.0e6f, 0.f);
+            sY[count + tid] = make_float2(-1.0e6f, 0.f);
+            sT[count + tid] = make_float2(-1.0e6f, 0.f);
         }
         __syncthreads();
 
