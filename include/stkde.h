@@ -78,12 +78,13 @@ typedef struct {
 } stkde_desc;
 
 /* Optional tuning of one plan.  Zero fields mean "library default".
- * tile_t must be 0, 16 or 32; cell_xy and cell_t in [4, 256].  The plan may
+ * tile_t must be 0, 16, 32 or 64 (64 is reduced to 32 under STKDE_FLAG_KAHAN);
+ * cell_xy and cell_t in [4, 256].  The plan may
  * enlarge the bins beyond these values when a tile would otherwise read
  * more bin rows than the gather supports.  Tuning changes the summation
  * order, so results differ between tunings in the last bits. */
 typedef struct {
-    int32_t tile_t;   /* voxel rows in time per output tile (16 or 32) */
+    int32_t tile_t;   /* voxel rows in time per output tile (16, 32 or 64) */
     int32_t cell_xy;  /* bin edge in x and y, voxels */
     int32_t cell_t;   /* bin edge in t, voxels */
     int32_t reserved; /* must be 0 */

@@ -56,7 +56,8 @@ stkde_status stkde_plan(const stkde_desc* d, const stkde_tuning* tun, stkde_plan
 
     int32_t tile_t = 0, cell_xy = 0, cell_t = 0;
     if (tun) {
-        if (tun->tile_t != 0 && tun->tile_t != 16 && tun->tile_t != 32) return STKDE_ERR_INVALID_ARG;
+        if (tun->tile_t != 0 && tun->tile_t != 16 && tun->tile_t != 32 && tun->tile_t != 64)
+            return STKDE_ERR_INVALID_ARG;
         if (tun->cell_xy != 0 && (tun->cell_xy < 4 || tun->cell_xy > 256))
             return STKDE_ERR_INVALID_ARG;
         if (tun->cell_t != 0 && (tun->cell_t < 4 || tun->cell_t > 256))
@@ -93,6 +94,9 @@ stkde_status stkde_plan(const stkde_desc* d, const stkde_tuning* tun, stkde_plan
     g.inv_tv2 = (float)(1.0 / (g.tv * g.tv));
 
     g.tile_t = tile_t ? tile_t : 32;
+    // compensated accumulation holds three accumulator sets; with 64-row
+    // tiles that would leave one wave per SIMD
+    if ((d->flags & STKDE_FLAG_KAHAN) && g.tile_t > 32) g.tile_t = 32;
     // Bins about as wide as the bandwidth (the paper's bandwidth-sized
     // blocks of points, Sec. 4.2 and Sec. 5.1): a tile then reads a few bin
     // rows, and few of the candidates it reads miss it.

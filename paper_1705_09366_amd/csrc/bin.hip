@@ -104,66 +104,61 @@ __global__ __launch_bounds__(kThreads) void k_transform(Geometry g, const double
 
 // ---- stable LSD radix sort, 8-bit digits --------------------------------
 
-// Per-block digit histogram.  hist is digit-major: hist[d * nblk + b].
+// Per-block digit histogram.  hist is digit-major: hist[d * nblk + b]; the
+// digit totals over all blocks are accumulated in `totals` (integer sums, so
+// the result does not depend on the order of the additions).
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                          int32_t n, int shift,
                                                          uint32_t* __restrict__ hist,
-                                                         int32_t nblk) {
+                                                         int32_t nblk, uint32_t* __restrict__ totals) {
     __shared__ uint32_t cnt[256];
     cnt[threadIdx.x] = 0;
     __syncthreads();
     const int32_t base = blockIdx.x * kSortTile;
-#pragma unroll 4
+#pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
         const int32_t i = base + it * kThreads + threadIdx.x;
         if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    hist[threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+    const uint32_t c = cnt[threadIdx.x];
+    hist[threadIdx.x * nblk + blockIdx.x] = c;
+    if (c) atomicAdd(&totals[threadIdx.x], c);
 }
 
-// Exclusive scan of hist (count entries) in place, by one workgroup of 1024
-// threads walking the array in order with a running carry.
-__global__ __launch_bounds__(1024) void k_scan_exclusive(uint32_t* __restrict__ a, int32_t count) {
-    __shared__ uint32_t wsum[16];
+// One workgroup per digit d: hist[d][b] <- (keys with a smaller digit) +
+// (keys with digit d in blocks before b), i.e. the scatter base of block b.
+__global__ __launch_bounds__(kThreads) void k_radix_scan(uint32_t* __restrict__ hist, int32_t nblk,
+                                                         const uint32_t* __restrict__ totals) {
+    __shared__ uint32_t wsum[kWaves];
     __shared__ uint32_t carry_s;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    if (tid == 0) carry_s = 0;
+    const int d = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    // keys of smaller digits
+    uint32_t lower = (tid < d) ? totals[tid] : 0u;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) lower += __shfl_xor(lower, o, 64);
+    if (lane == 0) wsum[wv] = lower;
     __syncthreads();
-    for (int32_t base = 0; base < count; base += 1024 * 4) {
-        uint32_t v[4], s = 0;
+    if (tid == 0) carry_s = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+    uint32_t* row = hist + (size_t)d * nblk;
+    for (int32_t base = 0; base < nblk; base += kThreads) {
+        const int32_t i = base + tid;
+        const uint32_t v = i < nblk ? row[i] : 0u;
+        uint32_t inc = v;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int32_t i = base + tid * 4 + k;
-            v[k] = i < count ? a[i] : 0u;
-            s += v[k];
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t u = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += u;
         }
-        // inclusive scan of s across the wave
-        uint32_t inc = s;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t o = __shfl_up(inc, d, 64);
-            if (lane >= d) inc += o;
-        }
+        __syncthreads();  // carry_s and wsum of the previous round are consumed
         if (lane == 63) wsum[wv] = inc;
         __syncthreads();
-        uint32_t wpre = 0, total = 0;
-        for (int k = 0; k < 16; ++k) {
-            const uint32_t ws = wsum[k];
-            if (k < wv) wpre += ws;
-            total += ws;
-        }
-        const uint32_t carry = carry_s;
-        uint32_t run = carry + wpre + inc - s;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int32_t i = base + tid * 4 + k;
-            if (i < count) a[i] = run;
-            run += v[k];
-        }
+        uint32_t pre = carry_s;
+        for (int w = 0; w < wv; ++w) pre += wsum[w];
+        if (i < nblk) row[i] = pre + inc - v;
         __syncthreads();
-        if (tid == 0) carry_s = carry + total;
-        __syncthreads();
+        if (tid == 0) carry_s += wsum[0] + wsum[1] + wsum[2] + wsum[3];
     }
 }
 
@@ -289,7 +284,8 @@ Workspace layout_workspace(const Geometry& g, int64_t n) {
     w.recs = o; o = al(o + nn * sizeof(PointRec));
     w.tile_part = o; o = al(o + (size_t)g.ntiles * kWaves * 8);
     w.pt_part = o; o = al(o + (size_t)w.nblk_pts * 4 * 8);
-    w.counters = o; o = al(o + 4 * 8);
+    w.counters = o; o = al(o + 4 * 8 + 3 * 256 * 4);
+    w.mass_part = o; o = al(o + (size_t)kMassBlocks * 8);
     w.total = o;
     return w;
 }
@@ -305,15 +301,17 @@ hipError_t launch_bin(const Geometry& g, const double* d_xyt, int32_t n, uint8_t
     unsigned long long* ctr = reinterpret_cast<unsigned long long*>(ws + w.counters);
     const int nb = (n + kThreads - 1) / kThreads;
 
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ctr, 4);
+    uint32_t* totals = reinterpret_cast<uint32_t*>(ws + w.counters + 4 * 8);
+    hipLaunchKernelGGL(k_zero_u64, dim3(2), dim3(256), 0, s, ctr, 4 + 3 * 256 / 2);
     hipLaunchKernelGGL(k_transform, dim3(nb), dim3(kThreads), 0, s, g, d_xyt, n, k0, v0, ctr);
 
     const int bits = bits_for((uint32_t)g.ncell);
     const int passes = bits <= 8 ? 1 : (bits + 7) / 8;
     for (int p = 0; p < passes; ++p) {
         hipLaunchKernelGGL(k_radix_hist, dim3(w.nblk_sort), dim3(kThreads), 0, s, k0, n, 8 * p,
-                           hist, w.nblk_sort);
-        hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, s, hist, 256 * w.nblk_sort);
+                           hist, w.nblk_sort, totals + 256 * p);
+        hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(kThreads), 0, s, hist, w.nblk_sort,
+                           totals + 256 * p);
         hipLaunchKernelGGL(k_radix_scatter, dim3(w.nblk_sort), dim3(kThreads), 0, s, k0, v0, n,
                            8 * p, hist, w.nblk_sort, k1, v1);
         std::swap(k0, k1);

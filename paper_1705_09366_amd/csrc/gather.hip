@@ -19,23 +19,26 @@
 //   setup   the bin rows (t, y) whose bins can hold points reaching the tile
 //           become a list of candidate ranges in LDS;
 //   stage   256 candidates at a time, one per thread: test the point's
-//           clipped footprint box against the tile, append the survivors'
+//           clipped footprint box against the tile and append the survivors'
 //           tile-local coordinates to an LDS list, together with the set of
-//           4 x 4 column groups and 16-row blocks the survivor's cylinder
-//           touches (a disc-versus-group test); repeat until the list is
-//           nearly full or the candidates are exhausted;
-//   mma     each wave owns an 8 x 8 quadrant (four 4 x 4 column groups) x
-//           TT/16 row blocks of accumulators.  For every group of 4
-//           survivors each lane builds its matrix-core operands in
-//           registers -- the Kt entry of one (point, row) and the Ks entry
-//           of one (point, column), Ks = max(0, 1 - (dx^2 + dy^2)/hv^2), the
-//           Epanechnikov disc, Kt = max(0, 1 - dt^2/tv^2) -- and issues one
-//           instruction per block the group touches;
+//           4 x 4 column groups and 16-row blocks its cylinder touches (a
+//           disc-versus-group test); repeat until the list is nearly full or
+//           the candidates are exhausted;
+//   lists   each wave owns an 8 x 8 quadrant (four 4 x 4 column groups) x
+//           TT/16 row blocks of accumulators and keeps, in list order, the
+//           survivors that touch its quadrant;
+//   mma     per group of 4 consecutive survivors of its list, each lane
+//           builds its matrix-core operands in registers -- the Kt entry of
+//           one (point, row) and the Ks entry of one (point, column),
+//           Ks = max(0, 1 - (dx^2 + dy^2)/hv^2) (the Epanechnikov disc),
+//           Kt = max(0, 1 - dt^2/tv^2) -- and the wave issues one instruction
+//           per block the group touches; the next group's operands are
+//           fetched while the current group's instructions run;
 //   store   each lane writes 4 consecutive rows of one column per block,
 //           scaled by the normalisation (2/pi)(3/4)/(n hs^2 ht).
-// With compensated accumulation each matrix-core phase accumulates into a
-// fresh pass accumulator that is then added into (sum, compensation) by
-// Kahan's rule; within a pass the sum is plain FP32.
+// With compensated accumulation each matrix-core phase (up to kCap points)
+// accumulates into a fresh pass accumulator that is then added into
+// (sum, compensation) by Kahan's rule; within a pass the sum is plain FP32.
 #include "stkde_internal.h"
 
 namespace stkde {
@@ -97,9 +100,9 @@ __device__ inline void kahan_fold(f32x4 (&acc)[4][NB], f32x4 (&comp)[4][NB], f32
 // (px, py) with rows [tlo, thi] (tile-local) reaches a column centre of
 // column group g and a row of block b.
 template <int NB>
-__device__ inline uint32_t touch_mask(float px, float py, int32_t tlo, int32_t thi, float inv_hv2) {
+__device__ inline uint64_t touch_mask(float px, float py, int32_t tlo, int32_t thi, float inv_hv2) {
     const int32_t b0 = max(0, tlo >> 4), b1 = min(NB - 1, thi >> 4);
-    const uint32_t rb = ((1u << (b1 + 1)) - 1u) & ~((1u << b0) - 1u);
+    const uint64_t rb = (uint64_t)(((1u << (b1 + 1)) - 1u) & ~((1u << b0) - 1u));
     float ex[4], ey[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -108,20 +111,36 @@ __device__ inline uint32_t touch_mask(float px, float py, int32_t tlo, int32_t t
         ex[k] = nx * nx * inv_hv2;
         ey[k] = ny * ny * inv_hv2;
     }
-    uint32_t m = 0;
+    uint64_t m = 0;
 #pragma unroll
     for (int g = 0; g < 16; ++g)
         if (ex[g & 3] + ey[g >> 2] < 1.0f + 1e-3f) m |= rb << (g * NB);
     return m;
 }
 
+// The bits of a tile-wide touch mask that concern wave w's column groups,
+// packed as bit (q * NB + b) for the wave's q-th group.
+template <int NB>
+__device__ inline uint32_t wave_bits(uint64_t m, int gqx, int gqy) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int g = (gqy + (q >> 1)) * 4 + gqx + (q & 1);
+        r |= (uint32_t)((m >> (g * NB)) & ((1u << NB) - 1u)) << (q * NB);
+    }
+    return r;
+}
+
 template <int TT, bool KAHAN, bool MASS>
 __global__ __launch_bounds__(kThreads) void k_gather(GatherArgs a) {
     constexpr int NB = TT / 16;  // 16-row blocks per tile
-    // survivor list: tile-local coordinates as (x head, x tail), (y head,
-    // y tail), (t head, t tail), and the touch mask
-    __shared__ float2 sX[kCap], sY[kCap], sT[kCap];
-    __shared__ __align__(16) uint32_t sM[kCap];
+    constexpr int kPad = kCap;   // index of the padding survivor
+    // survivor list: tile-local coordinates as (head, tail) pairs and the
+    // tile-wide touch mask; entry kPad is a point far outside the tile
+    __shared__ float2 sX[kCap + 1], sY[kCap + 1], sT[kCap + 1];
+    __shared__ uint64_t sM[kCap];
+    // per-wave lists: survivor index | wave touch bits << 16
+    __shared__ uint32_t sL[kWaves][kCap + 4];
     __shared__ int32_t sRB[kMaxRanges];
     __shared__ int32_t sRP[kMaxRanges + 1];
     __shared__ int32_t sWC[kWaves];
@@ -174,6 +193,11 @@ __global__ __launch_bounds__(kThreads) void k_gather(GatherArgs a) {
         }
         if (lane == nranges - 1) sRP[nranges] = inc;
     }
+    if (tid == 0) {
+        sX[kPad] = make_float2(-1.0e6f, 0.f);
+        sY[kPad] = make_float2(-1.0e6f, 0.f);
+        sT[kPad] = make_float2(-1.0e6f, 0.f);
+    }
     __syncthreads();
     const int32_t total = sRP[nranges];
 
@@ -196,9 +220,13 @@ __global__ __launch_bounds__(kThreads) void k_gather(GatherArgs a) {
     const int gqx = 2 * (wave & 1), gqy = 2 * (wave >> 1);
     const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     // lane roles in the matrix-core operands: point k of the group, row i of
-    // a block (Kt operand), column j of a group (Ks operand)
-    const int kq = lane >> 4, ri = lane & 15;
-    const float rowc = (float)ri + 0.5f;
+    // a block (Kt operand), column j = (lane & 3, (lane >> 2) & 3) of a group
+    // (Ks operand)
+    const int kq = lane >> 4;
+    const float rowc = (float)(lane & 15) + 0.5f;
+    const float xc0 = (float)(4 * gqx + (lane & 3)) + 0.5f;
+    const float yc0 = (float)(4 * gqy + ((lane >> 2) & 3)) + 0.5f;
+    uint32_t* myL = sL[wave];
 
     int32_t bb = 0;
     while (bb < total) {
@@ -247,49 +275,69 @@ __global__ __launch_bounds__(kThreads) void k_gather(GatherArgs a) {
             bb += kThreads;
             __syncthreads();  // sWC is rewritten by the next round
         }
-        // pad the last group with points far outside the tile, whose kernel
-        // values are exactly zero in every operand
-        if (tid < ((4 - (count & 3)) & 3)) {
-            sM[count + tid] = 0u;
-            sX[count + tid] = make_float2(-1.0e6f, 0.f);
-            sY[count + tid] = make_float2(-1.0e6f, 0.f);
-            sT[count + tid] = make_float2(-1.0e6f, 0.f);
+
+        // ---- this wave's list of survivors touching its quadrant ------------
+        int32_t nw = 0;
+        for (int32_t base = 0; base < count; base += 64) {
+            const int32_t s = base + lane;
+            const uint32_t wb = s < count ? wave_bits<NB>(sM[s], gqx, gqy) : 0u;
+            const unsigned long long bm = __ballot(wb != 0u);
+            if (wb) myL[nw + __popcll(bm & lt)] = (uint32_t)s | (wb << 16);
+            nw += __popcll(bm);
         }
-        __syncthreads();
+        if (lane < ((4 - (nw & 3)) & 3)) myL[nw + lane] = (uint32_t)kPad;
+        const int32_t ngroups = (nw + 3) >> 2;
 
         // ---- matrix-core accumulation ---------------------------------------
-        const int32_t ngroups = (count + 3) >> 2;
+        uint32_t e_n = 0;
+        float2 cx_n{}, cy_n{}, ct_n{};
+        if (ngroups > 0) {
+            e_n = myL[kq];
+            const int s = e_n & 0xffffu;
+            cx_n = sX[s];
+            cy_n = sY[s];
+            ct_n = sT[s];
+        }
         for (int32_t grp = 0; grp < ngroups; ++grp) {
-            const uint4 m4 = reinterpret_cast<const uint4*>(sM)[grp];
-            const uint32_t gm = __builtin_amdgcn_readfirstlane(m4.x | m4.y | m4.z | m4.w);
-            uint32_t mine[4];
-            uint32_t any = 0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int g = (gqy + (q >> 1)) * 4 + gqx + (q & 1);
-                mine[q] = (gm >> (g * NB)) & ((1u << NB) - 1u);
-                any |= mine[q];
+            const uint32_t e = e_n;
+            const float2 cx = cx_n, cy = cy_n, ctt = ct_n;
+            if (grp + 1 < ngroups) {  // fetch the next group's operands
+                e_n = myL[4 * (grp + 1) + kq];
+                const int s = e_n & 0xffffu;
+                cx_n = sX[s];
+                cy_n = sY[s];
+                ct_n = sT[s];
             }
-            if (any == 0) continue;
-            const int s = grp * 4 + kq;
-            const float2 cx = sX[s], cy = sY[s], ctt = sT[s];
+            // union of the group's wave touch bits (lanes 0, 16, 32, 48 hold
+            // the four points)
+            uint32_t wb = e >> 16;
+            wb |= __shfl_xor(wb, 16, 64);
+            wb |= __shfl_xor(wb, 32, 64);
+            const uint32_t gm = __builtin_amdgcn_readfirstlane(wb);
             float av[NB];
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 const float dt = ((float)(16 * b) + rowc - ctt.x) - ctt.y;
                 av[b] = fmaxf(0.0f, fmaf(-dt * dt, a.inv_tv2, 1.0f));
             }
+            // 1 - dx^2/hv^2 for the wave's two column-group columns in x,
+            // dy^2/hv^2 for its two in y
+            float ux[2], uy[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float dx = ((xc0 + 4.0f * h) - cx.x) - cx.y;
+                const float dy = ((yc0 + 4.0f * h) - cy.x) - cy.y;
+                ux[h] = fmaf(-dx * dx, a.inv_hv2, 1.0f);
+                uy[h] = dy * dy * a.inv_hv2;
+            }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                if (mine[q] == 0) continue;
-                const float xc = (float)(4 * (gqx + (q & 1)) + (lane & 3)) + 0.5f;
-                const float yc = (float)(4 * (gqy + (q >> 1)) + ((lane >> 2) & 3)) + 0.5f;
-                const float dx = (xc - cx.x) - cx.y;
-                const float dy = (yc - cy.x) - cy.y;
-                const float ks = fmaxf(0.0f, fmaf(-(dx * dx + dy * dy), a.inv_hv2, 1.0f));
+                const uint32_t mq = (gm >> (q * NB)) & ((1u << NB) - 1u);
+                if (mq == 0) continue;
+                const float ks = fmaxf(0.0f, ux[q & 1] - uy[q >> 1]);
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
-                    if (mine[q] & (1u << b)) {
+                    if (mq & (1u << b)) {
                         if constexpr (KAHAN)
                             pass[q][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[b], ks, pass[q][b], 0, 0, 0);
                         else
@@ -299,7 +347,7 @@ __global__ __launch_bounds__(kThreads) void k_gather(GatherArgs a) {
             }
         }
         if constexpr (KAHAN) kahan_fold<NB>(acc, comp, pass);
-        __syncthreads();  // the list is refilled next
+        __syncthreads();  // the lists are refilled next
     }
 
     // ---- store: lane holds rows 16b + 4(lane/16) + e of column (lane % 16)
@@ -337,21 +385,25 @@ __global__ __launch_bounds__(kThreads) void k_gather(GatherArgs a) {
     }
 }
 
-// Fixed-order FP64 sum of `count` partials into *dst (times `scale`), by one
-// workgroup: strided per-thread sums, then a tree in LDS.
+// Fixed-order FP64 sum of `count` partials: workgroup b sums the contiguous
+// chunk b (strided per-thread sums, then a tree in LDS) and writes
+// dst[b] = chunk sum * scale.
 __global__ __launch_bounds__(1024) void k_sum_partials(const double* __restrict__ part,
                                                        int64_t count, double scale,
                                                        double* __restrict__ dst) {
     __shared__ double sh[1024];
+    const int64_t chunk = (count + gridDim.x - 1) / gridDim.x;
+    const int64_t beg = (int64_t)blockIdx.x * chunk;
+    const int64_t end = beg + chunk < count ? beg + chunk : count;
     double s = 0.0;
-    for (int64_t i = threadIdx.x; i < count; i += 1024) s += part[i];
+    for (int64_t i = beg + threadIdx.x; i < end; i += 1024) s += part[i];
     sh[threadIdx.x] = s;
     __syncthreads();
     for (int w = 512; w >= 1; w >>= 1) {
         if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *dst = sh[0] * scale;
+    if (threadIdx.x == 0) dst[blockIdx.x] = sh[0] * scale;
 }
 
 template <int TT, bool K, bool M>
@@ -388,18 +440,24 @@ hipError_t launch_gather(const Geometry& g, float cnorm, bool kahan, bool mass, 
     if (g.tile_t == 16) {
         if (kahan) mass ? launch_one<16, true, true>(ga, s) : launch_one<16, true, false>(ga, s);
         else mass ? launch_one<16, false, true>(ga, s) : launch_one<16, false, false>(ga, s);
-    } else {
+    } else if (g.tile_t == 32) {
         if (kahan) mass ? launch_one<32, true, true>(ga, s) : launch_one<32, true, false>(ga, s);
         else mass ? launch_one<32, false, true>(ga, s) : launch_one<32, false, false>(ga, s);
+    } else {
+        if (kahan) mass ? launch_one<64, true, true>(ga, s) : launch_one<64, true, false>(ga, s);
+        else mass ? launch_one<64, false, true>(ga, s) : launch_one<64, false, false>(ga, s);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_mass_reduce(const Geometry& g, double* d_dst, uint8_t* ws, const Workspace& w,
                               hipStream_t s) {
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s,
+    double* mid = reinterpret_cast<double*>(ws + w.mass_part);
+    hipLaunchKernelGGL(k_sum_partials, dim3(kMassBlocks), dim3(1024), 0, s,
                        reinterpret_cast<const double*>(ws + w.tile_part),
-                       (int64_t)g.ntiles * kWaves, g.sres * g.sres * g.tres, d_dst);
+                       (int64_t)g.ntiles * kWaves, 1.0, mid);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, (const double*)mid,
+                       (int64_t)kMassBlocks, g.sres * g.sres * g.tres, d_dst);
     return hipGetLastError();
 }
 

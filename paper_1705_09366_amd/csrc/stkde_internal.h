@@ -66,15 +66,17 @@ struct Workspace {
     size_t recs;         // n PointRec
     size_t tile_part;    // ntiles * kWaves double (grid mass partials)
     size_t pt_part;      // nblk_pts * 4 double (per-point statistics partials)
-    size_t counters;     // 4 x u64 (non-finite, culled)
+    size_t counters;     // 4 x u64 (non-finite, culled), then 3 x 256 u32 digit totals
+    size_t mass_part;    // kMassBlocks double (first level of the grid-mass sum)
     size_t total;
     int32_t nblk_sort;
     int32_t nblk_pts;
 };
 
-constexpr int kSortItems = 16;                        // keys per thread per block
+constexpr int kSortItems = 4;                         // keys per thread per block
 constexpr int kSortTile = kThreads * kSortItems;      // keys per block
 constexpr int kStatBlock = 256;                       // points per statistics block
+constexpr int kMassBlocks = 256;                      // workgroups of the grid-mass sum
 
 Workspace layout_workspace(const Geometry& g, int64_t n);
 

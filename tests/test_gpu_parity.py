@@ -111,7 +111,7 @@ def test_golden_tiny_case(torch_cuda):
     assert int(st[2]) == evals
 
 
-@pytest.mark.parametrize("tuning", [None, (16, 8, 4), (32, 32, 32), (16, 64, 8), (32, 8, 64)])
+@pytest.mark.parametrize("tuning", [None, (16, 8, 4), (32, 32, 32), (16, 64, 8), (32, 8, 64), (64, 16, 16), (64, 4, 32)])
 def test_tunings_agree(torch_cuda, tuning):
     import paper_1705_09366_amd as m
     pts, g = workloads.small_random_case(77, max_g=90, max_n=600)
