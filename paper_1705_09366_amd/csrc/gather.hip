@@ -24,16 +24,19 @@
 //           4 x 4 column groups and 16-row blocks its cylinder touches (a
 //           disc-versus-group test); repeat until the list is nearly full or
 //           the candidates are exhausted;
-//   lists   each wave owns an 8 x 8 quadrant (four 4 x 4 column groups) x
-//           TT/16 row blocks of accumulators and keeps, in list order, the
-//           survivors that touch its quadrant;
+//   lists   each wave owns one 16-row block of the tile and 4, 8 or all 16
+//           of its 4 x 4 column groups (for 16-, 32- and 64-row tiles) as
+//           matrix-core accumulators, and keeps, in list order, the
+//           survivors that touch them;
 //   mma     per group of 4 consecutive survivors of its list, each lane
 //           builds its matrix-core operands in registers -- the Kt entry of
-//           one (point, row) and the Ks entry of one (point, column),
-//           Ks = max(0, 1 - (dx^2 + dy^2)/hv^2) (the Epanechnikov disc),
-//           Kt = max(0, 1 - dt^2/tv^2) -- and the wave issues one instruction
-//           per block the group touches; the next group's operands are
-//           fetched while the current group's instructions run;
+//           one (point, row), and the separable pieces 1 - dx^2/hv^2 and
+//           dy^2/hv^2 of the Ks entries of one point for its column in every
+//           column group, Ks = max(0, 1 - dx^2/hv^2 - dy^2/hv^2) (the
+//           Epanechnikov disc), Kt = max(0, 1 - dt^2/tv^2) -- and the wave
+//           issues one instruction per column group the group touches; the
+//           next group's coordinates are fetched while the current group's
+//           instructions run;
 //   store   each lane writes 4 consecutive rows of one column per block,
 //           scaled by the normalisation (2/pi)(3/4)/(n hs^2 ht).
 // With compensated accumulation each matrix-core phase (up to kCap points)
@@ -78,23 +81,6 @@ __device__ inline float half_hi(uint32_t v) {
     return (float)__builtin_bit_cast(_Float16, (uint16_t)(v >> 16));
 }
 
-template <int NB>
-__device__ inline void kahan_fold(f32x4 (&acc)[4][NB], f32x4 (&comp)[4][NB], f32x4 (&pass)[4][NB]) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const float y = __fsub_rn(pass[q][b][e], comp[q][b][e]);
-                const float t = __fadd_rn(acc[q][b][e], y);
-                comp[q][b][e] = __fsub_rn(__fsub_rn(t, acc[q][b][e]), y);
-                acc[q][b][e] = t;
-                pass[q][b][e] = 0.0f;
-            }
-        }
-    }
-}
 
 // Bit (g * NB + b) of the mask: the cylinder of a survivor at tile-local
 // (px, py) with rows [tlo, thi] (tile-local) reaches a column centre of
@@ -118,17 +104,35 @@ __device__ inline uint64_t touch_mask(float px, float py, int32_t tlo, int32_t t
     return m;
 }
 
-// The bits of a tile-wide touch mask that concern wave w's column groups,
-// packed as bit (q * NB + b) for the wave's q-th group.
-template <int NB>
-__device__ inline uint32_t wave_bits(uint64_t m, int gqx, int gqy) {
+// The bits of a tile-wide touch mask that concern a wave owning row block rb
+// and the column groups with gy in [gy0, gy0 + GY): bit (gy - gy0) * 4 + gx.
+template <int NB, int GY>
+__device__ inline uint32_t wave_bits(uint64_t m, int rb, int gy0) {
     uint32_t r = 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int g = (gqy + (q >> 1)) * 4 + gqx + (q & 1);
-        r |= (uint32_t)((m >> (g * NB)) & ((1u << NB) - 1u)) << (q * NB);
+    for (int j = 0; j < GY; ++j) {
+#pragma unroll
+        for (int gx = 0; gx < 4; ++gx) {
+            const int g = (gy0 + j) * 4 + gx;
+            r |= (uint32_t)((m >> (g * NB + rb)) & 1u) << (j * 4 + gx);
+        }
     }
     return r;
+}
+
+template <int CG>
+__device__ inline void kahan_fold(f32x4 (&acc)[CG], f32x4 (&comp)[CG], f32x4 (&pass)[CG]) {
+#pragma unroll
+    for (int q = 0; q < CG; ++q) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float y = __fsub_rn(pass[q][e], comp[q][e]);
+            const float t = __fadd_rn(acc[q][e], y);
+            comp[q][e] = __fsub_rn(__fsub_rn(t, acc[q][e]), y);
+            acc[q][e] = t;
+            pass[q][e] = 0.0f;
+        }
+    }
 }
 
 template <int TT, bool KAHAN, bool MASS>
@@ -202,30 +206,31 @@ __global__ __launch_bounds__(kThreads) void k_gather(GatherArgs a) {
     const int32_t total = sRP[nranges];
 
     // ---- accumulators ------------------------------------------------------
-    f32x4 acc[4][NB];
-    f32x4 comp[4][KAHAN ? NB : 1];
-    f32x4 pass[4][KAHAN ? NB : 1];
+    // wave -> (row block rb, column groups gy in [gy0, gy0 + GY), gx in 0..3)
+    constexpr int WPR = 4 / NB;   // waves per row block
+    constexpr int GY = 4 / WPR;   // rows of column groups per wave
+    constexpr int CG = 4 * GY;    // column groups per wave
+    const int rb = wave / WPR;
+    const int gy0 = (wave % WPR) * GY;
+    f32x4 acc[CG];
+    f32x4 comp[KAHAN ? CG : 1];
+    f32x4 pass[KAHAN ? CG : 1];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            acc[q][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-            if constexpr (KAHAN) {
-                comp[q][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-                pass[q][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-            }
+    for (int q = 0; q < CG; ++q) {
+        acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+        if constexpr (KAHAN) {
+            comp[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+            pass[q] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
     }
-    // this wave's four column groups (gx, gy) in the tile's 4 x 4 grid of groups
-    const int gqx = 2 * (wave & 1), gqy = 2 * (wave >> 1);
     const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     // lane roles in the matrix-core operands: point k of the group, row i of
-    // a block (Kt operand), column j = (lane & 3, (lane >> 2) & 3) of a group
-    // (Ks operand)
+    // the block (Kt operand), column j = (lane & 3, (lane >> 2) & 3) of a
+    // column group (Ks operand)
     const int kq = lane >> 4;
-    const float rowc = (float)(lane & 15) + 0.5f;
-    const float xc0 = (float)(4 * gqx + (lane & 3)) + 0.5f;
-    const float yc0 = (float)(4 * gqy + ((lane >> 2) & 3)) + 0.5f;
+    const float rowc = (float)(16 * rb + (lane & 15)) + 0.5f;
+    const float xc0 = (float)(lane & 3) + 0.5f;
+    const float yc0 = (float)(4 * gy0 + ((lane >> 2) & 3)) + 0.5f;
     uint32_t* myL = sL[wave];
 
     int32_t bb = 0;
@@ -276,11 +281,11 @@ __global__ __launch_bounds__(kThreads) void k_gather(GatherArgs a) {
             __syncthreads();  // sWC is rewritten by the next round
         }
 
-        // ---- this wave's list of survivors touching its quadrant ------------
+        // ---- this wave's list of survivors touching its blocks ---------------
         int32_t nw = 0;
         for (int32_t base = 0; base < count; base += 64) {
             const int32_t s = base + lane;
-            const uint32_t wb = s < count ? wave_bits<NB>(sM[s], gqx, gqy) : 0u;
+            const uint32_t wb = s < count ? wave_bits<NB, GY>(sM[s], rb, gy0) : 0u;
             const unsigned long long bm = __ballot(wb != 0u);
             if (wb) myL[nw + __popcll(bm & lt)] = (uint32_t)s | (wb << 16);
             nw += __popcll(bm);
@@ -301,79 +306,68 @@ __global__ __launch_bounds__(kThreads) void k_gather(GatherArgs a) {
         for (int32_t grp = 0; grp < ngroups; ++grp) {
             const uint32_t e = e_n;
             const float2 cx = cx_n, cy = cy_n, ctt = ct_n;
-            if (grp + 1 < ngroups) {  // fetch the next group's operands
+            if (grp + 1 < ngroups) {  // fetch the next group's coordinates
                 e_n = myL[4 * (grp + 1) + kq];
                 const int s = e_n & 0xffffu;
                 cx_n = sX[s];
                 cy_n = sY[s];
                 ct_n = sT[s];
             }
-            // union of the group's wave touch bits (lanes 0, 16, 32, 48 hold
-            // the four points)
+            // union of the group's touch bits (lanes 0, 16, 32, 48 hold the
+            // four points)
             uint32_t wb = e >> 16;
             wb |= __shfl_xor(wb, 16, 64);
             wb |= __shfl_xor(wb, 32, 64);
             const uint32_t gm = __builtin_amdgcn_readfirstlane(wb);
-            float av[NB];
+            const float dt = (rowc - ctt.x) - ctt.y;
+            const float av = fmaxf(0.0f, fmaf(-dt * dt, a.inv_tv2, 1.0f));
+            // 1 - dx^2/hv^2 for the lane's column in each gx, dy^2/hv^2 in each gy
+            float ux[4], uy[GY];
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const float dt = ((float)(16 * b) + rowc - ctt.x) - ctt.y;
-                av[b] = fmaxf(0.0f, fmaf(-dt * dt, a.inv_tv2, 1.0f));
-            }
-            // 1 - dx^2/hv^2 for the wave's two column-group columns in x,
-            // dy^2/hv^2 for its two in y
-            float ux[2], uy[2];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int h = 0; h < 4; ++h) {
                 const float dx = ((xc0 + 4.0f * h) - cx.x) - cx.y;
-                const float dy = ((yc0 + 4.0f * h) - cy.x) - cy.y;
                 ux[h] = fmaf(-dx * dx, a.inv_hv2, 1.0f);
+            }
+#pragma unroll
+            for (int h = 0; h < GY; ++h) {
+                const float dy = ((yc0 + 4.0f * h) - cy.x) - cy.y;
                 uy[h] = dy * dy * a.inv_hv2;
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint32_t mq = (gm >> (q * NB)) & ((1u << NB) - 1u);
-                if (mq == 0) continue;
-                const float ks = fmaxf(0.0f, ux[q & 1] - uy[q >> 1]);
-#pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    if (mq & (1u << b)) {
-                        if constexpr (KAHAN)
-                            pass[q][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[b], ks, pass[q][b], 0, 0, 0);
-                        else
-                            acc[q][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[b], ks, acc[q][b], 0, 0, 0);
-                    }
-                }
+            for (int q = 0; q < CG; ++q) {
+                if (!(gm & (1u << q))) continue;
+                const float ks = fmaxf(0.0f, ux[q & 3] - uy[q >> 2]);
+                if constexpr (KAHAN)
+                    pass[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, ks, pass[q], 0, 0, 0);
+                else
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, ks, acc[q], 0, 0, 0);
             }
         }
-        if constexpr (KAHAN) kahan_fold<NB>(acc, comp, pass);
+        if constexpr (KAHAN) kahan_fold<CG>(acc, comp, pass);
         __syncthreads();  // the lists are refilled next
     }
 
-    // ---- store: lane holds rows 16b + 4(lane/16) + e of column (lane % 16)
-    // of each of its four column groups ---------------------------------------
+    // ---- store: lane holds rows 16 rb + 4 (lane / 16) + e of column
+    // (lane % 4, (lane / 4) % 4) of each of its column groups -------------------
     double msum = 0.0;
     const bool vec = (a.gt & 3) == 0;
+    const int32_t T = T0 + 16 * rb + 4 * (lane >> 4);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int32_t X = X0 + 4 * (gqx + (q & 1)) + (lane & 3);
-        const int32_t Y = Y0 + 4 * (gqy + (q >> 1)) + ((lane >> 2) & 3);
+    for (int q = 0; q < CG; ++q) {
+        const int32_t X = X0 + 4 * (q & 3) + (lane & 3);
+        const int32_t Y = Y0 + 4 * (gy0 + (q >> 2)) + ((lane >> 2) & 3);
         if (X >= a.gx || Y >= a.gy) continue;
         float* col = a.out + ((size_t)X * a.gy + Y) * a.gt;
+        const f32x4 v = acc[q] * a.cnorm;
+        if (vec && T + 3 < a.gt) {
+            *reinterpret_cast<f32x4*>(col + T) = v;
+            if constexpr (MASS) msum += (double)v[0] + (double)v[1] + (double)v[2] + (double)v[3];
+        } else {
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const int32_t T = T0 + 16 * b + 4 * (lane >> 4);
-            const f32x4 v = acc[q][b] * a.cnorm;
-            if (vec && T + 3 < a.gt) {
-                *reinterpret_cast<f32x4*>(col + T) = v;
-                if constexpr (MASS) msum += (double)v[0] + (double)v[1] + (double)v[2] + (double)v[3];
-            } else {
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    if (T + e < a.gt) {
-                        col[T + e] = v[e];
-                        if constexpr (MASS) msum += (double)v[e];
-                    }
+            for (int e = 0; e < 4; ++e) {
+                if (T + e < a.gt) {
+                    col[T + e] = v[e];
+                    if constexpr (MASS) msum += (double)v[e];
                 }
             }
         }
