@@ -18,6 +18,10 @@ ARCH = os.environ.get("STKDE_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          # matrix-core accumulators in VGPRs: the gather skips untouched blocks
+          # with uniform branches, and AGPR accumulators would be copied to
+          # VGPRs and back around every one of them
+          "-mllvm", "-amdgpu-mfma-vgpr-form",
           "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
