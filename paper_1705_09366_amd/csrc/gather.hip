@@ -24,19 +24,19 @@
 //           4 x 4 column groups and 16-row blocks its cylinder touches (a
 //           disc-versus-group test); repeat until the list is nearly full or
 //           the candidates are exhausted;
-//   lists   each wave owns one 16-row block of the tile and 4, 8 or all 16
-//           of its 4 x 4 column groups (for 16-, 32- and 64-row tiles) as
-//           matrix-core accumulators, and keeps, in list order, the
-//           survivors that touch them;
+//   lists   each wave owns an 8 x 8 quadrant (four 4 x 4 column groups) x
+//           TT/16 blocks of 16 rows as matrix-core accumulators, and keeps,
+//           in list order, the survivors whose footprint box meets its
+//           quadrant;
 //   mma     per group of 4 consecutive survivors of its list, each lane
-//           builds its matrix-core operands in registers -- the Kt entry of
-//           one (point, row), and the separable pieces 1 - dx^2/hv^2 and
-//           dy^2/hv^2 of the Ks entries of one point for its column in every
-//           column group, Ks = max(0, 1 - dx^2/hv^2 - dy^2/hv^2) (the
-//           Epanechnikov disc), Kt = max(0, 1 - dt^2/tv^2) -- and the wave
-//           issues one instruction per column group the group touches; the
-//           next group's coordinates are fetched while the current group's
-//           instructions run;
+//           builds its matrix-core operands in registers -- the Kt entries
+//           of one point for one row of every block, and the separable pieces
+//           1 - dx^2/hv^2 and dy^2/hv^2 of the Ks entries of one point for its
+//           column in each column group, Ks = max(0, 1 - dx^2/hv^2 -
+//           dy^2/hv^2) (the Epanechnikov disc), Kt = max(0, 1 - dt^2/tv^2) --
+//           and the wave issues one instruction per (column group, row
+//           block).  The loop has no branches; the next group's coordinates
+//           are fetched while the current group's instructions run;
 //   store   each lane writes 4 consecutive rows of one column per block,
 //           scaled by the normalisation (2/pi)(3/4)/(n hs^2 ht).
 // With compensated accumulation each matrix-core phase (up to kCap points)
@@ -82,44 +82,6 @@ __device__ inline float half_hi(uint32_t v) {
 }
 
 
-// Bit (g * NB + b) of the mask: the cylinder of a survivor at tile-local
-// (px, py) with rows [tlo, thi] (tile-local) reaches a column centre of
-// column group g and a row of block b.
-template <int NB>
-__device__ inline uint64_t touch_mask(float px, float py, int32_t tlo, int32_t thi, float inv_hv2) {
-    const int32_t b0 = max(0, tlo >> 4), b1 = min(NB - 1, thi >> 4);
-    const uint64_t rb = (uint64_t)(((1u << (b1 + 1)) - 1u) & ~((1u << b0) - 1u));
-    float ex[4], ey[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const float nx = fminf(fmaxf(px, 4.0f * k + 0.5f), 4.0f * k + 3.5f) - px;
-        const float ny = fminf(fmaxf(py, 4.0f * k + 0.5f), 4.0f * k + 3.5f) - py;
-        ex[k] = nx * nx * inv_hv2;
-        ey[k] = ny * ny * inv_hv2;
-    }
-    uint64_t m = 0;
-#pragma unroll
-    for (int g = 0; g < 16; ++g)
-        if (ex[g & 3] + ey[g >> 2] < 1.0f + 1e-3f) m |= rb << (g * NB);
-    return m;
-}
-
-// The bits of a tile-wide touch mask that concern a wave owning row block rb
-// and the column groups with gy in [gy0, gy0 + GY): bit (gy - gy0) * 4 + gx.
-template <int NB, int GY>
-__device__ inline uint32_t wave_bits(uint64_t m, int rb, int gy0) {
-    uint32_t r = 0;
-#pragma unroll
-    for (int j = 0; j < GY; ++j) {
-#pragma unroll
-        for (int gx = 0; gx < 4; ++gx) {
-            const int g = (gy0 + j) * 4 + gx;
-            r |= (uint32_t)((m >> (g * NB + rb)) & 1u) << (j * 4 + gx);
-        }
-    }
-    return r;
-}
-
 template <int CG>
 __device__ inline void kahan_fold(f32x4 (&acc)[CG], f32x4 (&comp)[CG], f32x4 (&pass)[CG]) {
 #pragma unroll
@@ -138,13 +100,15 @@ __device__ inline void kahan_fold(f32x4 (&acc)[CG], f32x4 (&comp)[CG], f32x4 (&p
 template <int TT, bool KAHAN, bool MASS>
 __global__ __launch_bounds__(kThreads) void k_gather(GatherArgs a) {
     constexpr int NB = TT / 16;  // 16-row blocks per tile
+    constexpr int CG = 4 * NB;   // accumulator blocks per wave
     constexpr int kPad = kCap;   // index of the padding survivor
     // survivor list: tile-local coordinates as (head, tail) pairs and the
-    // tile-wide touch mask; entry kPad is a point far outside the tile
+    // quadrants its footprint box meets; entry kPad is a point far outside
+    // the tile
     __shared__ float2 sX[kCap + 1], sY[kCap + 1], sT[kCap + 1];
-    __shared__ uint64_t sM[kCap];
-    // per-wave lists: survivor index | wave touch bits << 16
-    __shared__ uint32_t sL[kWaves][kCap + 4];
+    __shared__ uint8_t sQ[kCap];
+    // per-wave lists of survivor indices
+    __shared__ uint16_t sL[kWaves][kCap + 8];
     __shared__ int32_t sRB[kMaxRanges];
     __shared__ int32_t sRP[kMaxRanges + 1];
     __shared__ int32_t sWC[kWaves];
@@ -205,13 +169,7 @@ __global__ __launch_bounds__(kThreads) void k_gather(GatherArgs a) {
     __syncthreads();
     const int32_t total = sRP[nranges];
 
-    // ---- accumulators ------------------------------------------------------
-    // wave -> (row block rb, column groups gy in [gy0, gy0 + GY), gx in 0..3)
-    constexpr int WPR = 4 / NB;   // waves per row block
-    constexpr int GY = 4 / WPR;   // rows of column groups per wave
-    constexpr int CG = 4 * GY;    // column groups per wave
-    const int rb = wave / WPR;
-    const int gy0 = (wave % WPR) * GY;
+    // ---- accumulators: [column group q][row block b] ------------------------
     f32x4 acc[CG];
     f32x4 comp[KAHAN ? CG : 1];
     f32x4 pass[KAHAN ? CG : 1];
@@ -223,15 +181,48 @@ __global__ __launch_bounds__(kThreads) void k_gather(GatherArgs a) {
             pass[q] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
     }
+    // this wave's quadrant: column groups gx in {gqx, gqx + 1}, gy in {gqy, gqy + 1}
+    const int gqx = 2 * (wave & 1), gqy = 2 * (wave >> 1);
+    const int32_t QX0 = X0 + 4 * gqx, QY0 = Y0 + 4 * gqy;
     const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     // lane roles in the matrix-core operands: point k of the group, row i of
-    // the block (Kt operand), column j = (lane & 3, (lane >> 2) & 3) of a
-    // column group (Ks operand)
+    // a block (Kt operand), column j = (lane & 3, (lane >> 2) & 3) of a column
+    // group (Ks operand)
     const int kq = lane >> 4;
-    const float rowc = (float)(16 * rb + (lane & 15)) + 0.5f;
-    const float xc0 = (float)(lane & 3) + 0.5f;
-    const float yc0 = (float)(4 * gy0 + ((lane >> 2) & 3)) + 0.5f;
-    uint32_t* myL = sL[wave];
+    const float rowc = (float)(lane & 15) + 0.5f;
+    const float xc0 = (float)(4 * gqx + (lane & 3)) + 0.5f;
+    const float yc0 = (float)(4 * gqy + ((lane >> 2) & 3)) + 0.5f;
+    uint16_t* myL = sL[wave];
+
+    // one group: operands from the coordinates of this lane's point, then
+    // all CG instructions
+    auto group = [&](const float2 cx, const float2 cy, const float2 ctt) {
+        float av[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const float dt = ((rowc + 16.0f * b) - ctt.x) - ctt.y;
+            av[b] = fmaxf(0.0f, fmaf(-dt * dt, a.inv_tv2, 1.0f));
+        }
+        float ux[2], uy[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const float dx = ((xc0 + 4.0f * h) - cx.x) - cx.y;
+            const float dy = ((yc0 + 4.0f * h) - cy.x) - cy.y;
+            ux[h] = fmaf(-dx * dx, a.inv_hv2, 1.0f);
+            uy[h] = dy * dy * a.inv_hv2;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float ks = fmaxf(0.0f, ux[q & 1] - uy[q >> 1]);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                if constexpr (KAHAN)
+                    pass[q * NB + b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[b], ks, pass[q * NB + b], 0, 0, 0);
+                else
+                    acc[q * NB + b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[b], ks, acc[q * NB + b], 0, 0, 0);
+            }
+        }
+    };
 
     int32_t bb = 0;
     while (bb < total) {
@@ -241,6 +232,7 @@ __global__ __launch_bounds__(kThreads) void k_gather(GatherArgs a) {
             const int32_t c = bb + tid;
             bool surv = false;
             PointRec r{};
+            uint32_t qm = 0;
             if (c < total) {
                 int32_t lo = 0, hi = nranges - 1;  // last range with sRP <= c
                 while (lo < hi) {
@@ -249,11 +241,17 @@ __global__ __launch_bounds__(kThreads) void k_gather(GatherArgs a) {
                     else hi = mid - 1;
                 }
                 r = a.recs[sRB[lo] + (c - sRP[lo])];
-                const int32_t xlo = (int32_t)(r.xb & 0xffffu), xhi = (int32_t)(r.xb >> 16);
-                const int32_t ylo = (int32_t)(r.yb & 0xffffu), yhi = (int32_t)(r.yb >> 16);
+                const int32_t xlo = (int32_t)(r.xb & 0xffffu) - X0, xhi = (int32_t)(r.xb >> 16) - X0;
+                const int32_t ylo = (int32_t)(r.yb & 0xffffu) - Y0, yhi = (int32_t)(r.yb >> 16) - Y0;
                 const int32_t tlo = (int32_t)(r.tb & 0xffffu), thi = (int32_t)(r.tb >> 16);
-                surv = xlo <= X0 + kTileXY - 1 && xhi >= X0 && ylo <= Y0 + kTileXY - 1 &&
-                       yhi >= Y0 && tlo <= T0 + TT - 1 && thi >= T0;
+                if (tlo <= T0 + TT - 1 && thi >= T0) {
+                    // quadrants (qx, qy) whose 8 x 8 columns the footprint box meets
+                    const bool x0 = xlo <= 7 && xhi >= 0, x1 = xlo <= 15 && xhi >= 8;
+                    const bool y0 = ylo <= 7 && yhi >= 0, y1 = ylo <= 15 && yhi >= 8;
+                    qm = (uint32_t)(x0 && y0) | ((uint32_t)(x1 && y0) << 1) |
+                         ((uint32_t)(x0 && y1) << 2) | ((uint32_t)(x1 && y1) << 3);
+                }
+                surv = qm != 0;
             }
             const unsigned long long m = __ballot(surv);
             if (lane == 0) sWC[wave] = __popcll(m);
@@ -268,106 +266,74 @@ __global__ __launch_bounds__(kThreads) void k_gather(GatherArgs a) {
             if (surv) {
                 const int s = off + __popcll(m & lt);
                 // head - origin is exact for the offsets that reach the tile
-                const float px = r.xh - (float)X0, py = r.yh - (float)Y0;
-                const float xl = half_lo(r.xl_yl), yl = half_hi(r.xl_yl);
-                sX[s] = make_float2(px, xl);
-                sY[s] = make_float2(py, yl);
+                sX[s] = make_float2(r.xh - (float)X0, half_lo(r.xl_yl));
+                sY[s] = make_float2(r.yh - (float)Y0, half_hi(r.xl_yl));
                 sT[s] = make_float2(r.th - (float)T0, half_lo(r.tl));
-                sM[s] = touch_mask<NB>(px + xl, py + yl, (int32_t)(r.tb & 0xffffu) - T0,
-                                       (int32_t)(r.tb >> 16) - T0, a.inv_hv2);
+                sQ[s] = (uint8_t)qm;
             }
             count += add;
             bb += kThreads;
             __syncthreads();  // sWC is rewritten by the next round
         }
 
-        // ---- this wave's list of survivors touching its blocks ---------------
+        // ---- this wave's list: survivors meeting its quadrant ---------------
         int32_t nw = 0;
         for (int32_t base = 0; base < count; base += 64) {
             const int32_t s = base + lane;
-            const uint32_t wb = s < count ? wave_bits<NB, GY>(sM[s], rb, gy0) : 0u;
-            const unsigned long long bm = __ballot(wb != 0u);
-            if (wb) myL[nw + __popcll(bm & lt)] = (uint32_t)s | (wb << 16);
+            const bool mine = s < count && ((sQ[s] >> wave) & 1u);
+            const unsigned long long bm = __ballot(mine);
+            if (mine) myL[nw + __popcll(bm & lt)] = (uint16_t)s;
             nw += __popcll(bm);
         }
-        if (lane < ((4 - (nw & 3)) & 3)) myL[nw + lane] = (uint32_t)kPad;
-        const int32_t ngroups = (nw + 3) >> 2;
+        // pad to a whole number of pairs of groups
+        if (lane < ((8 - (nw & 7)) & 7)) myL[nw + lane] = (uint16_t)kPad;
+        const int32_t npairs = (nw + 7) >> 3;
 
-        // ---- matrix-core accumulation ---------------------------------------
-        uint32_t e_n = 0;
-        float2 cx_n{}, cy_n{}, ct_n{};
-        if (ngroups > 0) {
-            e_n = myL[kq];
-            const int s = e_n & 0xffffu;
-            cx_n = sX[s];
-            cy_n = sY[s];
-            ct_n = sT[s];
-        }
-        for (int32_t grp = 0; grp < ngroups; ++grp) {
-            const uint32_t e = e_n;
-            const float2 cx = cx_n, cy = cy_n, ctt = ct_n;
-            if (grp + 1 < ngroups) {  // fetch the next group's coordinates
-                e_n = myL[4 * (grp + 1) + kq];
-                const int s = e_n & 0xffffu;
-                cx_n = sX[s];
-                cy_n = sY[s];
-                ct_n = sT[s];
-            }
-            // union of the group's touch bits (lanes 0, 16, 32, 48 hold the
-            // four points)
-            uint32_t wb = e >> 16;
-            wb |= __shfl_xor(wb, 16, 64);
-            wb |= __shfl_xor(wb, 32, 64);
-            const uint32_t gm = __builtin_amdgcn_readfirstlane(wb);
-            const float dt = (rowc - ctt.x) - ctt.y;
-            const float av = fmaxf(0.0f, fmaf(-dt * dt, a.inv_tv2, 1.0f));
-            // 1 - dx^2/hv^2 for the lane's column in each gx, dy^2/hv^2 in each gy
-            float ux[4], uy[GY];
-#pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                const float dx = ((xc0 + 4.0f * h) - cx.x) - cx.y;
-                ux[h] = fmaf(-dx * dx, a.inv_hv2, 1.0f);
-            }
-#pragma unroll
-            for (int h = 0; h < GY; ++h) {
-                const float dy = ((yc0 + 4.0f * h) - cy.x) - cy.y;
-                uy[h] = dy * dy * a.inv_hv2;
-            }
-#pragma unroll
-            for (int q = 0; q < CG; ++q) {
-                if (!(gm & (1u << q))) continue;
-                const float ks = fmaxf(0.0f, ux[q & 3] - uy[q >> 2]);
-                if constexpr (KAHAN)
-                    pass[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, ks, pass[q], 0, 0, 0);
-                else
-                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, ks, acc[q], 0, 0, 0);
+        // ---- matrix-core accumulation, two groups per iteration -------------
+        if (npairs > 0) {
+            int s = myL[kq];
+            float2 ax = sX[s], ay = sY[s], at = sT[s];
+            for (int32_t pr = 0; pr < npairs; ++pr) {
+                s = myL[8 * pr + 4 + kq];
+                const float2 bx = sX[s], by = sY[s], bt = sT[s];
+                group(ax, ay, at);
+                if (pr + 1 < npairs) {
+                    s = myL[8 * pr + 8 + kq];
+                    ax = sX[s];
+                    ay = sY[s];
+                    at = sT[s];
+                }
+                group(bx, by, bt);
             }
         }
         if constexpr (KAHAN) kahan_fold<CG>(acc, comp, pass);
         __syncthreads();  // the lists are refilled next
     }
 
-    // ---- store: lane holds rows 16 rb + 4 (lane / 16) + e of column
+    // ---- store: lane holds rows 16 b + 4 (lane / 16) + e of column
     // (lane % 4, (lane / 4) % 4) of each of its column groups -------------------
     double msum = 0.0;
     const bool vec = (a.gt & 3) == 0;
-    const int32_t T = T0 + 16 * rb + 4 * (lane >> 4);
 #pragma unroll
-    for (int q = 0; q < CG; ++q) {
-        const int32_t X = X0 + 4 * (q & 3) + (lane & 3);
-        const int32_t Y = Y0 + 4 * (gy0 + (q >> 2)) + ((lane >> 2) & 3);
+    for (int q = 0; q < 4; ++q) {
+        const int32_t X = QX0 + 4 * (q & 1) + (lane & 3);
+        const int32_t Y = QY0 + 4 * (q >> 1) + ((lane >> 2) & 3);
         if (X >= a.gx || Y >= a.gy) continue;
         float* col = a.out + ((size_t)X * a.gy + Y) * a.gt;
-        const f32x4 v = acc[q] * a.cnorm;
-        if (vec && T + 3 < a.gt) {
-            *reinterpret_cast<f32x4*>(col + T) = v;
-            if constexpr (MASS) msum += (double)v[0] + (double)v[1] + (double)v[2] + (double)v[3];
-        } else {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                if (T + e < a.gt) {
-                    col[T + e] = v[e];
-                    if constexpr (MASS) msum += (double)v[e];
+        for (int b = 0; b < NB; ++b) {
+            const int32_t T = T0 + 16 * b + 4 * (lane >> 4);
+            const f32x4 v = acc[q * NB + b] * a.cnorm;
+            if (vec && T + 3 < a.gt) {
+                *reinterpret_cast<f32x4*>(col + T) = v;
+                if constexpr (MASS) msum += (double)v[0] + (double)v[1] + (double)v[2] + (double)v[3];
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (T + e < a.gt) {
+                        col[T + e] = v[e];
+                        if constexpr (MASS) msum += (double)v[e];
+                    }
                 }
             }
         }
