@@ -114,6 +114,8 @@ def main():
     ap.add_argument("--tile-t", type=int, default=0, help="tuning: time rows per tile (16/32)")
     ap.add_argument("--cell-xy", type=int, default=0, help="tuning: bin edge in x, y")
     ap.add_argument("--cell-t", type=int, default=0, help="tuning: bin edge in t")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -132,6 +134,17 @@ def main():
     m.lib()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+
+    if args.calibrate_copy:
+        # a plain copy kernel of known size: 1 GiB read + 1 GiB written per launch
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read_per_launch": src.numel() * 4,
+                          "bytes_written_per_launch": dst.numel() * 4, "launches": 3}), flush=True)
+        return
 
     inst = _instance(args.workload)
     n = inst.points.shape[0]
