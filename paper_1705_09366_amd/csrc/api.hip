@@ -121,6 +121,25 @@ stkde_status stkde_plan(const stkde_desc* d, const stkde_tuning* tun, stkde_plan
         if ((ry >= rt && g.cxy < 65536) || g.ct >= 65536) g.cxy *= 2;
         else g.ct *= 2;
     }
+    // Keys of at most 16 bits sort in two radix passes instead of three:
+    // widen the bins in t (up to twice) when that alone gets there and the
+    // range limit still holds.
+    if (!cell_t && g.ncell >= 65536 && g.ncell < (1 << 20)) {
+        for (int32_t c = g.ct + 1; c <= 2 * g.ct; ++c) {
+            const int64_t nct = (d->gt + c - 1) / c;
+            const int64_t nc = (int64_t)g.ncx * g.ncy * nct;
+            const int64_t nt = span(g.tile_t + 2 * (int64_t)g.Ht + 2, c);
+            const int64_t ry = span(stkde::kTileXY + 2 * (int64_t)g.Hs + 2, g.cxy);
+            const int64_t rr = (ry < g.ncy ? ry : g.ncy) * (nt < nct ? nt : nct);
+            if (nc < 65536 && rr <= stkde::kMaxRanges) {
+                g.ct = c;
+                g.nct = (int32_t)nct;
+                g.ncell = (int32_t)nc;
+                g.max_ranges = (int32_t)rr;
+                break;
+            }
+        }
+    }
     g.ntx = ceil_div(d->gx, stkde::kTileXY);
     g.nty = ceil_div(d->gy, stkde::kTileXY);
     g.ntt = ceil_div(d->gt, g.tile_t);

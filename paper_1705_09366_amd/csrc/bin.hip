@@ -104,13 +104,11 @@ __global__ __launch_bounds__(kThreads) void k_transform(Geometry g, const double
 
 // ---- stable LSD radix sort, 8-bit digits --------------------------------
 
-// Per-block digit histogram.  hist is digit-major: hist[d * nblk + b]; the
-// digit totals over all blocks are accumulated in `totals` (integer sums, so
-// the result does not depend on the order of the additions).
+// Per-block digit histogram.  hist is digit-major: hist[d * nblk + b].
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                          int32_t n, int shift,
                                                          uint32_t* __restrict__ hist,
-                                                         int32_t nblk, uint32_t* __restrict__ totals) {
+                                                         int32_t nblk) {
     __shared__ uint32_t cnt[256];
     cnt[threadIdx.x] = 0;
     __syncthreads();
@@ -121,9 +119,21 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restr
         if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    const uint32_t c = cnt[threadIdx.x];
-    hist[threadIdx.x * nblk + blockIdx.x] = c;
-    if (c) atomicAdd(&totals[threadIdx.x], c);
+    hist[threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// totals[d] = sum over blocks of hist[d][b]; one workgroup per digit.
+__global__ __launch_bounds__(kThreads) void k_radix_rowsum(const uint32_t* __restrict__ hist,
+                                                           int32_t nblk, uint32_t* __restrict__ totals) {
+    __shared__ uint32_t wsum[kWaves];
+    const uint32_t* row = hist + (size_t)blockIdx.x * nblk;
+    uint32_t v = 0;
+    for (int32_t i = threadIdx.x; i < nblk; i += kThreads) v += row[i];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) totals[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
 // One workgroup per digit d: hist[d][b] <- (keys with a smaller digit) +
@@ -309,7 +319,9 @@ hipError_t launch_bin(const Geometry& g, const double* d_xyt, int32_t n, uint8_t
     const int passes = bits <= 8 ? 1 : (bits + 7) / 8;
     for (int p = 0; p < passes; ++p) {
         hipLaunchKernelGGL(k_radix_hist, dim3(w.nblk_sort), dim3(kThreads), 0, s, k0, n, 8 * p,
-                           hist, w.nblk_sort, totals + 256 * p);
+                           hist, w.nblk_sort);
+        hipLaunchKernelGGL(k_radix_rowsum, dim3(256), dim3(kThreads), 0, s, hist, w.nblk_sort,
+                           totals + 256 * p);
         hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(kThreads), 0, s, hist, w.nblk_sort,
                            totals + 256 * p);
         hipLaunchKernelGGL(k_radix_scatter, dim3(w.nblk_sort), dim3(kThreads), 0, s, k0, v0, n,

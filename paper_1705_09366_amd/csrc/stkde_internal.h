@@ -73,7 +73,7 @@ struct Workspace {
     int32_t nblk_pts;
 };
 
-constexpr int kSortItems = 4;                         // keys per thread per block
+constexpr int kSortItems = 8;                         // keys per thread per block
 constexpr int kSortTile = kThreads * kSortItems;      // keys per block
 constexpr int kStatBlock = 256;                       // points per statistics block
 constexpr int kMassBlocks = 256;                      // workgroups of the grid-mass sum
