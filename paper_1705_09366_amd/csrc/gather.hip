@@ -18,27 +18,30 @@
 // Per workgroup (256 threads) and 16 x 16 x TT tile:
 //   setup   the bin rows (t, y) whose bins can hold points reaching the tile
 //           become a list of candidate ranges in LDS;
-//   stage   128 candidates at a time, one per thread of the first two waves:
-//           test the point's clipped footprint box against the tile; each
-//           survivor writes its PB-SYM tables for this tile into LDS -- the
-//           temporal table Kt[T] = max(0, 1 - dt^2/tv^2) over the tile rows
-//           and the separable pieces of the spatial table, AX[X] =
-//           1 - dx^2/hv^2 and BY[Y] = dy^2/hv^2 (Ks = max(0, AX - BY), the
-//           Epanechnikov disc) -- and the set of blocks (4 x 4 columns x 16
-//           rows) its cylinder reaches; repeat while the list has room;
-//   lists   each wave owns 4 x TT/16 blocks (its 8 x 8 quadrant of columns
-//           times every 16-row block) as matrix-core accumulators and builds,
-//           for each block, the ordered list of survivors that reach it;
-//   mma     for each block, per group of 4 consecutive survivors of its list
-//           each lane reads its operands from the tables -- Kt of one
-//           (point, row) and Ks of one (point, column) -- and the wave issues
-//           one v_mfma_f32_16x16x4f32; the next group's operands are read
-//           while the current instruction runs;
+//   stage   256 candidates at a time, one per thread: test the point's
+//           clipped footprint box against the tile and append the survivors'
+//           tile-local coordinates to an LDS list, together with the set of
+//           4 x 4 column groups and 16-row blocks its cylinder touches (a
+//           disc-versus-group test); repeat until the list is nearly full or
+//           the candidates are exhausted;
+//   lists   each wave owns an 8 x 8 quadrant (four 4 x 4 column groups) x
+//           TT/16 blocks of 16 rows as matrix-core accumulators, and keeps,
+//           in list order, the survivors whose footprint box meets its
+//           quadrant;
+//   mma     per group of 4 consecutive survivors of its list, each lane
+//           builds its matrix-core operands in registers -- the Kt entries
+//           of one point for one row of every block, and the separable pieces
+//           1 - dx^2/hv^2 and dy^2/hv^2 of the Ks entries of one point for its
+//           column in each column group, Ks = max(0, 1 - dx^2/hv^2 -
+//           dy^2/hv^2) (the Epanechnikov disc), Kt = max(0, 1 - dt^2/tv^2) --
+//           and the wave issues one instruction per (column group, row
+//           block).  The loop has no branches; the next group's coordinates
+//           are fetched while the current group's instructions run;
 //   store   each lane writes 4 consecutive rows of one column per block,
 //           scaled by the normalisation (2/pi)(3/4)/(n hs^2 ht).
-// With compensated accumulation each matrix-core phase accumulates into a
-// fresh pass accumulator that is then added into (sum, compensation) by
-// Kahan's rule; within a pass the sum is plain FP32.
+// With compensated accumulation each matrix-core phase (up to kCap points)
+// accumulates into a fresh pass accumulator that is then added into
+// (sum, compensation) by Kahan's rule; within a pass the sum is plain FP32.
 #include "stkde_internal.h"
 
 namespace stkde {
@@ -46,8 +49,7 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kCap = 255;     // survivors per matrix-core phase (8-bit list entries)
-constexpr int kRound = 128;   // candidates tested per staging round
+constexpr int kCap = 1024;  // survivors held in LDS between matrix-core phases
 
 struct GatherArgs {
     const uint32_t* cell_start;
@@ -95,41 +97,21 @@ __device__ inline void kahan_fold(f32x4 (&acc)[CG], f32x4 (&comp)[CG], f32x4 (&p
     }
 }
 
-// Bit (g * NB + b): the cylinder of a point at tile-local (px, py) with rows
-// [tlo, thi] (tile-local) reaches a column centre of column group g (4 x 4
-// columns, g = 4 gy + gx) and a row of block b.
-template <int NB>
-__device__ inline uint64_t touch_mask(float px, float py, int32_t tlo, int32_t thi, float inv_hv2) {
-    const int32_t b0 = max(0, tlo >> 4), b1 = min(NB - 1, thi >> 4);
-    const uint64_t rb = (uint64_t)(((1u << (b1 + 1)) - 1u) & ~((1u << b0) - 1u));
-    float ex[4], ey[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const float nx = fminf(fmaxf(px, 4.0f * k + 0.5f), 4.0f * k + 3.5f) - px;
-        const float ny = fminf(fmaxf(py, 4.0f * k + 0.5f), 4.0f * k + 3.5f) - py;
-        ex[k] = nx * nx * inv_hv2;
-        ey[k] = ny * ny * inv_hv2;
-    }
-    uint64_t m = 0;
-#pragma unroll
-    for (int g = 0; g < 16; ++g)
-        if (ex[g & 3] + ey[g >> 2] < 1.0f + 1e-3f) m |= rb << (g * NB);
-    return m;
-}
-
 template <int TT, bool KAHAN, bool MASS>
-__global__ __launch_bounds__(kThreads, 2) void k_gather(GatherArgs a) {
-    constexpr int NB = TT / 16;   // 16-row blocks per tile
-    constexpr int CG = 4 * NB;    // blocks (accumulators) per wave
-    constexpr int kZero = kCap;   // table row of zeros, used to pad groups
-    constexpr int kTW = TT + 32;  // floats per survivor: Kt[TT], AX[16], BY[16]
-    constexpr int kLL = kCap + 4; // entries per block list
-    __shared__ __align__(16) float sTab[(kCap + 1) * kTW];
-    __shared__ uint64_t sM[kCap];
-    __shared__ uint8_t sL[kWaves][CG][kLL];
+__global__ __launch_bounds__(kThreads) void k_gather(GatherArgs a) {
+    constexpr int NB = TT / 16;  // 16-row blocks per tile
+    constexpr int CG = 4 * NB;   // accumulator blocks per wave
+    constexpr int kPad = kCap;   // index of the padding survivor
+    // survivor list: tile-local coordinates as (head, tail) pairs and the
+    // quadrants its footprint box meets; entry kPad is a point far outside
+    // the tile
+    __shared__ float2 sX[kCap + 1], sY[kCap + 1], sT[kCap + 1];
+    __shared__ uint8_t sQ[kCap];
+    // per-wave lists of survivor indices
+    __shared__ uint16_t sL[kWaves][kCap + 8];
     __shared__ int32_t sRB[kMaxRanges];
     __shared__ int32_t sRP[kMaxRanges + 1];
-    __shared__ int32_t sWC[2];
+    __shared__ int32_t sWC[kWaves];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -179,12 +161,15 @@ __global__ __launch_bounds__(kThreads, 2) void k_gather(GatherArgs a) {
         }
         if (lane == nranges - 1) sRP[nranges] = inc;
     }
-    if (tid < kTW) sTab[kZero * kTW + tid] = 0.0f;
+    if (tid == 0) {
+        sX[kPad] = make_float2(-1.0e6f, 0.f);
+        sY[kPad] = make_float2(-1.0e6f, 0.f);
+        sT[kPad] = make_float2(-1.0e6f, 0.f);
+    }
     __syncthreads();
     const int32_t total = sRP[nranges];
 
-    // ---- accumulators: block q * NB + b = (column group q of the quadrant,
-    // row block b) --------------------------------------------------------------
+    // ---- accumulators: [column group q][row block b] ------------------------
     f32x4 acc[CG];
     f32x4 comp[KAHAN ? CG : 1];
     f32x4 pass[KAHAN ? CG : 1];
@@ -196,23 +181,59 @@ __global__ __launch_bounds__(kThreads, 2) void k_gather(GatherArgs a) {
             pass[q] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
     }
+    // this wave's quadrant: column groups gx in {gqx, gqx + 1}, gy in {gqy, gqy + 1}
     const int gqx = 2 * (wave & 1), gqy = 2 * (wave >> 1);
     const int32_t QX0 = X0 + 4 * gqx, QY0 = Y0 + 4 * gqy;
     const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    // lane roles: point k of the group; row i of the block (Kt operand);
-    // column (lane & 3, (lane >> 2) & 3) of the column group (Ks operand)
-    const int kq = lane >> 4, ri = lane & 15;
-    const int jx = lane & 3, jy = (lane >> 2) & 3;
+    // lane roles in the matrix-core operands: point k of the group, row i of
+    // a block (Kt operand), column j = (lane & 3, (lane >> 2) & 3) of a column
+    // group (Ks operand)
+    const int kq = lane >> 4;
+    const float rowc = (float)(lane & 15) + 0.5f;
+    const float xc0 = (float)(4 * gqx + (lane & 3)) + 0.5f;
+    const float yc0 = (float)(4 * gqy + ((lane >> 2) & 3)) + 0.5f;
+    uint16_t* myL = sL[wave];
+
+    // one group: operands from the coordinates of this lane's point, then
+    // all CG instructions
+    auto group = [&](const float2 cx, const float2 cy, const float2 ctt) {
+        float av[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const float dt = ((rowc + 16.0f * b) - ctt.x) - ctt.y;
+            av[b] = fmaxf(0.0f, fmaf(-dt * dt, a.inv_tv2, 1.0f));
+        }
+        float ux[2], uy[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const float dx = ((xc0 + 4.0f * h) - cx.x) - cx.y;
+            const float dy = ((yc0 + 4.0f * h) - cy.x) - cy.y;
+            ux[h] = fmaf(-dx * dx, a.inv_hv2, 1.0f);
+            uy[h] = dy * dy * a.inv_hv2;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float ks = fmaxf(0.0f, ux[q & 1] - uy[q >> 1]);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                if constexpr (KAHAN)
+                    pass[q * NB + b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[b], ks, pass[q * NB + b], 0, 0, 0);
+                else
+                    acc[q * NB + b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[b], ks, acc[q * NB + b], 0, 0, 0);
+            }
+        }
+    };
 
     int32_t bb = 0;
     while (bb < total) {
-        // ---- stage ---------------------------------------------------------
+        // ---- stage: fill the survivor list ---------------------------------
         int32_t count = 0;
-        while (bb < total && count <= kCap - kRound) {
+        while (bb < total && count <= kCap - kThreads) {
             const int32_t c = bb + tid;
             bool surv = false;
             PointRec r{};
-            if (tid < kRound && c < total) {
+            uint32_t qm = 0;
+            if (c < total) {
                 int32_t lo = 0, hi = nranges - 1;  // last range with sRP <= c
                 while (lo < hi) {
                     const int32_t mid = (lo + hi + 1) >> 1;
@@ -220,126 +241,89 @@ __global__ __launch_bounds__(kThreads, 2) void k_gather(GatherArgs a) {
                     else hi = mid - 1;
                 }
                 r = a.recs[sRB[lo] + (c - sRP[lo])];
-                const int32_t xlo = (int32_t)(r.xb & 0xffffu), xhi = (int32_t)(r.xb >> 16);
-                const int32_t ylo = (int32_t)(r.yb & 0xffffu), yhi = (int32_t)(r.yb >> 16);
+                const int32_t xlo = (int32_t)(r.xb & 0xffffu) - X0, xhi = (int32_t)(r.xb >> 16) - X0;
+                const int32_t ylo = (int32_t)(r.yb & 0xffffu) - Y0, yhi = (int32_t)(r.yb >> 16) - Y0;
                 const int32_t tlo = (int32_t)(r.tb & 0xffffu), thi = (int32_t)(r.tb >> 16);
-                surv = xlo <= X0 + kTileXY - 1 && xhi >= X0 && ylo <= Y0 + kTileXY - 1 &&
-                       yhi >= Y0 && tlo <= T0 + TT - 1 && thi >= T0;
-            }
-            if (wave < 2) {
-                const unsigned long long m = __ballot(surv);
-                if (lane == 0) sWC[wave] = __popcll(m);
-                __syncthreads();
-                const int32_t add = sWC[0] + sWC[1];
-                if (surv) {
-                    const int s = count + (wave ? sWC[0] : 0) + __popcll(m & lt);
-                    // head - origin is exact for the offsets that reach the tile
-                    const float pxh = r.xh - (float)X0, pxl = half_lo(r.xl_yl);
-                    const float pyh = r.yh - (float)Y0, pyl = half_hi(r.xl_yl);
-                    const float pth = r.th - (float)T0, ptl = half_lo(r.tl);
-                    float* tb = sTab + s * kTW;
-#pragma unroll
-                    for (int rr = 0; rr < TT; rr += 4) {
-                        float v[4];
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            const float dt = ((float)(rr + e) + 0.5f - pth) - ptl;
-                            v[e] = fmaxf(0.0f, fmaf(-dt * dt, a.inv_tv2, 1.0f));
-                        }
-                        *reinterpret_cast<float4*>(tb + rr) = make_float4(v[0], v[1], v[2], v[3]);
-                    }
-#pragma unroll
-                    for (int k = 0; k < 16; k += 4) {
-                        float u[4], w[4];
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            const float dx = ((float)(k + e) + 0.5f - pxh) - pxl;
-                            const float dy = ((float)(k + e) + 0.5f - pyh) - pyl;
-                            u[e] = fmaf(-dx * dx, a.inv_hv2, 1.0f);
-                            w[e] = dy * dy * a.inv_hv2;
-                        }
-                        *reinterpret_cast<float4*>(tb + TT + k) = make_float4(u[0], u[1], u[2], u[3]);
-                        *reinterpret_cast<float4*>(tb + TT + 16 + k) = make_float4(w[0], w[1], w[2], w[3]);
-                    }
-                    sM[s] = touch_mask<NB>(pxh + pxl, pyh + pyl, (int32_t)(r.tb & 0xffffu) - T0,
-                                           (int32_t)(r.tb >> 16) - T0, a.inv_hv2);
+                if (tlo <= T0 + TT - 1 && thi >= T0) {
+                    // quadrants (qx, qy) whose 8 x 8 columns the footprint box meets
+                    const bool x0 = xlo <= 7 && xhi >= 0, x1 = xlo <= 15 && xhi >= 8;
+                    const bool y0 = ylo <= 7 && yhi >= 0, y1 = ylo <= 15 && yhi >= 8;
+                    qm = (uint32_t)(x0 && y0) | ((uint32_t)(x1 && y0) << 1) |
+                         ((uint32_t)(x0 && y1) << 2) | ((uint32_t)(x1 && y1) << 3);
                 }
-                count += add;
-            } else {
-                __syncthreads();
-                count += sWC[0] + sWC[1];
+                surv = qm != 0;
             }
-            bb += kRound;
+            const unsigned long long m = __ballot(surv);
+            if (lane == 0) sWC[wave] = __popcll(m);
+            __syncthreads();
+            int32_t off = count, add = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) {
+                const int32_t cw = sWC[w];
+                off += (w < wave) ? cw : 0;
+                add += cw;
+            }
+            if (surv) {
+                const int s = off + __popcll(m & lt);
+                // head - origin is exact for the offsets that reach the tile
+                sX[s] = make_float2(r.xh - (float)X0, half_lo(r.xl_yl));
+                sY[s] = make_float2(r.yh - (float)Y0, half_hi(r.xl_yl));
+                sT[s] = make_float2(r.th - (float)T0, half_lo(r.tl));
+                sQ[s] = (uint8_t)qm;
+            }
+            count += add;
+            bb += kThreads;
             __syncthreads();  // sWC is rewritten by the next round
         }
 
-        // ---- per-block lists of this wave -----------------------------------
-        int32_t nl[CG];
-#pragma unroll
-        for (int q = 0; q < CG; ++q) nl[q] = 0;
+        // ---- this wave's list: survivors meeting its quadrant ---------------
+        int32_t nw = 0;
         for (int32_t base = 0; base < count; base += 64) {
             const int32_t s = base + lane;
-            const uint64_t mk = s < count ? sM[s] : 0ull;
-#pragma unroll
-            for (int q = 0; q < CG; ++q) {
-                const int g = (gqy + ((q / NB) >> 1)) * 4 + gqx + ((q / NB) & 1);
-                const bool hit = (mk >> (g * NB + (q % NB))) & 1ull;
-                const unsigned long long bm = __ballot(hit);
-                if (hit) sL[wave][q][nl[q] + __popcll(bm & lt)] = (uint8_t)s;
-                nl[q] += __popcll(bm);
-            }
+            const bool mine = s < count && ((sQ[s] >> wave) & 1u);
+            const unsigned long long bm = __ballot(mine);
+            if (mine) myL[nw + __popcll(bm & lt)] = (uint16_t)s;
+            nw += __popcll(bm);
         }
-#pragma unroll
-        for (int q = 0; q < CG; ++q)
-            if (lane < ((4 - (nl[q] & 3)) & 3)) sL[wave][q][nl[q] + lane] = (uint8_t)kZero;
+        // pad to a whole number of pairs of groups
+        if (lane < ((8 - (nw & 7)) & 7)) myL[nw + lane] = (uint16_t)kPad;
+        const int32_t npairs = (nw + 7) >> 3;
 
-        // ---- matrix-core accumulation, block by block -----------------------
-#pragma unroll
-        for (int q = 0; q < CG; ++q) {
-            const int cq = q / NB, b = q % NB;
-            const int gx = gqx + (cq & 1), gy = gqy + (cq >> 1);
-            const int ngr = (nl[q] + 3) >> 2;
-            const uint8_t* L = sL[wave][q];
-            const int offA = 16 * b + ri, offX = TT + 4 * gx + jx, offY = TT + 16 + 4 * gy + jy;
-            float an = 0.f, xn = 0.f, yn = 0.f;
-            if (ngr > 0) {
-                const float* tb = sTab + (int)L[kq] * kTW;
-                an = tb[offA];
-                xn = tb[offX];
-                yn = tb[offY];
-            }
-            for (int g = 0; g < ngr; ++g) {
-                const float av = an, ks = fmaxf(0.0f, xn - yn);
-                if (g + 1 < ngr) {
-                    const float* tb = sTab + (int)L[4 * (g + 1) + kq] * kTW;
-                    an = tb[offA];
-                    xn = tb[offX];
-                    yn = tb[offY];
+        // ---- matrix-core accumulation, two groups per iteration -------------
+        if (npairs > 0) {
+            int s = myL[kq];
+            float2 ax = sX[s], ay = sY[s], at = sT[s];
+            for (int32_t pr = 0; pr < npairs; ++pr) {
+                s = myL[8 * pr + 4 + kq];
+                const float2 bx = sX[s], by = sY[s], bt = sT[s];
+                group(ax, ay, at);
+                if (pr + 1 < npairs) {
+                    s = myL[8 * pr + 8 + kq];
+                    ax = sX[s];
+                    ay = sY[s];
+                    at = sT[s];
                 }
-                if constexpr (KAHAN)
-                    pass[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, ks, pass[q], 0, 0, 0);
-                else
-                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, ks, acc[q], 0, 0, 0);
+                group(bx, by, bt);
             }
         }
         if constexpr (KAHAN) kahan_fold<CG>(acc, comp, pass);
-        __syncthreads();  // tables and lists are refilled next
+        __syncthreads();  // the lists are refilled next
     }
 
     // ---- store: lane holds rows 16 b + 4 (lane / 16) + e of column
-    // (lane % 4, (lane / 4) % 4) of each of its blocks ---------------------------
+    // (lane % 4, (lane / 4) % 4) of each of its column groups -------------------
     double msum = 0.0;
     const bool vec = (a.gt & 3) == 0;
 #pragma unroll
-    for (int cq = 0; cq < 4; ++cq) {
-        const int32_t X = QX0 + 4 * (cq & 1) + jx;
-        const int32_t Y = QY0 + 4 * (cq >> 1) + jy;
+    for (int q = 0; q < 4; ++q) {
+        const int32_t X = QX0 + 4 * (q & 1) + (lane & 3);
+        const int32_t Y = QY0 + 4 * (q >> 1) + ((lane >> 2) & 3);
         if (X >= a.gx || Y >= a.gy) continue;
         float* col = a.out + ((size_t)X * a.gy + Y) * a.gt;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const int32_t T = T0 + 16 * b + 4 * kq;
-            const f32x4 v = acc[cq * NB + b] * a.cnorm;
+            const int32_t T = T0 + 16 * b + 4 * (lane >> 4);
+            const f32x4 v = acc[q * NB + b] * a.cnorm;
             if (vec && T + 3 < a.gt) {
                 *reinterpret_cast<f32x4*>(col + T) = v;
                 if constexpr (MASS) msum += (double)v[0] + (double)v[1] + (double)v[2] + (double)v[3];
