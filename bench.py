@@ -16,8 +16,9 @@ Prints ONE JSON line:
   value            kernel evaluations per second = exact in-grid
                    (voxel, point) pairs inside both supports / step time
   roofline         the gather kernel (dominant): algorithmic bytes (grid
-                   written once + points read once) / its average duration,
-                   timed with HIP events on the stream it runs on
+                   written once + points read once) / its average duration
+                   over the timed steps, timed with HIP events that the
+                   library records around that launch on its stream
   cpu_baseline     the FP64 CPU oracle on a bounded sample of the same
                    workload, on this host's cores
 """
@@ -180,6 +181,7 @@ def main():
 
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
+    plan.profile(args.steps)  # HIP events around each step's gather kernel
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -190,11 +192,17 @@ def main():
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     step_ms = sorted(a.elapsed_time(b) for a, b in ev)
-    _log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step wall, median event {step_ms[len(step_ms) // 2]:.3f} ms")
+    kern_ms = plan.profile_read()
+    plan.profile(0)
+    if len(kern_ms) != args.steps:
+        raise SystemExit(f"expected {args.steps} gather timings, got {len(kern_ms)}")
+    gather_ms = sum(kern_ms) / len(kern_ms)
+    _log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step wall, median event "
+         f"{step_ms[len(step_ms) // 2]:.3f} ms, gather kernel {gather_ms:.3f} ms")
     st = stats.cpu().numpy()
 
-    # stage timing: binning and the gather kernel alone (accumulate without
-    # stats is exactly one launch of the gather kernel), on the same stream
+    # stage timing outside the timed region: binning, and the whole
+    # accumulation pass (work list, gather, split reduction, mass)
     reps = max(5, args.steps)
     bev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
     gev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
@@ -207,8 +215,8 @@ def main():
         gev[k][1].record(stream)
     torch.cuda.synchronize()
     bin_ms = sum(a.elapsed_time(b) for a, b in bev) / reps
-    gather_ms = sum(a.elapsed_time(b) for a, b in gev) / reps
-    _log(f"stage times: bin {bin_ms:.3f} ms, gather {gather_ms:.3f} ms")
+    pass_ms = sum(a.elapsed_time(b) for a, b in gev) / reps
+    _log(f"stage times: bin {bin_ms:.3f} ms, accumulation pass {pass_ms:.3f} ms")
 
     grid_bytes = inst.gx * inst.gy * inst.gt * 4
     alg_bytes = grid_bytes + n * 24
@@ -236,7 +244,7 @@ def main():
                    "tuning": [args.tile_t, args.cell_xy, args.cell_t] if tuning else "default"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
-        "stage_ms": {"bin": bin_ms, "gather": gather_ms},
+        "stage_ms": {"bin": bin_ms, "pass": pass_ms, "gather_kernel": gather_ms},
         "mass": {"grid": float(st[0]), "points": float(cs[1])},
     }
 

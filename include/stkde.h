@@ -102,6 +102,17 @@ stkde_status stkde_plan(const stkde_desc* desc, const stkde_tuning* tuning, stkd
 /* Release a plan.  NULL is accepted. */
 stkde_status stkde_plan_destroy(stkde_plan_t plan);
 
+/* Gather timing.  stkde_plan_profile(plan, k) makes the next k calls of
+ * stkde_compute / stkde_accumulate on the plan record a pair of HIP events
+ * on their stream right before and right after the gather kernel (the
+ * density accumulation and store, the dominant launch); k = 0 turns it off.
+ * stkde_plan_profile_read waits for the recorded pairs, writes up to `max`
+ * durations in milliseconds, in call order, to ms (host), sets *count, and
+ * starts a new recording of up to k calls.  While profiling, the plan is
+ * not safe to share between threads.  Errors: INVALID_ARG, HIP. */
+stkde_status stkde_plan_profile(stkde_plan_t plan, int32_t capacity);
+stkde_status stkde_plan_profile_read(stkde_plan_t plan, float* ms, int32_t max, int32_t* count);
+
 /* Bytes of device workspace stkde_compute needs for n points (n >= 1). */
 stkde_status stkde_workspace_bytes(stkde_plan_t plan, int64_t n, size_t* bytes);
 
@@ -141,7 +152,7 @@ stkde_status stkde_compute(stkde_plan_t plan, const double* d_xyt, int64_t n, fl
  *
  * stkde_bin: transform the points to voxel space, cull the ones whose
  * cylinder misses the grid, sort them stably into space-time bins and write
- * the per-point records and time-kernel tables into d_ws (the device form
+ * the per-point records into d_ws (the device form
  * of the point lists that the paper's decompositions build per subdomain,
  * Sec. 4.2 and Sec. 5.1).
  *
@@ -149,12 +160,104 @@ stkde_status stkde_compute(stkde_plan_t plan, const double* d_xyt, int64_t n, fl
  * (Sec. 3.2) from a workspace that stkde_bin filled for the same plan and
  * the same n; it must be ordered after that stkde_bin (same stream, or
  * synchronised).  Writes d_out completely, and d_stats[0] (with
- * STKDE_FLAG_MASS) and d_stats[3..7] when d_stats is given ([1], [2] = 0).
- * One kernel launch when d_stats is NULL. */
+ * STKDE_FLAG_MASS) and d_stats[3..7] when d_stats is given ([1], [2] = 0). */
 stkde_status stkde_bin(stkde_plan_t plan, const double* d_xyt, int64_t n, void* d_ws,
                        size_t ws_bytes, void* stream);
 stkde_status stkde_accumulate(stkde_plan_t plan, int64_t n, float* d_out, void* d_ws,
                               size_t ws_bytes, double* d_stats, void* stream);
+
+/* ---- binned point sets ---------------------------------------------------
+ *
+ * A binned set is the output of stkde_bin kept in caller memory of its own:
+ * the points transformed to the voxel space of a base grid, culled, sorted
+ * into space-time bins and stored as per-point records (the per-subdomain
+ * point lists of Sec. 4.2 and Sec. 5.1, built once on the device).  One set
+ * serves any number of later density computations (stkde_batch_*) on the
+ * base grid or on a voxel-aligned window of it, with any bandwidths up to
+ * the set's, e.g. a bandwidth sweep (the varying bandwidths of Sec. 2.1) or
+ * interactive exploration of sub-regions (the motivation of Sec. 1). */
+typedef struct stkde_set_s* stkde_set_t;
+
+/* Plan a set of n points on the base grid `base` (host only).  base->hs and
+ * base->ht are the largest bandwidths the set will be used with;
+ * base->flags must be 0.  tuning may be NULL; its cell_xy / cell_t choose
+ * the bin size (as for stkde_plan) and its tile_t is the largest tile_t of
+ * the plans the set will serve (default 32).
+ * Errors: INVALID_ARG, TOO_LARGE. */
+stkde_status stkde_set_plan(const stkde_desc* base, const stkde_tuning* tuning, int64_t n,
+                            stkde_set_t* out);
+
+/* Bytes of the set memory (persistent) and of the scratch stkde_set_build
+ * needs while it runs. */
+stkde_status stkde_set_bytes(stkde_set_t set, size_t* set_bytes, size_t* scratch_bytes);
+
+/* Bin d_xyt (device, n x 3 FP64 as in stkde_compute, the set's n) into
+ * d_set (device, >= set_bytes, 256-byte aligned, written completely), using
+ * d_scratch (device, >= scratch_bytes, 256-byte aligned) on `stream`.  The
+ * set stays valid until d_set is freed or rebuilt; d_xyt and d_scratch may
+ * be reused once the stream has passed this call.
+ * Errors: INVALID_ARG, WORKSPACE, HIP. */
+stkde_status stkde_set_build(stkde_set_t set, const double* d_xyt, void* d_set, size_t set_bytes,
+                             void* d_scratch, size_t scratch_bytes, void* stream);
+
+/* Release a set plan (not its device memory).  NULL is accepted. */
+stkde_status stkde_set_destroy(stkde_set_t set);
+
+/* ---- batches ---------------------------------------------------------------
+ *
+ * A batch computes many density grids with one work list and one persistent
+ * gather launch per (tile_t, Kahan) group, the tiles of all its grids
+ * scheduled together, costliest first.  Each item is one grid: */
+typedef struct {
+    stkde_plan_t plan;   /* the grid: gx, gy, gt, hs, ht, flags and tuning.tile_t of its
+                            desc; its sres and tres must equal the set's, its hs and ht
+                            must not exceed the set's, and its origin must be the corner of
+                            base voxel (ox, oy, ot): x0 = base x0 + ox * sres (likewise y,
+                            t), to 1e-6 of a voxel.  STKDE_FLAG_POINT_STATS is refused. */
+    stkde_set_t set;     /* the binned set the grid draws its points from */
+    const void* d_set;   /* device memory that stkde_set_build filled for `set` */
+    int64_t ox, oy, ot;  /* window origin in base voxels; the window must lie inside the
+                            base grid */
+    float* d_out;        /* device, gx*gy*gt FP32 [X][Y][T], fully overwritten */
+    double* d_stats;     /* device, 8 FP64 as in stkde_compute, or NULL; [1], [2] = 0 */
+} stkde_item;
+/* The estimate of an item divides by the set's n (every point of the set
+ * counts, in the window or not), so a window is a cut-out of the base grid's
+ * density.  Items may share sets; their outputs must not overlap. */
+
+typedef struct stkde_batch_s* stkde_batch_t;
+
+/* Validate and copy `count` items (1 <= count <= 4096; host only).
+ * Errors: INVALID_ARG (a null pointer, a mismatched resolution, a window
+ * outside the base grid, a bandwidth above the set's), TOO_LARGE,
+ * UNSUPPORTED (a plan whose tiles would read more bin rows of the set than
+ * the gather supports; plan the set with larger cells). */
+stkde_status stkde_batch_plan(const stkde_item* items, int32_t count, stkde_batch_t* out);
+
+/* Bytes of device workspace stkde_batch_run needs. */
+stkde_status stkde_batch_workspace_bytes(stkde_batch_t batch, size_t* bytes);
+
+/* Compute every item's grid on `stream` (d_ws: >= the workspace bytes,
+ * 256-byte aligned; scratch).  Each grid is the one stkde_compute would give
+ * for the set's points, within the tolerance of their rounding; it is
+ * bitwise the same as the item run alone when none of its tiles is split.
+ * Errors: WORKSPACE, HIP. */
+stkde_status stkde_batch_run(stkde_batch_t batch, void* d_ws, size_t ws_bytes, void* stream);
+
+/* Record stkde_batch_run(batch, d_ws, ws_bytes) into a HIP graph held by the
+ * batch (replacing an earlier one).  Nothing runs until stkde_batch_replay.
+ * The graph keeps the pointers it was recorded with: d_ws, the sets and
+ * the outputs must stay allocated while it is replayed.
+ * Errors: WORKSPACE, HIP. */
+stkde_status stkde_batch_capture(stkde_batch_t batch, void* d_ws, size_t ws_bytes);
+
+/* Launch the recorded graph on `stream`.  Errors: UNSUPPORTED (nothing
+ * recorded), HIP. */
+stkde_status stkde_batch_replay(stkde_batch_t batch, void* stream);
+
+/* Release a batch and its graph.  NULL is accepted.  The caller makes sure
+ * no replay is still running. */
+stkde_status stkde_batch_destroy(stkde_batch_t batch);
 
 /* Human-readable name of a status code (static storage). */
 const char* stkde_status_string(stkde_status s);

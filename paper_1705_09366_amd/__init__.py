@@ -34,7 +34,11 @@ FLAG_MASS = 4
 FLAG_POINT_STATS = 8
 
 EXPORTED = ("stkde_plan", "stkde_plan_destroy", "stkde_workspace_bytes", "stkde_compute",
-            "stkde_bin", "stkde_accumulate", "stkde_status_string", "stkde_version")
+            "stkde_bin", "stkde_accumulate", "stkde_status_string", "stkde_version",
+            "stkde_set_plan", "stkde_set_bytes", "stkde_set_build", "stkde_set_destroy",
+            "stkde_batch_plan", "stkde_batch_workspace_bytes", "stkde_batch_run",
+            "stkde_batch_capture", "stkde_batch_replay", "stkde_batch_destroy",
+            "stkde_plan_profile", "stkde_plan_profile_read")
 
 
 class StkdeError(RuntimeError):
@@ -53,6 +57,12 @@ class _Desc(ctypes.Structure):
 class _Tuning(ctypes.Structure):
     _fields_ = [("tile_t", ctypes.c_int32), ("cell_xy", ctypes.c_int32),
                 ("cell_t", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class _Item(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("set", ctypes.c_void_p), ("d_set", ctypes.c_void_p),
+                ("ox", ctypes.c_int64), ("oy", ctypes.c_int64), ("ot", ctypes.c_int64),
+                ("d_out", ctypes.c_void_p), ("d_stats", ctypes.c_void_p)]
 
 
 _LIB = None
@@ -78,9 +88,25 @@ def lib():
         L.stkde_accumulate.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                        ctypes.c_void_p]
-        for f in (L.stkde_plan, L.stkde_plan_destroy, L.stkde_workspace_bytes, L.stkde_compute,
-                  L.stkde_bin, L.stkde_accumulate):
-            f.restype = ctypes.c_int
+        L.stkde_set_plan.argtypes = [P(_Desc), P(_Tuning), ctypes.c_int64, P(ctypes.c_void_p)]
+        L.stkde_set_bytes.argtypes = [ctypes.c_void_p, P(ctypes.c_size_t), P(ctypes.c_size_t)]
+        L.stkde_set_build.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_size_t, ctypes.c_void_p, ctypes.c_size_t,
+                                      ctypes.c_void_p]
+        L.stkde_set_destroy.argtypes = [ctypes.c_void_p]
+        L.stkde_batch_plan.argtypes = [P(_Item), ctypes.c_int32, P(ctypes.c_void_p)]
+        L.stkde_batch_workspace_bytes.argtypes = [ctypes.c_void_p, P(ctypes.c_size_t)]
+        L.stkde_batch_run.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                      ctypes.c_void_p]
+        L.stkde_batch_capture.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]
+        L.stkde_batch_replay.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.stkde_batch_destroy.argtypes = [ctypes.c_void_p]
+        L.stkde_plan_profile.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+        L.stkde_plan_profile_read.argtypes = [ctypes.c_void_p, P(ctypes.c_float), ctypes.c_int32,
+                                              P(ctypes.c_int32)]
+        for name in EXPORTED:
+            if name not in ("stkde_status_string", "stkde_version"):
+                getattr(L, name).restype = ctypes.c_int
         L.stkde_status_string.argtypes = [ctypes.c_int]
         L.stkde_status_string.restype = ctypes.c_char_p
         L.stkde_version.restype = ctypes.c_int32
@@ -154,6 +180,24 @@ class Plan:
     @property
     def handle(self):
         return self._h
+
+    def profile(self, capacity: int):
+        """Record HIP events around the gather kernel of the next
+        ``capacity`` computations (0 turns it off)."""
+        st = lib().stkde_plan_profile(self._h, int(capacity))
+        if st != STKDE_OK:
+            raise StkdeError(st, "stkde_plan_profile")
+        self._prof_cap = int(capacity)
+
+    def profile_read(self):
+        """Gather kernel durations (ms) of the recorded computations, in order."""
+        cap = max(1, getattr(self, "_prof_cap", 0))
+        buf = (ctypes.c_float * cap)()
+        cnt = ctypes.c_int32(0)
+        st = lib().stkde_plan_profile_read(self._h, buf, cap, ctypes.byref(cnt))
+        if st != STKDE_OK:
+            raise StkdeError(st, "stkde_plan_profile_read")
+        return [float(buf[i]) for i in range(cnt.value)]
 
     def workspace_bytes(self, n: int) -> int:
         b = ctypes.c_size_t(0)
@@ -245,6 +289,161 @@ class Plan:
         d = self.desc
         out = torch.empty((d.gx, d.gy, d.gt), dtype=torch.float32, device=points.device)
         return self.compute_into(points, out, stats=stats)
+
+
+def _aligned(t):
+    """(pointer, bytes) of a uint8 tensor from its first 256-byte boundary."""
+    base = t.data_ptr()
+    off = (-base) % 256
+    return ctypes.c_void_p(base + off), ctypes.c_size_t(t.numel() - off)
+
+
+def _stream_arg(stream, device):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class BinnedSet:
+    """A point set binned once on the device for a base grid (``stkde_set_*``):
+    reusable by any number of :class:`Batch` items on the base grid or a
+    window of it, with bandwidths up to ``base.hs``, ``base.ht``."""
+
+    def __init__(self, base: Desc, n: int, tuning: Optional[Tuning] = None):
+        if base.flags:
+            raise ValueError("a set's base desc carries no flags")
+        self.base = base
+        self.n = int(n)
+        h = ctypes.c_void_p()
+        st = lib().stkde_set_plan(ctypes.byref(base._c()),
+                                  ctypes.byref(tuning._c()) if tuning is not None else None,
+                                  self.n, ctypes.byref(h))
+        if st != STKDE_OK:
+            raise StkdeError(st, "stkde_set_plan")
+        self._h = h
+        sb, cb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        st = lib().stkde_set_bytes(h, ctypes.byref(sb), ctypes.byref(cb))
+        if st != STKDE_OK:
+            raise StkdeError(st, "stkde_set_bytes")
+        self.set_bytes, self.scratch_bytes = int(sb.value), int(cb.value)
+        self.mem = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def build(self, points, scratch=None, stream=None):
+        """Bin the [n, 3] float64 CUDA points into device memory held by this
+        object (``self.mem``)."""
+        import torch
+        if points.dtype != torch.float64 or not points.is_cuda or points.dim() != 2 \
+                or points.shape[1] != 3 or not points.is_contiguous() or points.shape[0] != self.n:
+            raise ValueError("points must be a contiguous [n, 3] float64 CUDA tensor of the set's n")
+        if self.mem is None or self.mem.device != points.device:
+            self.mem = torch.empty(self.set_bytes + 256, dtype=torch.uint8, device=points.device)
+        if scratch is None:
+            scratch = torch.empty(self.scratch_bytes + 256, dtype=torch.uint8, device=points.device)
+        mp, mb = _aligned(self.mem)
+        sp, sb = _aligned(scratch)
+        st = lib().stkde_set_build(self._h, ctypes.c_void_p(points.data_ptr()), mp, mb, sp, sb,
+                                   _stream_arg(stream, points.device))
+        if st != STKDE_OK:
+            raise StkdeError(st, "stkde_set_build")
+        self._scratch = scratch  # kept until the stream has passed the build
+        return self
+
+    def device_ptr(self):
+        if self.mem is None:
+            raise RuntimeError("set not built")
+        return _aligned(self.mem)[0]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().stkde_set_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Item:
+    """One grid of a batch: ``plan`` gives the grid and bandwidths (its
+    origin must be base voxel (ox, oy, ot) of the set), ``out`` the float32
+    CUDA tensor it is written to, ``stats`` an optional float64 tensor of 8."""
+    plan: "Plan"
+    set: BinnedSet
+    out: object
+    ox: int = 0
+    oy: int = 0
+    ot: int = 0
+    stats: object = None
+
+
+class Batch:
+    """Many grids in one work list and one persistent gather launch per
+    (tile_t, Kahan) group (``stkde_batch_*``); optionally recorded once as a
+    HIP graph and replayed."""
+
+    def __init__(self, items):
+        import torch
+        self.items = list(items)
+        arr = (_Item * len(self.items))()
+        for k, it in enumerate(self.items):
+            d = it.plan.desc
+            if it.out.dtype != torch.float32 or not it.out.is_cuda or not it.out.is_contiguous() \
+                    or it.out.numel() != d.gx * d.gy * d.gt:
+                raise ValueError("out must be a contiguous float32 CUDA tensor of gx*gy*gt elements")
+            if it.stats is not None and (it.stats.dtype != torch.float64 or it.stats.numel() < 8
+                                         or not it.stats.is_cuda):
+                raise ValueError("stats must be a float64 CUDA tensor of 8 elements")
+            arr[k] = _Item(it.plan.handle.value, it.set.handle.value, it.set.device_ptr().value,
+                           it.ox, it.oy, it.ot, it.out.data_ptr(),
+                           it.stats.data_ptr() if it.stats is not None else None)
+        h = ctypes.c_void_p()
+        st = lib().stkde_batch_plan(arr, len(self.items), ctypes.byref(h))
+        if st != STKDE_OK:
+            raise StkdeError(st, "stkde_batch_plan")
+        self._h = h
+        b = ctypes.c_size_t(0)
+        st = lib().stkde_batch_workspace_bytes(h, ctypes.byref(b))
+        if st != STKDE_OK:
+            raise StkdeError(st, "stkde_batch_workspace_bytes")
+        self.workspace_bytes = int(b.value)
+        dev = self.items[0].out.device
+        self.ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=dev)
+
+    def run(self, stream=None):
+        p, nb = _aligned(self.ws)
+        st = lib().stkde_batch_run(self._h, p, nb, _stream_arg(stream, self.ws.device))
+        if st != STKDE_OK:
+            raise StkdeError(st, "stkde_batch_run")
+
+    def capture(self):
+        p, nb = _aligned(self.ws)
+        st = lib().stkde_batch_capture(self._h, p, nb)
+        if st != STKDE_OK:
+            raise StkdeError(st, "stkde_batch_capture")
+
+    def replay(self, stream=None):
+        st = lib().stkde_batch_replay(self._h, _stream_arg(stream, self.ws.device))
+        if st != STKDE_OK:
+            raise StkdeError(st, "stkde_batch_replay")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().stkde_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def compute(points, desc: Desc, tuning: Optional[Tuning] = None, stats=None):

@@ -1,29 +1,295 @@
 // api.hip -- host side of the C ABI declared in include/stkde.h: argument
-// validation, plan geometry, workspace layout and the launch sequence
-//   bin (transform, radix sort, bin offsets, records) -> gather/store
-//   -> optional statistics.
+// validation, plan and set geometry, workspace layouts and the launch
+// sequences
+//   compute = bin (transform, radix sort, bin offsets, records) into the
+//             workspace's set region -> one pass (work list, gather, split
+//             reduction, mass) -> optional point statistics;
+//   batch   = one pass per (tile_t, Kahan) group over the items' sets.
 #include <math.h>
 #include <stdlib.h>
+#include <string.h>
 
+#include <algorithm>
 #include <new>
+#include <vector>
 
 #include "../../include/stkde.h"
 #include "stkde_internal.h"
 
 struct stkde_plan_s {
     stkde_desc desc;
-    stkde::Geometry g;
+    stkde::InstGeom ig;  // the plan's grid as an instance of its own set
+    stkde::SetGeom sg;   // binning of the plan's own points
+    // gather timing (stkde_plan_profile): event pairs, filled in order
+    std::vector<hipEvent_t> ev;
+    int32_t ev_used = 0;
+};
+
+namespace {
+void release_events(stkde_plan_s* p) {
+    for (hipEvent_t e : p->ev)
+        if (e) (void)hipEventDestroy(e);
+    p->ev.clear();
+    p->ev_used = 0;
+}
+}  // namespace
+
+struct stkde_set_s {
+    stkde_desc base;
+    stkde::SetGeom sg;
+    int64_t n;
+    stkde::SetLayout sl;
+    stkde::SortLayout so;
+};
+
+struct stkde_batch_s {
+    struct Group {
+        int tile_t;
+        bool kahan;
+        std::vector<int32_t> idx;
+        std::vector<stkde::InstGeom> geo;
+        stkde::PassLayout pl;
+    };
+    std::vector<stkde_item> items;
+    std::vector<Group> groups;
+    size_t ws_bytes = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 namespace {
 
 constexpr int64_t kMaxDim = 65535;
 constexpr int32_t kMaxCells = 1 << 22;  // keys of at most 23 bits: <= 3 radix passes
+constexpr int32_t kMaxBatch = 4096;
 constexpr uint32_t kKnownFlags = STKDE_FLAG_KAHAN | STKDE_FLAG_MASS | STKDE_FLAG_POINT_STATS;
 
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
 int32_t ceil_div(int64_t a, int64_t b) { return (int32_t)((a + b - 1) / b); }
+
+size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+stkde_status check_desc(const stkde_desc* d) {
+    if (d->gx < 1 || d->gy < 1 || d->gt < 1) return STKDE_ERR_INVALID_ARG;
+    if (d->gx > kMaxDim || d->gy > kMaxDim || d->gt > kMaxDim) return STKDE_ERR_TOO_LARGE;
+    if (!finite_pos(d->sres) || !finite_pos(d->tres) || !finite_pos(d->hs) || !finite_pos(d->ht))
+        return STKDE_ERR_INVALID_ARG;
+    if (!isfinite(d->x0) || !isfinite(d->y0) || !isfinite(d->t0)) return STKDE_ERR_INVALID_ARG;
+    if (d->flags & ~kKnownFlags) return STKDE_ERR_INVALID_ARG;
+    const uint64_t nvox = (uint64_t)d->gx * (uint64_t)d->gy * (uint64_t)d->gt;
+    if (nvox > ((uint64_t)1 << 40)) return STKDE_ERR_TOO_LARGE;  // 4 TiB of FP32
+    if (!(d->hs / d->sres < 1e9) || !(d->ht / d->tres < 1e9)) return STKDE_ERR_TOO_LARGE;
+    return STKDE_OK;
+}
+
+stkde_status check_tuning(const stkde_tuning* t) {
+    if (!t) return STKDE_OK;
+    if (t->tile_t != 0 && t->tile_t != 16 && t->tile_t != 32 && t->tile_t != 64)
+        return STKDE_ERR_INVALID_ARG;
+    if (t->cell_xy != 0 && (t->cell_xy < 4 || t->cell_xy > 256)) return STKDE_ERR_INVALID_ARG;
+    if (t->cell_t != 0 && (t->cell_t < 4 || t->cell_t > 256)) return STKDE_ERR_INVALID_ARG;
+    if (t->reserved != 0) return STKDE_ERR_INVALID_ARG;
+    return STKDE_OK;
+}
+
+// Hs = ceil(hv), Ht = ceil(tv) (Sec. 2.1).  A bound beyond the base grid's
+// extent changes nothing: points farther out are binned into the edge bins.
+int32_t cap_hs(double hv, const stkde_desc& base) {
+    return (int32_t)fmin(ceil(hv), (double)(base.gx > base.gy ? base.gx : base.gy) + 2.0);
+}
+int32_t cap_ht(double tv, const stkde_desc& base) { return (int32_t)fmin(ceil(tv), (double)base.gt + 2.0); }
+
+// most bins an interval of L voxels can touch when bins are c wide
+int64_t span(int64_t L, int64_t c) { return (L - 1) / c + 2; }
+
+// bin rows (t, y) one tile of `rows` time rows reads with loop bounds Hs, Ht
+int64_t ranges_needed(const stkde::SetGeom& g, int32_t Hs, int32_t Ht, int32_t rows) {
+    const int64_t ny = span(stkde::kTileXY + 2 * (int64_t)Hs + 2, g.cxy);
+    const int64_t nt = span(rows + 2 * (int64_t)Ht + 2, g.ct);
+    return (ny < g.ncy ? ny : g.ncy) * (nt < g.nct ? nt : g.nct);
+}
+
+// Bins about as wide as the bandwidth (the paper's bandwidth-sized blocks of
+// points, Sec. 4.2 and Sec. 5.1): a tile then reads a few bin rows, and few of
+// the candidates it reads miss it.
+void make_set_geom(const stkde_desc& d, int32_t cell_xy, int32_t cell_t, int32_t rows,
+                   stkde::SetGeom* out) {
+    stkde::SetGeom g{};
+    g.gx = (int32_t)d.gx;
+    g.gy = (int32_t)d.gy;
+    g.gt = (int32_t)d.gt;
+    g.x0 = d.x0;
+    g.y0 = d.y0;
+    g.t0 = d.t0;
+    g.sres = d.sres;
+    g.tres = d.tres;
+    g.hv = d.hs / d.sres;
+    g.tv = d.ht / d.tres;
+    const int32_t Hs = cap_hs(g.hv, d), Ht = cap_ht(g.tv, d);
+    g.cxy = cell_xy ? cell_xy : (int32_t)fmin(256.0, fmax(16.0, 8.0 * ceil(Hs / 8.0)));
+    g.ct = cell_t ? cell_t : (int32_t)fmin(256.0, fmax(8.0, 4.0 * ceil(Ht / 4.0)));
+    for (;;) {
+        g.ncx = ceil_div(d.gx, g.cxy);
+        g.ncy = ceil_div(d.gy, g.cxy);
+        g.nct = ceil_div(d.gt, g.ct);
+        const int64_t nc = (int64_t)g.ncx * g.ncy * g.nct;
+        const int64_t ny = span(stkde::kTileXY + 2 * (int64_t)Hs + 2, g.cxy);
+        const int64_t nt = span(rows + 2 * (int64_t)Ht + 2, g.ct);
+        const int64_t ry = ny < g.ncy ? ny : g.ncy, rt = nt < g.nct ? nt : g.nct;
+        if (nc <= kMaxCells && ry * rt <= stkde::kMaxRanges) {
+            g.ncell = (int32_t)nc;
+            break;
+        }
+        // grow the dimension that contributes more bin rows
+        if ((ry >= rt && g.cxy < 65536) || g.ct >= 65536) g.cxy *= 2;
+        else g.ct *= 2;
+    }
+    // Keys of at most 16 bits sort in two radix passes instead of three:
+    // widen the bins in t (up to twice) when that alone gets there and the
+    // range limit still holds.
+    if (!cell_t && g.ncell >= 65536 && g.ncell < (1 << 20)) {
+        for (int32_t c = g.ct + 1; c <= 2 * g.ct; ++c) {
+            const int64_t nct = (d.gt + c - 1) / c;
+            const int64_t nc = (int64_t)g.ncx * g.ncy * nct;
+            const int64_t nt = span(rows + 2 * (int64_t)Ht + 2, c);
+            const int64_t ry = span(stkde::kTileXY + 2 * (int64_t)Hs + 2, g.cxy);
+            const int64_t rr = (ry < g.ncy ? ry : g.ncy) * (nt < nct ? nt : nct);
+            if (nc < 65536 && rr <= stkde::kMaxRanges) {
+                g.ct = c;
+                g.nct = (int32_t)nct;
+                g.ncell = (int32_t)nc;
+                break;
+            }
+        }
+    }
+    *out = g;
+}
+
+// The grid of `d` as an instance whose set has base grid `base`.
+stkde_status make_inst_geom(const stkde_desc& d, const stkde_desc& base, int32_t tile_t,
+                            stkde::InstGeom* out) {
+    stkde::InstGeom g{};
+    g.gx = (int32_t)d.gx;
+    g.gy = (int32_t)d.gy;
+    g.gt = (int32_t)d.gt;
+    g.x0 = d.x0;
+    g.y0 = d.y0;
+    g.t0 = d.t0;
+    g.sres = d.sres;
+    g.tres = d.tres;
+    g.hs = d.hs;
+    g.ht = d.ht;
+    g.hv = d.hs / d.sres;
+    g.tv = d.ht / d.tres;
+    g.Hs = cap_hs(g.hv, base);
+    g.Ht = cap_ht(g.tv, base);
+    g.Hs_d = ceil(g.hv);
+    g.Ht_d = ceil(g.tv);
+    g.inv_hv2 = (float)(1.0 / (g.hv * g.hv));
+    g.inv_tv2 = (float)(1.0 / (g.tv * g.tv));
+    g.tile_t = tile_t;
+    g.ntx = ceil_div(d.gx, stkde::kTileXY);
+    g.nty = ceil_div(d.gy, stkde::kTileXY);
+    g.ntt = ceil_div(d.gt, tile_t);
+    const int64_t nt = (int64_t)g.ntx * g.nty * g.ntt;
+    if (nt > 0x7fffffffLL) return STKDE_ERR_TOO_LARGE;
+    g.ntiles = (int32_t)nt;
+    *out = g;
+    return STKDE_OK;
+}
+
+// Default rows per tile: 16-row tiles waste fewer matrix-core rows on short
+// time windows; longer windows amortise the per-point setup over 32 rows.
+int32_t default_tile_t(double tv) { return ceil(tv) <= 12.0 ? 16 : 32; }
+
+// (2/pi) (3/4) / (n hs^2 ht): the constants of both kernels and the
+// estimator's normalisation, rounded once to FP32 at the store.
+float norm_const(double hs, double ht, int64_t n) {
+    return (float)((2.0 / 3.14159265358979323846) * 0.75 / ((double)n * hs * hs * ht));
+}
+
+stkde::InstDev make_dev(const stkde::InstGeom& ig, const stkde::SetGeom& sg, const uint8_t* set_mem,
+                        const stkde::SetLayout& sl, int64_t n_norm, int32_t ox, int32_t oy,
+                        int32_t ot, float* out, double* stats, bool mass) {
+    stkde::InstDev d{};
+    d.cell_start = reinterpret_cast<const uint32_t*>(set_mem + sl.cell_start);
+    d.recs = reinterpret_cast<const stkde::PointRec*>(set_mem + sl.recs);
+    d.counters = reinterpret_cast<const unsigned long long*>(set_mem + sl.counters);
+    d.out = out;
+    d.stats = stats;
+    d.tile_part = nullptr;
+    d.mass_scale = ig.sres * ig.sres * ig.tres;
+    d.gx = ig.gx;
+    d.gy = ig.gy;
+    d.gt = ig.gt;
+    d.ox = ox;
+    d.oy = oy;
+    d.ot = ot;
+    d.Hs = ig.Hs;
+    d.Ht = ig.Ht;
+    d.cxy = sg.cxy;
+    d.ct = sg.ct;
+    d.ncx = sg.ncx;
+    d.ncy = sg.ncy;
+    d.nct = sg.nct;
+    d.ntx = ig.ntx;
+    d.nty = ig.nty;
+    d.ntiles = ig.ntiles;
+    d.tile_base = 0;
+    d.flags = (mass && stats) ? stkde::kInstMass : 0u;
+    d.inv_hv2 = ig.inv_hv2;
+    d.inv_tv2 = ig.inv_tv2;
+    d.cnorm = norm_const(ig.hs, ig.ht, n_norm);
+    return d;
+}
+
+// Workspace of stkde_compute: the set region, then one region shared by the
+// binning sort, the pass and the point statistics (they run one after the
+// other on the stream).
+struct ComputeLayout {
+    stkde::SetLayout sl;
+    stkde::SortLayout so;
+    stkde::PassLayout pl;
+    size_t shared;  // offset of the shared region
+    size_t pstats;  // bytes of the point-statistics partials
+    int32_t nblk_pts;
+    size_t total;
+};
+
+ComputeLayout layout_compute(const stkde_plan_s* p, int64_t n) {
+    ComputeLayout c{};
+    c.sl = stkde::layout_set(p->sg, n);
+    c.so = stkde::layout_sort(n);
+    c.pl = stkde::layout_pass(&p->ig, 1, p->ig.tile_t);
+    c.nblk_pts = (int32_t)((n + stkde::kStatBlock - 1) / stkde::kStatBlock);
+    c.pstats = al256((size_t)c.nblk_pts * 4 * 8);
+    c.shared = al256(c.sl.total);
+    size_t u = c.so.total;
+    if (c.pl.total > u) u = c.pl.total;
+    if (c.pstats > u) u = c.pstats;
+    c.total = c.shared + u;
+    return c;
+}
+
+struct Call {
+    ComputeLayout L;
+    hipStream_t s;
+    uint8_t* ws;
+};
+
+stkde_status check_common(stkde_plan_t p, int64_t n, void* d_ws, size_t ws_bytes, void* stream,
+                          Call* c) {
+    if (!p || n < 1) return STKDE_ERR_INVALID_ARG;
+    if (n > 0x7fffffffLL) return STKDE_ERR_TOO_LARGE;
+    c->L = layout_compute(p, n);
+    if (!d_ws || ws_bytes < c->L.total || ((uintptr_t)d_ws & 255u)) return STKDE_ERR_WORKSPACE;
+    c->s = reinterpret_cast<hipStream_t>(stream);
+    c->ws = reinterpret_cast<uint8_t*>(d_ws);
+    return STKDE_OK;
+}
+
+bool same_res(double a, double b) { return fabs(a - b) <= 1e-12 * fabs(b); }
 
 }  // namespace
 
@@ -41,158 +307,69 @@ const char* stkde_status_string(stkde_status s) {
     return "unknown status";
 }
 
-int32_t stkde_version(void) { return 100; }
+int32_t stkde_version(void) { return 200; }
 
 stkde_status stkde_plan(const stkde_desc* d, const stkde_tuning* tun, stkde_plan_t* out) {
     if (!d || !out) return STKDE_ERR_INVALID_ARG;
-    if (d->gx < 1 || d->gy < 1 || d->gt < 1) return STKDE_ERR_INVALID_ARG;
-    if (d->gx > kMaxDim || d->gy > kMaxDim || d->gt > kMaxDim) return STKDE_ERR_TOO_LARGE;
-    if (!finite_pos(d->sres) || !finite_pos(d->tres) || !finite_pos(d->hs) || !finite_pos(d->ht))
-        return STKDE_ERR_INVALID_ARG;
-    if (!isfinite(d->x0) || !isfinite(d->y0) || !isfinite(d->t0)) return STKDE_ERR_INVALID_ARG;
-    if (d->flags & ~kKnownFlags) return STKDE_ERR_INVALID_ARG;
-    const uint64_t nvox = (uint64_t)d->gx * (uint64_t)d->gy * (uint64_t)d->gt;
-    if (nvox > ((uint64_t)1 << 40)) return STKDE_ERR_TOO_LARGE;  // 4 TiB of FP32
-
-    int32_t tile_t = 0, cell_xy = 0, cell_t = 0;
-    if (tun) {
-        if (tun->tile_t != 0 && tun->tile_t != 16 && tun->tile_t != 32 && tun->tile_t != 64)
-            return STKDE_ERR_INVALID_ARG;
-        if (tun->cell_xy != 0 && (tun->cell_xy < 4 || tun->cell_xy > 256))
-            return STKDE_ERR_INVALID_ARG;
-        if (tun->cell_t != 0 && (tun->cell_t < 4 || tun->cell_t > 256))
-            return STKDE_ERR_INVALID_ARG;
-        tile_t = tun->tile_t;
-        cell_xy = tun->cell_xy;
-        cell_t = tun->cell_t;
-    }
-
-    stkde::Geometry g{};
-    g.gx = (int32_t)d->gx;
-    g.gy = (int32_t)d->gy;
-    g.gt = (int32_t)d->gt;
-    g.x0 = d->x0;
-    g.y0 = d->y0;
-    g.t0 = d->t0;
-    g.sres = d->sres;
-    g.tres = d->tres;
-    g.inv_sres = 1.0 / d->sres;
-    g.inv_tres = 1.0 / d->tres;
-    g.hs = d->hs;
-    g.ht = d->ht;
-    g.hv = d->hs / d->sres;
-    g.tv = d->ht / d->tres;
-    // Hs = ceil(hs/sres), Ht = ceil(ht/tres) (Sec. 2.1).  Beyond the grid
-    // extent a larger bound changes nothing, so cap it there.
-    const double hcap = (double)(d->gx > d->gy ? d->gx : d->gy) + 2.0;
-    g.Hs = (int32_t)fmin(ceil(g.hv), hcap);
-    g.Ht = (int32_t)fmin(ceil(g.tv), (double)d->gt + 2.0);
-    if (!(g.hv < 1e9) || !(g.tv < 1e9)) return STKDE_ERR_TOO_LARGE;
-    g.Hs_d = ceil(g.hv);
-    g.Ht_d = ceil(g.tv);
-    g.inv_hv2 = (float)(1.0 / (g.hv * g.hv));
-    g.inv_tv2 = (float)(1.0 / (g.tv * g.tv));
-
-    g.tile_t = tile_t ? tile_t : 32;
+    stkde_status st = check_desc(d);
+    if (st != STKDE_OK) return st;
+    st = check_tuning(tun);
+    if (st != STKDE_OK) return st;
+    int32_t tile_t = tun && tun->tile_t ? tun->tile_t : default_tile_t(d->ht / d->tres);
     // compensated accumulation holds three accumulator sets; with 64-row
     // tiles that would leave one wave per SIMD
-    if ((d->flags & STKDE_FLAG_KAHAN) && g.tile_t > 32) g.tile_t = 32;
-    // Bins about as wide as the bandwidth (the paper's bandwidth-sized
-    // blocks of points, Sec. 4.2 and Sec. 5.1): a tile then reads a few bin
-    // rows, and few of the candidates it reads miss it.
-    g.cxy = cell_xy ? cell_xy : (int32_t)fmin(256.0, fmax(16.0, 8.0 * ceil(g.Hs / 8.0)));
-    g.ct = cell_t ? cell_t : (int32_t)fmin(256.0, fmax(8.0, 4.0 * ceil(g.Ht / 4.0)));
-    // most bins an interval of L voxels can touch when bins are c wide
-    auto span = [](int64_t L, int64_t c) { return (L - 1) / c + 2; };
-    for (;;) {
-        g.ncx = ceil_div(d->gx, g.cxy);
-        g.ncy = ceil_div(d->gy, g.cxy);
-        g.nct = ceil_div(d->gt, g.ct);
-        const int64_t nc = (int64_t)g.ncx * g.ncy * g.nct;
-        const int64_t ny = span(stkde::kTileXY + 2 * (int64_t)g.Hs + 2, g.cxy);
-        const int64_t nt = span(g.tile_t + 2 * (int64_t)g.Ht + 2, g.ct);
-        const int64_t ry = ny < g.ncy ? ny : g.ncy, rt = nt < g.nct ? nt : g.nct;
-        if (nc <= kMaxCells && ry * rt <= stkde::kMaxRanges) {
-            g.ncell = (int32_t)nc;
-            g.max_ranges = (int32_t)(ry * rt);
-            break;
-        }
-        // grow the dimension that contributes more bin rows
-        if ((ry >= rt && g.cxy < 65536) || g.ct >= 65536) g.cxy *= 2;
-        else g.ct *= 2;
-    }
-    // Keys of at most 16 bits sort in two radix passes instead of three:
-    // widen the bins in t (up to twice) when that alone gets there and the
-    // range limit still holds.
-    if (!cell_t && g.ncell >= 65536 && g.ncell < (1 << 20)) {
-        for (int32_t c = g.ct + 1; c <= 2 * g.ct; ++c) {
-            const int64_t nct = (d->gt + c - 1) / c;
-            const int64_t nc = (int64_t)g.ncx * g.ncy * nct;
-            const int64_t nt = span(g.tile_t + 2 * (int64_t)g.Ht + 2, c);
-            const int64_t ry = span(stkde::kTileXY + 2 * (int64_t)g.Hs + 2, g.cxy);
-            const int64_t rr = (ry < g.ncy ? ry : g.ncy) * (nt < nct ? nt : nct);
-            if (nc < 65536 && rr <= stkde::kMaxRanges) {
-                g.ct = c;
-                g.nct = (int32_t)nct;
-                g.ncell = (int32_t)nc;
-                g.max_ranges = (int32_t)rr;
-                break;
-            }
-        }
-    }
-    g.ntx = ceil_div(d->gx, stkde::kTileXY);
-    g.nty = ceil_div(d->gy, stkde::kTileXY);
-    g.ntt = ceil_div(d->gt, g.tile_t);
-    const int64_t nt = (int64_t)g.ntx * g.nty * g.ntt;
-    if (nt > 0x7fffffffLL) return STKDE_ERR_TOO_LARGE;
-    g.ntiles = (int32_t)nt;
-
-    stkde_plan_s* p = new (std::nothrow) stkde_plan_s;
+    if ((d->flags & STKDE_FLAG_KAHAN) && tile_t > 32) tile_t = 32;
+    stkde_plan_s tmp;
+    tmp.desc = *d;
+    make_set_geom(*d, tun ? tun->cell_xy : 0, tun ? tun->cell_t : 0, tile_t, &tmp.sg);
+    st = make_inst_geom(*d, *d, tile_t, &tmp.ig);
+    if (st != STKDE_OK) return st;
+    stkde_plan_s* p = new (std::nothrow) stkde_plan_s(tmp);
     if (!p) return STKDE_ERR_TOO_LARGE;
-    p->desc = *d;
-    p->g = g;
     *out = p;
     return STKDE_OK;
 }
 
 stkde_status stkde_plan_destroy(stkde_plan_t p) {
+    if (p) release_events(p);
     delete p;
+    return STKDE_OK;
+}
+
+stkde_status stkde_plan_profile(stkde_plan_t p, int32_t capacity) {
+    if (!p || capacity < 0 || capacity > (1 << 20)) return STKDE_ERR_INVALID_ARG;
+    release_events(p);
+    for (int32_t k = 0; k < 2 * capacity; ++k) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) {
+            release_events(p);
+            return STKDE_ERR_HIP;
+        }
+        p->ev.push_back(e);
+    }
+    return STKDE_OK;
+}
+
+stkde_status stkde_plan_profile_read(stkde_plan_t p, float* ms, int32_t max, int32_t* count) {
+    if (!p || !count || (max > 0 && !ms) || max < 0) return STKDE_ERR_INVALID_ARG;
+    const int32_t have = p->ev_used / 2;
+    const int32_t k = have < max ? have : max;
+    for (int32_t i = 0; i < k; ++i) {
+        if (hipEventSynchronize(p->ev[(size_t)(2 * i + 1)]) != hipSuccess) return STKDE_ERR_HIP;
+        if (hipEventElapsedTime(&ms[i], p->ev[(size_t)(2 * i)], p->ev[(size_t)(2 * i + 1)]) != hipSuccess)
+            return STKDE_ERR_HIP;
+    }
+    *count = k;
+    p->ev_used = 0;
     return STKDE_OK;
 }
 
 stkde_status stkde_workspace_bytes(stkde_plan_t p, int64_t n, size_t* bytes) {
     if (!p || !bytes || n < 1) return STKDE_ERR_INVALID_ARG;
     if (n > 0x7fffffffLL) return STKDE_ERR_TOO_LARGE;
-    *bytes = stkde::layout_workspace(p->g, n).total;
+    *bytes = layout_compute(p, n).total;
     return STKDE_OK;
 }
-
-namespace {
-
-struct Call {
-    stkde::Workspace w;
-    hipStream_t s;
-    uint8_t* ws;
-};
-
-stkde_status check_common(stkde_plan_t p, int64_t n, void* d_ws, size_t ws_bytes, void* stream,
-                          Call* c) {
-    if (!p || n < 1) return STKDE_ERR_INVALID_ARG;
-    if (n > 0x7fffffffLL) return STKDE_ERR_TOO_LARGE;
-    c->w = stkde::layout_workspace(p->g, n);
-    if (!d_ws || ws_bytes < c->w.total || ((uintptr_t)d_ws & 255u)) return STKDE_ERR_WORKSPACE;
-    c->s = reinterpret_cast<hipStream_t>(stream);
-    c->ws = reinterpret_cast<uint8_t*>(d_ws);
-    return STKDE_OK;
-}
-
-// (2/pi) (3/4) / (n hs^2 ht): the constants of both kernels and the
-// estimator's normalisation, rounded once to FP32 at the store.
-float norm_const(const stkde::Geometry& g, int64_t n) {
-    return (float)((2.0 / 3.14159265358979323846) * 0.75 / ((double)n * g.hs * g.hs * g.ht));
-}
-
-}  // namespace
 
 stkde_status stkde_bin(stkde_plan_t p, const double* d_xyt, int64_t n, void* d_ws, size_t ws_bytes,
                        void* stream) {
@@ -200,7 +377,9 @@ stkde_status stkde_bin(stkde_plan_t p, const double* d_xyt, int64_t n, void* d_w
     Call c;
     const stkde_status st = check_common(p, n, d_ws, ws_bytes, stream, &c);
     if (st != STKDE_OK) return st;
-    if (stkde::launch_bin(p->g, d_xyt, (int32_t)n, c.ws, c.w, c.s) != hipSuccess) return STKDE_ERR_HIP;
+    if (stkde::launch_bin(p->sg, d_xyt, (int32_t)n, c.ws, c.L.sl, c.ws + c.L.shared, c.L.so, c.s) !=
+        hipSuccess)
+        return STKDE_ERR_HIP;
     return STKDE_OK;
 }
 
@@ -210,18 +389,18 @@ stkde_status stkde_accumulate(stkde_plan_t p, int64_t n, float* d_out, void* d_w
     Call c;
     const stkde_status st = check_common(p, n, d_ws, ws_bytes, stream, &c);
     if (st != STKDE_OK) return st;
-    const stkde::Geometry& g = p->g;
     const uint32_t fl = p->desc.flags;
-    const bool mass = (fl & STKDE_FLAG_MASS) && d_stats;
-    if (stkde::launch_gather(g, norm_const(g, n), (fl & STKDE_FLAG_KAHAN) != 0, mass, d_out, c.ws, c.w,
-                             c.s) != hipSuccess)
-        return STKDE_ERR_HIP;
-    if (d_stats) {
-        if (stkde::launch_stats(g, nullptr, (int32_t)n, false, d_stats, c.ws, c.w, c.s) != hipSuccess)
-            return STKDE_ERR_HIP;
-        if (mass && stkde::launch_mass_reduce(g, d_stats, c.ws, c.w, c.s) != hipSuccess)
-            return STKDE_ERR_HIP;
+    stkde::InstDev d = make_dev(p->ig, p->sg, c.ws, c.L.sl, n, 0, 0, 0, d_out, d_stats,
+                                (fl & STKDE_FLAG_MASS) != 0);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (p->ev_used + 2 <= (int32_t)p->ev.size()) {
+        e0 = p->ev[(size_t)p->ev_used];
+        e1 = p->ev[(size_t)p->ev_used + 1];
+        p->ev_used += 2;
     }
+    if (stkde::launch_pass(&d, 1, c.ws + c.L.shared, c.L.pl, p->ig.tile_t, (fl & STKDE_FLAG_KAHAN) != 0,
+                           c.s, e0, e1) != hipSuccess)
+        return STKDE_ERR_HIP;
     return STKDE_OK;
 }
 
@@ -236,9 +415,199 @@ stkde_status stkde_compute(stkde_plan_t p, const double* d_xyt, int64_t n, float
     st = stkde_accumulate(p, n, d_out, d_ws, ws_bytes, d_stats, stream);
     if (st != STKDE_OK) return st;
     if (d_stats && (p->desc.flags & STKDE_FLAG_POINT_STATS)) {
-        if (stkde::launch_point_stats(p->g, d_xyt, (int32_t)n, d_stats, c.ws, c.w, c.s) != hipSuccess)
+        double* part = reinterpret_cast<double*>(c.ws + c.L.shared);
+        if (stkde::launch_point_stats(p->ig, n, d_xyt, (int32_t)n, d_stats, part, c.L.nblk_pts, c.s) !=
+            hipSuccess)
             return STKDE_ERR_HIP;
     }
+    return STKDE_OK;
+}
+
+// ---- binned sets ------------------------------------------------------------
+
+stkde_status stkde_set_plan(const stkde_desc* base, const stkde_tuning* tun, int64_t n,
+                            stkde_set_t* out) {
+    if (!base || !out || n < 1) return STKDE_ERR_INVALID_ARG;
+    if (n > 0x7fffffffLL) return STKDE_ERR_TOO_LARGE;
+    stkde_status st = check_desc(base);
+    if (st != STKDE_OK) return st;
+    if (base->flags != 0) return STKDE_ERR_INVALID_ARG;
+    st = check_tuning(tun);
+    if (st != STKDE_OK) return st;
+    const int32_t rows = tun && tun->tile_t ? tun->tile_t : 32;
+    stkde_set_s tmp;
+    tmp.base = *base;
+    tmp.n = n;
+    make_set_geom(*base, tun ? tun->cell_xy : 0, tun ? tun->cell_t : 0, rows, &tmp.sg);
+    tmp.sl = stkde::layout_set(tmp.sg, n);
+    tmp.so = stkde::layout_sort(n);
+    stkde_set_s* s = new (std::nothrow) stkde_set_s(tmp);
+    if (!s) return STKDE_ERR_TOO_LARGE;
+    *out = s;
+    return STKDE_OK;
+}
+
+stkde_status stkde_set_bytes(stkde_set_t s, size_t* set_bytes, size_t* scratch_bytes) {
+    if (!s || !set_bytes || !scratch_bytes) return STKDE_ERR_INVALID_ARG;
+    *set_bytes = s->sl.total;
+    *scratch_bytes = s->so.total;
+    return STKDE_OK;
+}
+
+stkde_status stkde_set_build(stkde_set_t s, const double* d_xyt, void* d_set, size_t set_bytes,
+                             void* d_scratch, size_t scratch_bytes, void* stream) {
+    if (!s || !d_xyt) return STKDE_ERR_INVALID_ARG;
+    if (!d_set || set_bytes < s->sl.total || ((uintptr_t)d_set & 255u)) return STKDE_ERR_WORKSPACE;
+    if (!d_scratch || scratch_bytes < s->so.total || ((uintptr_t)d_scratch & 255u))
+        return STKDE_ERR_WORKSPACE;
+    if (stkde::launch_bin(s->sg, d_xyt, (int32_t)s->n, reinterpret_cast<uint8_t*>(d_set), s->sl,
+                          reinterpret_cast<uint8_t*>(d_scratch), s->so,
+                          reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
+        return STKDE_ERR_HIP;
+    return STKDE_OK;
+}
+
+stkde_status stkde_set_destroy(stkde_set_t s) {
+    delete s;
+    return STKDE_OK;
+}
+
+// ---- batches ----------------------------------------------------------------
+
+stkde_status stkde_batch_plan(const stkde_item* items, int32_t count, stkde_batch_t* out) {
+    if (!items || !out || count < 1) return STKDE_ERR_INVALID_ARG;
+    if (count > kMaxBatch) return STKDE_ERR_TOO_LARGE;
+    std::vector<stkde::InstGeom> geo((size_t)count);
+    for (int32_t i = 0; i < count; ++i) {
+        const stkde_item& it = items[i];
+        if (!it.plan || !it.set || !it.d_set || !it.d_out) return STKDE_ERR_INVALID_ARG;
+        if ((uintptr_t)it.d_set & 255u) return STKDE_ERR_INVALID_ARG;
+        const stkde_desc& d = it.plan->desc;
+        const stkde_desc& b = it.set->base;
+        if (d.flags & STKDE_FLAG_POINT_STATS) return STKDE_ERR_UNSUPPORTED;
+        if (!same_res(d.sres, b.sres) || !same_res(d.tres, b.tres)) return STKDE_ERR_INVALID_ARG;
+        if (d.hs > b.hs || d.ht > b.ht) return STKDE_ERR_INVALID_ARG;
+        if (it.ox < 0 || it.oy < 0 || it.ot < 0 || it.ox + d.gx > b.gx || it.oy + d.gy > b.gy ||
+            it.ot + d.gt > b.gt)
+            return STKDE_ERR_INVALID_ARG;
+        const double tol_s = 1e-6 * b.sres, tol_t = 1e-6 * b.tres;
+        if (fabs(d.x0 - (b.x0 + (double)it.ox * b.sres)) > tol_s ||
+            fabs(d.y0 - (b.y0 + (double)it.oy * b.sres)) > tol_s ||
+            fabs(d.t0 - (b.t0 + (double)it.ot * b.tres)) > tol_t)
+            return STKDE_ERR_INVALID_ARG;
+        const stkde_status st = make_inst_geom(d, b, it.plan->ig.tile_t, &geo[(size_t)i]);
+        if (st != STKDE_OK) return st;
+        if (ranges_needed(it.set->sg, geo[(size_t)i].Hs, geo[(size_t)i].Ht, geo[(size_t)i].tile_t) >
+            stkde::kMaxRanges)
+            return STKDE_ERR_UNSUPPORTED;
+    }
+    stkde_batch_s* bt = new (std::nothrow) stkde_batch_s;
+    if (!bt) return STKDE_ERR_TOO_LARGE;
+    bt->items.assign(items, items + count);
+    const int tts[3] = {16, 32, 64};
+    for (int kahan = 0; kahan < 2; ++kahan) {
+        for (int tt : tts) {
+            stkde_batch_s::Group g;
+            g.tile_t = tt;
+            g.kahan = kahan != 0;
+            for (int32_t i = 0; i < count; ++i) {
+                const bool k = (items[i].plan->desc.flags & STKDE_FLAG_KAHAN) != 0;
+                if (k == g.kahan && geo[(size_t)i].tile_t == tt) {
+                    g.idx.push_back(i);
+                    g.geo.push_back(geo[(size_t)i]);
+                }
+            }
+            if (g.idx.empty()) continue;
+            g.pl = stkde::layout_pass(g.geo.data(), (int32_t)g.geo.size(), tt);
+            if (g.pl.T > 0x7fffffffLL) {
+                delete bt;
+                return STKDE_ERR_TOO_LARGE;
+            }
+            bt->ws_bytes = std::max(bt->ws_bytes, g.pl.total);
+            bt->groups.push_back(std::move(g));
+        }
+    }
+    *out = bt;
+    return STKDE_OK;
+}
+
+stkde_status stkde_batch_workspace_bytes(stkde_batch_t b, size_t* bytes) {
+    if (!b || !bytes) return STKDE_ERR_INVALID_ARG;
+    *bytes = b->ws_bytes;
+    return STKDE_OK;
+}
+
+namespace {
+
+stkde_status batch_enqueue(stkde_batch_t b, uint8_t* ws, hipStream_t s) {
+    std::vector<stkde::InstDev> devs;
+    for (const auto& g : b->groups) {
+        devs.clear();
+        for (size_t k = 0; k < g.idx.size(); ++k) {
+            const stkde_item& it = b->items[(size_t)g.idx[k]];
+            devs.push_back(make_dev(g.geo[k], it.set->sg, reinterpret_cast<const uint8_t*>(it.d_set),
+                                    it.set->sl, it.set->n, (int32_t)it.ox, (int32_t)it.oy,
+                                    (int32_t)it.ot, it.d_out, it.d_stats,
+                                    (it.plan->desc.flags & STKDE_FLAG_MASS) != 0));
+        }
+        if (stkde::launch_pass(devs.data(), (int32_t)devs.size(), ws, g.pl, g.tile_t, g.kahan, s) !=
+            hipSuccess)
+            return STKDE_ERR_HIP;
+    }
+    return STKDE_OK;
+}
+
+}  // namespace
+
+stkde_status stkde_batch_run(stkde_batch_t b, void* d_ws, size_t ws_bytes, void* stream) {
+    if (!b) return STKDE_ERR_INVALID_ARG;
+    if (!d_ws || ws_bytes < b->ws_bytes || ((uintptr_t)d_ws & 255u)) return STKDE_ERR_WORKSPACE;
+    return batch_enqueue(b, reinterpret_cast<uint8_t*>(d_ws), reinterpret_cast<hipStream_t>(stream));
+}
+
+stkde_status stkde_batch_capture(stkde_batch_t b, void* d_ws, size_t ws_bytes) {
+    if (!b) return STKDE_ERR_INVALID_ARG;
+    if (!d_ws || ws_bytes < b->ws_bytes || ((uintptr_t)d_ws & 255u)) return STKDE_ERR_WORKSPACE;
+    for (const auto& g : b->groups) stkde::prepare_gather(g.tile_t, g.kahan);
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return STKDE_ERR_HIP;
+    hipGraph_t graph = nullptr;
+    stkde_status st = STKDE_OK;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        st = STKDE_ERR_HIP;
+    } else {
+        st = batch_enqueue(b, reinterpret_cast<uint8_t*>(d_ws), cs);
+        // always end the capture, also after a failed launch
+        if (hipStreamEndCapture(cs, &graph) != hipSuccess && st == STKDE_OK) st = STKDE_ERR_HIP;
+    }
+    hipGraphExec_t exec = nullptr;
+    if (st == STKDE_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+        st = STKDE_ERR_HIP;
+    if (st != STKDE_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipStreamDestroy(cs);
+        return st;
+    }
+    (void)hipStreamDestroy(cs);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->graph = graph;
+    b->exec = exec;
+    return STKDE_OK;
+}
+
+stkde_status stkde_batch_replay(stkde_batch_t b, void* stream) {
+    if (!b) return STKDE_ERR_INVALID_ARG;
+    if (!b->exec) return STKDE_ERR_UNSUPPORTED;
+    if (hipGraphLaunch(b->exec, reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return STKDE_ERR_HIP;
+    return STKDE_OK;
+}
+
+stkde_status stkde_batch_destroy(stkde_batch_t b) {
+    if (!b) return STKDE_OK;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    delete b;
     return STKDE_OK;
 }
 

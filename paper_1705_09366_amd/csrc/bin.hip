@@ -12,6 +12,11 @@
 //   3. bin offsets: cell_start[c] = first sorted position with key >= c.
 //   4. records: per sorted point, the 32-byte PointRec (voxel-space
 //      coordinates as FP32 head + FP16 tail, and the clipped footprint box).
+// The bin offsets, records and counters form the *binned set*, which stays
+// valid for any number of later density computations on the base grid or a
+// window of it with bandwidths up to the set's; the sort buffers are scratch.
+#include <utility>
+
 #include "stkde_internal.h"
 
 namespace stkde {
@@ -37,7 +42,7 @@ __device__ inline int32_t floordiv(int32_t a, int32_t b) {
 // |X + 1/2 - xr| < hv; row T is inside the window when |T + 1/2 - tr| <= tv.
 // The integer ranges below are those sets up to rows where the kernel value
 // is zero to rounding, clipped to the grid.
-__device__ inline Footprint footprint(const Geometry& g, double x, double y, double t) {
+__device__ inline Footprint footprint(const SetGeom& g, double x, double y, double t) {
     Footprint f;
     f.finite = isfinite(x) && isfinite(y) && isfinite(t);
     f.inside = false;
@@ -67,7 +72,7 @@ __device__ inline Footprint footprint(const Geometry& g, double x, double y, dou
     return f;
 }
 
-__device__ inline uint32_t bin_key(const Geometry& g, const Footprint& f) {
+__device__ inline uint32_t bin_key(const SetGeom& g, const Footprint& f) {
     const int32_t cx = clamp_i(floordiv(f.fx, g.cxy), 0, g.ncx - 1);
     const int32_t cy = clamp_i(floordiv(f.fy, g.cxy), 0, g.ncy - 1);
     const int32_t ct = clamp_i(floordiv(f.ft, g.ct), 0, g.nct - 1);
@@ -79,7 +84,7 @@ __global__ void k_zero_u64(unsigned long long* p, int count) {
     if (i < count) p[i] = 0ull;
 }
 
-__global__ __launch_bounds__(kThreads) void k_transform(Geometry g, const double* __restrict__ xyt,
+__global__ __launch_bounds__(kThreads) void k_transform(SetGeom g, const double* __restrict__ xyt,
                                                         int32_t n, uint32_t* __restrict__ keys,
                                                         uint32_t* __restrict__ vals,
                                                         unsigned long long* __restrict__ counters) {
@@ -247,7 +252,7 @@ __device__ inline uint32_t pack_tail(double v, float head) {
     return (uint32_t)__builtin_bit_cast(uint16_t, h);
 }
 
-__global__ __launch_bounds__(kThreads) void k_records(Geometry g, const double* __restrict__ xyt,
+__global__ __launch_bounds__(kThreads) void k_records(SetGeom g, const double* __restrict__ xyt,
                                                       const uint32_t* __restrict__ vals,
                                                       const uint32_t* __restrict__ cell_start,
                                                       int32_t n, PointRec* __restrict__ recs) {
@@ -278,61 +283,68 @@ inline int bits_for(uint32_t v) {
 
 }  // namespace
 
-Workspace layout_workspace(const Geometry& g, int64_t n) {
-    Workspace w{};
-    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+namespace {
+size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
+}  // namespace
+
+SetLayout layout_set(const SetGeom& g, int64_t n) {
+    SetLayout l{};
     size_t o = 0;
-    const size_t nn = (size_t)n;
-    w.nblk_sort = (int32_t)((n + kSortTile - 1) / kSortTile);
-    w.nblk_pts = (int32_t)((n + kStatBlock - 1) / kStatBlock);
-    w.keys0 = o; o = al(o + nn * 4);
-    w.vals0 = o; o = al(o + nn * 4);
-    w.keys1 = o; o = al(o + nn * 4);
-    w.vals1 = o; o = al(o + nn * 4);
-    w.hist = o; o = al(o + (size_t)256 * w.nblk_sort * 4);
-    w.cell_start = o; o = al(o + ((size_t)g.ncell + 1) * 4);
-    w.recs = o; o = al(o + nn * sizeof(PointRec));
-    w.tile_part = o; o = al(o + (size_t)g.ntiles * kWaves * 8);
-    w.pt_part = o; o = al(o + (size_t)w.nblk_pts * 4 * 8);
-    w.counters = o; o = al(o + 4 * 8 + 3 * 256 * 4);
-    w.mass_part = o; o = al(o + (size_t)kMassBlocks * 8);
-    w.total = o;
-    return w;
+    l.cell_start = o; o = al256(o + ((size_t)g.ncell + 1) * 4);
+    l.recs = o; o = al256(o + (size_t)n * sizeof(PointRec));
+    l.counters = o; o = al256(o + 4 * 8);
+    l.total = o;
+    return l;
 }
 
-hipError_t launch_bin(const Geometry& g, const double* d_xyt, int32_t n, uint8_t* ws,
-                      const Workspace& w, hipStream_t s) {
-    uint32_t* k0 = reinterpret_cast<uint32_t*>(ws + w.keys0);
-    uint32_t* v0 = reinterpret_cast<uint32_t*>(ws + w.vals0);
-    uint32_t* k1 = reinterpret_cast<uint32_t*>(ws + w.keys1);
-    uint32_t* v1 = reinterpret_cast<uint32_t*>(ws + w.vals1);
-    uint32_t* hist = reinterpret_cast<uint32_t*>(ws + w.hist);
-    uint32_t* cs = reinterpret_cast<uint32_t*>(ws + w.cell_start);
-    unsigned long long* ctr = reinterpret_cast<unsigned long long*>(ws + w.counters);
+SortLayout layout_sort(int64_t n) {
+    SortLayout l{};
+    size_t o = 0;
+    const size_t nn = (size_t)n;
+    l.nblk = (int32_t)((n + kSortTile - 1) / kSortTile);
+    l.keys0 = o; o = al256(o + nn * 4);
+    l.vals0 = o; o = al256(o + nn * 4);
+    l.keys1 = o; o = al256(o + nn * 4);
+    l.vals1 = o; o = al256(o + nn * 4);
+    l.hist = o; o = al256(o + (size_t)256 * l.nblk * 4);
+    l.totals = o; o = al256(o + 4 * 256 * 4);
+    l.total = o;
+    return l;
+}
+
+hipError_t launch_bin(const SetGeom& g, const double* d_xyt, int32_t n, uint8_t* set,
+                      const SetLayout& sl, uint8_t* sort, const SortLayout& so, hipStream_t s) {
+    uint32_t* k0 = reinterpret_cast<uint32_t*>(sort + so.keys0);
+    uint32_t* v0 = reinterpret_cast<uint32_t*>(sort + so.vals0);
+    uint32_t* k1 = reinterpret_cast<uint32_t*>(sort + so.keys1);
+    uint32_t* v1 = reinterpret_cast<uint32_t*>(sort + so.vals1);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(sort + so.hist);
+    uint32_t* totals = reinterpret_cast<uint32_t*>(sort + so.totals);
+    uint32_t* cs = reinterpret_cast<uint32_t*>(set + sl.cell_start);
+    unsigned long long* ctr = reinterpret_cast<unsigned long long*>(set + sl.counters);
     const int nb = (n + kThreads - 1) / kThreads;
 
-    uint32_t* totals = reinterpret_cast<uint32_t*>(ws + w.counters + 4 * 8);
-    hipLaunchKernelGGL(k_zero_u64, dim3(2), dim3(256), 0, s, ctr, 4 + 3 * 256 / 2);
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ctr, 4);
     hipLaunchKernelGGL(k_transform, dim3(nb), dim3(kThreads), 0, s, g, d_xyt, n, k0, v0, ctr);
 
     const int bits = bits_for((uint32_t)g.ncell);
     const int passes = bits <= 8 ? 1 : (bits + 7) / 8;
     for (int p = 0; p < passes; ++p) {
-        hipLaunchKernelGGL(k_radix_hist, dim3(w.nblk_sort), dim3(kThreads), 0, s, k0, n, 8 * p,
-                           hist, w.nblk_sort);
-        hipLaunchKernelGGL(k_radix_rowsum, dim3(256), dim3(kThreads), 0, s, hist, w.nblk_sort,
+        hipLaunchKernelGGL(k_radix_hist, dim3(so.nblk), dim3(kThreads), 0, s, k0, n, 8 * p, hist,
+                           so.nblk);
+        hipLaunchKernelGGL(k_radix_rowsum, dim3(256), dim3(kThreads), 0, s, hist, so.nblk,
                            totals + 256 * p);
-        hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(kThreads), 0, s, hist, w.nblk_sort,
+        hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(kThreads), 0, s, hist, so.nblk,
                            totals + 256 * p);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(w.nblk_sort), dim3(kThreads), 0, s, k0, v0, n,
-                           8 * p, hist, w.nblk_sort, k1, v1);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(so.nblk), dim3(kThreads), 0, s, k0, v0, n, 8 * p,
+                           hist, so.nblk, k1, v1);
         std::swap(k0, k1);
         std::swap(v0, v1);
     }
     const int nc = (g.ncell + 1 + kThreads - 1) / kThreads;
     hipLaunchKernelGGL(k_cell_start, dim3(nc), dim3(kThreads), 0, s, k0, n, g.ncell, cs);
     hipLaunchKernelGGL(k_records, dim3(nb), dim3(kThreads), 0, s, g, d_xyt, v0, cs, n,
-                       reinterpret_cast<PointRec*>(ws + w.recs));
+                       reinterpret_cast<PointRec*>(set + sl.recs));
     return hipGetLastError();
 }
 

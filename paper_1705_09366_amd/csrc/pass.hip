@@ -1,0 +1,368 @@
+// pass.hip -- one gather pass over a list of instances: the tile work list
+// (candidate cost per tile, heaviest-first order, splitting of the costliest
+// tiles), the gather, the reduction of split tiles, and the per-instance
+// FP64 mass and statistics.
+//
+// Load balance follows Sec. 5.2.  Greedy list scheduling finishes within
+// (total work - longest task)/P + longest task (Graham's bound quoted there),
+// so two things matter: the order and the longest task.  The cost of a tile
+// is the number of points it must examine (the points of its neighbouring
+// bins); the costliest tiles are queued first, in non-increasing cost (the
+// order of PB-SYM-PD-SCHED), and a tile whose cost exceeds a fixed share of
+// its instance's total is cut into contiguous candidate ranges whose partial
+// grids are added afterwards in part order (the replication of the critical
+// path of PB-SYM-PD-REP, with its extra initialisation and reduction).
+// Everything here is deterministic: the queues only change which workgroup
+// computes an item, never what it computes.
+#include "stkde_internal.h"
+
+namespace stkde {
+namespace {
+
+struct DescChunk {
+    InstDev d[kDescChunk];
+};
+
+size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Descriptors arrive as kernel arguments, so that a captured pass carries
+// them in its graph; the first chunk also clears the pass counters.
+__global__ __launch_bounds__(256) void k_put_desc(DescChunk c, int32_t first, int32_t m,
+                                                  InstDev* __restrict__ dst,
+                                                  unsigned long long* __restrict__ inst_cost,
+                                                  uint32_t* __restrict__ hist,
+                                                  uint32_t* __restrict__ sc, int32_t clear) {
+    const int tid = threadIdx.x;
+    if (tid < m) {
+        dst[first + tid] = c.d[tid];
+        inst_cost[first + tid] = 0ull;
+    }
+    if (clear) {
+        for (int k = tid; k < kCostClasses; k += 256) hist[k] = 0u;
+        if (tid < kScCount) sc[tid] = 0u;
+    }
+}
+
+__device__ inline uint32_t cost_class(uint32_t c) { return __float_as_uint((float)c) >> 20; }
+
+// Candidates per tile (the points of the bins the gather reads), the cost
+// class histogram, and per-instance totals.
+__global__ __launch_bounds__(256) void k_tile_cost(const InstDev* __restrict__ descs, int32_t count,
+                                                   uint32_t T, int32_t rows,
+                                                   uint32_t* __restrict__ cost,
+                                                   uint32_t* __restrict__ hist,
+                                                   unsigned long long* __restrict__ inst_cost) {
+    __shared__ uint32_t h[kCostClasses];
+    const int tid = threadIdx.x, lane = tid & 63;
+    for (int k = tid; k < kCostClasses; k += 256) h[k] = 0u;
+    __syncthreads();
+    const uint32_t j = blockIdx.x * 256u + (uint32_t)tid;
+    const bool valid = j < T;
+    uint32_t c = 0;
+    int32_t inst = 0;
+    if (valid) {
+        inst = find_inst(descs, count, j);
+        const InstDev& D = descs[inst];
+        const int32_t tile = (int32_t)(j - (uint32_t)D.tile_base);
+        const int32_t tx = tile % D.ntx;
+        const int32_t rest = tile / D.ntx;
+        const int32_t ty = rest % D.nty;
+        const int32_t tt = rest / D.nty;
+        const TileBins b = tile_bins(D, tx * kTileXY + D.ox, ty * kTileXY + D.oy, tt * rows + D.ot, rows);
+        for (int32_t cz = b.ct0; cz <= b.ct1; ++cz) {
+            for (int32_t cy = b.cy0; cy <= b.cy1; ++cy) {
+                const int32_t row = (cz * D.ncy + cy) * D.ncx;
+                c += D.cell_start[row + b.cx1 + 1] - D.cell_start[row + b.cx0];
+            }
+        }
+        cost[j] = c;
+        atomicAdd(&h[cost_class(c)], 1u);
+    }
+    // per-instance totals: one atomic per wave unless the wave spans instances
+    const int32_t i0 = __shfl(inst, 0, 64);
+    if (__ballot(valid && inst != i0) == 0ull) {
+        unsigned long long v = c;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+        if (lane == 0 && v) atomicAdd(&inst_cost[i0], v);
+    } else if (valid && c) {
+        atomicAdd(&inst_cost[inst], (unsigned long long)c);
+    }
+    __syncthreads();
+    for (int k = tid; k < kCostClasses; k += 256)
+        if (h[k]) atomicAdd(&hist[k], h[k]);
+}
+
+// Exclusive prefix sum over a 1024-thread workgroup; *total gets the sum.
+__device__ inline uint32_t block_scan(uint32_t v, uint32_t* ws, uint32_t* total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += u;
+    }
+    __syncthreads();  // the previous scan's readers are done with ws
+    if (lane == 63) ws[w] = inc;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const uint32_t x = ws[k];
+        pre += k < w ? x : 0u;
+        tot += x;
+    }
+    *total = tot;
+    return pre + inc - v;
+}
+
+// The work list (one workgroup of 1024 threads):
+//  1. the heaviest cost classes holding at most kTopTiles tiles form the
+//     heaviest-first queue, sorted by cost, descending (ties by tile);
+//  2. every other tile goes, in tile order, to one of 8 contiguous XCD
+//     ranges;
+//  3. a heavy tile whose cost exceeds max(kSplitFloor, its instance's total
+//     cost / kBalanceItems) is cut into up to kMaxParts equal candidate
+//     ranges, while partial slots last (costliest first).
+__global__ __launch_bounds__(1024) void k_plan_items(const InstDev* __restrict__ descs, int32_t count,
+                                                     uint32_t T, const uint32_t* __restrict__ cost,
+                                                     const uint32_t* __restrict__ hist,
+                                                     const unsigned long long* __restrict__ inst_cost,
+                                                     WorkItem* __restrict__ items,
+                                                     uint32_t* __restrict__ top,
+                                                     uint32_t* __restrict__ sc, uint32_t nslots) {
+    __shared__ unsigned long long keys[kTopTiles];
+    __shared__ uint32_t ws[16];
+    __shared__ uint32_t s_cls;
+    const int tid = threadIdx.x;
+    static_assert(kCostClasses == 2 * 1024, "two cost classes per thread");
+
+    // ---- 1. threshold class: smallest class c >= class(1) whose suffix count
+    // (tiles of class >= c) is at most kTopTiles
+    if (tid == 0) s_cls = kCostClasses;
+    const uint32_t chi = kCostClasses - 1 - 2 * tid, clo = chi - 1;
+    const uint32_t hhi = hist[chi], hlo = hist[clo];
+    uint32_t tot;
+    const uint32_t above = block_scan(hhi + hlo, ws, &tot);  // tiles of classes > chi
+    const uint32_t cmin = cost_class(1u);
+    if (chi >= cmin && above + hhi <= (uint32_t)kTopTiles) atomicMin(&s_cls, chi);
+    if (clo >= cmin && above + hhi + hlo <= (uint32_t)kTopTiles) atomicMin(&s_cls, clo);
+    __syncthreads();
+    const uint32_t cls = s_cls;
+
+    // ---- 2. partition the tiles
+    const uint32_t sbase = (uint32_t)kTopTiles * kMaxParts;
+    uint32_t nh = 0, ns = 0;
+    for (uint32_t base = 0; base < T; base += 1024) {
+        const uint32_t j = base + (uint32_t)tid;
+        uint32_t c = 0;
+        bool heavy = false, light = false;
+        if (j < T) {
+            c = cost[j];
+            heavy = cost_class(c) >= cls;
+            light = !heavy;
+        }
+        uint32_t th, tl;
+        const uint32_t ph = block_scan(heavy ? 1u : 0u, ws, &th);
+        const uint32_t pl = block_scan(light ? 1u : 0u, ws, &tl);
+        if (heavy) keys[nh + ph] = ((unsigned long long)(~c) << 32) | j;
+        if (light) items[sbase + ns + pl] = WorkItem{j, 0u, kAll, kNoSlot};
+        nh += th;
+        ns += tl;
+    }
+    // bitonic sort of the heavy keys, ascending: cost descending, then tile
+    if ((uint32_t)tid >= nh) keys[tid] = ~0ull;
+    for (int k = 2; k <= kTopTiles; k <<= 1) {
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            __syncthreads();
+            const int p = tid ^ jj;
+            if (p > tid) {
+                const unsigned long long a = keys[tid], b = keys[p];
+                const bool up = (tid & k) == 0;
+                if ((a > b) == up) {
+                    keys[tid] = b;
+                    keys[p] = a;
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- 3. splitting
+    uint32_t tile = 0, c = 0, parts = 1;
+    if ((uint32_t)tid < nh) {
+        const unsigned long long k = keys[tid];
+        tile = (uint32_t)k;
+        c = ~(uint32_t)(k >> 32);
+        const int32_t inst = find_inst(descs, count, tile);
+        const unsigned long long share = (inst_cost[inst] + kBalanceItems - 1) / kBalanceItems;
+        const uint32_t thr = share > kSplitFloor ? (share > 0xffffffffull ? 0xffffffffu : (uint32_t)share)
+                                                 : kSplitFloor;
+        if (c > thr) {
+            const uint32_t want = (uint32_t)(((unsigned long long)c + thr - 1) / thr);
+            parts = want < (uint32_t)kMaxParts ? want : (uint32_t)kMaxParts;
+        }
+    }
+    uint32_t need = parts > 1 ? parts : 0u;
+    uint32_t tot_need;
+    const uint32_t pre_need = block_scan(need, ws, &tot_need);
+    if (pre_need + need > nslots) {
+        parts = 1;
+        need = 0;
+    }
+    uint32_t nslot_used, nitems_h, nsplit;
+    const uint32_t slot0 = block_scan(need, ws, &nslot_used);
+    const uint32_t ipos = block_scan((uint32_t)tid < nh ? parts : 0u, ws, &nitems_h);
+    const uint32_t spos = block_scan(parts > 1 ? 1u : 0u, ws, &nsplit);
+    if ((uint32_t)tid < nh) {
+        for (uint32_t p = 0; p < parts; ++p) {
+            const uint32_t b = (uint32_t)(((unsigned long long)c * p) / parts);
+            const uint32_t e = p + 1 == parts ? kAll : (uint32_t)(((unsigned long long)c * (p + 1)) / parts);
+            items[ipos + p] = WorkItem{tile, b, e, parts > 1 ? slot0 + p : kNoSlot};
+        }
+        if (parts > 1) {
+            top[4 * spos + 0] = tile;
+            top[4 * spos + 1] = parts;
+            top[4 * spos + 2] = slot0;
+            top[4 * spos + 3] = c;
+        }
+    }
+
+    // ---- 4. queue bounds
+    if (tid < kQueues) sc[kScNext + tid] = 0u;
+    if (tid == 0) {
+        sc[kScBeg] = 0u;
+        sc[kScLen] = nitems_h;
+        sc[kScSplit] = nsplit;
+    }
+    if (tid < 8) {
+        const uint32_t b = (uint32_t)(((unsigned long long)ns * tid) / 8);
+        const uint32_t e = (uint32_t)(((unsigned long long)ns * (tid + 1)) / 8);
+        sc[kScBeg + 1 + tid] = sbase + b;
+        sc[kScLen + 1 + tid] = e - b;
+    }
+}
+
+// First level of each instance's FP64 grid sum: chunk blockIdx.x of the
+// tile partials of instance blockIdx.y, strided per-thread sums, then a tree.
+__global__ __launch_bounds__(256) void k_mass_chunks(const InstDev* __restrict__ descs,
+                                                     double* __restrict__ mid) {
+    __shared__ double sh[256];
+    const int inst = blockIdx.y, ch = blockIdx.x, tid = threadIdx.x;
+    const InstDev& D = descs[inst];
+    double s = 0.0;
+    if (D.flags & kInstMass) {
+        const int64_t cnt = (int64_t)D.ntiles * kWaves;
+        const int64_t chunk = (cnt + kMassChunks - 1) / kMassChunks;
+        const int64_t beg = (int64_t)ch * chunk;
+        const int64_t end = beg + chunk < cnt ? beg + chunk : cnt;
+        for (int64_t i = beg + tid; i < end; i += 256) s += D.tile_part[i];
+    }
+    sh[tid] = s;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (tid < w) sh[tid] += sh[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) mid[(size_t)inst * kMassChunks + ch] = sh[0];
+}
+
+// Per instance: stats[0] = grid mass (sum * sres^2 tres, or 0 without the
+// mass flag), [1], [2], [5..7] = 0, [3], [4] = the set's non-finite and
+// culled counts.
+__global__ __launch_bounds__(64) void k_finalize(const InstDev* __restrict__ descs,
+                                                 const double* __restrict__ mid) {
+    static_assert(kMassChunks == 64, "one wave per instance");
+    const InstDev& D = descs[blockIdx.x];
+    double* st = D.stats;
+    if (!st) return;
+    const int lane = threadIdx.x;
+    double v = mid[(size_t)blockIdx.x * kMassChunks + lane];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    if (lane == 0) {
+        st[0] = (D.flags & kInstMass) ? v * D.mass_scale : 0.0;
+        st[1] = 0.0;
+        st[2] = 0.0;
+        st[3] = (double)D.counters[0];
+        st[4] = (double)D.counters[1];
+        st[5] = 0.0;
+        st[6] = 0.0;
+        st[7] = 0.0;
+    }
+}
+
+}  // namespace
+
+PassLayout layout_pass(const InstGeom* inst, int32_t count, int tile_t) {
+    PassLayout l{};
+    int64_t T = 0, parts = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        T += inst[i].ntiles;
+        parts += (int64_t)inst[i].ntiles * kWaves;
+    }
+    size_t o = 0;
+    l.T = T;
+    l.desc = o; o = al256(o + (size_t)count * sizeof(InstDev));
+    l.inst_cost = o; o = al256(o + (size_t)count * 8);
+    l.cost = o; o = al256(o + (size_t)T * 4);
+    l.hist = o; o = al256(o + (size_t)kCostClasses * 4);
+    l.scalars = o; o = al256(o + (size_t)kScCount * 4);
+    l.top = o; o = al256(o + (size_t)kTopTiles * 16);
+    l.items = o; o = al256(o + ((size_t)kTopTiles * kMaxParts + (size_t)T) * sizeof(WorkItem));
+    l.partials = o; o = al256(o + (size_t)kPartSlots * kTileXY * kTileXY * tile_t * 4);
+    l.tile_part = o; o = al256(o + (size_t)parts * 8);
+    l.mass_mid = o; o = al256(o + (size_t)count * kMassChunks * 8);
+    l.total = o;
+    return l;
+}
+
+hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassLayout& pl,
+                       int tile_t, bool kahan, hipStream_t s, hipEvent_t ev_before,
+                       hipEvent_t ev_after) {
+    InstDev* d_desc = reinterpret_cast<InstDev*>(pass + pl.desc);
+    auto* inst_cost = reinterpret_cast<unsigned long long*>(pass + pl.inst_cost);
+    auto* cost = reinterpret_cast<uint32_t*>(pass + pl.cost);
+    auto* hist = reinterpret_cast<uint32_t*>(pass + pl.hist);
+    auto* sc = reinterpret_cast<uint32_t*>(pass + pl.scalars);
+    auto* top = reinterpret_cast<uint32_t*>(pass + pl.top);
+    auto* items = reinterpret_cast<WorkItem*>(pass + pl.items);
+    auto* partials = reinterpret_cast<float*>(pass + pl.partials);
+    auto* tile_part = reinterpret_cast<double*>(pass + pl.tile_part);
+    auto* mid = reinterpret_cast<double*>(pass + pl.mass_mid);
+
+    int64_t tb = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        descs[i].tile_base = (int32_t)tb;
+        descs[i].tile_part = tile_part + tb * kWaves;
+        tb += descs[i].ntiles;
+    }
+    for (int32_t first = 0; first < count; first += kDescChunk) {
+        DescChunk c{};
+        const int32_t m = count - first < kDescChunk ? count - first : kDescChunk;
+        for (int32_t k = 0; k < m; ++k) c.d[k] = descs[first + k];
+        hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(256), 0, s, c, first, m, d_desc, inst_cost,
+                           hist, sc, first == 0 ? 1 : 0);
+    }
+    const uint32_t T = (uint32_t)pl.T;
+    hipLaunchKernelGGL(k_tile_cost, dim3((T + 255) / 256), dim3(256), 0, s, (const InstDev*)d_desc,
+                       count, T, tile_t, cost, hist, inst_cost);
+    hipLaunchKernelGGL(k_plan_items, dim3(1), dim3(1024), 0, s, (const InstDev*)d_desc, count, T,
+                       (const uint32_t*)cost, (const uint32_t*)hist,
+                       (const unsigned long long*)inst_cost, items, top, sc, (uint32_t)kPartSlots);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (ev_before && (e = hipEventRecord(ev_before, s)) != hipSuccess) return e;
+    e = launch_gather_items(d_desc, count, items, sc, partials, pl.T, tile_t, kahan, s);
+    if (e != hipSuccess) return e;
+    if (ev_after && (e = hipEventRecord(ev_after, s)) != hipSuccess) return e;
+    e = launch_reduce_split(d_desc, count, top, sc, partials, tile_t, kahan, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mass_chunks, dim3(kMassChunks, (uint32_t)count), dim3(256), 0, s,
+                       (const InstDev*)d_desc, mid);
+    hipLaunchKernelGGL(k_finalize, dim3((uint32_t)count), dim3(64), 0, s, (const InstDev*)d_desc,
+                       (const double*)mid);
+    return hipGetLastError();
+}
+
+}  // namespace stkde

@@ -23,7 +23,7 @@ __device__ inline bool clip_rng(double v, double h, int32_t lo, int32_t hi, int3
     return *a <= *b;
 }
 
-__global__ __launch_bounds__(kStatBlock) void k_point_stats(Geometry g, const double* __restrict__ xyt,
+__global__ __launch_bounds__(kStatBlock) void k_point_stats(InstGeom g, const double* __restrict__ xyt,
                                                             int32_t n, double* __restrict__ part) {
 #pragma clang fp contract(off)
     __shared__ double sm[kStatBlock];
@@ -112,38 +112,14 @@ __global__ __launch_bounds__(1024) void k_stats_final(const double* __restrict__
     }
 }
 
-// d_stats[3], [4] from the binning counters; [5..7] = 0; [0..2] = 0 unless
-// another stage fills them afterwards.
-__global__ void k_stats_counters(const unsigned long long* __restrict__ ctr, double* __restrict__ stats) {
-    if (threadIdx.x == 0) {
-        stats[0] = 0.0;
-        stats[1] = 0.0;
-        stats[2] = 0.0;
-        stats[3] = (double)ctr[0];
-        stats[4] = (double)ctr[1];
-        stats[5] = 0.0;
-        stats[6] = 0.0;
-        stats[7] = 0.0;
-    }
-}
-
 }  // namespace
 
-hipError_t launch_stats(const Geometry& g, const double* d_xyt, int32_t n, bool point_stats,
-                        double* d_stats, uint8_t* ws, const Workspace& w, hipStream_t s) {
-    hipLaunchKernelGGL(k_stats_counters, dim3(1), dim3(64), 0, s,
-                       reinterpret_cast<const unsigned long long*>(ws + w.counters), d_stats);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !point_stats) return e;
-    return launch_point_stats(g, d_xyt, n, d_stats, ws, w, s);
-}
-
-hipError_t launch_point_stats(const Geometry& g, const double* d_xyt, int32_t n, double* d_stats,
-                              uint8_t* ws, const Workspace& w, hipStream_t s) {
-    double* part = reinterpret_cast<double*>(ws + w.pt_part);
-    hipLaunchKernelGGL(k_point_stats, dim3(w.nblk_pts), dim3(kStatBlock), 0, s, g, d_xyt, n, part);
-    const double scale = g.sres * g.sres * g.tres / ((double)n * g.hs * g.hs * g.ht);
-    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(1024), 0, s, part, w.nblk_pts, scale, d_stats);
+hipError_t launch_point_stats(const InstGeom& g, int64_t n_norm, const double* d_xyt, int32_t n,
+                              double* d_stats, double* part, int32_t nblk, hipStream_t s) {
+    hipLaunchKernelGGL(k_point_stats, dim3(nblk), dim3(kStatBlock), 0, s, g, d_xyt, n, part);
+    const double scale = g.sres * g.sres * g.tres / ((double)n_norm * g.hs * g.hs * g.ht);
+    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(1024), 0, s, (const double*)part, nblk, scale,
+                       d_stats);
     return hipGetLastError();
 }
 

@@ -1,10 +1,18 @@
 // stkde_internal.h -- layouts and launch interfaces shared by the library's
-// HIP sources (binning, gather, statistics) and its host entry points.
+// HIP sources (binning, work lists, gather, statistics) and its host entry
+// points.
 //
 // Units: every quantity below is in voxel units unless named otherwise.  A
 // point's voxel-space coordinate is xr = (x - x0)/sres (likewise y, and t with
 // tres); the voxel bandwidths are hv = hs/sres and tv = ht/tres, and the
 // integer loop bounds Hs = ceil(hv), Ht = ceil(tv) of Sec. 2.1.
+//
+// Two geometries meet in every computation:
+//  * a *binned set*: points transformed into the voxel space of a base grid,
+//    sorted into bins and stored as 32-byte records, with the largest
+//    bandwidths the set will be used with (they clip the footprint boxes);
+//  * an *instance*: one density grid -- the base grid or a voxel-aligned
+//    window of it -- with its own bandwidths, at most the set's.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>
@@ -15,7 +23,6 @@ namespace stkde {
 // A 256-thread workgroup owns a 16 x 16 x TT tile of voxels; each of its four
 // waves owns an 8 x 8 quadrant of columns, i.e. four 4 x 4 column groups,
 // times TT/16 blocks of 16 rows, as FP32 matrix-core accumulators.
-constexpr int kPatch = 8;
 constexpr int kTileXY = 16;
 constexpr int kWaves = 4;
 constexpr int kThreads = 256;
@@ -28,7 +35,7 @@ constexpr int kMaxRanges = 64;
 // it matters (near the point) although every kernel below works in FP32.
 struct alignas(16) PointRec {
     float xh, yh, th;
-    uint32_t xb;       // footprint columns in x: lo | hi << 16, clipped to the grid
+    uint32_t xb;       // footprint columns in x: lo | hi << 16, clipped to the base grid
     uint32_t yb;       // footprint columns in y: lo | hi << 16
     uint32_t tb;       // footprint rows in t: lo | hi << 16
     uint32_t xl_yl;    // tails of x and y as two FP16 (x in the low half)
@@ -36,62 +43,181 @@ struct alignas(16) PointRec {
 };
 static_assert(sizeof(PointRec) == 32, "record layout");
 
-// Geometry of one plan, in the form the kernels consume.
-struct Geometry {
-    int32_t gx, gy, gt;
-    int32_t Hs, Ht;           // ceil(hv), ceil(tv)
+// Binning geometry of a point set.
+struct SetGeom {
+    int32_t gx, gy, gt;       // base grid
     int32_t cxy, ct;          // bin edge in x/y and in t (voxels)
     int32_t ncx, ncy, nct;    // bins per axis
     int32_t ncell;            // ncx * ncy * nct
-    int32_t key_bits;         // bits of the largest key (ncell, used for culled points)
-    int32_t tile_t;           // time rows per lane (16 or 32)
+    double x0, y0, t0;
+    double sres, tres;
+    double hv, tv;            // largest voxel bandwidths (footprint boxes)
+};
+
+// Geometry of one density grid (an instance).
+struct InstGeom {
+    int32_t gx, gy, gt;       // instance grid
+    int32_t ox, oy, ot;       // its voxel (0,0,0) in the base grid of its set
+    int32_t Hs, Ht;           // ceil(hv), ceil(tv), capped by the grid extent
+    int32_t tile_t;           // rows per tile (16 or 32)
     int32_t ntx, nty, ntt;    // tiles per axis
     int32_t ntiles;
-    int32_t max_ranges;       // most (t, y) bin rows one tile reads
-    double x0, y0, t0;
-    double inv_sres, inv_tres;  // used as multipliers only where exact (see binning)
-    double sres, tres;
+    double x0, y0, t0, sres, tres;
+    double hs, ht;            // domain bandwidths (normalisation)
     double hv, tv;            // voxel bandwidths
     double Hs_d, Ht_d;        // ceil(hv), ceil(tv) uncapped (loop bounds of the statistics)
-    double hs, ht;            // domain bandwidths
-    float inv_hv2;            // 1/hv^2 (FP32)
-    float inv_tv2;            // 1/tv^2 (FP32)
+    float inv_hv2, inv_tv2;   // 1/hv^2, 1/tv^2 (FP32)
 };
 
-// Workspace carve-up (byte offsets from d_ws, each 256-byte aligned).
-struct Workspace {
-    size_t keys0, vals0, keys1, vals1;
-    size_t hist;         // radix digit counts, 256 * nblk_sort u32
+// Per-instance descriptor the device work list refers to (pass scratch copy).
+struct alignas(16) InstDev {
+    const uint32_t* cell_start;          // set: bin offsets
+    const PointRec* recs;                // set: records in bin order
+    const unsigned long long* counters;  // set: non-finite, culled
+    float* out;                          // instance grid, [X][Y][T], T fastest
+    double* stats;                       // optional 8 doubles, null for none
+    double* tile_part;                   // pass scratch: ntiles * kWaves FP64 mass partials
+    double mass_scale;                   // sres^2 tres
+    int32_t gx, gy, gt;                  // instance grid
+    int32_t ox, oy, ot;                  // its voxel (0,0,0) in the set's base grid
+    int32_t Hs, Ht;                      // instance loop bounds
+    int32_t cxy, ct, ncx, ncy, nct;      // set bins
+    int32_t ntx, nty, ntiles, tile_base; // instance tiles; first global tile index
+    uint32_t flags;                      // kInstMass
+    float inv_hv2, inv_tv2, cnorm;
+};
+constexpr uint32_t kInstMass = 1u;
+
+// One unit of gather work: a tile, a range of its candidate sequence and
+// where the result goes (the grid, or a partial slot of a split tile).
+struct alignas(16) WorkItem {
+    uint32_t tile;            // global tile index (instances concatenated)
+    uint32_t cbeg, cend;      // candidate range; cend = kAll for "to the end"
+    uint32_t slot;            // partial slot, kNoSlot = store to the grid
+};
+constexpr uint32_t kAll = 0xffffffffu;
+constexpr uint32_t kNoSlot = 0xffffffffu;
+
+constexpr int kSortItems = 8;                         // keys per thread per radix block
+constexpr int kSortTile = kThreads * kSortItems;      // keys per radix block
+constexpr int kStatBlock = 256;                       // points per statistics block
+constexpr int kTopTiles = 1024;                       // most tiles in the heaviest-first queue
+constexpr int kMaxParts = 8;                          // parts of one split tile
+constexpr int kPartSlots = 1024;                      // partial tiles of one pass
+constexpr uint32_t kSplitFloor = 2048;                // never split below this many candidates
+constexpr uint32_t kBalanceItems = 2048;              // split above 1/kBalanceItems of an instance's cost
+constexpr int kMassChunks = 64;                       // first-level chunks of an instance's mass sum
+constexpr int kDescChunk = 16;                        // descriptors written per launch
+constexpr int kQueues = 9;                            // heaviest-first queue + one per XCD
+// Cost class of a tile: the FP32 bit pattern of its candidate count without
+// the low 20 bits (exponent and 3 mantissa bits), monotone in the count.
+constexpr int kCostClasses = 2048;
+
+// Scalars of a pass (u32 offsets into PassLayout::scalars).
+constexpr int kScNext = 0;                 // [kQueues] next item of each queue
+constexpr int kScBeg = kScNext + kQueues;  // [kQueues] first item of each queue
+constexpr int kScLen = kScBeg + kQueues;   // [kQueues] items in each queue
+constexpr int kScSplit = kScLen + kQueues; // split tiles
+constexpr int kScCount = 32;
+
+// ---- set memory (caller-owned, persistent) --------------------------------
+struct SetLayout {
     size_t cell_start;   // (ncell + 1) u32
     size_t recs;         // n PointRec
-    size_t tile_part;    // ntiles * kWaves double (grid mass partials)
-    size_t pt_part;      // nblk_pts * 4 double (per-point statistics partials)
-    size_t counters;     // 4 x u64 (non-finite, culled), then 3 x 256 u32 digit totals
-    size_t mass_part;    // kMassBlocks double (first level of the grid-mass sum)
+    size_t counters;     // 4 x u64: non-finite, culled, 0, 0
     size_t total;
-    int32_t nblk_sort;
-    int32_t nblk_pts;
 };
+SetLayout layout_set(const SetGeom& s, int64_t n);
 
-constexpr int kSortItems = 8;                         // keys per thread per block
-constexpr int kSortTile = kThreads * kSortItems;      // keys per block
-constexpr int kStatBlock = 256;                       // points per statistics block
-constexpr int kMassBlocks = 256;                      // workgroups of the grid-mass sum
+// ---- scratch of the binning radix sort --------------------------------------
+struct SortLayout {
+    size_t keys0, vals0, keys1, vals1, hist, totals;
+    size_t total;
+    int32_t nblk;
+};
+SortLayout layout_sort(int64_t n);
 
-Workspace layout_workspace(const Geometry& g, int64_t n);
+// ---- scratch of one gather pass over `count` instances ---------------------
+struct PassLayout {
+    size_t desc;         // count InstDev
+    size_t inst_cost;    // count u64: candidates summed over the instance's tiles
+    size_t cost;         // T u32: candidates per tile
+    size_t hist;         // kCostClasses u32: tiles per cost class
+    size_t scalars;      // kScCount u32
+    size_t top;          // kTopTiles x 4 u32 split tiles: tile, parts, slot0, candidates
+    size_t items;        // kTopTiles * kMaxParts + T WorkItem
+    size_t partials;     // kPartSlots x 16 x 16 x tile_t FP32
+    size_t tile_part;    // sum over instances of ntiles * kWaves FP64
+    size_t mass_mid;     // count * kMassChunks FP64
+    size_t total;
+    int64_t T;           // total tiles
+};
+PassLayout layout_pass(const InstGeom* inst, int32_t count, int tile_t);
 
-// Stage launchers (all asynchronous on `s`; return the launch error).
-hipError_t launch_bin(const Geometry& g, const double* d_xyt, int32_t n, uint8_t* ws,
-                      const Workspace& w, hipStream_t s);
-hipError_t launch_gather(const Geometry& g, float cnorm, bool kahan, bool mass, float* d_out,
-                         uint8_t* ws, const Workspace& w, hipStream_t s);
-hipError_t launch_mass_reduce(const Geometry& g, double* d_dst, uint8_t* ws, const Workspace& w,
-                              hipStream_t s);
-// d_stats[0..7] = 0 except the binning counters in [3], [4]
-hipError_t launch_stats(const Geometry& g, const double* d_xyt, int32_t n, bool point_stats,
-                        double* d_stats, uint8_t* ws, const Workspace& w, hipStream_t s);
-// d_stats[1], [2] from per-point FP64 sums
-hipError_t launch_point_stats(const Geometry& g, const double* d_xyt, int32_t n, double* d_stats,
-                              uint8_t* ws, const Workspace& w, hipStream_t s);
+// Instance holding global tile `tile` (descriptors ordered by tile_base).
+__device__ inline int32_t find_inst(const InstDev* __restrict__ d, int32_t count, uint32_t tile) {
+    int32_t lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if ((uint32_t)d[mid].tile_base <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ inline int32_t floordiv_i(int32_t a, int32_t b) {
+    const int32_t q = a / b;
+    return (a % b != 0 && a < 0) ? q - 1 : q;
+}
+
+__device__ inline int32_t clamp_i32(int32_t v, int32_t lo, int32_t hi) {
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+// Bins a tile may draw points from: a point reaches column X only if floor(xr)
+// lies in [X - Hs, X + Hs] (rows likewise with Ht); one voxel of margin on each
+// side absorbs rounding of the footprint bounds.  (bx0, by0, bt0) is the tile
+// origin in the set's base grid.  The plan keeps
+// (cy1 - cy0 + 1) * (ct1 - ct0 + 1) <= kMaxRanges.
+struct TileBins {
+    int32_t cx0, cx1, cy0, cy1, ct0, ct1;
+};
+__device__ inline TileBins tile_bins(const InstDev& D, int32_t bx0, int32_t by0, int32_t bt0,
+                                     int32_t rows) {
+    TileBins b;
+    b.cx0 = clamp_i32(floordiv_i(bx0 - D.Hs - 1, D.cxy), 0, D.ncx - 1);
+    b.cx1 = clamp_i32(floordiv_i(bx0 + kTileXY - 1 + D.Hs + 1, D.cxy), 0, D.ncx - 1);
+    b.cy0 = clamp_i32(floordiv_i(by0 - D.Hs - 1, D.cxy), 0, D.ncy - 1);
+    b.cy1 = clamp_i32(floordiv_i(by0 + kTileXY - 1 + D.Hs + 1, D.cxy), 0, D.ncy - 1);
+    b.ct0 = clamp_i32(floordiv_i(bt0 - D.Ht - 1, D.ct), 0, D.nct - 1);
+    b.ct1 = clamp_i32(floordiv_i(bt0 + rows - 1 + D.Ht + 1, D.ct), 0, D.nct - 1);
+    return b;
+}
+
+// ---- launchers (asynchronous on s; return the launch error) ---------------
+// Bin n points into set memory `set` using radix scratch `sort`.
+hipError_t launch_bin(const SetGeom& g, const double* d_xyt, int32_t n, uint8_t* set,
+                      const SetLayout& sl, uint8_t* sort, const SortLayout& so, hipStream_t s);
+// Work list, gather, split reduction, mass and statistics over `count`
+// instances.  The descriptors' tile_part and tile_base fields are filled in
+// here; every other field is the caller's.
+// ev_before / ev_after (may be null) are recorded on s right before and
+// right after the gather kernel.
+hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassLayout& pl,
+                       int tile_t, bool kahan, hipStream_t s, hipEvent_t ev_before = nullptr,
+                       hipEvent_t ev_after = nullptr);
+// The gather proper (called by launch_pass).
+hipError_t launch_gather_items(const InstDev* d_desc, int32_t count, const WorkItem* d_items,
+                               uint32_t* d_scalars, float* d_partials, int64_t T, int tile_t,
+                               bool kahan, hipStream_t s);
+// Query (and cache) the gather's launch size for the current device ahead of a
+// stream capture.
+void prepare_gather(int tile_t, bool kahan);
+hipError_t launch_reduce_split(const InstDev* d_desc, int32_t count, const uint32_t* d_top,
+                               const uint32_t* d_scalars, const float* d_partials, int tile_t,
+                               bool kahan, hipStream_t s);
+// d_stats[1], [2] from per-point FP64 sums of one instance (part: nblk x 4 doubles)
+hipError_t launch_point_stats(const InstGeom& g, int64_t n_norm, const double* d_xyt, int32_t n,
+                              double* d_stats, double* part, int32_t nblk, hipStream_t s);
 
 }  // namespace stkde

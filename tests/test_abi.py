@@ -110,3 +110,108 @@ def test_oracle_and_library_share_no_code():
         if f.endswith((".py", ".c", ".h")):
             s = open(os.path.join(ROOT, "oracle", f)).read()
             assert "paper_1705_09366_amd" not in s and "stkde.h" not in s, f
+
+
+# ------------------------------------------------------- sets and batches (host)
+def _set(L, n=100, **kw):
+    base = dict(gx=96, gy=80, gt=48, hs=6.0, ht=4.0)
+    base.update(kw)
+    return L.BinnedSet(L.Desc(**base), n)
+
+
+def _item_status(L, s, plan_kw, ox=0, oy=0, ot=0, d_set=0x10000, count=1):
+    plan = L.Plan(L.Desc(**plan_kw))
+    arr = (L._Item * count)()
+    for k in range(count):
+        arr[k] = L._Item(plan.handle.value, s.handle.value, d_set, ox, oy, ot, 0x20000, None)
+    h = ctypes.c_void_p()
+    st = L.lib().stkde_batch_plan(arr, count, ctypes.byref(h))
+    if st == 0:
+        b = ctypes.c_size_t(0)
+        assert L.lib().stkde_batch_workspace_bytes(h, ctypes.byref(b)) == 0 and b.value > 0
+        # nothing recorded yet: replay is refused without touching the device
+        assert L.lib().stkde_batch_replay(h, None) == L.STKDE_ERR_UNSUPPORTED
+        L.lib().stkde_batch_destroy(h)
+    plan.close()
+    return st
+
+
+def test_set_plan_validation(L):
+    s = _set(L)
+    assert s.set_bytes > 100 * 32 and s.scratch_bytes > 100 * 16
+    with pytest.raises(L.StkdeError):
+        L.BinnedSet(L.Desc(gx=16, gy=16, gt=16, hs=2.0, ht=2.0), 0)
+    with pytest.raises(ValueError):
+        L.BinnedSet(L.Desc(gx=16, gy=16, gt=16, hs=2.0, ht=2.0, flags=1), 10)
+    h = ctypes.c_void_p()
+    d = L.Desc(gx=16, gy=16, gt=16, hs=2.0, ht=2.0)
+    assert L.lib().stkde_set_plan(ctypes.byref(d._c()), None, 2**31, ctypes.byref(h)) == L.STKDE_ERR_TOO_LARGE
+    # build refuses missing or small buffers before any launch
+    assert L.lib().stkde_set_build(s.handle, ctypes.c_void_p(0x1000), None, 0, None, 0, None) == \
+        L.STKDE_ERR_WORKSPACE
+    assert L.lib().stkde_set_build(s.handle, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x10000),
+                                   s.set_bytes - 1, ctypes.c_void_p(0x100000), s.scratch_bytes,
+                                   None) == L.STKDE_ERR_WORKSPACE
+    s.close()
+
+
+@pytest.mark.parametrize("plan_kw,off,expect", [
+    (dict(gx=96, gy=80, gt=48, hs=6.0, ht=4.0), (0, 0, 0), 0),
+    (dict(gx=32, gy=16, gt=16, hs=3.0, ht=2.5, x0=10.0, y0=20.0, t0=5.0), (10, 20, 5), 0),
+    (dict(gx=32, gy=16, gt=16, hs=3.0, ht=2.5, x0=10.0, y0=20.0, t0=5.0, flags=1 | 4), (10, 20, 5), 0),
+    # origin does not match the window offset
+    (dict(gx=32, gy=16, gt=16, hs=3.0, ht=2.5, x0=10.5), (10, 0, 0), -1),
+    # window leaves the base grid
+    (dict(gx=32, gy=16, gt=16, hs=3.0, ht=2.5, x0=70.0), (70, 0, 0), -1),
+    (dict(gx=32, gy=16, gt=16, hs=3.0, ht=2.5, x0=-1.0), (-1, 0, 0), -1),
+    # bandwidth above the set's
+    (dict(gx=96, gy=80, gt=48, hs=6.5, ht=4.0), (0, 0, 0), -1),
+    (dict(gx=96, gy=80, gt=48, hs=6.0, ht=4.5), (0, 0, 0), -1),
+    # another resolution
+    (dict(gx=48, gy=40, gt=48, hs=6.0, ht=4.0, sres=2.0), (0, 0, 0), -1),
+    # point statistics are computed only by stkde_compute
+    (dict(gx=96, gy=80, gt=48, hs=6.0, ht=4.0, flags=8), (0, 0, 0), -5),
+])
+def test_batch_plan_validation(L, plan_kw, off, expect):
+    s = _set(L)
+    assert _item_status(L, s, plan_kw, *off) == expect
+    s.close()
+
+
+def test_batch_plan_rejects_bad_items(L):
+    s = _set(L)
+    kw = dict(gx=96, gy=80, gt=48, hs=6.0, ht=4.0)
+    assert _item_status(L, s, kw, d_set=0x10001) == L.STKDE_ERR_INVALID_ARG  # unaligned set memory
+    assert _item_status(L, s, kw, d_set=0) == L.STKDE_ERR_INVALID_ARG
+    assert _item_status(L, s, kw, count=4096) == 0
+    assert _item_status(L, s, kw, count=4097) == L.STKDE_ERR_TOO_LARGE
+    h = ctypes.c_void_p()
+    assert L.lib().stkde_batch_plan(None, 1, ctypes.byref(h)) == L.STKDE_ERR_INVALID_ARG
+    s.close()
+
+
+def test_batch_plan_refuses_too_many_bin_rows(L):
+    # a set binned with small cells cannot serve the same bandwidth with
+    # 64-row tiles: a tile would read more bin rows than the gather holds
+    d = L.Desc(gx=512, gy=512, gt=256, hs=40.0, ht=40.0)
+    s = L.BinnedSet(d, 1000, L.Tuning(tile_t=16, cell_xy=16, cell_t=16))
+    ok = _item_status(L, s, dict(gx=512, gy=512, gt=256, hs=40.0, ht=40.0))
+    plan_kw = dict(gx=512, gy=512, gt=256, hs=40.0, ht=40.0)
+    plan = L.Plan(L.Desc(**plan_kw), L.Tuning(tile_t=64))
+    arr = (L._Item * 1)()
+    arr[0] = L._Item(plan.handle.value, s.handle.value, 0x10000, 0, 0, 0, 0x20000, None)
+    h = ctypes.c_void_p()
+    assert L.lib().stkde_batch_plan(arr, 1, ctypes.byref(h)) == L.STKDE_ERR_UNSUPPORTED
+    assert ok in (0, L.STKDE_ERR_UNSUPPORTED)
+    plan.close()
+    s.close()
+
+
+def test_profile_api_host_checks(L):
+    plan = L.Plan(L.Desc(gx=16, gy=16, gt=16, hs=2.0, ht=2.0))
+    assert L.lib().stkde_plan_profile(plan.handle, -1) == L.STKDE_ERR_INVALID_ARG
+    assert L.lib().stkde_plan_profile(plan.handle, 0) == 0
+    cnt = ctypes.c_int32(7)
+    assert L.lib().stkde_plan_profile_read(plan.handle, None, 0, ctypes.byref(cnt)) == 0
+    assert cnt.value == 0
+    plan.close()
