@@ -199,9 +199,11 @@ stkde_status make_inst_geom(const stkde_desc& d, const stkde_desc& base, int32_t
     return STKDE_OK;
 }
 
-// Default rows per tile: 16-row tiles waste fewer matrix-core rows on short
-// time windows; longer windows amortise the per-point setup over 32 rows.
-int32_t default_tile_t(double tv) { return ceil(tv) <= 12.0 ? 16 : 32; }
+// Default rows per tile (measured on gfx950): with short time windows a
+// 32-row tile halves the per-tile setup and candidate reads; with long ones
+// most points reach most rows of a tile either way, and 16-row tiles give
+// the scheduler twice as many, smaller items.
+int32_t default_tile_t(double tv) { return ceil(tv) <= 12.0 ? 32 : 16; }
 
 // (2/pi) (3/4) / (n hs^2 ht): the constants of both kernels and the
 // estimator's normalisation, rounded once to FP32 at the store.

@@ -17,14 +17,14 @@
 //
 // Scheduling.  The kernel is persistent: each workgroup takes work items --
 // a tile, or one part of a tile whose candidate sequence was split into
-// contiguous ranges -- from queues filled by the work-list stage: first the
-// heaviest-first queue (the costliest tiles, longest processing time first),
-// then the queue of its own XCD (the remaining tiles in grid order, dealt to
-// the 8 XCDs in contiguous ranges so that neighbouring tiles, which read the
-// same bins, share an L2), then the other XCDs' queues.  Every queue is a
-// counter that only grows, so every workgroup leaves after at most one
-// failed fetch per queue.  One launch serves any number of instances (grids
-// with their own bandwidths and windows over their own binned sets).
+// contiguous ranges -- first from the heaviest-first queue (the costliest
+// tiles, longest processing time first), then from the spatial queue: every
+// tile of every instance with t fastest, minus those the first queue took,
+// so that the tiles in flight at any time are neighbours that read the same
+// bins.  Both queues are counters that only grow, so every workgroup leaves
+// after one failed fetch per queue.  One launch serves any number of
+// instances (grids with their own bandwidths and windows over their own
+// binned sets).
 //
 // Per work item (256 threads, 16 x 16 x TT tile):
 //   setup   the bin rows (t, y) whose bins can hold points reaching the tile
@@ -92,8 +92,9 @@ __device__ inline void kahan_fold(f32x4 (&acc)[CG], f32x4 (&comp)[CG], f32x4 (&p
 
 template <int TT, bool KAHAN>
 __global__ __launch_bounds__(kThreads) void k_gather_items(const InstDev* __restrict__ descs,
-                                                           int32_t count,
+                                                           int32_t count, int32_t ntiles_total,
                                                            const WorkItem* __restrict__ items,
+                                                           const uint32_t* __restrict__ bits,
                                                            uint32_t* __restrict__ sc,
                                                            float* __restrict__ partials) {
     constexpr int NB = TT / 16;  // 16-row blocks per tile
@@ -131,18 +132,28 @@ __global__ __launch_bounds__(kThreads) void k_gather_items(const InstDev* __rest
     const float xc0 = (float)(4 * gqx + (lane & 3)) + 0.5f;
     const float yc0 = (float)(4 * gqy + ((lane >> 2) & 3)) + 0.5f;
     uint16_t* myL = sL[wave];
-    const int xcd = blockIdx.x & 7;
 
-    for (int qi = 0; qi < kQueues; ++qi) {
-        const int q = qi == 0 ? 0 : 1 + ((xcd + qi - 1) & 7);
-        const uint32_t qbeg = sc[kScBeg + q], qlen = sc[kScLen + q];
+    const uint32_t T = (uint32_t)ntiles_total;
+    for (int q = 0; q < 2; ++q) {
+        const uint32_t qlen = q == 0 ? sc[kScHeavyItems] : T;
         for (;;) {
-            if (tid == 0) sIdx = atomicAdd(&sc[kScNext + q], 1u);
+            if (tid == 0) sIdx = atomicAdd(&sc[q == 0 ? kScNextHeavy : kScNextSpatial], 1u);
             __syncthreads();
             const uint32_t idx = __builtin_amdgcn_readfirstlane(sIdx);
             __syncthreads();  // sIdx is rewritten by the next fetch
             if (idx >= qlen) break;
-            const WorkItem it = items[qbeg + idx];
+            WorkItem it;
+            if (q == 0) {
+                it = items[idx];
+            } else {
+                // spatial queue: every tile in spatial order, minus those the
+                // heaviest-first queue took
+                if ((bits[idx >> 5] >> (idx & 31)) & 1u) continue;
+                it.tile = spatial_tile(descs[find_inst(descs, count, idx)], idx);
+                it.cbeg = 0;
+                it.cend = kAll;
+                it.slot = kNoSlot;
+            }
             const int32_t inst = find_inst(descs, count, it.tile);
             const InstDev& D = descs[inst];
             const float inv_hv2 = D.inv_hv2, inv_tv2 = D.inv_tv2;
@@ -452,14 +463,14 @@ int resident_groups() {
 }
 
 template <int TT, bool K>
-void launch_items_t(const InstDev* d, int32_t count, const WorkItem* items, uint32_t* sc,
-                    float* partials, int64_t T, hipStream_t s) {
+void launch_items_t(const InstDev* d, int32_t count, const WorkItem* items, const uint32_t* bits,
+                    uint32_t* sc, float* partials, int64_t T, hipStream_t s) {
     int64_t g = resident_groups<TT, K>();
     const int64_t most = T + kPartSlots;  // items never exceed tiles + partial slots
     if (g > most) g = most;
     if (g < 1) g = 1;
     hipLaunchKernelGGL((k_gather_items<TT, K>), dim3((uint32_t)g), dim3(kThreads), 0, s, d, count,
-                       items, sc, partials);
+                       (int32_t)T, items, bits, sc, partials);
 }
 
 template <int TT, bool K>
@@ -472,16 +483,16 @@ void launch_reduce_t(const InstDev* d, int32_t count, const uint32_t* top, const
 }  // namespace
 
 hipError_t launch_gather_items(const InstDev* d_desc, int32_t count, const WorkItem* d_items,
-                               uint32_t* d_scalars, float* d_partials, int64_t T, int tile_t,
-                               bool kahan, hipStream_t s) {
+                               const uint32_t* d_bits, uint32_t* d_scalars, float* d_partials,
+                               int64_t T, int tile_t, bool kahan, hipStream_t s) {
     if (tile_t == 16) {
-        kahan ? launch_items_t<16, true>(d_desc, count, d_items, d_scalars, d_partials, T, s)
-              : launch_items_t<16, false>(d_desc, count, d_items, d_scalars, d_partials, T, s);
+        kahan ? launch_items_t<16, true>(d_desc, count, d_items, d_bits, d_scalars, d_partials, T, s)
+              : launch_items_t<16, false>(d_desc, count, d_items, d_bits, d_scalars, d_partials, T, s);
     } else if (tile_t == 32) {
-        kahan ? launch_items_t<32, true>(d_desc, count, d_items, d_scalars, d_partials, T, s)
-              : launch_items_t<32, false>(d_desc, count, d_items, d_scalars, d_partials, T, s);
+        kahan ? launch_items_t<32, true>(d_desc, count, d_items, d_bits, d_scalars, d_partials, T, s)
+              : launch_items_t<32, false>(d_desc, count, d_items, d_bits, d_scalars, d_partials, T, s);
     } else {
-        launch_items_t<64, false>(d_desc, count, d_items, d_scalars, d_partials, T, s);
+        launch_items_t<64, false>(d_desc, count, d_items, d_bits, d_scalars, d_partials, T, s);
     }
     return hipGetLastError();
 }

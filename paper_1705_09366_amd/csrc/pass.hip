@@ -51,13 +51,15 @@ __global__ __launch_bounds__(256) void k_tile_cost(const InstDev* __restrict__ d
                                                    uint32_t T, int32_t rows,
                                                    uint32_t* __restrict__ cost,
                                                    uint32_t* __restrict__ hist,
-                                                   unsigned long long* __restrict__ inst_cost) {
+                                                   unsigned long long* __restrict__ inst_cost,
+                                                   uint32_t* __restrict__ bits) {
     __shared__ uint32_t h[kCostClasses];
     const int tid = threadIdx.x, lane = tid & 63;
     for (int k = tid; k < kCostClasses; k += 256) h[k] = 0u;
     __syncthreads();
     const uint32_t j = blockIdx.x * 256u + (uint32_t)tid;
     const bool valid = j < T;
+    if (valid && (j & 31u) == 0) bits[j >> 5] = 0u;
     uint32_t c = 0;
     int32_t inst = 0;
     if (valid) {
@@ -116,12 +118,11 @@ __device__ inline uint32_t block_scan(uint32_t v, uint32_t* ws, uint32_t* total)
     return pre + inc - v;
 }
 
-// The work list (one workgroup of 1024 threads):
-//  1. the heaviest cost classes holding at most kTopTiles tiles form the
-//     heaviest-first queue, sorted by cost, descending (ties by tile);
-//  2. every other tile goes, in tile order, to one of 8 contiguous XCD
-//     ranges;
-//  3. a heavy tile whose cost exceeds max(kSplitFloor, its instance's total
+// The heaviest-first queue (one workgroup of 1024 threads):
+//  1. the heaviest cost classes holding at most kTopTiles tiles are taken,
+//     sorted by cost, descending (ties by tile), and flagged in the
+//     spatial queue's bitmask;
+//  2. a taken tile whose cost exceeds max(kSplitFloor, its instance's total
 //     cost / kBalanceItems) is cut into up to kMaxParts equal candidate
 //     ranges, while partial slots last (costliest first).
 __global__ __launch_bounds__(1024) void k_plan_items(const InstDev* __restrict__ descs, int32_t count,
@@ -130,16 +131,20 @@ __global__ __launch_bounds__(1024) void k_plan_items(const InstDev* __restrict__
                                                      const unsigned long long* __restrict__ inst_cost,
                                                      WorkItem* __restrict__ items,
                                                      uint32_t* __restrict__ top,
+                                                     uint32_t* __restrict__ bits,
                                                      uint32_t* __restrict__ sc, uint32_t nslots) {
     __shared__ unsigned long long keys[kTopTiles];
     __shared__ uint32_t ws[16];
-    __shared__ uint32_t s_cls;
+    __shared__ uint32_t s_cls, s_nh;
     const int tid = threadIdx.x;
     static_assert(kCostClasses == 2 * 1024, "two cost classes per thread");
 
     // ---- 1. threshold class: smallest class c >= class(1) whose suffix count
     // (tiles of class >= c) is at most kTopTiles
-    if (tid == 0) s_cls = kCostClasses;
+    if (tid == 0) {
+        s_cls = kCostClasses;
+        s_nh = 0;
+    }
     const uint32_t chi = kCostClasses - 1 - 2 * tid, clo = chi - 1;
     const uint32_t hhi = hist[chi], hlo = hist[clo];
     uint32_t tot;
@@ -150,26 +155,27 @@ __global__ __launch_bounds__(1024) void k_plan_items(const InstDev* __restrict__
     __syncthreads();
     const uint32_t cls = s_cls;
 
-    // ---- 2. partition the tiles
-    const uint32_t sbase = (uint32_t)kTopTiles * kMaxParts;
-    uint32_t nh = 0, ns = 0;
-    for (uint32_t base = 0; base < T; base += 1024) {
-        const uint32_t j = base + (uint32_t)tid;
-        uint32_t c = 0;
-        bool heavy = false, light = false;
-        if (j < T) {
-            c = cost[j];
-            heavy = cost_class(c) >= cls;
-            light = !heavy;
+    // collect the heavy tiles (in any order: they are sorted next); each
+    // thread reads a contiguous stripe, eight independent loads at a time
+    const uint32_t stripe = (T + 1023u) / 1024u;
+    const uint32_t j0 = (uint32_t)tid * stripe;
+    for (uint32_t a = 0; a < stripe; a += 8) {
+        uint32_t c[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t j = j0 + a + u;
+            c[u] = (a + u < stripe && j < T) ? cost[j] : 0u;
         }
-        uint32_t th, tl;
-        const uint32_t ph = block_scan(heavy ? 1u : 0u, ws, &th);
-        const uint32_t pl = block_scan(light ? 1u : 0u, ws, &tl);
-        if (heavy) keys[nh + ph] = ((unsigned long long)(~c) << 32) | j;
-        if (light) items[sbase + ns + pl] = WorkItem{j, 0u, kAll, kNoSlot};
-        nh += th;
-        ns += tl;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (c[u] != 0u && cost_class(c[u]) >= cls) {
+                const uint32_t pos = atomicAdd(&s_nh, 1u);
+                keys[pos] = ((unsigned long long)(~c[u]) << 32) | (j0 + a + u);
+            }
+        }
     }
+    __syncthreads();
+    const uint32_t nh = s_nh;  // <= kTopTiles by the choice of cls
     // bitonic sort of the heavy keys, ascending: cost descending, then tile
     if ((uint32_t)tid >= nh) keys[tid] = ~0ull;
     for (int k = 2; k <= kTopTiles; k <<= 1) {
@@ -188,7 +194,7 @@ __global__ __launch_bounds__(1024) void k_plan_items(const InstDev* __restrict__
     }
     __syncthreads();
 
-    // ---- 3. splitting
+    // ---- 2. splitting
     uint32_t tile = 0, c = 0, parts = 1;
     if ((uint32_t)tid < nh) {
         const unsigned long long k = keys[tid];
@@ -202,6 +208,8 @@ __global__ __launch_bounds__(1024) void k_plan_items(const InstDev* __restrict__
             const uint32_t want = (uint32_t)(((unsigned long long)c + thr - 1) / thr);
             parts = want < (uint32_t)kMaxParts ? want : (uint32_t)kMaxParts;
         }
+        const uint32_t pos = spatial_pos(descs[inst], tile);
+        atomicOr(&bits[pos >> 5], 1u << (pos & 31u));
     }
     uint32_t need = parts > 1 ? parts : 0u;
     uint32_t tot_need;
@@ -227,19 +235,12 @@ __global__ __launch_bounds__(1024) void k_plan_items(const InstDev* __restrict__
             top[4 * spos + 3] = c;
         }
     }
-
-    // ---- 4. queue bounds
-    if (tid < kQueues) sc[kScNext + tid] = 0u;
     if (tid == 0) {
-        sc[kScBeg] = 0u;
-        sc[kScLen] = nitems_h;
+        sc[kScNextHeavy] = 0u;
+        sc[kScNextSpatial] = 0u;
+        sc[kScHeavyItems] = nitems_h;
         sc[kScSplit] = nsplit;
-    }
-    if (tid < 8) {
-        const uint32_t b = (uint32_t)(((unsigned long long)ns * tid) / 8);
-        const uint32_t e = (uint32_t)(((unsigned long long)ns * (tid + 1)) / 8);
-        sc[kScBeg + 1 + tid] = sbase + b;
-        sc[kScLen + 1 + tid] = e - b;
+        sc[kScHeavyTiles] = nh;
     }
 }
 
@@ -307,9 +308,10 @@ PassLayout layout_pass(const InstGeom* inst, int32_t count, int tile_t) {
     l.inst_cost = o; o = al256(o + (size_t)count * 8);
     l.cost = o; o = al256(o + (size_t)T * 4);
     l.hist = o; o = al256(o + (size_t)kCostClasses * 4);
+    l.bits = o; o = al256(o + ((size_t)T + 31) / 32 * 4);
     l.scalars = o; o = al256(o + (size_t)kScCount * 4);
     l.top = o; o = al256(o + (size_t)kTopTiles * 16);
-    l.items = o; o = al256(o + ((size_t)kTopTiles * kMaxParts + (size_t)T) * sizeof(WorkItem));
+    l.items = o; o = al256(o + (size_t)kTopTiles * kMaxParts * sizeof(WorkItem));
     l.partials = o; o = al256(o + (size_t)kPartSlots * kTileXY * kTileXY * tile_t * 4);
     l.tile_part = o; o = al256(o + (size_t)parts * 8);
     l.mass_mid = o; o = al256(o + (size_t)count * kMassChunks * 8);
@@ -324,6 +326,7 @@ hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassL
     auto* inst_cost = reinterpret_cast<unsigned long long*>(pass + pl.inst_cost);
     auto* cost = reinterpret_cast<uint32_t*>(pass + pl.cost);
     auto* hist = reinterpret_cast<uint32_t*>(pass + pl.hist);
+    auto* bits = reinterpret_cast<uint32_t*>(pass + pl.bits);
     auto* sc = reinterpret_cast<uint32_t*>(pass + pl.scalars);
     auto* top = reinterpret_cast<uint32_t*>(pass + pl.top);
     auto* items = reinterpret_cast<WorkItem*>(pass + pl.items);
@@ -346,14 +349,14 @@ hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassL
     }
     const uint32_t T = (uint32_t)pl.T;
     hipLaunchKernelGGL(k_tile_cost, dim3((T + 255) / 256), dim3(256), 0, s, (const InstDev*)d_desc,
-                       count, T, tile_t, cost, hist, inst_cost);
+                       count, T, tile_t, cost, hist, inst_cost, bits);
     hipLaunchKernelGGL(k_plan_items, dim3(1), dim3(1024), 0, s, (const InstDev*)d_desc, count, T,
                        (const uint32_t*)cost, (const uint32_t*)hist,
-                       (const unsigned long long*)inst_cost, items, top, sc, (uint32_t)kPartSlots);
+                       (const unsigned long long*)inst_cost, items, top, bits, sc, (uint32_t)kPartSlots);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev_before && (e = hipEventRecord(ev_before, s)) != hipSuccess) return e;
-    e = launch_gather_items(d_desc, count, items, sc, partials, pl.T, tile_t, kahan, s);
+    e = launch_gather_items(d_desc, count, items, bits, sc, partials, pl.T, tile_t, kahan, s);
     if (e != hipSuccess) return e;
     if (ev_after && (e = hipEventRecord(ev_after, s)) != hipSuccess) return e;
     e = launch_reduce_split(d_desc, count, top, sc, partials, tile_t, kahan, s);

@@ -108,17 +108,17 @@ constexpr uint32_t kSplitFloor = 2048;                // never split below this 
 constexpr uint32_t kBalanceItems = 2048;              // split above 1/kBalanceItems of an instance's cost
 constexpr int kMassChunks = 64;                       // first-level chunks of an instance's mass sum
 constexpr int kDescChunk = 16;                        // descriptors written per launch
-constexpr int kQueues = 9;                            // heaviest-first queue + one per XCD
 // Cost class of a tile: the FP32 bit pattern of its candidate count without
 // the low 20 bits (exponent and 3 mantissa bits), monotone in the count.
 constexpr int kCostClasses = 2048;
 
 // Scalars of a pass (u32 offsets into PassLayout::scalars).
-constexpr int kScNext = 0;                 // [kQueues] next item of each queue
-constexpr int kScBeg = kScNext + kQueues;  // [kQueues] first item of each queue
-constexpr int kScLen = kScBeg + kQueues;   // [kQueues] items in each queue
-constexpr int kScSplit = kScLen + kQueues; // split tiles
-constexpr int kScCount = 32;
+constexpr int kScNextHeavy = 0;    // next item of the heaviest-first queue
+constexpr int kScNextSpatial = 1;  // next position of the spatial queue
+constexpr int kScHeavyItems = 2;   // items in the heaviest-first queue
+constexpr int kScSplit = 3;        // split tiles
+constexpr int kScHeavyTiles = 4;   // tiles in the heaviest-first queue
+constexpr int kScCount = 8;
 
 // ---- set memory (caller-owned, persistent) --------------------------------
 struct SetLayout {
@@ -143,9 +143,10 @@ struct PassLayout {
     size_t inst_cost;    // count u64: candidates summed over the instance's tiles
     size_t cost;         // T u32: candidates per tile
     size_t hist;         // kCostClasses u32: tiles per cost class
+    size_t bits;         // ceil(T / 32) u32: spatial-queue positions taken by the heavy queue
     size_t scalars;      // kScCount u32
     size_t top;          // kTopTiles x 4 u32 split tiles: tile, parts, slot0, candidates
-    size_t items;        // kTopTiles * kMaxParts + T WorkItem
+    size_t items;        // kTopTiles * kMaxParts WorkItem (the heaviest-first queue)
     size_t partials;     // kPartSlots x 16 x 16 x tile_t FP32
     size_t tile_part;    // sum over instances of ntiles * kWaves FP64
     size_t mass_mid;     // count * kMassChunks FP64
@@ -194,6 +195,25 @@ __device__ inline TileBins tile_bins(const InstDev& D, int32_t bx0, int32_t by0,
     return b;
 }
 
+// The spatial queue visits an instance's tiles with t fastest, then y, then
+// x (consecutive tiles share bins and write neighbouring runs of each
+// column); global tile index = tile_base + (tt * nty + ty) * ntx + tx.
+__device__ inline uint32_t spatial_tile(const InstDev& D, uint32_t k) {
+    const uint32_t local = k - (uint32_t)D.tile_base;
+    const uint32_t ntt = (uint32_t)D.ntiles / ((uint32_t)D.ntx * (uint32_t)D.nty);
+    const uint32_t tt = local % ntt, r = local / ntt;
+    const uint32_t ty = r % (uint32_t)D.nty, tx = r / (uint32_t)D.nty;
+    return (uint32_t)D.tile_base + (tt * (uint32_t)D.nty + ty) * (uint32_t)D.ntx + tx;
+}
+// Inverse of spatial_tile: the queue position of global tile j.
+__device__ inline uint32_t spatial_pos(const InstDev& D, uint32_t j) {
+    const uint32_t local = j - (uint32_t)D.tile_base;
+    const uint32_t ntt = (uint32_t)D.ntiles / ((uint32_t)D.ntx * (uint32_t)D.nty);
+    const uint32_t tx = local % (uint32_t)D.ntx, r = local / (uint32_t)D.ntx;
+    const uint32_t ty = r % (uint32_t)D.nty, tt = r / (uint32_t)D.nty;
+    return (uint32_t)D.tile_base + (tx * (uint32_t)D.nty + ty) * ntt + tt;
+}
+
 // ---- launchers (asynchronous on s; return the launch error) ---------------
 // Bin n points into set memory `set` using radix scratch `sort`.
 hipError_t launch_bin(const SetGeom& g, const double* d_xyt, int32_t n, uint8_t* set,
@@ -208,8 +228,8 @@ hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassL
                        hipEvent_t ev_after = nullptr);
 // The gather proper (called by launch_pass).
 hipError_t launch_gather_items(const InstDev* d_desc, int32_t count, const WorkItem* d_items,
-                               uint32_t* d_scalars, float* d_partials, int64_t T, int tile_t,
-                               bool kahan, hipStream_t s);
+                               const uint32_t* d_bits, uint32_t* d_scalars, float* d_partials,
+                               int64_t T, int tile_t, bool kahan, hipStream_t s);
 // Query (and cache) the gather's launch size for the current device ahead of a
 // stream capture.
 void prepare_gather(int tile_t, bool kahan);
