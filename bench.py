@@ -103,6 +103,180 @@ def cpu_baseline(inst, gpu_plan_fn, budget_s=20.0):
             "sample": sample, "seconds": round(dt, 3), "evals": int(evals)}, err
 
 
+def _median(v):
+    v = sorted(v)
+    return v[len(v) // 2]
+
+
+def bench_batch(args, dev):
+    """Bandwidth sweep (8 point sets x 8 bandwidth pairs = 64 grids).
+    Baseline: 64 stkde_compute calls in sequence on one stream, each binning
+    its own points.  Candidate: the 8 sets binned once each, then one batch
+    (one work list, one gather launch per tile group) replayed from a HIP
+    graph.  Both steps are timed with events around the whole sequence."""
+    import numpy as np
+    import torch
+    import workloads
+    import paper_1705_09366_amd as m
+    from paper_1705_09366_amd import autotune
+    insts = workloads.config3_sets()
+    kahan = not args.plain
+    flags = m.FLAG_KAHAN if kahan else 0
+    by_set = {}
+    for it in insts:
+        by_set.setdefault(it.meta["set"], []).append(it)
+    pts = {k: torch.from_numpy(v[0].points).to(dev) for k, v in by_set.items()}
+    outs_a = [torch.empty((i.gx, i.gy, i.gt), dtype=torch.float32, device=dev) for i in insts]
+    outs_b = [torch.empty_like(o) for o in outs_a]
+    descs = [m.Desc(gx=i.gx, gy=i.gy, gt=i.gt, hs=i.hs, ht=i.ht, flags=flags) for i in insts]
+    n_of = [i.points.shape[0] for i in insts]
+    plans = [m.Plan(d, autotune.lookup(d, n) if args.tuning == "auto" else None)
+             for d, n in zip(descs, n_of)]
+    ws_bytes = max(p.workspace_bytes(n) for p, n in zip(plans, n_of))
+    ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
+    # exact evaluation counts, once
+    evals = 0
+    st = torch.zeros(8, dtype=torch.float64, device=dev)
+    for i, d, o in zip(insts, descs, outs_a):
+        c = m.Plan(m.Desc(**{**d.__dict__, "flags": m.FLAG_POINT_STATS}))
+        c.compute_into(pts[i.meta["set"]], o, stats=st, workspace=ws)
+        torch.cuda.synchronize()
+        evals += int(st[2].item())
+        c.close()
+    _log(f"batch workload: {len(insts)} grids over {len(by_set)} sets, {evals} evals")
+
+    def baseline():
+        for i, p, o in zip(insts, plans, outs_a):
+            p.compute_into(pts[i.meta["set"]], o, workspace=ws)
+
+    # candidate: sets binned for the largest bandwidths of their instances
+    sets, items = {}, []
+    rows = {}
+    for i, p in zip(insts, plans):
+        tt = p.tuning.tile_t if (p.tuning and p.tuning.tile_t) else 32
+        rows[i.meta["set"]] = max(rows.get(i.meta["set"], 16), tt)
+    for k, lst in by_set.items():
+        i0 = lst[0]
+        base = m.Desc(gx=i0.gx, gy=i0.gy, gt=i0.gt, hs=max(i.hs for i in lst), ht=max(i.ht for i in lst))
+        sets[k] = m.BinnedSet(base, i0.points.shape[0], m.Tuning(tile_t=rows[k]))
+    scratch = torch.empty(max(s.scratch_bytes for s in sets.values()) + 256, dtype=torch.uint8, device=dev)
+    for k, s in sets.items():
+        s.build(pts[k], scratch=scratch)
+    for i, p, o in zip(insts, plans, outs_b):
+        items.append(m.Item(plan=p, set=sets[i.meta["set"]], out=o))
+    batch = m.Batch(items)
+    batch.capture()
+
+    def candidate():
+        for k, s in sets.items():
+            s.build(pts[k], scratch=scratch)
+        batch.replay()
+
+    res = {}
+    for name, fn in (("sequential", baseline), ("batched", candidate)):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(args.steps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        res[name] = _median(ts)
+        _log(f"{name}: median {res[name]:.3f} ms over {args.steps}")
+    torch.cuda.synchronize()
+    diff = 0.0
+    for oa, ob in zip(outs_a, outs_b):
+        sc = float(oa.abs().max())
+        if sc > 0:
+            diff = max(diff, float((oa - ob).abs().max()) / sc)
+    rec = {"metric": "bandwidth-sweep makespan", "value": res["batched"], "unit": "ms",
+           "higher_is_better": False, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "sweep-8sets-x8bw", "grids": len(insts), "evals": evals,
+                      "accumulation": "kahan" if kahan else "plain", "tuning": args.tuning},
+           "sequential_ms": res["sequential"], "batched_ms": res["batched"],
+           "speedup": res["sequential"] / res["batched"],
+           "evals_per_s": {"sequential": evals / (res["sequential"] * 1e-3),
+                           "batched": evals / (res["batched"] * 1e-3)},
+           "max_rel_diff_batched_vs_sequential": diff}
+    print(json.dumps(rec), flush=True)
+
+
+def bench_serve(args, dev):
+    """Serving: 4 resident sets (100k..2M points over a 2048 x 2048 x 512
+    domain), requests for windows of 64..1024 x 64..1024 x 64..128 voxels
+    at hs, ht in [3, 40].  First the saturation rate of the batching server
+    (all requests at once); then Poisson arrivals at 0.25..0.9 of it, for
+    the batching server and for one-request-at-a-time launches."""
+    import numpy as np
+    import torch
+    import workloads
+    import paper_1705_09366_amd as m
+    from paper_1705_09366_amd.serve import GpuExecutor, Request, Server
+    sets = workloads.config4_sets()
+    ex = GpuExecutor(device=dev)
+    names = []
+    for k, inst in enumerate(sets):
+        base = m.Desc(gx=inst.gx, gy=inst.gy, gt=inst.gt, hs=40.0, ht=40.0)
+        ex.add_set(f"s{k}", torch.from_numpy(inst.points).to(dev), base, m.Tuning(tile_t=16))
+        names.append(f"s{k}")
+    resident = sum(s.set_bytes for s in ex.sets.values())
+    nreq = args.requests
+    raw = workloads.config4_requests(nreq + 100)
+
+    def mk(r):
+        return Request(set=names[r["set"]], gx=r["gx"], gy=r["gy"], gt=r["gt"], ox=int(r["x0"]),
+                       oy=int(r["y0"]), ot=int(r["t0"]), hs=r["hs"], ht=r["ht"])
+    reqs = [mk(r) for r in raw]
+    warm, reqs = reqs[:100], reqs[100:]
+
+    def serve(requests, rate, batching):
+        srv = Server(executor=ex, max_batch=256 if batching else 1, max_inflight=2 if batching else 1)
+        srv.resident = resident
+        rng = np.random.default_rng(170509366 + int(rate * 1000))
+        t0 = time.perf_counter()
+        arr = t0 + (np.cumsum(rng.exponential(1.0 / rate, len(requests))) if rate else np.zeros(len(requests)))
+        i = 0
+        vox = 0
+        while i < len(requests) or not srv.idle():
+            now = time.perf_counter()
+            while i < len(requests) and arr[i] <= now:
+                srv.submit(requests[i], t_arrival=float(arr[i]))
+                i += 1
+            srv.poll()
+            for tk in srv.finished:
+                if tk.out is not None:
+                    vox += tk.out.numel()
+                    tk.out = None
+        dt = time.perf_counter() - t0
+        st = srv.latency_stats()
+        st.update({"requests_per_s": len(requests) / dt, "voxels_per_s": vox / dt, "seconds": dt})
+        return st
+
+    serve(warm, 0, True)
+    sat = serve(reqs, 0, True)
+    rate_sat = sat["requests_per_s"]
+    _log(f"saturation: {rate_sat:.1f} req/s ({sat['ticks']} ticks)")
+    levels = []
+    for frac in (0.25, 0.5, 0.75, 0.9):
+        lam = frac * rate_sat
+        b = serve(reqs, lam, True)
+        f = serve(reqs, lam, False)
+        _log(f"load {frac:.2f} ({lam:.1f} req/s): batched p50 {b['p50_ms']:.2f} p99 {b['p99_ms']:.2f} ms; "
+             f"one-at-a-time p50 {f['p50_ms']:.2f} p99 {f['p99_ms']:.2f} ms")
+        levels.append({"load": frac, "rate": lam, "batched": b, "one_at_a_time": f})
+    rec = {"metric": "serve saturation rate", "value": rate_sat, "unit": "requests/s",
+           "higher_is_better": True, "n_gpus": 1, "data": "synthetic", "dtype": "f32",
+           "config": {"workload": "serve-4sets-2048x2048x512", "requests": nreq,
+                      "resident_bytes": resident},
+           "saturation": sat, "levels": levels}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +289,13 @@ def main():
     ap.add_argument("--tile-t", type=int, default=0, help="tuning: time rows per tile (16/32)")
     ap.add_argument("--cell-xy", type=int, default=0, help="tuning: bin edge in x, y")
     ap.add_argument("--cell-t", type=int, default=0, help="tuning: bin edge in t")
+    ap.add_argument("--tuning", default="auto", choices=("auto", "default"),
+                    help="auto: the autotune cache's pinned tuning for the workload (when it has "
+                         "one); default: the library defaults (explicit --tile-t etc. override both)")
+    ap.add_argument("--mode", default="compute", choices=("compute", "batch", "serve"),
+                    help="compute: the headline step; batch: the bandwidth-sweep batch against "
+                         "sequential computes; serve: request latency under Poisson load")
+    ap.add_argument("--requests", type=int, default=400, help="serve mode: requests per load level")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
@@ -135,6 +316,10 @@ def main():
     m.lib()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.mode == "batch":
+        return bench_batch(args, dev)
+    if args.mode == "serve":
+        return bench_serve(args, dev)
 
     if args.calibrate_copy:
         # a plain copy kernel of known size: 1 GiB read + 1 GiB written per launch
@@ -153,8 +338,14 @@ def main():
     flags = m.FLAG_MASS | (m.FLAG_KAHAN if kahan else 0)
     desc = m.Desc(gx=inst.gx, gy=inst.gy, gt=inst.gt, hs=inst.hs, ht=inst.ht, sres=inst.sres,
                   tres=inst.tres, x0=inst.x0, y0=inst.y0, t0=inst.t0, flags=flags)
-    tuning = m.Tuning(args.tile_t, args.cell_xy, args.cell_t) \
-        if (args.tile_t or args.cell_xy or args.cell_t) else None
+    if args.tile_t or args.cell_xy or args.cell_t:
+        tuning, tuning_src = m.Tuning(args.tile_t, args.cell_xy, args.cell_t), "manual"
+    elif args.tuning == "auto":
+        from paper_1705_09366_amd import autotune
+        tuning = autotune.lookup(desc, n)
+        tuning_src = f"autotune {autotune.key(desc, n)}" if tuning else "default (no cache entry)"
+    else:
+        tuning, tuning_src = None, "default"
     plan = m.Plan(desc, tuning)
     pts = torch.from_numpy(inst.points).to(dev)
     out = torch.empty((inst.gx, inst.gy, inst.gt), dtype=torch.float32, device=dev)
@@ -241,7 +432,9 @@ def main():
         "config": {"workload": inst.name, "n": n, "grid": [inst.gx, inst.gy, inst.gt],
                    "hs": inst.hs, "ht": inst.ht, "accumulation": "kahan" if kahan else "plain",
                    "evals": evals,
-                   "tuning": [args.tile_t, args.cell_xy, args.cell_t] if tuning else "default"},
+                   "tuning": ([tuning.tile_t, tuning.cell_xy, tuning.cell_t, tuning.split_share]
+                              if tuning else [0, 0, 0, 0]),
+                   "tuning_source": tuning_src},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "stage_ms": {"bin": bin_ms, "pass": pass_ms, "gather_kernel": gather_ms},

@@ -56,7 +56,7 @@ class _Desc(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("tile_t", ctypes.c_int32), ("cell_xy", ctypes.c_int32),
-                ("cell_t", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("cell_t", ctypes.c_int32), ("split_share", ctypes.c_int32)]
 
 
 class _Item(ctypes.Structure):
@@ -142,12 +142,15 @@ class Desc:
 
 @dataclass(frozen=True)
 class Tuning:
+    """Tuning of one plan (0 = library default): time rows per tile, bin
+    edges, and the split share of the work list."""
     tile_t: int = 0
     cell_xy: int = 0
     cell_t: int = 0
+    split_share: int = 0
 
     def _c(self):
-        return _Tuning(self.tile_t, self.cell_xy, self.cell_t, 0)
+        return _Tuning(self.tile_t, self.cell_xy, self.cell_t, self.split_share)
 
 
 class Plan:
@@ -387,9 +390,10 @@ class Item:
 class Batch:
     """Many grids in one work list and one persistent gather launch per
     (tile_t, Kahan) group (``stkde_batch_*``); optionally recorded once as a
-    HIP graph and replayed."""
+    HIP graph and replayed.  ``allocate=False`` plans (and validates) only;
+    :meth:`allocate` then provides the workspace."""
 
-    def __init__(self, items):
+    def __init__(self, items, allocate: bool = True):
         import torch
         self.items = list(items)
         arr = (_Item * len(self.items))()
@@ -414,8 +418,15 @@ class Batch:
         if st != STKDE_OK:
             raise StkdeError(st, "stkde_batch_workspace_bytes")
         self.workspace_bytes = int(b.value)
-        dev = self.items[0].out.device
+        self.ws = None
+        if allocate:
+            self.allocate(self.items[0].out.device)
+
+    def allocate(self, device=None):
+        import torch
+        dev = device if device is not None else self.items[0].out.device
         self.ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=dev)
+        return self
 
     def run(self, stream=None):
         p, nb = _aligned(self.ws)

@@ -18,6 +18,7 @@
 
 struct stkde_plan_s {
     stkde_desc desc;
+    uint32_t split_share;
     stkde::InstGeom ig;  // the plan's grid as an instance of its own set
     stkde::SetGeom sg;   // binning of the plan's own points
     // gather timing (stkde_plan_profile): event pairs, filled in order
@@ -89,7 +90,8 @@ stkde_status check_tuning(const stkde_tuning* t) {
         return STKDE_ERR_INVALID_ARG;
     if (t->cell_xy != 0 && (t->cell_xy < 4 || t->cell_xy > 256)) return STKDE_ERR_INVALID_ARG;
     if (t->cell_t != 0 && (t->cell_t < 4 || t->cell_t > 256)) return STKDE_ERR_INVALID_ARG;
-    if (t->reserved != 0) return STKDE_ERR_INVALID_ARG;
+    if (t->split_share != 0 && (t->split_share < 64 || t->split_share > 65536))
+        return STKDE_ERR_INVALID_ARG;
     return STKDE_OK;
 }
 
@@ -213,7 +215,7 @@ float norm_const(double hs, double ht, int64_t n) {
 
 stkde::InstDev make_dev(const stkde::InstGeom& ig, const stkde::SetGeom& sg, const uint8_t* set_mem,
                         const stkde::SetLayout& sl, int64_t n_norm, int32_t ox, int32_t oy,
-                        int32_t ot, float* out, double* stats, bool mass) {
+                        int32_t ot, float* out, double* stats, bool mass, uint32_t split_share) {
     stkde::InstDev d{};
     d.cell_start = reinterpret_cast<const uint32_t*>(set_mem + sl.cell_start);
     d.recs = reinterpret_cast<const stkde::PointRec*>(set_mem + sl.recs);
@@ -243,6 +245,7 @@ stkde::InstDev make_dev(const stkde::InstGeom& ig, const stkde::SetGeom& sg, con
     d.inv_hv2 = ig.inv_hv2;
     d.inv_tv2 = ig.inv_tv2;
     d.cnorm = norm_const(ig.hs, ig.ht, n_norm);
+    d.split_share = split_share;
     return d;
 }
 
@@ -323,6 +326,7 @@ stkde_status stkde_plan(const stkde_desc* d, const stkde_tuning* tun, stkde_plan
     if ((d->flags & STKDE_FLAG_KAHAN) && tile_t > 32) tile_t = 32;
     stkde_plan_s tmp;
     tmp.desc = *d;
+    tmp.split_share = tun && tun->split_share ? (uint32_t)tun->split_share : stkde::kBalanceItems;
     make_set_geom(*d, tun ? tun->cell_xy : 0, tun ? tun->cell_t : 0, tile_t, &tmp.sg);
     st = make_inst_geom(*d, *d, tile_t, &tmp.ig);
     if (st != STKDE_OK) return st;
@@ -393,7 +397,7 @@ stkde_status stkde_accumulate(stkde_plan_t p, int64_t n, float* d_out, void* d_w
     if (st != STKDE_OK) return st;
     const uint32_t fl = p->desc.flags;
     stkde::InstDev d = make_dev(p->ig, p->sg, c.ws, c.L.sl, n, 0, 0, 0, d_out, d_stats,
-                                (fl & STKDE_FLAG_MASS) != 0);
+                                (fl & STKDE_FLAG_MASS) != 0, p->split_share);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (p->ev_used + 2 <= (int32_t)p->ev.size()) {
         e0 = p->ev[(size_t)p->ev_used];
@@ -550,7 +554,8 @@ stkde_status batch_enqueue(stkde_batch_t b, uint8_t* ws, hipStream_t s) {
             devs.push_back(make_dev(g.geo[k], it.set->sg, reinterpret_cast<const uint8_t*>(it.d_set),
                                     it.set->sl, it.set->n, (int32_t)it.ox, (int32_t)it.oy,
                                     (int32_t)it.ot, it.d_out, it.d_stats,
-                                    (it.plan->desc.flags & STKDE_FLAG_MASS) != 0));
+                                    (it.plan->desc.flags & STKDE_FLAG_MASS) != 0,
+                                    it.plan->split_share));
         }
         if (stkde::launch_pass(devs.data(), (int32_t)devs.size(), ws, g.pl, g.tile_t, g.kahan, s) !=
             hipSuccess)

@@ -123,7 +123,7 @@ __device__ inline uint32_t block_scan(uint32_t v, uint32_t* ws, uint32_t* total)
 //     sorted by cost, descending (ties by tile), and flagged in the
 //     spatial queue's bitmask;
 //  2. a taken tile whose cost exceeds max(kSplitFloor, its instance's total
-//     cost / kBalanceItems) is cut into up to kMaxParts equal candidate
+//     cost / its split share) is cut into up to kMaxParts equal candidate
 //     ranges, while partial slots last (costliest first).
 __global__ __launch_bounds__(1024) void k_plan_items(const InstDev* __restrict__ descs, int32_t count,
                                                      uint32_t T, const uint32_t* __restrict__ cost,
@@ -201,7 +201,8 @@ __global__ __launch_bounds__(1024) void k_plan_items(const InstDev* __restrict__
         tile = (uint32_t)k;
         c = ~(uint32_t)(k >> 32);
         const int32_t inst = find_inst(descs, count, tile);
-        const unsigned long long share = (inst_cost[inst] + kBalanceItems - 1) / kBalanceItems;
+        const unsigned long long ss = descs[inst].split_share;
+        const unsigned long long share = (inst_cost[inst] + ss - 1) / ss;
         const uint32_t thr = share > kSplitFloor ? (share > 0xffffffffull ? 0xffffffffu : (uint32_t)share)
                                                  : kSplitFloor;
         if (c > thr) {

@@ -85,6 +85,7 @@ struct alignas(16) InstDev {
     int32_t ntx, nty, ntiles, tile_base; // instance tiles; first global tile index
     uint32_t flags;                      // kInstMass
     float inv_hv2, inv_tv2, cnorm;
+    uint32_t split_share;                // split tiles above total cost / split_share
 };
 constexpr uint32_t kInstMass = 1u;
 
@@ -105,7 +106,7 @@ constexpr int kTopTiles = 1024;                       // most tiles in the heavi
 constexpr int kMaxParts = 8;                          // parts of one split tile
 constexpr int kPartSlots = 1024;                      // partial tiles of one pass
 constexpr uint32_t kSplitFloor = 2048;                // never split below this many candidates
-constexpr uint32_t kBalanceItems = 2048;              // split above 1/kBalanceItems of an instance's cost
+constexpr uint32_t kBalanceItems = 2048;              // default split share of an instance's cost
 constexpr int kMassChunks = 64;                       // first-level chunks of an instance's mass sum
 constexpr int kDescChunk = 16;                        // descriptors written per launch
 // Cost class of a tile: the FP32 bit pattern of its candidate count without

@@ -1,0 +1,51 @@
+"""Autotune cache keys and lookups (host only)."""
+import json
+
+from paper_1705_09366_amd import Desc, FLAG_KAHAN, Tuning, autotune
+
+
+def test_buckets_and_density_classes():
+    assert [autotune._bucket(v) for v in (0.3, 1, 1.5, 2, 3, 4, 5, 8, 9, 50)] == [0, 0, 1, 1, 2, 2, 3, 3, 4, 6]
+    d = Desc(gx=1024, gy=1024, gt=256, hs=10.0, ht=7.0)
+    # 1e6 points covering pi 10^2 * 14 voxels each over 2^28 voxels: about 16 per voxel
+    assert 15 < autotune.density(d, 1_000_000) < 18
+    assert autotune.density_class(d, 1_000_000) == 2
+    assert autotune.key(d, 1_000_000) == "gfx950/hs4/ht3/d2/g14/plain"
+    dk = Desc(**{**d.__dict__, "flags": FLAG_KAHAN})
+    assert autotune.key(dk, 1_000_000).endswith("/kahan")
+    # domain units: the buckets use hs/sres, ht/tres
+    d2 = Desc(gx=512, gy=512, gt=128, hs=20.0, ht=14.0, sres=2.0, tres=2.0)
+    assert autotune.key(d2, 1_000_000).startswith("gfx950/hs4/ht3/")
+    assert autotune.grid_class(Desc(gx=256, gy=256, gt=64, hs=1.0, ht=1.0)) == 11
+
+
+def test_lookup_prefers_explicit_cache_and_caps_kahan(tmp_path):
+    d = Desc(gx=256, gy=256, gt=64, hs=5.0, ht=4.0)
+    k_plain = autotune.key(d, 20_000)
+    dk = Desc(**{**d.__dict__, "flags": FLAG_KAHAN})
+    k_kahan = autotune.key(dk, 20_000)
+    path = tmp_path / "c.json"
+    path.write_text(json.dumps({"version": 1, "arch": "gfx950", "entries": {
+        k_plain: {"tuning": [64, 16, 8, 512]}, k_kahan: {"tuning": [64, 0, 0, 0]}}}))
+    assert autotune.lookup(d, 20_000, str(path)) == Tuning(64, 16, 8, 512)
+    assert autotune.lookup(dk, 20_000, str(path)) == Tuning(32, 0, 0, 0)
+    other = tmp_path / "other.json"
+    other.write_text(json.dumps({"version": 1, "arch": "gfx942", "entries": {
+        k_plain: {"tuning": [16, 0, 0, 0]}}}))
+    # another architecture's cache is ignored
+    assert autotune.lookup(d, 20_000, str(other)) == autotune.lookup(d, 20_000, None)
+
+
+def test_shipped_cache_is_well_formed():
+    import os
+    if not os.path.exists(autotune.SHIPPED_CACHE):
+        return
+    data = json.load(open(autotune.SHIPPED_CACHE))
+    assert data["version"] == autotune.CACHE_VERSION and data["arch"] == autotune.ARCH
+    for k, e in data["entries"].items():
+        assert k.startswith("gfx950/hs")
+        tt, cxy, ct, ss = e["tuning"]
+        assert tt in (16, 32, 64) and (cxy == 0 or 4 <= cxy <= 256) and (ct == 0 or 4 <= ct <= 256)
+        assert ss == 0 or 64 <= ss <= 65536
+        if k.endswith("/kahan"):
+            assert tt <= 32
