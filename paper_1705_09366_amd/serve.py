@@ -10,9 +10,10 @@ set's n, so a window is a cut-out of the full grid).
 Scheduling is continuous batching: each tick packs every admitted waiting
 request into one ``Batch`` (one work list, one persistent gather launch per
 tile group, the requests' tiles scheduled together costliest first) and
-enqueues it on the server's stream; while at most ``max_inflight`` ticks run
-on the device, the next tick collects whatever arrived meanwhile, so batches
-grow with the load.  Admission is first come, first served, against a byte
+enqueues it on the next of the executor's streams, so that a new tick's
+work starts while the previous one drains; while ``max_inflight`` ticks are
+on the device, the next tick collects whatever arrived meanwhile, so
+batches grow with the load.  Admission is first come, first served, against a byte
 budget: the outputs of admitted, unfinished requests plus the ticks'
 workspaces must fit in the device memory left after the resident sets and
 a reserve.  A request completes when its tick's completion event has been
@@ -69,13 +70,16 @@ class Ticket:
 
 
 class GpuExecutor:
-    """Runs ticks as Batch launches on one stream; completion by events."""
+    """Runs ticks as Batch launches on round-robin streams; completion by events."""
 
-    def __init__(self, device=None, tuning_cache: Optional[str] = None):
+    def __init__(self, device=None, tuning_cache: Optional[str] = None, streams: int = 2):
         import torch
         self.torch = torch
         self.device = torch.device(device if device is not None else "cuda")
-        self.stream = torch.cuda.Stream(device=self.device)
+        # default priority on every stream
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(max(1, streams))]
+        self.stream = self.streams[0]
+        self._next_stream = 0
         self.tuning_cache = tuning_cache
         self.sets: Dict[str, BinnedSet] = {}
         self.base: Dict[str, Desc] = {}
@@ -109,7 +113,7 @@ class GpuExecutor:
         torch = self.torch
         s = self.sets[tk.req.set]
         plan = self._plan(tk.req)
-        with torch.cuda.stream(self.stream):
+        with torch.cuda.stream(self.streams[self._next_stream]):
             out = torch.empty((tk.req.gx, tk.req.gy, tk.req.gt), dtype=torch.float32, device=self.device)
             stats = torch.empty(8, dtype=torch.float64, device=self.device) \
                 if tk.req.flags & FLAG_MASS else None
@@ -127,13 +131,17 @@ class GpuExecutor:
         return item
 
     def launch(self, items: List[Item]):
+        """Enqueue one tick on the next stream (its outputs were allocated on
+        that stream by prepare)."""
         torch = self.torch
+        st = self.streams[self._next_stream]
+        self._next_stream = (self._next_stream + 1) % len(self.streams)
         b = Batch(items, allocate=False)
-        with torch.cuda.stream(self.stream):
+        with torch.cuda.stream(st):
             b.allocate(self.device)
-            b.run(stream=self.stream)
+            b.run(stream=st)
             ev = torch.cuda.Event()
-            ev.record(self.stream)
+            ev.record(st)
         return (b, ev, b.workspace_bytes)
 
     def workspace_bytes(self, token) -> int:
