@@ -21,8 +21,8 @@
 // tiles, longest processing time first), then from the spatial queue: every
 // tile of every instance with t fastest, minus those the first queue took,
 // so that the tiles in flight at any time are neighbours that read the same
-// bins.  Both queues are counters that only grow, so every workgroup leaves
-// after one failed fetch per queue.  One launch serves any number of
+// bins.  Each queue is served by interleaved counters that only grow, so
+// every workgroup leaves after one failed fetch per counter.  One launch serves any number of
 // instances (grids with their own bandwidths and windows over their own
 // binned sets).
 //
@@ -64,7 +64,7 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kCap = 1024;  // survivors held in LDS between matrix-core phases
+constexpr int kCap = 768;  // survivors held in LDS between matrix-core phases
 constexpr int kMaxDevices = 64;
 
 __device__ inline float half_lo(uint32_t v) {
@@ -90,12 +90,18 @@ __device__ inline void kahan_fold(f32x4 (&acc)[CG], f32x4 (&comp)[CG], f32x4 (&p
     }
 }
 
+// At most 128 VGPRs, so that four workgroups fit on a compute unit also with
+// the three accumulator sets of compensated 32-row tiles (a few registers
+// spill outside the matrix-core loop; measured 4-7 % faster than three
+// workgroups).  With 768 survivors the LDS holds five workgroups where the
+// registers allow it.
 template <int TT, bool KAHAN>
-__global__ __launch_bounds__(kThreads) void k_gather_items(const InstDev* __restrict__ descs,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_gather_items(const InstDev* __restrict__ descs,
                                                            int32_t count, int32_t ntiles_total,
                                                            const WorkItem* __restrict__ items,
                                                            const uint32_t* __restrict__ bits,
-                                                           uint32_t* __restrict__ sc,
+                                                           const uint32_t* __restrict__ sc,
+                                                           uint32_t* __restrict__ ctr,
                                                            float* __restrict__ partials) {
     constexpr int NB = TT / 16;  // 16-row blocks per tile
     constexpr int CG = 4 * NB;   // accumulator blocks per wave
@@ -134,248 +140,259 @@ __global__ __launch_bounds__(kThreads) void k_gather_items(const InstDev* __rest
     uint16_t* myL = sL[wave];
 
     const uint32_t T = (uint32_t)ntiles_total;
+    const uint32_t home = blockIdx.x % kFetchLanes;
     for (int q = 0; q < 2; ++q) {
         const uint32_t qlen = q == 0 ? sc[kScHeavyItems] : T;
-        for (;;) {
-            if (tid == 0) sIdx = atomicAdd(&sc[q == 0 ? kScNextHeavy : kScNextSpatial], 1u);
-            __syncthreads();
-            const uint32_t idx = __builtin_amdgcn_readfirstlane(sIdx);
-            __syncthreads();  // sIdx is rewritten by the next fetch
-            if (idx >= qlen) break;
-            WorkItem it;
-            if (q == 0) {
-                it = items[idx];
-            } else {
-                // spatial queue: every tile in spatial order, minus those the
-                // heaviest-first queue took
-                if ((bits[idx >> 5] >> (idx & 31)) & 1u) continue;
-                it.tile = spatial_tile(descs[find_inst(descs, count, idx)], idx);
-                it.cbeg = 0;
-                it.cend = kAll;
-                it.slot = kNoSlot;
-            }
-            const int32_t inst = find_inst(descs, count, it.tile);
-            const InstDev& D = descs[inst];
-            const float inv_hv2 = D.inv_hv2, inv_tv2 = D.inv_tv2;
+        for (uint32_t lane_off = 0; lane_off < (uint32_t)kFetchLanes; ++lane_off) {
+            const uint32_t k = (home + lane_off) % kFetchLanes;
+            uint32_t* c = ctr + (q * kFetchLanes + k) * kCtrStride;
+            for (;;) {
+                if (tid == 0) {
+                    // a counter only grows: when even a stale value shows it
+                    // exhausted it is, and the atomic can be skipped
+                    const uint32_t seen = __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    sIdx = (k + kFetchLanes * seen >= qlen) ? 0xffffffffu
+                                                            : k + kFetchLanes * atomicAdd(c, 1u);
+                }
+                __syncthreads();
+                const uint32_t idx = __builtin_amdgcn_readfirstlane(sIdx);
+                __syncthreads();  // sIdx is rewritten by the next fetch
+                if (idx >= qlen) break;
+                WorkItem it;
+                if (q == 0) {
+                    it = items[idx];
+                } else {
+                    // spatial queue: every tile in spatial order, minus those the
+                    // heaviest-first queue took
+                    if ((bits[idx >> 5] >> (idx & 31)) & 1u) continue;
+                    it.tile = spatial_tile(descs[find_inst(descs, count, idx)], idx);
+                    it.cbeg = 0;
+                    it.cend = kAll;
+                    it.slot = kNoSlot;
+                }
+                const int32_t inst = find_inst(descs, count, it.tile);
+                const InstDev& D = descs[inst];
+                const float inv_hv2 = D.inv_hv2, inv_tv2 = D.inv_tv2;
 
-            const int32_t tile = (int32_t)(it.tile - (uint32_t)D.tile_base);
-            const int32_t tx = tile % D.ntx;
-            const int32_t rest = tile / D.ntx;
-            const int32_t ty = rest % D.nty;
-            const int32_t tt = rest / D.nty;
-            // tile origin in the instance grid and in the set's base grid
-            const int32_t X0 = tx * kTileXY, Y0 = ty * kTileXY, T0 = tt * TT;
-            const int32_t BX0 = X0 + D.ox, BY0 = Y0 + D.oy, BT0 = T0 + D.ot;
+                const int32_t tile = (int32_t)(it.tile - (uint32_t)D.tile_base);
+                const int32_t tx = tile % D.ntx;
+                const int32_t rest = tile / D.ntx;
+                const int32_t ty = rest % D.nty;
+                const int32_t tt = rest / D.nty;
+                // tile origin in the instance grid and in the set's base grid
+                const int32_t X0 = tx * kTileXY, Y0 = ty * kTileXY, T0 = tt * TT;
+                const int32_t BX0 = X0 + D.ox, BY0 = Y0 + D.oy, BT0 = T0 + D.ot;
 
-            // ---- setup: candidate ranges (one per bin row (t, y)) -----------
-            const TileBins tb = tile_bins(D, BX0, BY0, BT0, TT);
-            const int32_t nyr = tb.cy1 - tb.cy0 + 1;
-            const int32_t nranges = nyr * (tb.ct1 - tb.ct0 + 1);
-            if (wave == 0) {
-                int32_t beg = 0, len = 0;
-                if (lane < nranges) {
-                    const int32_t cz = tb.ct0 + lane / nyr, cy = tb.cy0 + lane % nyr;
-                    const int32_t row = (cz * D.ncy + cy) * D.ncx;
-                    beg = (int32_t)D.cell_start[row + tb.cx0];
-                    len = (int32_t)D.cell_start[row + tb.cx1 + 1] - beg;
+                // ---- setup: candidate ranges (one per bin row (t, y)) -----------
+                const TileBins tb = tile_bins(D, BX0, BY0, BT0, TT);
+                const int32_t nyr = tb.cy1 - tb.cy0 + 1;
+                const int32_t nranges = nyr * (tb.ct1 - tb.ct0 + 1);
+                if (wave == 0) {
+                    int32_t beg = 0, len = 0;
+                    if (lane < nranges) {
+                        const int32_t cz = tb.ct0 + lane / nyr, cy = tb.cy0 + lane % nyr;
+                        const int32_t row = (cz * D.ncy + cy) * D.ncx;
+                        beg = (int32_t)D.cell_start[row + tb.cx0];
+                        len = (int32_t)D.cell_start[row + tb.cx1 + 1] - beg;
+                    }
+                    int32_t inc = len;
+    #pragma unroll
+                    for (int d = 1; d < 64; d <<= 1) {
+                        const int32_t o = __shfl_up(inc, d, 64);
+                        if (lane >= d) inc += o;
+                    }
+                    if (lane < nranges) {
+                        sRB[lane] = beg;
+                        sRP[lane] = inc - len;
+                    }
+                    if (lane == nranges - 1) sRP[nranges] = inc;
                 }
-                int32_t inc = len;
-#pragma unroll
-                for (int d = 1; d < 64; d <<= 1) {
-                    const int32_t o = __shfl_up(inc, d, 64);
-                    if (lane >= d) inc += o;
-                }
-                if (lane < nranges) {
-                    sRB[lane] = beg;
-                    sRP[lane] = inc - len;
-                }
-                if (lane == nranges - 1) sRP[nranges] = inc;
-            }
-            __syncthreads();
-            const int32_t total = sRP[nranges];
-            const int32_t cend = it.cend == kAll ? total : min((int32_t)it.cend, total);
-            const PointRec* __restrict__ recs = D.recs;
+                __syncthreads();
+                const int32_t total = sRP[nranges];
+                const int32_t cend = it.cend == kAll ? total : min((int32_t)it.cend, total);
+                const PointRec* __restrict__ recs = D.recs;
 
-            // ---- accumulators: [column group q][row block b] ----------------
-            f32x4 acc[CG];
-            f32x4 comp[KAHAN ? CG : 1];
-            f32x4 pass[KAHAN ? CG : 1];
-#pragma unroll
-            for (int k = 0; k < CG; ++k) {
-                acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
-                if constexpr (KAHAN) {
-                    comp[k] = f32x4{0.f, 0.f, 0.f, 0.f};
-                    pass[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+                // ---- accumulators: [column group q][row block b] ----------------
+                f32x4 acc[CG];
+                f32x4 comp[KAHAN ? CG : 1];
+                f32x4 pass[KAHAN ? CG : 1];
+    #pragma unroll
+                for (int k = 0; k < CG; ++k) {
+                    acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+                    if constexpr (KAHAN) {
+                        comp[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+                        pass[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+                    }
                 }
-            }
 
-            // one group: operands from the coordinates of this lane's point,
-            // then all CG instructions
-            auto group = [&](const float2 cx, const float2 cy, const float2 ctt) {
-                float av[NB];
-#pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    const float dt = ((rowc + 16.0f * b) - ctt.x) - ctt.y;
-                    av[b] = fmaxf(0.0f, fmaf(-dt * dt, inv_tv2, 1.0f));
-                }
-                float ux[2], uy[2];
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const float dx = ((xc0 + 4.0f * h) - cx.x) - cx.y;
-                    const float dy = ((yc0 + 4.0f * h) - cy.x) - cy.y;
-                    ux[h] = fmaf(-dx * dx, inv_hv2, 1.0f);
-                    uy[h] = dy * dy * inv_hv2;
-                }
-#pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    const float ks = fmaxf(0.0f, ux[g & 1] - uy[g >> 1]);
-#pragma unroll
+                // one group: operands from the coordinates of this lane's point,
+                // then all CG instructions
+                auto group = [&](const float2 cx, const float2 cy, const float2 ctt) {
+                    float av[NB];
+    #pragma unroll
                     for (int b = 0; b < NB; ++b) {
-                        if constexpr (KAHAN)
-                            pass[g * NB + b] =
-                                __builtin_amdgcn_mfma_f32_16x16x4f32(av[b], ks, pass[g * NB + b], 0, 0, 0);
-                        else
-                            acc[g * NB + b] =
-                                __builtin_amdgcn_mfma_f32_16x16x4f32(av[b], ks, acc[g * NB + b], 0, 0, 0);
+                        const float dt = ((rowc + 16.0f * b) - ctt.x) - ctt.y;
+                        av[b] = fmaxf(0.0f, fmaf(-dt * dt, inv_tv2, 1.0f));
                     }
-                }
-            };
-
-            int32_t bb = (int32_t)min(it.cbeg, (uint32_t)cend);
-            while (bb < cend) {
-                // ---- stage: fill the survivor list ------------------------------
-                int32_t count_s = 0;
-                while (bb < cend && count_s <= kCap - kThreads) {
-                    const int32_t c = bb + tid;
-                    bool surv = false;
-                    PointRec r{};
-                    uint32_t qm = 0;
-                    if (c < cend) {
-                        int32_t lo = 0, hi = nranges - 1;  // last range with sRP <= c
-                        while (lo < hi) {
-                            const int32_t mid = (lo + hi + 1) >> 1;
-                            if (sRP[mid] <= c) lo = mid;
-                            else hi = mid - 1;
+                    float ux[2], uy[2];
+    #pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const float dx = ((xc0 + 4.0f * h) - cx.x) - cx.y;
+                        const float dy = ((yc0 + 4.0f * h) - cy.x) - cy.y;
+                        ux[h] = fmaf(-dx * dx, inv_hv2, 1.0f);
+                        uy[h] = dy * dy * inv_hv2;
+                    }
+    #pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        const float ks = fmaxf(0.0f, ux[g & 1] - uy[g >> 1]);
+    #pragma unroll
+                        for (int b = 0; b < NB; ++b) {
+                            if constexpr (KAHAN)
+                                pass[g * NB + b] =
+                                    __builtin_amdgcn_mfma_f32_16x16x4f32(av[b], ks, pass[g * NB + b], 0, 0, 0);
+                            else
+                                acc[g * NB + b] =
+                                    __builtin_amdgcn_mfma_f32_16x16x4f32(av[b], ks, acc[g * NB + b], 0, 0, 0);
                         }
-                        r = recs[sRB[lo] + (c - sRP[lo])];
-                        const int32_t xlo = (int32_t)(r.xb & 0xffffu) - BX0, xhi = (int32_t)(r.xb >> 16) - BX0;
-                        const int32_t ylo = (int32_t)(r.yb & 0xffffu) - BY0, yhi = (int32_t)(r.yb >> 16) - BY0;
-                        const int32_t tlo = (int32_t)(r.tb & 0xffffu), thi = (int32_t)(r.tb >> 16);
-                        if (tlo <= BT0 + TT - 1 && thi >= BT0) {
-                            // quadrants (qx, qy) whose 8 x 8 columns the footprint box meets
-                            const bool x0 = xlo <= 7 && xhi >= 0, x1 = xlo <= 15 && xhi >= 8;
-                            const bool y0 = ylo <= 7 && yhi >= 0, y1 = ylo <= 15 && yhi >= 8;
-                            qm = (uint32_t)(x0 && y0) | ((uint32_t)(x1 && y0) << 1) |
-                                 ((uint32_t)(x0 && y1) << 2) | ((uint32_t)(x1 && y1) << 3);
+                    }
+                };
+
+                int32_t bb = (int32_t)min(it.cbeg, (uint32_t)cend);
+                while (bb < cend) {
+                    // ---- stage: fill the survivor list ------------------------------
+                    int32_t count_s = 0;
+                    while (bb < cend && count_s <= kCap - kThreads) {
+                        const int32_t c = bb + tid;
+                        bool surv = false;
+                        PointRec r{};
+                        uint32_t qm = 0;
+                        if (c < cend) {
+                            int32_t lo = 0, hi = nranges - 1;  // last range with sRP <= c
+                            while (lo < hi) {
+                                const int32_t mid = (lo + hi + 1) >> 1;
+                                if (sRP[mid] <= c) lo = mid;
+                                else hi = mid - 1;
+                            }
+                            r = recs[sRB[lo] + (c - sRP[lo])];
+                            const int32_t xlo = (int32_t)(r.xb & 0xffffu) - BX0, xhi = (int32_t)(r.xb >> 16) - BX0;
+                            const int32_t ylo = (int32_t)(r.yb & 0xffffu) - BY0, yhi = (int32_t)(r.yb >> 16) - BY0;
+                            const int32_t tlo = (int32_t)(r.tb & 0xffffu), thi = (int32_t)(r.tb >> 16);
+                            if (tlo <= BT0 + TT - 1 && thi >= BT0) {
+                                // quadrants (qx, qy) whose 8 x 8 columns the footprint box meets
+                                const bool x0 = xlo <= 7 && xhi >= 0, x1 = xlo <= 15 && xhi >= 8;
+                                const bool y0 = ylo <= 7 && yhi >= 0, y1 = ylo <= 15 && yhi >= 8;
+                                qm = (uint32_t)(x0 && y0) | ((uint32_t)(x1 && y0) << 1) |
+                                     ((uint32_t)(x0 && y1) << 2) | ((uint32_t)(x1 && y1) << 3);
+                            }
+                            surv = qm != 0;
                         }
-                        surv = qm != 0;
-                    }
-                    const unsigned long long m = __ballot(surv);
-                    if (lane == 0) sWC[wave] = __popcll(m);
-                    __syncthreads();
-                    int32_t off = count_s, add = 0;
-#pragma unroll
-                    for (int w = 0; w < kWaves; ++w) {
-                        const int32_t cw = sWC[w];
-                        off += (w < wave) ? cw : 0;
-                        add += cw;
-                    }
-                    if (surv) {
-                        const int s = off + __popcll(m & lt);
-                        // head - origin is exact for the offsets that reach the tile
-                        sX[s] = make_float2(r.xh - (float)BX0, half_lo(r.xl_yl));
-                        sY[s] = make_float2(r.yh - (float)BY0, half_hi(r.xl_yl));
-                        sT[s] = make_float2(r.th - (float)BT0, half_lo(r.tl));
-                        sQ[s] = (uint8_t)qm;
-                    }
-                    count_s += add;
-                    bb += kThreads;
-                    __syncthreads();  // sWC is rewritten by the next round
-                }
-
-                // ---- this wave's list: survivors meeting its quadrant -----------
-                int32_t nw = 0;
-                for (int32_t base = 0; base < count_s; base += 64) {
-                    const int32_t s = base + lane;
-                    const bool mine = s < count_s && ((sQ[s] >> wave) & 1u);
-                    const unsigned long long bm = __ballot(mine);
-                    if (mine) myL[nw + __popcll(bm & lt)] = (uint16_t)s;
-                    nw += __popcll(bm);
-                }
-                // pad to a whole number of pairs of groups
-                if (lane < ((8 - (nw & 7)) & 7)) myL[nw + lane] = (uint16_t)kPad;
-                const int32_t npairs = (nw + 7) >> 3;
-
-                // ---- matrix-core accumulation, two groups per iteration ---------
-                if (npairs > 0) {
-                    int s = myL[kq];
-                    float2 ax = sX[s], ay = sY[s], at = sT[s];
-                    for (int32_t pr = 0; pr < npairs; ++pr) {
-                        s = myL[8 * pr + 4 + kq];
-                        const float2 bx = sX[s], by = sY[s], bt = sT[s];
-                        group(ax, ay, at);
-                        if (pr + 1 < npairs) {
-                            s = myL[8 * pr + 8 + kq];
-                            ax = sX[s];
-                            ay = sY[s];
-                            at = sT[s];
+                        const unsigned long long m = __ballot(surv);
+                        if (lane == 0) sWC[wave] = __popcll(m);
+                        __syncthreads();
+                        int32_t off = count_s, add = 0;
+    #pragma unroll
+                        for (int w = 0; w < kWaves; ++w) {
+                            const int32_t cw = sWC[w];
+                            off += (w < wave) ? cw : 0;
+                            add += cw;
                         }
-                        group(bx, by, bt);
+                        if (surv) {
+                            const int s = off + __popcll(m & lt);
+                            // head - origin is exact for the offsets that reach the tile
+                            sX[s] = make_float2(r.xh - (float)BX0, half_lo(r.xl_yl));
+                            sY[s] = make_float2(r.yh - (float)BY0, half_hi(r.xl_yl));
+                            sT[s] = make_float2(r.th - (float)BT0, half_lo(r.tl));
+                            sQ[s] = (uint8_t)qm;
+                        }
+                        count_s += add;
+                        bb += kThreads;
+                        __syncthreads();  // sWC is rewritten by the next round
                     }
-                }
-                if constexpr (KAHAN) kahan_fold<CG>(acc, comp, pass);
-                __syncthreads();  // the lists are refilled next
-            }
 
-            // ---- store: lane holds rows 16 b + 4 (lane / 16) + e of column
-            // (lane % 4, (lane / 4) % 4) of each of its column groups -------------
-            if (it.slot != kNoSlot) {
-                float* P = partials + (size_t)it.slot * (kTileXY * kTileXY * TT);
-#pragma unroll
+                    // ---- this wave's list: survivors meeting its quadrant -----------
+                    int32_t nw = 0;
+                    for (int32_t base = 0; base < count_s; base += 64) {
+                        const int32_t s = base + lane;
+                        const bool mine = s < count_s && ((sQ[s] >> wave) & 1u);
+                        const unsigned long long bm = __ballot(mine);
+                        if (mine) myL[nw + __popcll(bm & lt)] = (uint16_t)s;
+                        nw += __popcll(bm);
+                    }
+                    // pad to a whole number of pairs of groups
+                    if (lane < ((8 - (nw & 7)) & 7)) myL[nw + lane] = (uint16_t)kPad;
+                    const int32_t npairs = (nw + 7) >> 3;
+
+                    // ---- matrix-core accumulation, two groups per iteration ---------
+                    if (npairs > 0) {
+                        int s = myL[kq];
+                        float2 ax = sX[s], ay = sY[s], at = sT[s];
+                        for (int32_t pr = 0; pr < npairs; ++pr) {
+                            s = myL[8 * pr + 4 + kq];
+                            const float2 bx = sX[s], by = sY[s], bt = sT[s];
+                            group(ax, ay, at);
+                            if (pr + 1 < npairs) {
+                                s = myL[8 * pr + 8 + kq];
+                                ax = sX[s];
+                                ay = sY[s];
+                                at = sT[s];
+                            }
+                            group(bx, by, bt);
+                        }
+                    }
+                    if constexpr (KAHAN) kahan_fold<CG>(acc, comp, pass);
+                    __syncthreads();  // the lists are refilled next
+                }
+
+                // ---- store: lane holds rows 16 b + 4 (lane / 16) + e of column
+                // (lane % 4, (lane / 4) % 4) of each of its column groups -------------
+                if (it.slot != kNoSlot) {
+                    float* P = partials + (size_t)it.slot * (kTileXY * kTileXY * TT);
+    #pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        const int32_t lx = 4 * gqx + 4 * (g & 1) + (lane & 3);
+                        const int32_t ly = 4 * gqy + 4 * (g >> 1) + ((lane >> 2) & 3);
+    #pragma unroll
+                        for (int b = 0; b < NB; ++b)
+                            *reinterpret_cast<f32x4*>(P + (lx * kTileXY + ly) * TT + 16 * b + 4 * (lane >> 4)) =
+                                acc[g * NB + b];
+                    }
+                    continue;
+                }
+                const bool mass = (D.flags & kInstMass) != 0;
+                const int32_t gxI = D.gx, gyI = D.gy, gtI = D.gt;
+                const float cnorm = D.cnorm;
+                float* __restrict__ out = D.out;
+                double msum = 0.0;
+                const bool vec = (gtI & 3) == 0;
+    #pragma unroll
                 for (int g = 0; g < 4; ++g) {
-                    const int32_t lx = 4 * gqx + 4 * (g & 1) + (lane & 3);
-                    const int32_t ly = 4 * gqy + 4 * (g >> 1) + ((lane >> 2) & 3);
-#pragma unroll
-                    for (int b = 0; b < NB; ++b)
-                        *reinterpret_cast<f32x4*>(P + (lx * kTileXY + ly) * TT + 16 * b + 4 * (lane >> 4)) =
-                            acc[g * NB + b];
-                }
-                continue;
-            }
-            const bool mass = (D.flags & kInstMass) != 0;
-            const int32_t gxI = D.gx, gyI = D.gy, gtI = D.gt;
-            const float cnorm = D.cnorm;
-            float* __restrict__ out = D.out;
-            double msum = 0.0;
-            const bool vec = (gtI & 3) == 0;
-#pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                const int32_t X = X0 + 4 * gqx + 4 * (g & 1) + (lane & 3);
-                const int32_t Y = Y0 + 4 * gqy + 4 * (g >> 1) + ((lane >> 2) & 3);
-                if (X >= gxI || Y >= gyI) continue;
-                float* col = out + ((size_t)X * gyI + Y) * gtI;
-#pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    const int32_t T = T0 + 16 * b + 4 * (lane >> 4);
-                    const f32x4 v = acc[g * NB + b] * cnorm;
-                    if (vec && T + 3 < gtI) {
-                        *reinterpret_cast<f32x4*>(col + T) = v;
-                        msum += (double)v[0] + (double)v[1] + (double)v[2] + (double)v[3];
-                    } else {
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            if (T + e < gtI) {
-                                col[T + e] = v[e];
-                                msum += (double)v[e];
+                    const int32_t X = X0 + 4 * gqx + 4 * (g & 1) + (lane & 3);
+                    const int32_t Y = Y0 + 4 * gqy + 4 * (g >> 1) + ((lane >> 2) & 3);
+                    if (X >= gxI || Y >= gyI) continue;
+                    float* col = out + ((size_t)X * gyI + Y) * gtI;
+    #pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        const int32_t T = T0 + 16 * b + 4 * (lane >> 4);
+                        const f32x4 v = acc[g * NB + b] * cnorm;
+                        if (vec && T + 3 < gtI) {
+                            *reinterpret_cast<f32x4*>(col + T) = v;
+                            msum += (double)v[0] + (double)v[1] + (double)v[2] + (double)v[3];
+                        } else {
+    #pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                if (T + e < gtI) {
+                                    col[T + e] = v[e];
+                                    msum += (double)v[e];
+                                }
                             }
                         }
                     }
                 }
-            }
-            if (mass) {
-#pragma unroll
-                for (int d = 32; d >= 1; d >>= 1) msum += __shfl_xor(msum, d, 64);
-                if (lane == 0) D.tile_part[(size_t)tile * kWaves + wave] = msum;
+                if (mass) {
+    #pragma unroll
+                    for (int d = 32; d >= 1; d >>= 1) msum += __shfl_xor(msum, d, 64);
+                    if (lane == 0) D.tile_part[(size_t)tile * kWaves + wave] = msum;
+                }
             }
         }
     }
@@ -464,13 +481,13 @@ int resident_groups() {
 
 template <int TT, bool K>
 void launch_items_t(const InstDev* d, int32_t count, const WorkItem* items, const uint32_t* bits,
-                    uint32_t* sc, float* partials, int64_t T, hipStream_t s) {
+                    const uint32_t* sc, uint32_t* ctr, float* partials, int64_t T, hipStream_t s) {
     int64_t g = resident_groups<TT, K>();
     const int64_t most = T + kPartSlots;  // items never exceed tiles + partial slots
     if (g > most) g = most;
     if (g < 1) g = 1;
     hipLaunchKernelGGL((k_gather_items<TT, K>), dim3((uint32_t)g), dim3(kThreads), 0, s, d, count,
-                       (int32_t)T, items, bits, sc, partials);
+                       (int32_t)T, items, bits, sc, ctr, partials);
 }
 
 template <int TT, bool K>
@@ -483,16 +500,17 @@ void launch_reduce_t(const InstDev* d, int32_t count, const uint32_t* top, const
 }  // namespace
 
 hipError_t launch_gather_items(const InstDev* d_desc, int32_t count, const WorkItem* d_items,
-                               const uint32_t* d_bits, uint32_t* d_scalars, float* d_partials,
-                               int64_t T, int tile_t, bool kahan, hipStream_t s) {
+                               const uint32_t* d_bits, const uint32_t* d_scalars,
+                               uint32_t* d_counters, float* d_partials, int64_t T, int tile_t,
+                               bool kahan, hipStream_t s) {
     if (tile_t == 16) {
-        kahan ? launch_items_t<16, true>(d_desc, count, d_items, d_bits, d_scalars, d_partials, T, s)
-              : launch_items_t<16, false>(d_desc, count, d_items, d_bits, d_scalars, d_partials, T, s);
+        kahan ? launch_items_t<16, true>(d_desc, count, d_items, d_bits, d_scalars, d_counters, d_partials, T, s)
+              : launch_items_t<16, false>(d_desc, count, d_items, d_bits, d_scalars, d_counters, d_partials, T, s);
     } else if (tile_t == 32) {
-        kahan ? launch_items_t<32, true>(d_desc, count, d_items, d_bits, d_scalars, d_partials, T, s)
-              : launch_items_t<32, false>(d_desc, count, d_items, d_bits, d_scalars, d_partials, T, s);
+        kahan ? launch_items_t<32, true>(d_desc, count, d_items, d_bits, d_scalars, d_counters, d_partials, T, s)
+              : launch_items_t<32, false>(d_desc, count, d_items, d_bits, d_scalars, d_counters, d_partials, T, s);
     } else {
-        launch_items_t<64, false>(d_desc, count, d_items, d_bits, d_scalars, d_partials, T, s);
+        launch_items_t<64, false>(d_desc, count, d_items, d_bits, d_scalars, d_counters, d_partials, T, s);
     }
     return hipGetLastError();
 }

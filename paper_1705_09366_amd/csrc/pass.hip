@@ -132,7 +132,8 @@ __global__ __launch_bounds__(1024) void k_plan_items(const InstDev* __restrict__
                                                      WorkItem* __restrict__ items,
                                                      uint32_t* __restrict__ top,
                                                      uint32_t* __restrict__ bits,
-                                                     uint32_t* __restrict__ sc, uint32_t nslots) {
+                                                     uint32_t* __restrict__ sc,
+                                                     uint32_t* __restrict__ ctr, uint32_t nslots) {
     __shared__ unsigned long long keys[kTopTiles];
     __shared__ uint32_t ws[16];
     __shared__ uint32_t s_cls, s_nh;
@@ -236,9 +237,8 @@ __global__ __launch_bounds__(1024) void k_plan_items(const InstDev* __restrict__
             top[4 * spos + 3] = c;
         }
     }
+    for (int k = tid; k < kCtrWords; k += 1024) ctr[k] = 0u;  // both queues' counters
     if (tid == 0) {
-        sc[kScNextHeavy] = 0u;
-        sc[kScNextSpatial] = 0u;
         sc[kScHeavyItems] = nitems_h;
         sc[kScSplit] = nsplit;
         sc[kScHeavyTiles] = nh;
@@ -311,6 +311,7 @@ PassLayout layout_pass(const InstGeom* inst, int32_t count, int tile_t) {
     l.hist = o; o = al256(o + (size_t)kCostClasses * 4);
     l.bits = o; o = al256(o + ((size_t)T + 31) / 32 * 4);
     l.scalars = o; o = al256(o + (size_t)kScCount * 4);
+    l.counters = o; o = al256(o + (size_t)kCtrWords * 4);
     l.top = o; o = al256(o + (size_t)kTopTiles * 16);
     l.items = o; o = al256(o + (size_t)kTopTiles * kMaxParts * sizeof(WorkItem));
     l.partials = o; o = al256(o + (size_t)kPartSlots * kTileXY * kTileXY * tile_t * 4);
@@ -329,6 +330,7 @@ hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassL
     auto* hist = reinterpret_cast<uint32_t*>(pass + pl.hist);
     auto* bits = reinterpret_cast<uint32_t*>(pass + pl.bits);
     auto* sc = reinterpret_cast<uint32_t*>(pass + pl.scalars);
+    auto* ctr = reinterpret_cast<uint32_t*>(pass + pl.counters);
     auto* top = reinterpret_cast<uint32_t*>(pass + pl.top);
     auto* items = reinterpret_cast<WorkItem*>(pass + pl.items);
     auto* partials = reinterpret_cast<float*>(pass + pl.partials);
@@ -353,11 +355,12 @@ hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassL
                        count, T, tile_t, cost, hist, inst_cost, bits);
     hipLaunchKernelGGL(k_plan_items, dim3(1), dim3(1024), 0, s, (const InstDev*)d_desc, count, T,
                        (const uint32_t*)cost, (const uint32_t*)hist,
-                       (const unsigned long long*)inst_cost, items, top, bits, sc, (uint32_t)kPartSlots);
+                       (const unsigned long long*)inst_cost, items, top, bits, sc, ctr,
+                       (uint32_t)kPartSlots);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev_before && (e = hipEventRecord(ev_before, s)) != hipSuccess) return e;
-    e = launch_gather_items(d_desc, count, items, bits, sc, partials, pl.T, tile_t, kahan, s);
+    e = launch_gather_items(d_desc, count, items, bits, sc, ctr, partials, pl.T, tile_t, kahan, s);
     if (e != hipSuccess) return e;
     if (ev_after && (e = hipEventRecord(ev_after, s)) != hipSuccess) return e;
     e = launch_reduce_split(d_desc, count, top, sc, partials, tile_t, kahan, s);

@@ -113,13 +113,26 @@ constexpr int kDescChunk = 16;                        // descriptors written per
 // the low 20 bits (exponent and 3 mantissa bits), monotone in the count.
 constexpr int kCostClasses = 2048;
 
+// Queue positions are handed out by kFetchLanes interleaved counters:
+// counter k gives positions k, k + kFetchLanes, k + 2 kFetchLanes, ...  A
+// workgroup draws from counter (its index mod kFetchLanes) and then from the
+// others, so the positions in flight stay compact while no single address
+// takes every workgroup's atomic (same-address atomics serialise; one
+// counter per queue measured ~12 ns per fetch times the number of
+// workgroups).
+constexpr int kFetchLanes = 16;
+// Counters sit 256 bytes apart: atomics to one cache line serialise like
+// atomics to one address.
+constexpr int kCtrStride = 64;  // u32
+
 // Scalars of a pass (u32 offsets into PassLayout::scalars).
-constexpr int kScNextHeavy = 0;    // next item of the heaviest-first queue
-constexpr int kScNextSpatial = 1;  // next position of the spatial queue
-constexpr int kScHeavyItems = 2;   // items in the heaviest-first queue
-constexpr int kScSplit = 3;        // split tiles
-constexpr int kScHeavyTiles = 4;   // tiles in the heaviest-first queue
+constexpr int kScHeavyItems = 0;  // items in the heaviest-first queue
+constexpr int kScSplit = 1;       // split tiles
+constexpr int kScHeavyTiles = 2;  // tiles in the heaviest-first queue
 constexpr int kScCount = 8;
+// Counters (u32 offsets into PassLayout::counters): queue q, lane k at
+// (q * kFetchLanes + k) * kCtrStride.
+constexpr int kCtrWords = 2 * kFetchLanes * kCtrStride;
 
 // ---- set memory (caller-owned, persistent) --------------------------------
 struct SetLayout {
@@ -146,6 +159,7 @@ struct PassLayout {
     size_t hist;         // kCostClasses u32: tiles per cost class
     size_t bits;         // ceil(T / 32) u32: spatial-queue positions taken by the heavy queue
     size_t scalars;      // kScCount u32
+    size_t counters;     // kCtrWords u32: the queues' fetch counters
     size_t top;          // kTopTiles x 4 u32 split tiles: tile, parts, slot0, candidates
     size_t items;        // kTopTiles * kMaxParts WorkItem (the heaviest-first queue)
     size_t partials;     // kPartSlots x 16 x 16 x tile_t FP32
@@ -229,8 +243,9 @@ hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassL
                        hipEvent_t ev_after = nullptr);
 // The gather proper (called by launch_pass).
 hipError_t launch_gather_items(const InstDev* d_desc, int32_t count, const WorkItem* d_items,
-                               const uint32_t* d_bits, uint32_t* d_scalars, float* d_partials,
-                               int64_t T, int tile_t, bool kahan, hipStream_t s);
+                               const uint32_t* d_bits, const uint32_t* d_scalars,
+                               uint32_t* d_counters, float* d_partials, int64_t T, int tile_t,
+                               bool kahan, hipStream_t s);
 // Query (and cache) the gather's launch size for the current device ahead of a
 // stream capture.
 void prepare_gather(int tile_t, bool kahan);
