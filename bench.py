@@ -15,10 +15,13 @@ is available here).
 Prints ONE JSON line:
   value            kernel evaluations per second = exact in-grid
                    (voxel, point) pairs inside both supports / step time
-  roofline         the gather kernel (dominant): algorithmic bytes (grid
-                   written once + points read once) / its average duration
-                   over the timed steps, timed with HIP events that the
-                   library records around that launch on its stream
+  roofline         the gather kernel (dominant) against the roofline that
+                   binds the workload: HBM (algorithmic bytes = grid written
+                   once + points read once) when 2 flops per evaluation per
+                   byte is below the ridge point, else FP32 matrix cores
+                   (2 flops per evaluation); over its average duration in the
+                   timed steps, from HIP events that the library records
+                   around that launch on its stream
   cpu_baseline     the FP64 CPU oracle on a bounded sample of the same
                    workload, on this host's cores
 """
@@ -33,6 +36,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_F32_PEAK_TFLOPS = 157.3  # dense FP32 matrix-core peak of MI355X
 WORKLOADS = ("clustered-1M", "clustered-200k-hs50", "uniform-10k")
 
 
@@ -411,7 +415,14 @@ def main():
 
     grid_bytes = inst.gx * inst.gy * inst.gt * 4
     alg_bytes = grid_bytes + n * 24
-    achieved = alg_bytes / (gather_ms * 1e-3) / 1e9
+    alg_flops = 2.0 * evals  # one multiply and one add per (voxel, point) pair
+    # the binding roofline: HBM below the ridge point, FP32 matrix cores above it
+    if alg_flops / alg_bytes < MFMA_F32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9):
+        bound, unit, peak = "hbm", "GB/s", HBM_PEAK_GBS
+        achieved = alg_bytes / (gather_ms * 1e-3) / 1e9
+    else:
+        bound, unit, peak = "mfma", "TFLOP/s", MFMA_F32_PEAK_TFLOPS
+        achieved = alg_flops / (gather_ms * 1e-3) / 1e12
     # the counters hold for the kernel source and work list they were taken on
     src = b"".join(open(os.path.join(ROOT, "paper_1705_09366_amd", "csrc", f), "rb").read()
                    for f in ("gather.hip", "pass.hip"))
@@ -437,8 +448,9 @@ def main():
                    "tuning": ([tuning.tile_t, tuning.cell_xy, tuning.cell_t, tuning.split_share]
                               if tuning else [0, 0, 0, 0]),
                    "tuning_source": tuning_src},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                     "frac": achieved / peak, "traffic": traffic if bound == "hbm" else None,
+                     "algorithmic": {"bytes": alg_bytes, "flops": alg_flops}},
         "stage_ms": {"bin": bin_ms, "pass": pass_ms, "gather_kernel": gather_ms},
         "mass": {"grid": float(st[0]), "points": float(cs[1])},
     }

@@ -232,7 +232,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
     #pragma unroll
                     for (int b = 0; b < NB; ++b) {
                         const float dt = ((rowc + 16.0f * b) - ctt.x) - ctt.y;
-                        av[b] = fmaxf(0.0f, fmaf(-dt * dt, inv_tv2, 1.0f));
+                        // the operands never exceed 1, so max(0, .) is a clamp to
+                    // [0, 1], which folds into the producing instruction
+                    av[b] = __builtin_amdgcn_fmed3f(fmaf(-dt * dt, inv_tv2, 1.0f), 0.0f, 1.0f);
                     }
                     float ux[2], uy[2];
     #pragma unroll
@@ -244,7 +246,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                     }
     #pragma unroll
                     for (int g = 0; g < 4; ++g) {
-                        const float ks = fmaxf(0.0f, ux[g & 1] - uy[g >> 1]);
+                        const float ks = __builtin_amdgcn_fmed3f(ux[g & 1] - uy[g >> 1], 0.0f, 1.0f);
     #pragma unroll
                         for (int b = 0; b < NB; ++b) {
                             if constexpr (KAHAN)
