@@ -61,7 +61,7 @@ struct stkde_batch_s {
 namespace {
 
 constexpr int64_t kMaxDim = 65535;
-constexpr int32_t kMaxCells = 1 << 22;  // keys of at most 23 bits: <= 3 radix passes
+constexpr int32_t kMaxCells = 1 << 22;  // keys of at most 23 bits: <= 3 radix passes (<= 2 below 2^22 - 1 bins)
 constexpr int32_t kMaxBatch = 4096;
 constexpr uint32_t kKnownFlags = STKDE_FLAG_KAHAN | STKDE_FLAG_MASS | STKDE_FLAG_POINT_STATS;
 
@@ -146,24 +146,6 @@ void make_set_geom(const stkde_desc& d, int32_t cell_xy, int32_t cell_t, int32_t
         // grow the dimension that contributes more bin rows
         if ((ry >= rt && g.cxy < 65536) || g.ct >= 65536) g.cxy *= 2;
         else g.ct *= 2;
-    }
-    // Keys of at most 16 bits sort in two radix passes instead of three:
-    // widen the bins in t (up to twice) when that alone gets there and the
-    // range limit still holds.
-    if (!cell_t && g.ncell >= 65536 && g.ncell < (1 << 20)) {
-        for (int32_t c = g.ct + 1; c <= 2 * g.ct; ++c) {
-            const int64_t nct = (d.gt + c - 1) / c;
-            const int64_t nc = (int64_t)g.ncx * g.ncy * nct;
-            const int64_t nt = span(rows + 2 * (int64_t)Ht + 2, c);
-            const int64_t ry = span(stkde::kTileXY + 2 * (int64_t)Hs + 2, g.cxy);
-            const int64_t rr = (ry < g.ncy ? ry : g.ncy) * (nt < nct ? nt : nct);
-            if (nc < 65536 && rr <= stkde::kMaxRanges) {
-                g.ct = c;
-                g.nct = (int32_t)nct;
-                g.ncell = (int32_t)nc;
-                break;
-            }
-        }
     }
     *out = g;
 }

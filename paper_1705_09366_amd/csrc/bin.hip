@@ -6,7 +6,8 @@
 //      to the grid, bin key.  Points whose footprint misses the grid, and
 //      points with a non-finite coordinate, get the key `ncell`, which sorts
 //      after every bin and is never visited.
-//   2. stable LSD radix sort of (key, index) with 8-bit digits, 1-3 passes.
+//   2. stable LSD radix sort of (key, index) with 8- to 11-bit digits, 1-3
+//      passes.
 //      This is the device form of the per-subdomain point lists that the
 //      paper's domain decompositions build on the host (Sec. 4.2, Sec. 5.1).
 //   3. bin offsets: cell_start[c] = first sorted position with key >= c.
@@ -107,24 +108,30 @@ __global__ __launch_bounds__(kThreads) void k_transform(SetGeom g, const double*
     }
 }
 
-// ---- stable LSD radix sort, 8-bit digits --------------------------------
+// ---- stable LSD radix sort, digits of 8 to 11 bits --------------------------
+//
+// A key of b bits is sorted in ceil(b / 11) passes of equal digits (18-bit
+// keys: two 9-bit passes).
+constexpr int kMaxDigitBits = 11;
+constexpr int kMaxBuckets = 1 << kMaxDigitBits;
 
 // Per-block digit histogram.  hist is digit-major: hist[d * nblk + b].
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
-                                                         int32_t n, int shift,
+                                                         int32_t n, int shift, int nbuck,
                                                          uint32_t* __restrict__ hist,
                                                          int32_t nblk) {
-    __shared__ uint32_t cnt[256];
-    cnt[threadIdx.x] = 0;
+    __shared__ uint32_t cnt[kMaxBuckets];
+    for (int d = threadIdx.x; d < nbuck; d += kThreads) cnt[d] = 0;
     __syncthreads();
+    const uint32_t mask = (uint32_t)nbuck - 1u;
     const int32_t base = blockIdx.x * kSortTile;
 #pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
         const int32_t i = base + it * kThreads + threadIdx.x;
-        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
+        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & mask], 1u);
     }
     __syncthreads();
-    hist[threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+    for (int d = threadIdx.x; d < nbuck; d += kThreads) hist[(size_t)d * nblk + blockIdx.x] = cnt[d];
 }
 
 // totals[d] = sum over blocks of hist[d][b]; one workgroup per digit.
@@ -149,7 +156,8 @@ __global__ __launch_bounds__(kThreads) void k_radix_scan(uint32_t* __restrict__ 
     __shared__ uint32_t carry_s;
     const int d = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     // keys of smaller digits
-    uint32_t lower = (tid < d) ? totals[tid] : 0u;
+    uint32_t lower = 0;
+    for (int e = tid; e < d; e += kThreads) lower += totals[e];
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) lower += __shfl_xor(lower, o, 64);
     if (lane == 0) wsum[wv] = lower;
@@ -183,14 +191,18 @@ __global__ __launch_bounds__(kThreads) void k_radix_scan(uint32_t* __restrict__ 
 // rounds) + (in earlier waves of this round) + (in earlier lanes).
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, int32_t n, int shift,
-    const uint32_t* __restrict__ hist, int32_t nblk, uint32_t* __restrict__ kout,
+    int dbits, const uint32_t* __restrict__ hist, int32_t nblk, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout) {
-    __shared__ uint32_t off[256];
-    __shared__ uint32_t wcnt[kWaves][256];
+    __shared__ uint32_t off[kMaxBuckets];
+    __shared__ uint32_t wcnt[kWaves][kMaxBuckets];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    off[tid] = hist[tid * nblk + blockIdx.x];
+    const int nbuck = 1 << dbits;
+    const uint32_t mask = (uint32_t)nbuck - 1u;
+    for (int d = tid; d < nbuck; d += kThreads) {
+        off[d] = hist[(size_t)d * nblk + blockIdx.x];
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0;
+        for (int w = 0; w < kWaves; ++w) wcnt[w][d] = 0;
+    }
     __syncthreads();
     const int32_t base = blockIdx.x * kSortTile;
     const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -201,11 +213,10 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
         if (valid) {
             key = kin[i];
             val = vin[i];
-            d = (key >> shift) & 255u;
+            d = (key >> shift) & mask;
         }
         unsigned long long peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
+        for (int b = 0; b < dbits; ++b) {
             const unsigned long long bb = __ballot((d >> b) & 1u);
             peers &= ((d >> b) & 1u) ? bb : ~bb;
         }
@@ -219,14 +230,14 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
             vout[pos] = val;
         }
         __syncthreads();
-        {
+        for (int dd = tid; dd < nbuck; dd += kThreads) {
             uint32_t add = 0;
 #pragma unroll
             for (int w = 0; w < kWaves; ++w) {
-                add += wcnt[w][tid];
-                wcnt[w][tid] = 0;
+                add += wcnt[w][dd];
+                wcnt[w][dd] = 0;
             }
-            off[tid] += add;
+            off[dd] += add;
         }
         __syncthreads();
     }
@@ -306,8 +317,8 @@ SortLayout layout_sort(int64_t n) {
     l.vals0 = o; o = al256(o + nn * 4);
     l.keys1 = o; o = al256(o + nn * 4);
     l.vals1 = o; o = al256(o + nn * 4);
-    l.hist = o; o = al256(o + (size_t)256 * l.nblk * 4);
-    l.totals = o; o = al256(o + 4 * 256 * 4);
+    l.hist = o; o = al256(o + (size_t)kMaxBuckets * l.nblk * 4);
+    l.totals = o; o = al256(o + 3 * (size_t)kMaxBuckets * 4);
     l.total = o;
     return l;
 }
@@ -327,17 +338,20 @@ hipError_t launch_bin(const SetGeom& g, const double* d_xyt, int32_t n, uint8_t*
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ctr, 4);
     hipLaunchKernelGGL(k_transform, dim3(nb), dim3(kThreads), 0, s, g, d_xyt, n, k0, v0, ctr);
 
+    // keys are at most ncell (culled points): ceil(bits / 11) passes of equal digits
     const int bits = bits_for((uint32_t)g.ncell);
-    const int passes = bits <= 8 ? 1 : (bits + 7) / 8;
+    const int passes = bits <= 8 ? 1 : (bits + kMaxDigitBits - 1) / kMaxDigitBits;
+    const int dbits = bits <= 8 ? 8 : (bits + passes - 1) / passes;
+    const int nbuck = 1 << dbits;
     for (int p = 0; p < passes; ++p) {
-        hipLaunchKernelGGL(k_radix_hist, dim3(so.nblk), dim3(kThreads), 0, s, k0, n, 8 * p, hist,
-                           so.nblk);
-        hipLaunchKernelGGL(k_radix_rowsum, dim3(256), dim3(kThreads), 0, s, hist, so.nblk,
-                           totals + 256 * p);
-        hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(kThreads), 0, s, hist, so.nblk,
-                           totals + 256 * p);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(so.nblk), dim3(kThreads), 0, s, k0, v0, n, 8 * p,
-                           hist, so.nblk, k1, v1);
+        hipLaunchKernelGGL(k_radix_hist, dim3(so.nblk), dim3(kThreads), 0, s, k0, n, dbits * p, nbuck,
+                           hist, so.nblk);
+        hipLaunchKernelGGL(k_radix_rowsum, dim3(nbuck), dim3(kThreads), 0, s, hist, so.nblk,
+                           totals + kMaxBuckets * p);
+        hipLaunchKernelGGL(k_radix_scan, dim3(nbuck), dim3(kThreads), 0, s, hist, so.nblk,
+                           totals + kMaxBuckets * p);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(so.nblk), dim3(kThreads), 0, s, k0, v0, n, dbits * p,
+                           dbits, hist, so.nblk, k1, v1);
         std::swap(k0, k1);
         std::swap(v0, v1);
     }

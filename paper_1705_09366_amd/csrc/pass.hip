@@ -156,43 +156,45 @@ __global__ __launch_bounds__(1024) void k_plan_items(const InstDev* __restrict__
     __syncthreads();
     const uint32_t cls = s_cls;
 
-    // collect the heavy tiles (in any order: they are sorted next); each
-    // thread reads a contiguous stripe, eight independent loads at a time
-    const uint32_t stripe = (T + 1023u) / 1024u;
-    const uint32_t j0 = (uint32_t)tid * stripe;
-    for (uint32_t a = 0; a < stripe; a += 8) {
-        uint32_t c[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const uint32_t j = j0 + a + u;
-            c[u] = (a + u < stripe && j < T) ? cost[j] : 0u;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            if (c[u] != 0u && cost_class(c[u]) >= cls) {
-                const uint32_t pos = atomicAdd(&s_nh, 1u);
-                keys[pos] = ((unsigned long long)(~c[u]) << 32) | (j0 + a + u);
-            }
+    // collect the heavy tiles (in any order: they are sorted next)
+    for (uint32_t j = (uint32_t)tid; j < T; j += 1024u) {
+        const uint32_t c = cost[j];
+        if (c != 0u && cost_class(c) >= cls) {
+            const uint32_t pos = atomicAdd(&s_nh, 1u);
+            keys[pos] = ((unsigned long long)(~c) << 32) | j;
         }
     }
     __syncthreads();
     const uint32_t nh = s_nh;  // <= kTopTiles by the choice of cls
-    // bitonic sort of the heavy keys, ascending: cost descending, then tile
-    if ((uint32_t)tid >= nh) keys[tid] = ~0ull;
-    for (int k = 2; k <= kTopTiles; k <<= 1) {
-        for (int jj = k >> 1; jj > 0; jj >>= 1) {
-            __syncthreads();
-            const int p = tid ^ jj;
-            if (p > tid) {
-                const unsigned long long a = keys[tid], b = keys[p];
-                const bool up = (tid & k) == 0;
-                if ((a > b) == up) {
-                    keys[tid] = b;
-                    keys[p] = a;
+    // bitonic sort of the heavy keys, ascending: cost descending, then tile.
+    // One key per thread; exchanges with partners in the same wave go through
+    // lane shuffles, the others through LDS.
+    unsigned long long key = (uint32_t)tid < nh ? keys[tid] : ~0ull;
+    if (nh > 1) {
+        for (int k = 2; k <= kTopTiles; k <<= 1) {
+            for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                unsigned long long other;
+                if (jj >= 64) {
+                    __syncthreads();  // every thread has read the previous exchange
+                    keys[tid] = key;
+                    __syncthreads();
+                    other = keys[tid ^ jj];
+                } else {
+                    const uint32_t lo = __shfl_xor((uint32_t)key, jj, 64);
+                    const uint32_t hi = __shfl_xor((uint32_t)(key >> 32), jj, 64);
+                    other = ((unsigned long long)hi << 32) | lo;
                 }
+                // the lower index of a pair keeps the smaller key in an
+                // ascending run, the larger one in a descending run
+                const bool up = (tid & k) == 0;
+                const bool lower = (tid & jj) == 0;
+                const bool keep_small = (up == lower);
+                key = keep_small ? (key < other ? key : other) : (key < other ? other : key);
             }
         }
     }
+    __syncthreads();
+    keys[tid] = key;
     __syncthreads();
 
     // ---- 2. splitting

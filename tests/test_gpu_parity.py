@@ -224,3 +224,28 @@ def test_full_size_sampled(torch_cuda, which, flags):
         assert int(st[2]) == oracle.exact_evals(inst.points, _grid(g))
         assert st[0] == pytest.approx(m_pts, rel=1e-5)
     assert st[3] == 0
+
+
+@pytest.mark.parametrize("grid,cells", [
+    ((96, 80, 40), (16, 8)),       # few bins: one 8-bit pass
+    ((512, 512, 64), (4, 4)),      # 2^18 bins: two 10-bit passes
+    ((512, 512, 256), (4, 4)),     # 2^20 bins: two 11-bit passes
+    ((1024, 1024, 256), (4, 4)),   # 2^22 bins: three 8-bit passes
+])
+def test_radix_digit_widths(torch_cuda, grid, cells):
+    """Small bins force keys of 7 to 23 bits through every digit width of the
+    binning sort; the grid is checked on sampled voxels (Alg. VB) and by the
+    exact evaluation count."""
+    import paper_1705_09366_amd as m
+    gx, gy, gt = grid
+    rng = np.random.default_rng(31)
+    pts = rng.uniform(-2, 1, (20_000, 3)) * 0 + rng.uniform(0, 1, (20_000, 3)) * [gx, gy, gt]
+    g = dict(gx=gx, gy=gy, gt=gt, hs=1.3, ht=1.2)
+    _say(f"radix grid {grid} cells {cells}")
+    gpu, st = _run(torch_cuda, pts, g, flags=4 | 8, tuning=m.Tuning(32, cells[0], cells[1]))
+    vox = _sample_voxels(pts, g, rng, m_near=256, m_rand=64)
+    ref = oracle.vb_voxels(pts, _grid(g), vox)
+    got = gpu[vox[:, 0], vox[:, 1], vox[:, 2]].astype(np.float64)
+    assert float(np.max(np.abs(got - ref))) <= TOL * float(np.max(ref))
+    assert int(st[2]) == oracle.exact_evals(pts, _grid(g))
+    assert st[0] == pytest.approx(st[1], rel=1e-6)
