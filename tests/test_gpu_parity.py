@@ -228,9 +228,9 @@ def test_full_size_sampled(torch_cuda, which, flags):
 
 @pytest.mark.parametrize("grid,cells", [
     ((96, 80, 40), (16, 8)),       # few bins: one 8-bit pass
-    ((512, 512, 64), (4, 4)),      # 2^18 bins: two 10-bit passes
-    ((512, 512, 256), (4, 4)),     # 2^20 bins: two 11-bit passes
-    ((1024, 1024, 256), (4, 4)),   # 2^22 bins: three 8-bit passes
+    ((512, 512, 64), (4, 4)),      # 2^18 bins: 19-bit keys, two 10-bit passes
+    ((512, 512, 256), (4, 4)),     # 2^20 bins: 21-bit keys, two 11-bit passes
+    ((1024, 1024, 256), (4, 4)),   # 2^22 bins: 23-bit keys, three 8-bit passes
 ])
 def test_radix_digit_widths(torch_cuda, grid, cells):
     """Small bins force keys of 7 to 23 bits through every digit width of the
@@ -240,7 +240,8 @@ def test_radix_digit_widths(torch_cuda, grid, cells):
     gx, gy, gt = grid
     rng = np.random.default_rng(31)
     pts = rng.uniform(-2, 1, (20_000, 3)) * 0 + rng.uniform(0, 1, (20_000, 3)) * [gx, gy, gt]
-    g = dict(gx=gx, gy=gy, gt=gt, hs=1.3, ht=1.2)
+    # bandwidths below a voxel keep the bins at the requested 4 voxels
+    g = dict(gx=gx, gy=gy, gt=gt, hs=0.9, ht=0.9)
     _say(f"radix grid {grid} cells {cells}")
     gpu, st = _run(torch_cuda, pts, g, flags=4 | 8, tuning=m.Tuning(32, cells[0], cells[1]))
     vox = _sample_voxels(pts, g, rng, m_near=256, m_rand=64)
