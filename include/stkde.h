@@ -79,10 +79,11 @@ typedef struct {
 
 /* Optional tuning of one plan.  Zero fields mean "library default".
  * tile_t must be 0, 16, 32 or 64 (64 is reduced to 32 under STKDE_FLAG_KAHAN);
- * cell_xy and cell_t in [4, 256]; split_share 0 or in [64, 65536].  The plan
- * may enlarge the bins beyond these values when a tile would otherwise read
- * more bin rows than the gather supports.  Tuning changes the summation
- * order, so results differ between tunings in the last bits. */
+ * cell_xy and cell_t in [4, 256]; split_share 0 or in [64, 65536]; kahan_mode
+ * 0, 1 or 2.  The plan may enlarge the bins beyond these values when a tile
+ * would otherwise read more bin rows than the gather supports.  Tuning
+ * changes the summation order, so results differ between tunings in the last
+ * bits -- except kahan_mode, whose settings give identical results. */
 typedef struct {
     int32_t tile_t;      /* voxel rows in time per output tile (16, 32 or 64) */
     int32_t cell_xy;     /* bin edge in x and y, voxels */
@@ -90,6 +91,10 @@ typedef struct {
     int32_t split_share; /* a tile costlier than 1/split_share of its grid's total
                             candidate count (and than 2048 candidates) is split
                             into up to 8 parts; default 2048 */
+    int32_t kahan_mode;  /* with STKDE_FLAG_KAHAN, where the running (sum,
+                            compensation) pair lives: 1 registers, 2 a per-workgroup
+                            scratch slot touched only by tiles that take more
+                            than one pass; 0 picks by the expected points per tile */
 } stkde_tuning;
 
 typedef struct stkde_plan_s* stkde_plan_t;

@@ -19,6 +19,7 @@
 struct stkde_plan_s {
     stkde_desc desc;
     uint32_t split_share;
+    int32_t kahan_mode;  // 0 automatic, else kAccKahanReg / kAccKahanMem
     stkde::InstGeom ig;  // the plan's grid as an instance of its own set
     stkde::SetGeom sg;   // binning of the plan's own points
     // gather timing (stkde_plan_profile): event pairs, filled in order
@@ -47,6 +48,7 @@ struct stkde_batch_s {
     struct Group {
         int tile_t;
         bool kahan;
+        int mode;  // accumulation mode of the gather (kAcc*)
         std::vector<int32_t> idx;
         std::vector<stkde::InstGeom> geo;
         stkde::PassLayout pl;
@@ -63,6 +65,7 @@ namespace {
 constexpr int64_t kMaxDim = 65535;
 constexpr int32_t kMaxCells = 1 << 22;  // keys of at most 23 bits: <= 3 radix passes (<= 2 below 2^22 - 1 bins)
 constexpr int32_t kMaxBatch = 4096;
+constexpr double kSparseCandidates = 384.0;  // half the gather's survivor buffer
 constexpr uint32_t kKnownFlags = STKDE_FLAG_KAHAN | STKDE_FLAG_MASS | STKDE_FLAG_POINT_STATS;
 
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
@@ -92,6 +95,7 @@ stkde_status check_tuning(const stkde_tuning* t) {
     if (t->cell_t != 0 && (t->cell_t < 4 || t->cell_t > 256)) return STKDE_ERR_INVALID_ARG;
     if (t->split_share != 0 && (t->split_share < 64 || t->split_share > 65536))
         return STKDE_ERR_INVALID_ARG;
+    if (t->kahan_mode < 0 || t->kahan_mode > 2) return STKDE_ERR_INVALID_ARG;
     return STKDE_OK;
 }
 
@@ -189,6 +193,23 @@ stkde_status make_inst_geom(const stkde_desc& d, const stkde_desc& base, int32_t
 // the scheduler twice as many, smaller items.
 int32_t default_tile_t(double tv) { return ceil(tv) <= 12.0 ? 32 : 16; }
 
+// Compensated accumulation keeps its running pair in memory when tiles are
+// expected to finish in one matrix-core phase (the pair is then never
+// touched): n points spread over the base grid put about
+// n * (16 + 2 Hs + 2)^2 (TT + 2 Ht + 2) / voxels candidates into a tile's bins.
+// Either mode gives the same bits; this only picks the faster one.
+int acc_mode(bool kahan, int32_t requested, int64_t n, const stkde_desc& base, int32_t Hs, int32_t Ht,
+             int32_t rows) {
+    if (!kahan) return stkde::kAccPlain;
+    if (requested == 1) return stkde::kAccKahanReg;
+    if (requested == 2) return stkde::kAccKahanMem;
+    const double side = 16.0 + 2.0 * Hs + 2.0;
+    const double reach = side * side * (rows + 2.0 * Ht + 2.0);
+    const double vox = (double)base.gx * (double)base.gy * (double)base.gt;
+    const double est = (double)n * (reach < vox ? reach / vox : 1.0);
+    return est <= kSparseCandidates ? stkde::kAccKahanMem : stkde::kAccKahanReg;
+}
+
 // (2/pi) (3/4) / (n hs^2 ht): the constants of both kernels and the
 // estimator's normalisation, rounded once to FP32 at the store.
 float norm_const(double hs, double ht, int64_t n) {
@@ -248,7 +269,7 @@ ComputeLayout layout_compute(const stkde_plan_s* p, int64_t n) {
     ComputeLayout c{};
     c.sl = stkde::layout_set(p->sg, n);
     c.so = stkde::layout_sort(n);
-    c.pl = stkde::layout_pass(&p->ig, 1, p->ig.tile_t);
+    c.pl = stkde::layout_pass(&p->ig, 1, p->ig.tile_t, (p->desc.flags & STKDE_FLAG_KAHAN) != 0);
     c.nblk_pts = (int32_t)((n + stkde::kStatBlock - 1) / stkde::kStatBlock);
     c.pstats = al256((size_t)c.nblk_pts * 4 * 8);
     c.shared = al256(c.sl.total);
@@ -309,6 +330,7 @@ stkde_status stkde_plan(const stkde_desc* d, const stkde_tuning* tun, stkde_plan
     stkde_plan_s tmp;
     tmp.desc = *d;
     tmp.split_share = tun && tun->split_share ? (uint32_t)tun->split_share : stkde::kBalanceItems;
+    tmp.kahan_mode = tun ? tun->kahan_mode : 0;
     make_set_geom(*d, tun ? tun->cell_xy : 0, tun ? tun->cell_t : 0, tile_t, &tmp.sg);
     st = make_inst_geom(*d, *d, tile_t, &tmp.ig);
     if (st != STKDE_OK) return st;
@@ -386,8 +408,10 @@ stkde_status stkde_accumulate(stkde_plan_t p, int64_t n, float* d_out, void* d_w
         e1 = p->ev[(size_t)p->ev_used + 1];
         p->ev_used += 2;
     }
-    if (stkde::launch_pass(&d, 1, c.ws + c.L.shared, c.L.pl, p->ig.tile_t, (fl & STKDE_FLAG_KAHAN) != 0,
-                           c.s, e0, e1) != hipSuccess)
+    const int mode = acc_mode((fl & STKDE_FLAG_KAHAN) != 0, p->kahan_mode, n, p->desc, p->ig.Hs, p->ig.Ht,
+                              p->ig.tile_t);
+    if (stkde::launch_pass(&d, 1, c.ws + c.L.shared, c.L.pl, p->ig.tile_t, mode, c.s, e0, e1) !=
+        hipSuccess)
         return STKDE_ERR_HIP;
     return STKDE_OK;
 }
@@ -492,21 +516,30 @@ stkde_status stkde_batch_plan(const stkde_item* items, int32_t count, stkde_batc
     stkde_batch_s* bt = new (std::nothrow) stkde_batch_s;
     if (!bt) return STKDE_ERR_TOO_LARGE;
     bt->items.assign(items, items + count);
+    // one pass per (tile rows, accumulation mode)
+    std::vector<int> mode((size_t)count);
+    for (int32_t i = 0; i < count; ++i) {
+        const stkde_item& it = items[i];
+        mode[(size_t)i] = acc_mode((it.plan->desc.flags & STKDE_FLAG_KAHAN) != 0, it.plan->kahan_mode,
+                                   it.set->n, it.set->base, geo[(size_t)i].Hs, geo[(size_t)i].Ht,
+                                   geo[(size_t)i].tile_t);
+    }
     const int tts[3] = {16, 32, 64};
-    for (int kahan = 0; kahan < 2; ++kahan) {
+    const int modes[3] = {stkde::kAccPlain, stkde::kAccKahanReg, stkde::kAccKahanMem};
+    for (int md : modes) {
         for (int tt : tts) {
             stkde_batch_s::Group g;
             g.tile_t = tt;
-            g.kahan = kahan != 0;
+            g.mode = md;
+            g.kahan = md != stkde::kAccPlain;
             for (int32_t i = 0; i < count; ++i) {
-                const bool k = (items[i].plan->desc.flags & STKDE_FLAG_KAHAN) != 0;
-                if (k == g.kahan && geo[(size_t)i].tile_t == tt) {
+                if (mode[(size_t)i] == md && geo[(size_t)i].tile_t == tt) {
                     g.idx.push_back(i);
                     g.geo.push_back(geo[(size_t)i]);
                 }
             }
             if (g.idx.empty()) continue;
-            g.pl = stkde::layout_pass(g.geo.data(), (int32_t)g.geo.size(), tt);
+            g.pl = stkde::layout_pass(g.geo.data(), (int32_t)g.geo.size(), tt, g.kahan);
             if (g.pl.T > 0x7fffffffLL) {
                 delete bt;
                 return STKDE_ERR_TOO_LARGE;
@@ -539,7 +572,7 @@ stkde_status batch_enqueue(stkde_batch_t b, uint8_t* ws, hipStream_t s) {
                                     (it.plan->desc.flags & STKDE_FLAG_MASS) != 0,
                                     it.plan->split_share));
         }
-        if (stkde::launch_pass(devs.data(), (int32_t)devs.size(), ws, g.pl, g.tile_t, g.kahan, s) !=
+        if (stkde::launch_pass(devs.data(), (int32_t)devs.size(), ws, g.pl, g.tile_t, g.mode, s) !=
             hipSuccess)
             return STKDE_ERR_HIP;
     }
@@ -557,7 +590,7 @@ stkde_status stkde_batch_run(stkde_batch_t b, void* d_ws, size_t ws_bytes, void*
 stkde_status stkde_batch_capture(stkde_batch_t b, void* d_ws, size_t ws_bytes) {
     if (!b) return STKDE_ERR_INVALID_ARG;
     if (!d_ws || ws_bytes < b->ws_bytes || ((uintptr_t)d_ws & 255u)) return STKDE_ERR_WORKSPACE;
-    for (const auto& g : b->groups) stkde::prepare_gather(g.tile_t, g.kahan);
+    for (const auto& g : b->groups) stkde::prepare_gather(g.tile_t, g.mode);
     hipStream_t cs = nullptr;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return STKDE_ERR_HIP;
     hipGraph_t graph = nullptr;

@@ -75,16 +75,17 @@ __device__ inline float half_hi(uint32_t v) {
     return (float)__builtin_bit_cast(_Float16, (uint16_t)(v >> 16));
 }
 
+// (sum, comp) += pass by Kahan's rule; pass is cleared.
 template <int CG>
-__device__ inline void kahan_fold(f32x4 (&acc)[CG], f32x4 (&comp)[CG], f32x4 (&pass)[CG]) {
+__device__ inline void kahan_fold(f32x4 (&sum)[CG], f32x4 (&comp)[CG], f32x4 (&pass)[CG]) {
 #pragma unroll
     for (int q = 0; q < CG; ++q) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const float y = __fsub_rn(pass[q][e], comp[q][e]);
-            const float t = __fadd_rn(acc[q][e], y);
-            comp[q][e] = __fsub_rn(__fsub_rn(t, acc[q][e]), y);
-            acc[q][e] = t;
+            const float t = __fadd_rn(sum[q][e], y);
+            comp[q][e] = __fsub_rn(__fsub_rn(t, sum[q][e]), y);
+            sum[q][e] = t;
             pass[q][e] = 0.0f;
         }
     }
@@ -95,16 +96,20 @@ __device__ inline void kahan_fold(f32x4 (&acc)[CG], f32x4 (&comp)[CG], f32x4 (&p
 // spill outside the matrix-core loop; measured 4-7 % faster than three
 // workgroups).  With 768 survivors the LDS holds five workgroups where the
 // registers allow it.
-template <int TT, bool KAHAN>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_gather_items(const InstDev* __restrict__ descs,
-                                                           int32_t count, int32_t ntiles_total,
-                                                           const WorkItem* __restrict__ items,
-                                                           const uint32_t* __restrict__ bits,
-                                                           const uint32_t* __restrict__ sc,
-                                                           uint32_t* __restrict__ ctr,
-                                                           float* __restrict__ partials) {
+template <int TT, int MODE>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_gather_items(
+    const InstDev* __restrict__ descs, int32_t count, int32_t ntiles_total,
+    const WorkItem* __restrict__ items, const uint32_t* __restrict__ bits,
+    const uint32_t* __restrict__ sc, uint32_t* __restrict__ ctr, float* __restrict__ partials,
+    float* __restrict__ kscratch) {
     constexpr int NB = TT / 16;  // 16-row blocks per tile
     constexpr int CG = 4 * NB;   // accumulator blocks per wave
+    // Kahan with the running (sum, compensation) in memory: this thread's
+    // slot of kscratch, sum of block k at [k], compensation at [CG + k]
+    f32x4* __restrict__ kslot =
+        MODE == kAccKahanMem
+            ? reinterpret_cast<f32x4*>(kscratch) + ((size_t)blockIdx.x * kThreads + threadIdx.x) * (2 * CG)
+            : nullptr;
     constexpr int kPad = kCap;   // index of the padding survivor
     // survivor list: tile-local coordinates as (head, tail) pairs and the
     // quadrants its footprint box meets; entry kPad is a point far outside
@@ -196,7 +201,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                         len = (int32_t)D.cell_start[row + tb.cx1 + 1] - beg;
                     }
                     int32_t inc = len;
-    #pragma unroll
+#pragma unroll
                     for (int d = 1; d < 64; d <<= 1) {
                         const int32_t o = __shfl_up(inc, d, 64);
                         if (lane >= d) inc += o;
@@ -212,50 +217,50 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                 const int32_t cend = it.cend == kAll ? total : min((int32_t)it.cend, total);
                 const PointRec* __restrict__ recs = D.recs;
 
-                // ---- accumulators: [column group q][row block b] ----------------
+                // ---- accumulators: [column group q][row block b].  acc is the
+                // matrix-core target: the whole sum in plain mode, the current
+                // phase's sum with Kahan; sum and comp hold the running Kahan
+                // pair in registers (in kslot in memory mode).
+                constexpr bool REG = MODE == kAccKahanReg;
                 f32x4 acc[CG];
-                f32x4 comp[KAHAN ? CG : 1];
-                f32x4 pass[KAHAN ? CG : 1];
-    #pragma unroll
+                f32x4 sum[REG ? CG : 1];
+                f32x4 comp[REG ? CG : 1];
+#pragma unroll
                 for (int k = 0; k < CG; ++k) {
                     acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
-                    if constexpr (KAHAN) {
+                    if constexpr (REG) {
+                        sum[k] = f32x4{0.f, 0.f, 0.f, 0.f};
                         comp[k] = f32x4{0.f, 0.f, 0.f, 0.f};
-                        pass[k] = f32x4{0.f, 0.f, 0.f, 0.f};
                     }
                 }
+                int32_t nphase = 0;
 
                 // one group: operands from the coordinates of this lane's point,
                 // then all CG instructions
                 auto group = [&](const float2 cx, const float2 cy, const float2 ctt) {
                     float av[NB];
-    #pragma unroll
+#pragma unroll
                     for (int b = 0; b < NB; ++b) {
                         const float dt = ((rowc + 16.0f * b) - ctt.x) - ctt.y;
                         // the operands never exceed 1, so max(0, .) is a clamp to
-                    // [0, 1], which folds into the producing instruction
-                    av[b] = __builtin_amdgcn_fmed3f(fmaf(-dt * dt, inv_tv2, 1.0f), 0.0f, 1.0f);
+                        // [0, 1], which folds into the producing instruction
+                        av[b] = __builtin_amdgcn_fmed3f(fmaf(-dt * dt, inv_tv2, 1.0f), 0.0f, 1.0f);
                     }
                     float ux[2], uy[2];
-    #pragma unroll
+#pragma unroll
                     for (int h = 0; h < 2; ++h) {
                         const float dx = ((xc0 + 4.0f * h) - cx.x) - cx.y;
                         const float dy = ((yc0 + 4.0f * h) - cy.x) - cy.y;
                         ux[h] = fmaf(-dx * dx, inv_hv2, 1.0f);
                         uy[h] = dy * dy * inv_hv2;
                     }
-    #pragma unroll
+#pragma unroll
                     for (int g = 0; g < 4; ++g) {
                         const float ks = __builtin_amdgcn_fmed3f(ux[g & 1] - uy[g >> 1], 0.0f, 1.0f);
-    #pragma unroll
-                        for (int b = 0; b < NB; ++b) {
-                            if constexpr (KAHAN)
-                                pass[g * NB + b] =
-                                    __builtin_amdgcn_mfma_f32_16x16x4f32(av[b], ks, pass[g * NB + b], 0, 0, 0);
-                            else
-                                acc[g * NB + b] =
-                                    __builtin_amdgcn_mfma_f32_16x16x4f32(av[b], ks, acc[g * NB + b], 0, 0, 0);
-                        }
+#pragma unroll
+                        for (int b = 0; b < NB; ++b)
+                            acc[g * NB + b] =
+                                __builtin_amdgcn_mfma_f32_16x16x4f32(av[b], ks, acc[g * NB + b], 0, 0, 0);
                     }
                 };
 
@@ -292,7 +297,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                         if (lane == 0) sWC[wave] = __popcll(m);
                         __syncthreads();
                         int32_t off = count_s, add = 0;
-    #pragma unroll
+#pragma unroll
                         for (int w = 0; w < kWaves; ++w) {
                             const int32_t cw = sWC[w];
                             off += (w < wave) ? cw : 0;
@@ -341,19 +346,51 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                             group(bx, by, bt);
                         }
                     }
-                    if constexpr (KAHAN) kahan_fold<CG>(acc, comp, pass);
+                    if constexpr (MODE == kAccKahanReg) {
+                        kahan_fold<CG>(sum, comp, acc);
+                    } else if constexpr (MODE == kAccKahanMem) {
+                        // the same operations as in registers; a tile that ends in
+                        // its first phase (sum = comp = 0) keeps acc as it is
+                        const bool last = bb >= cend;
+                        if (!(nphase == 0 && last)) {
+#pragma unroll
+                            for (int k = 0; k < CG; ++k) {
+                                const f32x4 s0 = nphase == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : kslot[k];
+                                const f32x4 c0 = nphase == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : kslot[CG + k];
+                                f32x4 t, c1;
+#pragma unroll
+                                for (int e = 0; e < 4; ++e) {
+                                    const float y = __fsub_rn(acc[k][e], c0[e]);
+                                    t[e] = __fadd_rn(s0[e], y);
+                                    c1[e] = __fsub_rn(__fsub_rn(t[e], s0[e]), y);
+                                }
+                                if (last) {
+                                    acc[k] = t;
+                                } else {
+                                    kslot[k] = t;
+                                    kslot[CG + k] = c1;
+                                    acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+                                }
+                            }
+                        }
+                    }
+                    ++nphase;
                     __syncthreads();  // the lists are refilled next
                 }
 
                 // ---- store: lane holds rows 16 b + 4 (lane / 16) + e of column
                 // (lane % 4, (lane / 4) % 4) of each of its column groups -------------
+                if constexpr (REG) {
+#pragma unroll
+                    for (int k = 0; k < CG; ++k) acc[k] = sum[k];
+                }
                 if (it.slot != kNoSlot) {
                     float* P = partials + (size_t)it.slot * (kTileXY * kTileXY * TT);
-    #pragma unroll
+#pragma unroll
                     for (int g = 0; g < 4; ++g) {
                         const int32_t lx = 4 * gqx + 4 * (g & 1) + (lane & 3);
                         const int32_t ly = 4 * gqy + 4 * (g >> 1) + ((lane >> 2) & 3);
-    #pragma unroll
+#pragma unroll
                         for (int b = 0; b < NB; ++b)
                             *reinterpret_cast<f32x4*>(P + (lx * kTileXY + ly) * TT + 16 * b + 4 * (lane >> 4)) =
                                 acc[g * NB + b];
@@ -366,13 +403,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                 float* __restrict__ out = D.out;
                 double msum = 0.0;
                 const bool vec = (gtI & 3) == 0;
-    #pragma unroll
+#pragma unroll
                 for (int g = 0; g < 4; ++g) {
                     const int32_t X = X0 + 4 * gqx + 4 * (g & 1) + (lane & 3);
                     const int32_t Y = Y0 + 4 * gqy + 4 * (g >> 1) + ((lane >> 2) & 3);
                     if (X >= gxI || Y >= gyI) continue;
                     float* col = out + ((size_t)X * gyI + Y) * gtI;
-    #pragma unroll
+#pragma unroll
                     for (int b = 0; b < NB; ++b) {
                         const int32_t T = T0 + 16 * b + 4 * (lane >> 4);
                         const f32x4 v = acc[g * NB + b] * cnorm;
@@ -380,7 +417,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                             *reinterpret_cast<f32x4*>(col + T) = v;
                             msum += (double)v[0] + (double)v[1] + (double)v[2] + (double)v[3];
                         } else {
-    #pragma unroll
+#pragma unroll
                             for (int e = 0; e < 4; ++e) {
                                 if (T + e < gtI) {
                                     col[T + e] = v[e];
@@ -391,7 +428,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                     }
                 }
                 if (mass) {
-    #pragma unroll
+#pragma unroll
                     for (int d = 32; d >= 1; d >>= 1) msum += __shfl_xor(msum, d, 64);
                     if (lane == 0) D.tile_part[(size_t)tile * kWaves + wave] = msum;
                 }
@@ -463,8 +500,9 @@ __global__ __launch_bounds__(kThreads) void k_reduce_split(const InstDev* __rest
 }
 
 // Workgroups of the persistent gather: compute units x resident workgroups
-// per compute unit, cached per device.
-template <int TT, bool K>
+// per compute unit, cached per device (memory-mode Kahan at most
+// kMemKahanGroups, the slots of its scratch).
+template <int TT, int MODE>
 int resident_groups() {
     static std::atomic<int> cache[kMaxDevices];
     int dev = 0;
@@ -473,23 +511,25 @@ int resident_groups() {
     if (v > 0) return v;
     int ncu = 0, occ = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_gather_items<TT, K>, kThreads, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_gather_items<TT, MODE>, kThreads, 0) !=
         hipSuccess)
         occ = 0;
     v = (ncu > 0 ? ncu : 256) * (occ > 0 ? occ : 1);
+    if (MODE == kAccKahanMem && v > kMemKahanGroups) v = kMemKahanGroups;
     cache[dev].store(v, std::memory_order_relaxed);
     return v;
 }
 
-template <int TT, bool K>
+template <int TT, int MODE>
 void launch_items_t(const InstDev* d, int32_t count, const WorkItem* items, const uint32_t* bits,
-                    const uint32_t* sc, uint32_t* ctr, float* partials, int64_t T, hipStream_t s) {
-    int64_t g = resident_groups<TT, K>();
+                    const uint32_t* sc, uint32_t* ctr, float* partials, float* kscratch, int64_t T,
+                    hipStream_t s) {
+    int64_t g = resident_groups<TT, MODE>();
     const int64_t most = T + kPartSlots;  // items never exceed tiles + partial slots
     if (g > most) g = most;
     if (g < 1) g = 1;
-    hipLaunchKernelGGL((k_gather_items<TT, K>), dim3((uint32_t)g), dim3(kThreads), 0, s, d, count,
-                       (int32_t)T, items, bits, sc, ctr, partials);
+    hipLaunchKernelGGL((k_gather_items<TT, MODE>), dim3((uint32_t)g), dim3(kThreads), 0, s, d, count,
+                       (int32_t)T, items, bits, sc, ctr, partials, kscratch);
 }
 
 template <int TT, bool K>
@@ -503,24 +543,38 @@ void launch_reduce_t(const InstDev* d, int32_t count, const uint32_t* top, const
 
 hipError_t launch_gather_items(const InstDev* d_desc, int32_t count, const WorkItem* d_items,
                                const uint32_t* d_bits, const uint32_t* d_scalars,
-                               uint32_t* d_counters, float* d_partials, int64_t T, int tile_t,
-                               bool kahan, hipStream_t s) {
+                               uint32_t* d_counters, float* d_partials, float* d_kscratch, int64_t T,
+                               int tile_t, int mode, hipStream_t s) {
+#define STKDE_ITEMS(TT, M) \
+    launch_items_t<TT, M>(d_desc, count, d_items, d_bits, d_scalars, d_counters, d_partials, \
+                          d_kscratch, T, s)
     if (tile_t == 16) {
-        kahan ? launch_items_t<16, true>(d_desc, count, d_items, d_bits, d_scalars, d_counters, d_partials, T, s)
-              : launch_items_t<16, false>(d_desc, count, d_items, d_bits, d_scalars, d_counters, d_partials, T, s);
+        if (mode == kAccKahanReg) STKDE_ITEMS(16, kAccKahanReg);
+        else if (mode == kAccKahanMem) STKDE_ITEMS(16, kAccKahanMem);
+        else STKDE_ITEMS(16, kAccPlain);
     } else if (tile_t == 32) {
-        kahan ? launch_items_t<32, true>(d_desc, count, d_items, d_bits, d_scalars, d_counters, d_partials, T, s)
-              : launch_items_t<32, false>(d_desc, count, d_items, d_bits, d_scalars, d_counters, d_partials, T, s);
+        if (mode == kAccKahanReg) STKDE_ITEMS(32, kAccKahanReg);
+        else if (mode == kAccKahanMem) STKDE_ITEMS(32, kAccKahanMem);
+        else STKDE_ITEMS(32, kAccPlain);
     } else {
-        launch_items_t<64, false>(d_desc, count, d_items, d_bits, d_scalars, d_counters, d_partials, T, s);
+        STKDE_ITEMS(64, kAccPlain);
     }
+#undef STKDE_ITEMS
     return hipGetLastError();
 }
 
-void prepare_gather(int tile_t, bool kahan) {
-    if (tile_t == 16) (void)(kahan ? resident_groups<16, true>() : resident_groups<16, false>());
-    else if (tile_t == 32) (void)(kahan ? resident_groups<32, true>() : resident_groups<32, false>());
-    else (void)resident_groups<64, false>();
+void prepare_gather(int tile_t, int mode) {
+    if (tile_t == 16) {
+        if (mode == kAccKahanReg) (void)resident_groups<16, kAccKahanReg>();
+        else if (mode == kAccKahanMem) (void)resident_groups<16, kAccKahanMem>();
+        else (void)resident_groups<16, kAccPlain>();
+    } else if (tile_t == 32) {
+        if (mode == kAccKahanReg) (void)resident_groups<32, kAccKahanReg>();
+        else if (mode == kAccKahanMem) (void)resident_groups<32, kAccKahanMem>();
+        else (void)resident_groups<32, kAccPlain>();
+    } else {
+        (void)resident_groups<64, kAccPlain>();
+    }
 }
 
 hipError_t launch_reduce_split(const InstDev* d_desc, int32_t count, const uint32_t* d_top,

@@ -298,7 +298,7 @@ __global__ __launch_bounds__(64) void k_finalize(const InstDev* __restrict__ des
 
 }  // namespace
 
-PassLayout layout_pass(const InstGeom* inst, int32_t count, int tile_t) {
+PassLayout layout_pass(const InstGeom* inst, int32_t count, int tile_t, bool kahan) {
     PassLayout l{};
     int64_t T = 0, parts = 0;
     for (int32_t i = 0; i < count; ++i) {
@@ -317,6 +317,9 @@ PassLayout layout_pass(const InstGeom* inst, int32_t count, int tile_t) {
     l.top = o; o = al256(o + (size_t)kTopTiles * 16);
     l.items = o; o = al256(o + (size_t)kTopTiles * kMaxParts * sizeof(WorkItem));
     l.partials = o; o = al256(o + (size_t)kPartSlots * kTileXY * kTileXY * tile_t * 4);
+    l.kscratch = o;
+    // per thread: (sum, compensation) of 4 column groups x tile_t/16 row blocks, f32x4 each
+    if (kahan) o = al256(o + (size_t)kMemKahanGroups * kThreads * 2 * (4 * (tile_t / 16)) * 16);
     l.tile_part = o; o = al256(o + (size_t)parts * 8);
     l.mass_mid = o; o = al256(o + (size_t)count * kMassChunks * 8);
     l.total = o;
@@ -324,8 +327,9 @@ PassLayout layout_pass(const InstGeom* inst, int32_t count, int tile_t) {
 }
 
 hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassLayout& pl,
-                       int tile_t, bool kahan, hipStream_t s, hipEvent_t ev_before,
+                       int tile_t, int mode, hipStream_t s, hipEvent_t ev_before,
                        hipEvent_t ev_after) {
+    const bool kahan = mode != kAccPlain;
     InstDev* d_desc = reinterpret_cast<InstDev*>(pass + pl.desc);
     auto* inst_cost = reinterpret_cast<unsigned long long*>(pass + pl.inst_cost);
     auto* cost = reinterpret_cast<uint32_t*>(pass + pl.cost);
@@ -336,6 +340,7 @@ hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassL
     auto* top = reinterpret_cast<uint32_t*>(pass + pl.top);
     auto* items = reinterpret_cast<WorkItem*>(pass + pl.items);
     auto* partials = reinterpret_cast<float*>(pass + pl.partials);
+    auto* kscratch = reinterpret_cast<float*>(pass + pl.kscratch);
     auto* tile_part = reinterpret_cast<double*>(pass + pl.tile_part);
     auto* mid = reinterpret_cast<double*>(pass + pl.mass_mid);
 
@@ -362,7 +367,8 @@ hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassL
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev_before && (e = hipEventRecord(ev_before, s)) != hipSuccess) return e;
-    e = launch_gather_items(d_desc, count, items, bits, sc, ctr, partials, pl.T, tile_t, kahan, s);
+    e = launch_gather_items(d_desc, count, items, bits, sc, ctr, partials, kscratch, pl.T, tile_t, mode,
+                            s);
     if (e != hipSuccess) return e;
     if (ev_after && (e = hipEventRecord(ev_after, s)) != hipSuccess) return e;
     e = launch_reduce_split(d_desc, count, top, sc, partials, tile_t, kahan, s);

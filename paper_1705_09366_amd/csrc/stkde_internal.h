@@ -107,7 +107,16 @@ constexpr int kMaxParts = 8;                          // parts of one split tile
 constexpr int kPartSlots = 1024;                      // partial tiles of one pass
 constexpr uint32_t kSplitFloor = 2048;                // never split below this many candidates
 constexpr uint32_t kBalanceItems = 2048;              // default split share of an instance's cost
-constexpr int kMassChunks = 64;                       // first-level chunks of an instance's mass sum
+constexpr int kMassChunks = 64;
+// Accumulation modes of the gather: plain FP32; Kahan with the running
+// (sum, compensation) pair in registers; the same pair kept in a per-workgroup
+// scratch slot, touched only when a tile takes more than one phase (fewer
+// registers, so more resident workgroups).  The two Kahan modes perform the
+// same operations in the same order and give identical bits.
+constexpr int kAccPlain = 0;
+constexpr int kAccKahanReg = 1;
+constexpr int kAccKahanMem = 2;
+constexpr int kMemKahanGroups = 1536;  // workgroups (scratch slots) in memory mode                       // first-level chunks of an instance's mass sum
 constexpr int kDescChunk = 16;                        // descriptors written per launch
 // Cost class of a tile: the FP32 bit pattern of its candidate count without
 // the low 20 bits (exponent and 3 mantissa bits), monotone in the count.
@@ -163,12 +172,13 @@ struct PassLayout {
     size_t top;          // kTopTiles x 4 u32 split tiles: tile, parts, slot0, candidates
     size_t items;        // kTopTiles * kMaxParts WorkItem (the heaviest-first queue)
     size_t partials;     // kPartSlots x 16 x 16 x tile_t FP32
+    size_t kscratch;     // Kahan plans: kMemKahanGroups x kThreads x 2 x (4 tile_t/16) f32x4
     size_t tile_part;    // sum over instances of ntiles * kWaves FP64
     size_t mass_mid;     // count * kMassChunks FP64
     size_t total;
     int64_t T;           // total tiles
 };
-PassLayout layout_pass(const InstGeom* inst, int32_t count, int tile_t);
+PassLayout layout_pass(const InstGeom* inst, int32_t count, int tile_t, bool kahan);
 
 // Instance holding global tile `tile` (descriptors ordered by tile_base).
 __device__ inline int32_t find_inst(const InstDev* __restrict__ d, int32_t count, uint32_t tile) {
@@ -239,16 +249,16 @@ hipError_t launch_bin(const SetGeom& g, const double* d_xyt, int32_t n, uint8_t*
 // ev_before / ev_after (may be null) are recorded on s right before and
 // right after the gather kernel.
 hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassLayout& pl,
-                       int tile_t, bool kahan, hipStream_t s, hipEvent_t ev_before = nullptr,
+                       int tile_t, int mode, hipStream_t s, hipEvent_t ev_before = nullptr,
                        hipEvent_t ev_after = nullptr);
 // The gather proper (called by launch_pass).
 hipError_t launch_gather_items(const InstDev* d_desc, int32_t count, const WorkItem* d_items,
                                const uint32_t* d_bits, const uint32_t* d_scalars,
-                               uint32_t* d_counters, float* d_partials, int64_t T, int tile_t,
-                               bool kahan, hipStream_t s);
+                               uint32_t* d_counters, float* d_partials, float* d_kscratch, int64_t T,
+                               int tile_t, int mode, hipStream_t s);
 // Query (and cache) the gather's launch size for the current device ahead of a
 // stream capture.
-void prepare_gather(int tile_t, bool kahan);
+void prepare_gather(int tile_t, int mode);
 hipError_t launch_reduce_split(const InstDev* d_desc, int32_t count, const uint32_t* d_top,
                                const uint32_t* d_scalars, const float* d_partials, int tile_t,
                                bool kahan, hipStream_t s);

@@ -250,3 +250,28 @@ def test_radix_digit_widths(torch_cuda, grid, cells):
     assert float(np.max(np.abs(got - ref))) <= TOL * float(np.max(ref))
     assert int(st[2]) == oracle.exact_evals(pts, _grid(g))
     assert st[0] == pytest.approx(st[1], rel=1e-6)
+
+
+@pytest.mark.parametrize("split_share", [0, 65536])
+def test_kahan_modes_identical(torch_cuda, split_share):
+    """Compensated accumulation with its running pair in registers or in the
+    per-workgroup scratch slot performs the same operations: identical bits,
+    also for tiles that take many passes (a dense pile) and for split parts."""
+    import paper_1705_09366_amd as m
+    rng = np.random.default_rng(41)
+    g = dict(gx=48, gy=48, gt=40, hs=6.0, ht=5.0)
+    pile = np.array([24.0, 24.0, 20.0]) + rng.uniform(0, 1, (30_000, 3))
+    pts = np.concatenate([pile, rng.uniform(0, 1, (3000, 3)) * [48, 48, 40]])
+    res = []
+    for mode in (1, 2):
+        for tt in (16, 32):
+            _say(f"kahan mode {mode} tile_t {tt} split_share {split_share}")
+            out, st = _run(torch_cuda, pts, g, flags=1 | 4,
+                           tuning=m.Tuning(tile_t=tt, split_share=split_share, kahan_mode=mode))
+            res.append((mode, tt, out, st))
+    ref, _ = oracle.pbsym(pts, _grid(g))
+    for mode, tt, out, st in res:
+        _check_close(out, ref)
+    for tt in (16, 32):
+        a = [r for r in res if r[1] == tt]
+        assert np.array_equal(a[0][2], a[1][2]) and np.array_equal(a[0][3], a[1][3])
