@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libstkde.so")
 SOURCES = ["api.hip", "bin.hip", "gather.hip", "pass.hip", "stats.hip"]
 ARCH = os.environ.get("STKDE_OFFLOAD_ARCH", "gfx950")
 
-COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+COMMON = ["-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           # matrix-core accumulators in VGPRs: the gather skips untouched blocks
           # with uniform branches, and AGPR accumulators would be copied to

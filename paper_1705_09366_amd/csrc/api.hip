@@ -49,6 +49,7 @@ struct stkde_batch_s {
         int tile_t;
         bool kahan;
         int mode;  // accumulation mode of the gather (kAcc*)
+        bool full; // full-cover path
         std::vector<int32_t> idx;
         std::vector<stkde::InstGeom> geo;
         stkde::PassLayout pl;
@@ -209,6 +210,9 @@ int acc_mode(bool kahan, int32_t requested, int64_t n, const stkde_desc& base, i
     const double est = (double)n * (reach < vox ? reach / vox : 1.0);
     return est <= kSparseCandidates ? stkde::kAccKahanMem : stkde::kAccKahanReg;
 }
+
+// The gather's full-cover path pays off when discs are large against a tile.
+bool use_full(double hv, int32_t tile_t) { return tile_t <= 32 && hv >= stkde::kFullMinHv; }
 
 // (2/pi) (3/4) / (n hs^2 ht): the constants of both kernels and the
 // estimator's normalisation, rounded once to FP32 at the store.
@@ -410,8 +414,8 @@ stkde_status stkde_accumulate(stkde_plan_t p, int64_t n, float* d_out, void* d_w
     }
     const int mode = acc_mode((fl & STKDE_FLAG_KAHAN) != 0, p->kahan_mode, n, p->desc, p->ig.Hs, p->ig.Ht,
                               p->ig.tile_t);
-    if (stkde::launch_pass(&d, 1, c.ws + c.L.shared, c.L.pl, p->ig.tile_t, mode, c.s, e0, e1) !=
-        hipSuccess)
+    if (stkde::launch_pass(&d, 1, c.ws + c.L.shared, c.L.pl, p->ig.tile_t, mode,
+                           use_full(p->ig.hv, p->ig.tile_t), c.s, e0, e1) != hipSuccess)
         return STKDE_ERR_HIP;
     return STKDE_OK;
 }
@@ -526,26 +530,30 @@ stkde_status stkde_batch_plan(const stkde_item* items, int32_t count, stkde_batc
     }
     const int tts[3] = {16, 32, 64};
     const int modes[3] = {stkde::kAccPlain, stkde::kAccKahanReg, stkde::kAccKahanMem};
-    for (int md : modes) {
-        for (int tt : tts) {
-            stkde_batch_s::Group g;
-            g.tile_t = tt;
-            g.mode = md;
-            g.kahan = md != stkde::kAccPlain;
-            for (int32_t i = 0; i < count; ++i) {
-                if (mode[(size_t)i] == md && geo[(size_t)i].tile_t == tt) {
-                    g.idx.push_back(i);
-                    g.geo.push_back(geo[(size_t)i]);
+    for (int fl = 0; fl < 2; ++fl) {
+        for (int md : modes) {
+            for (int tt : tts) {
+                stkde_batch_s::Group g;
+                g.tile_t = tt;
+                g.mode = md;
+                g.full = fl != 0;
+                g.kahan = md != stkde::kAccPlain;
+                for (int32_t i = 0; i < count; ++i) {
+                    if (mode[(size_t)i] == md && geo[(size_t)i].tile_t == tt &&
+                        use_full(geo[(size_t)i].hv, tt) == g.full) {
+                        g.idx.push_back(i);
+                        g.geo.push_back(geo[(size_t)i]);
+                    }
                 }
+                if (g.idx.empty()) continue;
+                g.pl = stkde::layout_pass(g.geo.data(), (int32_t)g.geo.size(), tt, g.kahan);
+                if (g.pl.T > 0x7fffffffLL) {
+                    delete bt;
+                    return STKDE_ERR_TOO_LARGE;
+                }
+                bt->ws_bytes = std::max(bt->ws_bytes, g.pl.total);
+                bt->groups.push_back(std::move(g));
             }
-            if (g.idx.empty()) continue;
-            g.pl = stkde::layout_pass(g.geo.data(), (int32_t)g.geo.size(), tt, g.kahan);
-            if (g.pl.T > 0x7fffffffLL) {
-                delete bt;
-                return STKDE_ERR_TOO_LARGE;
-            }
-            bt->ws_bytes = std::max(bt->ws_bytes, g.pl.total);
-            bt->groups.push_back(std::move(g));
         }
     }
     *out = bt;
@@ -572,7 +580,7 @@ stkde_status batch_enqueue(stkde_batch_t b, uint8_t* ws, hipStream_t s) {
                                     (it.plan->desc.flags & STKDE_FLAG_MASS) != 0,
                                     it.plan->split_share));
         }
-        if (stkde::launch_pass(devs.data(), (int32_t)devs.size(), ws, g.pl, g.tile_t, g.mode, s) !=
+        if (stkde::launch_pass(devs.data(), (int32_t)devs.size(), ws, g.pl, g.tile_t, g.mode, g.full, s) !=
             hipSuccess)
             return STKDE_ERR_HIP;
     }
@@ -590,7 +598,7 @@ stkde_status stkde_batch_run(stkde_batch_t b, void* d_ws, size_t ws_bytes, void*
 stkde_status stkde_batch_capture(stkde_batch_t b, void* d_ws, size_t ws_bytes) {
     if (!b) return STKDE_ERR_INVALID_ARG;
     if (!d_ws || ws_bytes < b->ws_bytes || ((uintptr_t)d_ws & 255u)) return STKDE_ERR_WORKSPACE;
-    for (const auto& g : b->groups) stkde::prepare_gather(g.tile_t, g.mode);
+    for (const auto& g : b->groups) stkde::prepare_gather(g.tile_t, g.mode, g.full);
     hipStream_t cs = nullptr;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return STKDE_ERR_HIP;
     hipGraph_t graph = nullptr;

@@ -65,6 +65,8 @@ namespace {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kCap = 768;  // survivors held in LDS between matrix-core phases
+constexpr uint32_t kFullFlag = 0x10u;      // survivor mask: disc covers the whole tile
+constexpr float kFullMargin = 0.99998f;    // largest a + b at a tile corner for that
 constexpr int kMaxDevices = 64;
 
 __device__ inline float half_lo(uint32_t v) {
@@ -96,7 +98,7 @@ __device__ inline void kahan_fold(f32x4 (&sum)[CG], f32x4 (&comp)[CG], f32x4 (&p
 // spill outside the matrix-core loop; measured 4-7 % faster than three
 // workgroups).  With 768 survivors the LDS holds five workgroups where the
 // registers allow it.
-template <int TT, int MODE>
+template <int TT, int MODE, bool FULL>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_gather_items(
     const InstDev* __restrict__ descs, int32_t count, int32_t ntiles_total,
     const WorkItem* __restrict__ items, const uint32_t* __restrict__ bits,
@@ -114,10 +116,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
     // survivor list: tile-local coordinates as (head, tail) pairs and the
     // quadrants its footprint box meets; entry kPad is a point far outside
     // every tile
-    __shared__ float2 sX[kCap + 1], sY[kCap + 1], sT[kCap + 1];
+    // (one block, so that the full-cover partial sums can reuse it)
+    __shared__ float2 sXYT[3 * (kCap + 1)];
+    float2* const sX = sXYT;
+    float2* const sY = sXYT + (kCap + 1);
+    float2* const sT = sXYT + 2 * (kCap + 1);
     __shared__ uint8_t sQ[kCap];
-    // per-wave lists of survivor indices
-    __shared__ uint16_t sL[kWaves][kCap + 8];
+    // per-wave lists of survivor indices: the quadrant list, then (full-cover
+    // path) the wave's share of the full-cover list, each padded to 8
+    __shared__ uint16_t sL[kWaves][kCap + 16];
     __shared__ int32_t sRB[kMaxRanges];
     __shared__ int32_t sRP[kMaxRanges + 1];
     __shared__ int32_t sWC[kWaves];
@@ -264,6 +271,32 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                     }
                 };
 
+                // full-cover group: A = Kt of one (point, row), B = a(x) - 1 and
+                // b(y) of one (point, column), a = dx^2/hv^2, b = dy^2/hv^2
+                f32x4 fa[FULL ? NB : 1], fb[FULL ? NB : 1];
+#pragma unroll
+                for (int b = 0; b < (FULL ? NB : 1); ++b) {
+                    fa[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+                    fb[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+                }
+                auto group_full = [&](const float2 cx, const float2 cy, const float2 ctt) {
+                    float av[NB];
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        const float dt = ((rowc + 16.0f * b) - ctt.x) - ctt.y;
+                        av[b] = __builtin_amdgcn_fmed3f(fmaf(-dt * dt, inv_tv2, 1.0f), 0.0f, 1.0f);
+                    }
+                    const float dx = (rowc - cx.x) - cx.y;  // column x = lane % 16
+                    const float dy = (rowc - cy.x) - cy.y;  // column y = lane % 16
+                    const float am1 = fmaf(dx * dx, inv_hv2, -1.0f);
+                    const float bv = dy * dy * inv_hv2;
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        fa[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[b], am1, fa[b], 0, 0, 0);
+                        fb[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[b], bv, fb[b], 0, 0, 0);
+                    }
+                };
+
                 int32_t bb = (int32_t)min(it.cbeg, (uint32_t)cend);
                 while (bb < cend) {
                     // ---- stage: fill the survivor list ------------------------------
@@ -290,6 +323,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                                 const bool y0 = ylo <= 7 && yhi >= 0, y1 = ylo <= 15 && yhi >= 8;
                                 qm = (uint32_t)(x0 && y0) | ((uint32_t)(x1 && y0) << 1) |
                                      ((uint32_t)(x0 && y1) << 2) | ((uint32_t)(x1 && y1) << 3);
+                                if constexpr (FULL) {
+                                    // the disc covers every column centre of the tile
+                                    // (its farthest corner with a margin): the
+                                    // spatial kernel is then 1 - a(x) - b(y) on the
+                                    // whole tile, separable in x and y
+                                    const float px = (r.xh - (float)BX0) + half_lo(r.xl_yl);
+                                    const float py = (r.yh - (float)BY0) + half_hi(r.xl_yl);
+                                    const float dxm = fmaxf(fabsf(0.5f - px), fabsf(15.5f - px));
+                                    const float dym = fmaxf(fabsf(0.5f - py), fabsf(15.5f - py));
+                                    if ((dxm * dxm + dym * dym) * inv_hv2 <= kFullMargin) qm = kFullFlag;
+                                }
                             }
                             surv = qm != 0;
                         }
@@ -328,6 +372,23 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                     // pad to a whole number of pairs of groups
                     if (lane < ((8 - (nw & 7)) & 7)) myL[nw + lane] = (uint16_t)kPad;
                     const int32_t npairs = (nw + 7) >> 3;
+                    // full-cover survivors, dealt to the waves in groups of 4 by rank
+                    int32_t nfull = 0, nf = 0;
+                    uint16_t* const myF = myL + 8 * npairs;
+                    if constexpr (FULL) {
+                        for (int32_t base = 0; base < count_s; base += 64) {
+                            const int32_t s = base + lane;
+                            const bool isf = s < count_s && (sQ[s] & kFullFlag);
+                            const unsigned long long fm = __ballot(isf);
+                            const int32_t rk = nfull + __popcll(fm & lt);
+                            const bool mine = isf && ((rk >> 2) & 3) == wave;
+                            const unsigned long long bm = __ballot(mine);
+                            if (mine) myF[nf + __popcll(bm & lt)] = (uint16_t)s;
+                            nf += __popcll(bm);
+                            nfull += __popcll(fm);
+                        }
+                        if (lane < ((8 - (nf & 7)) & 7)) myF[nf + lane] = (uint16_t)kPad;
+                    }
 
                     // ---- matrix-core accumulation, two groups per iteration ---------
                     if (npairs > 0) {
@@ -344,6 +405,68 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                                 at = sT[s];
                             }
                             group(bx, by, bt);
+                        }
+                    }
+                    if constexpr (FULL) {
+                        const int32_t nfp = (nf + 7) >> 3;
+                        if (nfp > 0) {
+                            int s = myF[kq];
+                            float2 ax = sX[s], ay = sY[s], at = sT[s];
+                            for (int32_t pr = 0; pr < nfp; ++pr) {
+                                s = myF[8 * pr + 4 + kq];
+                                const float2 bx = sX[s], by = sY[s], bt = sT[s];
+                                group_full(ax, ay, at);
+                                if (pr + 1 < nfp) {
+                                    s = myF[8 * pr + 8 + kq];
+                                    ax = sX[s];
+                                    ay = sY[s];
+                                    at = sT[s];
+                                }
+                                group_full(bx, by, bt);
+                            }
+                        }
+                        if (nfull > 0) {
+                            // add -(sum Kt (a - 1))[T][X] - (sum Kt b)[T][Y] of the
+                            // four waves, in wave order, to this phase's sums
+                            __syncthreads();  // the survivor arrays are no longer read
+                            float* const W = reinterpret_cast<float*>(sXYT);
+                            const int32_t t4 = (lane >> 4) * 4, c16 = (lane & 15) * 16;
+#pragma unroll
+                            for (int b = 0; b < NB; ++b) {
+                                *reinterpret_cast<f32x4*>(W + ((wave * 2 + 0) * NB + b) * 256 + c16 + t4) = fa[b];
+                                *reinterpret_cast<f32x4*>(W + ((wave * 2 + 1) * NB + b) * 256 + c16 + t4) = fb[b];
+                                fa[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+                                fb[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+                            }
+                            __syncthreads();
+                            // sum the four waves' entries, in wave order, into
+                            // wave 0's region (each thread reads its entry of
+                            // every wave before it writes)
+                            if (tid < 128 * NB) {
+                                f32x4* const W4 = reinterpret_cast<f32x4*>(W);
+                                f32x4 v = W4[tid];
+#pragma unroll
+                                for (int w = 1; w < kWaves; ++w) v += W4[w * 128 * NB + tid];
+                                W4[tid] = v;
+                            }
+                            __syncthreads();
+#pragma unroll
+                            for (int g = 0; g < 4; ++g) {
+                                const int32_t lx = 4 * gqx + 4 * (g & 1) + (lane & 3);
+                                const int32_t ly = 4 * gqy + 4 * (g >> 1) + ((lane >> 2) & 3);
+#pragma unroll
+                                for (int b = 0; b < NB; ++b) {
+                                    const f32x4 sa = *reinterpret_cast<const f32x4*>(W + (0 * NB + b) * 256 + lx * 16 + t4);
+                                    const f32x4 sbv = *reinterpret_cast<const f32x4*>(W + (1 * NB + b) * 256 + ly * 16 + t4);
+                                    acc[g * NB + b] -= sa + sbv;
+                                }
+                            }
+                            __syncthreads();  // W is the survivor list again
+                            if (tid == 0) {
+                                sX[kPad] = make_float2(-1.0e6f, 0.f);
+                                sY[kPad] = make_float2(-1.0e6f, 0.f);
+                                sT[kPad] = make_float2(-1.0e6f, 0.f);
+                            }
                         }
                     }
                     if constexpr (MODE == kAccKahanReg) {
@@ -502,8 +625,9 @@ __global__ __launch_bounds__(kThreads) void k_reduce_split(const InstDev* __rest
 // Workgroups of the persistent gather: compute units x resident workgroups
 // per compute unit, cached per device (memory-mode Kahan at most
 // kMemKahanGroups, the slots of its scratch).
-template <int TT, int MODE>
+template <int TT, int MODE, bool FULL>
 int resident_groups() {
+    static_assert(!FULL || TT <= 32, "the full-cover sums of 64-row tiles do not fit the survivor LDS");
     static std::atomic<int> cache[kMaxDevices];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) dev = 0;
@@ -511,7 +635,7 @@ int resident_groups() {
     if (v > 0) return v;
     int ncu = 0, occ = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_gather_items<TT, MODE>, kThreads, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_gather_items<TT, MODE, FULL>, kThreads, 0) !=
         hipSuccess)
         occ = 0;
     v = (ncu > 0 ? ncu : 256) * (occ > 0 ? occ : 1);
@@ -520,16 +644,37 @@ int resident_groups() {
     return v;
 }
 
-template <int TT, int MODE>
+template <int TT, int MODE, bool FULL>
 void launch_items_t(const InstDev* d, int32_t count, const WorkItem* items, const uint32_t* bits,
                     const uint32_t* sc, uint32_t* ctr, float* partials, float* kscratch, int64_t T,
                     hipStream_t s) {
-    int64_t g = resident_groups<TT, MODE>();
+    int64_t g = resident_groups<TT, MODE, FULL>();
     const int64_t most = T + kPartSlots;  // items never exceed tiles + partial slots
     if (g > most) g = most;
     if (g < 1) g = 1;
-    hipLaunchKernelGGL((k_gather_items<TT, MODE>), dim3((uint32_t)g), dim3(kThreads), 0, s, d, count,
-                       (int32_t)T, items, bits, sc, ctr, partials, kscratch);
+    hipLaunchKernelGGL((k_gather_items<TT, MODE, FULL>), dim3((uint32_t)g), dim3(kThreads), 0, s, d,
+                       count, (int32_t)T, items, bits, sc, ctr, partials, kscratch);
+}
+
+// Calls f.template operator()<TT, MODE, FULL>() for the kernel variant of
+// (tile_t, mode, full); 64-row tiles are plain and without the full-cover path.
+template <typename F>
+void dispatch(int tile_t, int mode, bool full, F&& f) {
+    if (tile_t == 16) {
+        if (mode == kAccKahanReg) full ? f.template operator()<16, kAccKahanReg, true>()
+                                       : f.template operator()<16, kAccKahanReg, false>();
+        else if (mode == kAccKahanMem) full ? f.template operator()<16, kAccKahanMem, true>()
+                                            : f.template operator()<16, kAccKahanMem, false>();
+        else full ? f.template operator()<16, kAccPlain, true>() : f.template operator()<16, kAccPlain, false>();
+    } else if (tile_t == 32) {
+        if (mode == kAccKahanReg) full ? f.template operator()<32, kAccKahanReg, true>()
+                                       : f.template operator()<32, kAccKahanReg, false>();
+        else if (mode == kAccKahanMem) full ? f.template operator()<32, kAccKahanMem, true>()
+                                            : f.template operator()<32, kAccKahanMem, false>();
+        else full ? f.template operator()<32, kAccPlain, true>() : f.template operator()<32, kAccPlain, false>();
+    } else {
+        f.template operator()<64, kAccPlain, false>();
+    }
 }
 
 template <int TT, bool K>
@@ -544,37 +689,16 @@ void launch_reduce_t(const InstDev* d, int32_t count, const uint32_t* top, const
 hipError_t launch_gather_items(const InstDev* d_desc, int32_t count, const WorkItem* d_items,
                                const uint32_t* d_bits, const uint32_t* d_scalars,
                                uint32_t* d_counters, float* d_partials, float* d_kscratch, int64_t T,
-                               int tile_t, int mode, hipStream_t s) {
-#define STKDE_ITEMS(TT, M) \
-    launch_items_t<TT, M>(d_desc, count, d_items, d_bits, d_scalars, d_counters, d_partials, \
-                          d_kscratch, T, s)
-    if (tile_t == 16) {
-        if (mode == kAccKahanReg) STKDE_ITEMS(16, kAccKahanReg);
-        else if (mode == kAccKahanMem) STKDE_ITEMS(16, kAccKahanMem);
-        else STKDE_ITEMS(16, kAccPlain);
-    } else if (tile_t == 32) {
-        if (mode == kAccKahanReg) STKDE_ITEMS(32, kAccKahanReg);
-        else if (mode == kAccKahanMem) STKDE_ITEMS(32, kAccKahanMem);
-        else STKDE_ITEMS(32, kAccPlain);
-    } else {
-        STKDE_ITEMS(64, kAccPlain);
-    }
-#undef STKDE_ITEMS
+                               int tile_t, int mode, bool full, hipStream_t s) {
+    dispatch(tile_t, mode, full, [&]<int TT, int M, bool F>() {
+        launch_items_t<TT, M, F>(d_desc, count, d_items, d_bits, d_scalars, d_counters, d_partials,
+                                 d_kscratch, T, s);
+    });
     return hipGetLastError();
 }
 
-void prepare_gather(int tile_t, int mode) {
-    if (tile_t == 16) {
-        if (mode == kAccKahanReg) (void)resident_groups<16, kAccKahanReg>();
-        else if (mode == kAccKahanMem) (void)resident_groups<16, kAccKahanMem>();
-        else (void)resident_groups<16, kAccPlain>();
-    } else if (tile_t == 32) {
-        if (mode == kAccKahanReg) (void)resident_groups<32, kAccKahanReg>();
-        else if (mode == kAccKahanMem) (void)resident_groups<32, kAccKahanMem>();
-        else (void)resident_groups<32, kAccPlain>();
-    } else {
-        (void)resident_groups<64, kAccPlain>();
-    }
+void prepare_gather(int tile_t, int mode, bool full) {
+    dispatch(tile_t, mode, full, []<int TT, int M, bool F>() { (void)resident_groups<TT, M, F>(); });
 }
 
 hipError_t launch_reduce_split(const InstDev* d_desc, int32_t count, const uint32_t* d_top,

@@ -116,7 +116,13 @@ constexpr int kMassChunks = 64;
 constexpr int kAccPlain = 0;
 constexpr int kAccKahanReg = 1;
 constexpr int kAccKahanMem = 2;
-constexpr int kMemKahanGroups = 1536;  // workgroups (scratch slots) in memory mode                       // first-level chunks of an instance's mass sum
+constexpr int kMemKahanGroups = 1536;  // workgroups (scratch slots) in memory mode
+// Full-cover path of the gather: a point whose disc covers the whole 16 x 16
+// columns of a tile adds Kt (1 - a(x) - b(y)) there, which two 16 x 16
+// products (sum of Kt (a - 1) over x, sum of Kt b over y) give for all the
+// tile's columns at once.  Used from this voxel bandwidth on (below it few
+// discs can cover a tile).
+constexpr double kFullMinHv = 14.0;                       // first-level chunks of an instance's mass sum
 constexpr int kDescChunk = 16;                        // descriptors written per launch
 // Cost class of a tile: the FP32 bit pattern of its candidate count without
 // the low 20 bits (exponent and 3 mantissa bits), monotone in the count.
@@ -248,17 +254,18 @@ hipError_t launch_bin(const SetGeom& g, const double* d_xyt, int32_t n, uint8_t*
 // here; every other field is the caller's.
 // ev_before / ev_after (may be null) are recorded on s right before and
 // right after the gather kernel.
+// full: use the gather's full-cover path (tile_t <= 32).
 hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassLayout& pl,
-                       int tile_t, int mode, hipStream_t s, hipEvent_t ev_before = nullptr,
-                       hipEvent_t ev_after = nullptr);
+                       int tile_t, int mode, bool full, hipStream_t s,
+                       hipEvent_t ev_before = nullptr, hipEvent_t ev_after = nullptr);
 // The gather proper (called by launch_pass).
 hipError_t launch_gather_items(const InstDev* d_desc, int32_t count, const WorkItem* d_items,
                                const uint32_t* d_bits, const uint32_t* d_scalars,
                                uint32_t* d_counters, float* d_partials, float* d_kscratch, int64_t T,
-                               int tile_t, int mode, hipStream_t s);
+                               int tile_t, int mode, bool full, hipStream_t s);
 // Query (and cache) the gather's launch size for the current device ahead of a
 // stream capture.
-void prepare_gather(int tile_t, int mode);
+void prepare_gather(int tile_t, int mode, bool full);
 hipError_t launch_reduce_split(const InstDev* d_desc, int32_t count, const uint32_t* d_top,
                                const uint32_t* d_scalars, const float* d_partials, int tile_t,
                                bool kahan, hipStream_t s);

@@ -275,3 +275,25 @@ def test_kahan_modes_identical(torch_cuda, split_share):
     for tt in (16, 32):
         a = [r for r in res if r[1] == tt]
         assert np.array_equal(a[0][2], a[1][2]) and np.array_equal(a[0][3], a[1][3])
+
+
+@pytest.mark.parametrize("tuning", [(16, 0), (32, 0), (16, 1), (32, 1), (16, 2), (32, 2), (64, 0)])
+def test_large_bandwidth_full_cover(torch_cuda, tuning):
+    """Discs much larger than a tile take the full-cover path (Ks separable in
+    x and y over the whole tile); checked against the oracle with clustered
+    points, ragged grid edges, a non-unit voxel and an origin."""
+    import paper_1705_09366_amd as m
+    tt, kmode = tuning
+    rng = np.random.default_rng(51)
+    g = dict(gx=75, gy=61, gt=37, hs=40.0, ht=7.0, sres=2.0, tres=1.5, x0=-10.0, y0=4.0, t0=100.0)
+    centre = np.array([g["x0"] + 70.0, g["y0"] + 60.0, g["t0"] + 25.0])
+    pts = np.concatenate([centre + rng.normal(0, 6.0, (1500, 3)),
+                          np.array([g["x0"], g["y0"], g["t0"]]) + rng.uniform(0, 1, (1500, 3))
+                          * [75 * 2.0, 61 * 2.0, 37 * 1.5]])
+    flags = (1 if kmode else 0) | 4 | 8
+    _say(f"full cover tile_t={tt} kahan_mode={kmode}")
+    ref, evals = oracle.pbsym(pts, _grid(g))
+    gpu, st = _run(torch_cuda, pts, g, flags=flags, tuning=m.Tuning(tile_t=tt, kahan_mode=kmode))
+    _check_close(gpu, ref)
+    assert int(st[2]) == evals
+    assert st[0] == pytest.approx(st[1], rel=1e-6)
