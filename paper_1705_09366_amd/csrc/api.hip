@@ -211,14 +211,14 @@ int acc_mode(bool kahan, int32_t requested, int64_t n, const stkde_desc& base, i
     return est <= kSparseCandidates ? stkde::kAccKahanMem : stkde::kAccKahanReg;
 }
 
-// The gather's full-cover path pays off when discs are large against a tile.
-bool use_full(double hv, int32_t tile_t) { return tile_t <= 32 && hv >= stkde::kFullMinHv; }
-
 // (2/pi) (3/4) / (n hs^2 ht): the constants of both kernels and the
 // estimator's normalisation, rounded once to FP32 at the store.
 float norm_const(double hs, double ht, int64_t n) {
     return (float)((2.0 / 3.14159265358979323846) * 0.75 / ((double)n * hs * hs * ht));
 }
+
+// The gather's full-cover path pays off when discs are large against a tile.
+bool use_full(double hv, int32_t tile_t) { return tile_t <= 32 && hv >= stkde::kFullMinHv; }
 
 stkde::InstDev make_dev(const stkde::InstGeom& ig, const stkde::SetGeom& sg, const uint8_t* set_mem,
                         const stkde::SetLayout& sl, int64_t n_norm, int32_t ox, int32_t oy,
@@ -249,6 +249,7 @@ stkde::InstDev make_dev(const stkde::InstGeom& ig, const stkde::SetGeom& sg, con
     d.ntiles = ig.ntiles;
     d.tile_base = 0;
     d.flags = (mass && stats) ? stkde::kInstMass : 0u;
+    if (use_full(ig.hv, ig.tile_t)) d.flags |= stkde::kInstFull;
     d.inv_hv2 = ig.inv_hv2;
     d.inv_tv2 = ig.inv_tv2;
     d.cnorm = norm_const(ig.hs, ig.ht, n_norm);
@@ -528,32 +529,34 @@ stkde_status stkde_batch_plan(const stkde_item* items, int32_t count, stkde_batc
                                    it.set->n, it.set->base, geo[(size_t)i].Hs, geo[(size_t)i].Ht,
                                    geo[(size_t)i].tile_t);
     }
+    // one pass per (tile rows, plain or compensated); the pass takes the
+    // register form of Kahan if any of its grids expects dense tiles (both
+    // forms give the same bits) and the kernel with the full-cover path if
+    // any of its grids uses it (the path is switched per grid)
     const int tts[3] = {16, 32, 64};
-    const int modes[3] = {stkde::kAccPlain, stkde::kAccKahanReg, stkde::kAccKahanMem};
-    for (int fl = 0; fl < 2; ++fl) {
-        for (int md : modes) {
-            for (int tt : tts) {
-                stkde_batch_s::Group g;
-                g.tile_t = tt;
-                g.mode = md;
-                g.full = fl != 0;
-                g.kahan = md != stkde::kAccPlain;
-                for (int32_t i = 0; i < count; ++i) {
-                    if (mode[(size_t)i] == md && geo[(size_t)i].tile_t == tt &&
-                        use_full(geo[(size_t)i].hv, tt) == g.full) {
-                        g.idx.push_back(i);
-                        g.geo.push_back(geo[(size_t)i]);
-                    }
+    for (int kahan = 0; kahan < 2; ++kahan) {
+        for (int tt : tts) {
+            stkde_batch_s::Group g;
+            g.tile_t = tt;
+            g.kahan = kahan != 0;
+            g.mode = g.kahan ? stkde::kAccKahanMem : stkde::kAccPlain;
+            g.full = false;
+            for (int32_t i = 0; i < count; ++i) {
+                if ((mode[(size_t)i] != stkde::kAccPlain) == g.kahan && geo[(size_t)i].tile_t == tt) {
+                    g.idx.push_back(i);
+                    g.geo.push_back(geo[(size_t)i]);
+                    if (mode[(size_t)i] == stkde::kAccKahanReg) g.mode = stkde::kAccKahanReg;
+                    if (use_full(geo[(size_t)i].hv, tt)) g.full = true;
                 }
-                if (g.idx.empty()) continue;
-                g.pl = stkde::layout_pass(g.geo.data(), (int32_t)g.geo.size(), tt, g.kahan);
-                if (g.pl.T > 0x7fffffffLL) {
-                    delete bt;
-                    return STKDE_ERR_TOO_LARGE;
-                }
-                bt->ws_bytes = std::max(bt->ws_bytes, g.pl.total);
-                bt->groups.push_back(std::move(g));
             }
+            if (g.idx.empty()) continue;
+            g.pl = stkde::layout_pass(g.geo.data(), (int32_t)g.geo.size(), tt, g.kahan);
+            if (g.pl.T > 0x7fffffffLL) {
+                delete bt;
+                return STKDE_ERR_TOO_LARGE;
+            }
+            bt->ws_bytes = std::max(bt->ws_bytes, g.pl.total);
+            bt->groups.push_back(std::move(g));
         }
     }
     *out = bt;

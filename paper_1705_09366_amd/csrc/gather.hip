@@ -323,7 +323,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                                 const bool y0 = ylo <= 7 && yhi >= 0, y1 = ylo <= 15 && yhi >= 8;
                                 qm = (uint32_t)(x0 && y0) | ((uint32_t)(x1 && y0) << 1) |
                                      ((uint32_t)(x0 && y1) << 2) | ((uint32_t)(x1 && y1) << 3);
-                                if constexpr (FULL) {
+                                if (FULL && (D.flags & kInstFull)) {
                                     // the disc covers every column centre of the tile
                                     // (its farthest corner with a margin): the
                                     // spatial kernel is then 1 - a(x) - b(y) on the

@@ -83,11 +83,12 @@ struct alignas(16) InstDev {
     int32_t Hs, Ht;                      // instance loop bounds
     int32_t cxy, ct, ncx, ncy, nct;      // set bins
     int32_t ntx, nty, ntiles, tile_base; // instance tiles; first global tile index
-    uint32_t flags;                      // kInstMass
+    uint32_t flags;                      // kInstMass, kInstFull
     float inv_hv2, inv_tv2, cnorm;
     uint32_t split_share;                // split tiles above total cost / split_share
 };
 constexpr uint32_t kInstMass = 1u;
+constexpr uint32_t kInstFull = 2u;  // use the full-cover path (in a kernel that has it)
 
 // One unit of gather work: a tile, a range of its candidate sequence and
 // where the result goes (the grid, or a partial slot of a split tile).
