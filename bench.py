@@ -281,6 +281,103 @@ def bench_serve(args, dev):
     print(json.dumps(rec), flush=True)
 
 
+def bench_ablation(args, dev):
+    """The production gather against the two baselines of stkde_ablation.h
+    (point-parallel atomic scatter, Alg. PB; voxel-parallel gather over
+    bins, VB-DEC) on the workloads named in --ablation-workloads.  Each
+    method's step is bin + accumulate through the C ABI, timed with events
+    (median); the accumulation stage alone is timed after one binning.
+    Accuracy is the max difference from the Kahan gather (which the parity
+    tests hold to the oracle) relative to its max; repeatability counts the
+    voxels that differ between two runs of the same method."""
+    import torch
+    import paper_1705_09366_amd as m
+    from paper_1705_09366_amd import autotune
+    names = [w for w in args.ablation_workloads.split(",") if w]
+    results = []
+    for wname in names:
+        inst = _instance(wname)
+        n = inst.points.shape[0]
+        pts = torch.from_numpy(inst.points).to(dev)
+        base = dict(gx=inst.gx, gy=inst.gy, gt=inst.gt, hs=inst.hs, ht=inst.ht, sres=inst.sres,
+                    tres=inst.tres, x0=inst.x0, y0=inst.y0, t0=inst.t0)
+        dk, dp = m.Desc(**base, flags=m.FLAG_KAHAN), m.Desc(**base)
+        pk = m.Plan(dk, autotune.lookup(dk, n) if args.tuning == "auto" else None)
+        pp = m.Plan(dp, autotune.lookup(dp, n) if args.tuning == "auto" else None)
+        ws = torch.empty(max(pk.workspace_bytes(n), pp.workspace_bytes(n)) + 256, dtype=torch.uint8,
+                         device=dev)
+        ref = torch.empty((inst.gx, inst.gy, inst.gt), dtype=torch.float32, device=dev)
+        out = torch.empty_like(ref)
+        st = torch.zeros(8, dtype=torch.float64, device=dev)
+        c = m.Plan(m.Desc(**base, flags=m.FLAG_POINT_STATS))
+        c.compute_into(pts, out, stats=st, workspace=ws)
+        torch.cuda.synchronize()
+        evals = int(st[2].item())
+        c.close()
+        pk.compute_into(pts, ref, workspace=ws)
+        torch.cuda.synchronize()
+        scale = float(ref.abs().max())
+        _log(f"ablation {inst.name}: n={n}, {evals} evals")
+
+        methods = {
+            "gather_kahan": (lambda o: pk.compute_into(pts, o, workspace=ws),
+                             lambda o: pk.accumulate(n, o, ws)),
+            "gather_plain": (lambda o: pp.compute_into(pts, o, workspace=ws),
+                             lambda o: pp.accumulate(n, o, ws)),
+            "scatter": (lambda o: pp.ablation_compute(m.ABLATION_SCATTER, pts, o),
+                        lambda o: pp.ablation_accumulate(m.ABLATION_SCATTER, n, o, pp.workspace(n, dev))),
+            "voxel": (lambda o: pp.ablation_compute(m.ABLATION_VOXEL, pts, o),
+                      lambda o: pp.ablation_accumulate(m.ABLATION_VOXEL, n, o, pp.workspace(n, dev))),
+        }
+
+        def timed(fn, steps):
+            ts = []
+            for _ in range(steps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                fn(out)
+                b.record()
+                torch.cuda.synchronize()
+                ts.append(a.elapsed_time(b))
+            return _median(ts)
+
+        rows = {}
+        for meth, (step, acc) in methods.items():
+            first = timed(step, 1)  # also the warm-up
+            steps = args.steps if first < 50.0 else max(2, min(args.steps, int(2000.0 / first)))
+            step_ms = timed(step, steps)
+            if meth in ("scatter", "voxel"):
+                pp.bin(pts, pp.workspace(n, dev))
+            else:
+                (pk if meth == "gather_kahan" else pp).bin(pts, ws)
+            acc_ms = timed(acc, steps)
+            step(out)
+            torch.cuda.synchronize()
+            err = float((out - ref).abs().max()) / scale if scale > 0 else 0.0
+            again = out.clone()
+            step(out)
+            torch.cuda.synchronize()
+            ndiff = int((out != again).sum())
+            del again
+            rows[meth] = {"step_ms": step_ms, "accumulate_ms": acc_ms, "steps": steps,
+                          "evals_per_s": evals / (step_ms * 1e-3), "max_rel_diff_vs_gather_kahan": err,
+                          "voxels_differing_between_runs": ndiff}
+            _log(f"  {meth}: step {step_ms:.3f} ms, accumulate {acc_ms:.3f} ms, "
+                 f"diff vs kahan gather {err:.2e}, {ndiff} voxels differ between runs")
+        g = rows["gather_kahan"]["step_ms"]
+        for meth in ("scatter", "voxel"):
+            rows[meth]["gather_speedup"] = rows[meth]["step_ms"] / g
+        results.append({"workload": inst.name, "n": n, "evals": evals, "methods": rows})
+        pk.close()
+        pp.close()
+        del pts, ws, ref, out
+        torch.cuda.empty_cache()
+    rec = {"metric": "ablation step time", "unit": "ms", "higher_is_better": False, "n_gpus": 1,
+           "dtype": "f32", "data": "synthetic", "config": {"workload": "ablation", "tuning": args.tuning},
+           "results": results}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -296,9 +393,12 @@ def main():
     ap.add_argument("--tuning", default="auto", choices=("auto", "default"),
                     help="auto: the autotune cache's pinned tuning for the workload (when it has "
                          "one); default: the library defaults (explicit --tile-t etc. override both)")
-    ap.add_argument("--mode", default="compute", choices=("compute", "batch", "serve"),
+    ap.add_argument("--mode", default="compute", choices=("compute", "batch", "serve", "ablation"),
                     help="compute: the headline step; batch: the bandwidth-sweep batch against "
-                         "sequential computes; serve: request latency under Poisson load")
+                         "sequential computes; serve: request latency under Poisson load; "
+                         "ablation: the gather against the atomic scatter and voxel baselines")
+    ap.add_argument("--ablation-workloads", default="uniform-10k,clustered-1M,clustered-200k-hs50",
+                    help="ablation mode: comma-separated workloads")
     ap.add_argument("--requests", type=int, default=400, help="serve mode: requests per load level")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE)")
@@ -324,6 +424,8 @@ def main():
         return bench_batch(args, dev)
     if args.mode == "serve":
         return bench_serve(args, dev)
+    if args.mode == "ablation":
+        return bench_ablation(args, dev)
 
     if args.calibrate_copy:
         # a plain copy kernel of known size: 1 GiB read + 1 GiB written per launch

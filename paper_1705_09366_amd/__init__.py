@@ -38,7 +38,12 @@ EXPORTED = ("stkde_plan", "stkde_plan_destroy", "stkde_workspace_bytes", "stkde_
             "stkde_set_plan", "stkde_set_bytes", "stkde_set_build", "stkde_set_destroy",
             "stkde_batch_plan", "stkde_batch_workspace_bytes", "stkde_batch_run",
             "stkde_batch_capture", "stkde_batch_replay", "stkde_batch_destroy",
-            "stkde_plan_profile", "stkde_plan_profile_read")
+            "stkde_plan_profile", "stkde_plan_profile_read",
+            "stkde_ablation_accumulate", "stkde_ablation_compute")
+
+# Baselines of include/stkde_ablation.h (benchmarks and tests only).
+ABLATION_SCATTER = 1
+ABLATION_VOXEL = 2
 
 
 class StkdeError(RuntimeError):
@@ -103,6 +108,12 @@ def lib():
         L.stkde_batch_replay.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         L.stkde_batch_destroy.argtypes = [ctypes.c_void_p]
         L.stkde_plan_profile.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+        L.stkde_ablation_accumulate.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                                ctypes.c_void_p]
+        L.stkde_ablation_compute.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                             ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_size_t, ctypes.c_void_p]
         L.stkde_plan_profile_read.argtypes = [ctypes.c_void_p, P(ctypes.c_float), ctypes.c_int32,
                                               P(ctypes.c_int32)]
         for name in EXPORTED:
@@ -288,6 +299,47 @@ class Plan:
                                     ctypes.c_void_p(stream.cuda_stream))
         if st != STKDE_OK:
             raise StkdeError(st, "stkde_accumulate")
+        return out
+
+    def ablation_accumulate(self, method: int, n, out, workspace, stream=None):
+        """Baseline accumulation (stkde_ablation_accumulate): ABLATION_SCATTER
+        or ABLATION_VOXEL over a workspace that :meth:`bin` filled for n."""
+        import torch
+        d = self.desc
+        if out.dtype != torch.float32 or not out.is_cuda or out.numel() != d.gx * d.gy * d.gt \
+                or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 CUDA tensor of gx*gy*gt elements")
+        if stream is None:
+            stream = torch.cuda.current_stream(out.device)
+        p, nb = self._ws_args(workspace)
+        st = lib().stkde_ablation_accumulate(self._h, int(method), int(n), ctypes.c_void_p(out.data_ptr()),
+                                             p, nb, ctypes.c_void_p(stream.cuda_stream))
+        if st != STKDE_OK:
+            raise StkdeError(st, "stkde_ablation_accumulate")
+        return out
+
+    def ablation_compute(self, method: int, points, out=None, stream=None):
+        """Bin then run a baseline accumulation (stkde_ablation_compute)."""
+        import torch
+        d = self.desc
+        if points.dtype != torch.float64 or not points.is_cuda or points.dim() != 2 \
+                or points.shape[1] != 3 or not points.is_contiguous():
+            raise ValueError("points must be a contiguous [n, 3] float64 CUDA tensor")
+        if out is None:
+            out = torch.empty((d.gx, d.gy, d.gt), dtype=torch.float32, device=points.device)
+        if out.dtype != torch.float32 or not out.is_cuda or out.numel() != d.gx * d.gy * d.gt \
+                or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 CUDA tensor of gx*gy*gt elements")
+        n = int(points.shape[0])
+        ws = self.workspace(n, points.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(points.device)
+        p, nb = self._ws_args(ws)
+        st = lib().stkde_ablation_compute(self._h, int(method), ctypes.c_void_p(points.data_ptr()), n,
+                                          ctypes.c_void_p(out.data_ptr()), p, nb,
+                                          ctypes.c_void_p(stream.cuda_stream))
+        if st != STKDE_OK:
+            raise StkdeError(st, "stkde_ablation_compute")
         return out
 
     def __call__(self, points, stats=None):

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libstkde.so")
-SOURCES = ["api.hip", "bin.hip", "gather.hip", "pass.hip", "stats.hip"]
+SOURCES = ["ablation.hip", "api.hip", "bin.hip", "gather.hip", "pass.hip", "stats.hip"]
 ARCH = os.environ.get("STKDE_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}",

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/stkde.h"
+#include "../../include/stkde_ablation.h"
 #include "stkde_internal.h"
 
 struct stkde_plan_s {
@@ -642,6 +643,39 @@ stkde_status stkde_batch_destroy(stkde_batch_t b) {
     if (b->graph) (void)hipGraphDestroy(b->graph);
     delete b;
     return STKDE_OK;
+}
+
+// ---- baselines (stkde_ablation.h) ------------------------------------------------
+
+stkde_status stkde_ablation_accumulate(stkde_plan_t p, int32_t method, int64_t n, float* d_out,
+                                       void* d_ws, size_t ws_bytes, void* stream) {
+    if (!d_out || (method != STKDE_ABLATION_SCATTER && method != STKDE_ABLATION_VOXEL))
+        return STKDE_ERR_INVALID_ARG;
+    Call c;
+    const stkde_status st = check_common(p, n, d_ws, ws_bytes, stream, &c);
+    if (st != STKDE_OK) return st;
+    // the scatter indexes a footprint box, the voxel gather its grid, in 32 bits
+    const stkde::InstGeom& g = p->ig;
+    const int64_t box = (int64_t)std::min<int64_t>(g.gx, 2 * (int64_t)g.Hs + 2) *
+                        std::min<int64_t>(g.gy, 2 * (int64_t)g.Hs + 2) *
+                        std::min<int64_t>(g.gt, 2 * (int64_t)g.Ht + 2);
+    const int64_t blocks = ((int64_t)g.gx * g.gy * g.gt + 255) / 256;
+    if (box > 0x7fffffffLL || blocks > 0x7fffffffLL) return STKDE_ERR_UNSUPPORTED;
+    const float cn = norm_const(p->ig.hs, p->ig.ht, n);
+    const hipError_t e =
+        method == STKDE_ABLATION_SCATTER
+            ? stkde::launch_ablation_scatter(p->sg, p->ig, c.ws, c.L.sl, cn, d_out, c.s)
+            : stkde::launch_ablation_voxel(p->sg, p->ig, c.ws, c.L.sl, cn, d_out, c.s);
+    return e == hipSuccess ? STKDE_OK : STKDE_ERR_HIP;
+}
+
+stkde_status stkde_ablation_compute(stkde_plan_t p, int32_t method, const double* d_xyt, int64_t n,
+                                    float* d_out, void* d_ws, size_t ws_bytes, void* stream) {
+    if (!p || !d_xyt || !d_out || (method != STKDE_ABLATION_SCATTER && method != STKDE_ABLATION_VOXEL))
+        return STKDE_ERR_INVALID_ARG;
+    stkde_status st = stkde_bin(p, d_xyt, n, d_ws, ws_bytes, stream);
+    if (st != STKDE_OK) return st;
+    return stkde_ablation_accumulate(p, method, n, d_out, d_ws, ws_bytes, stream);
 }
 
 }  // extern "C"

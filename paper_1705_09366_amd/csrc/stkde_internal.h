@@ -274,4 +274,11 @@ hipError_t launch_reduce_split(const InstDev* d_desc, int32_t count, const uint3
 hipError_t launch_point_stats(const InstGeom& g, int64_t n_norm, const double* d_xyt, int32_t n,
                               double* d_stats, double* part, int32_t nblk, hipStream_t s);
 
+// Baselines over a binned set on its own base grid (no window): a zero fill
+// then a point-parallel atomic scatter, or a voxel-parallel gather over bins.
+hipError_t launch_ablation_scatter(const SetGeom& sg, const InstGeom& ig, const uint8_t* set,
+                                   const SetLayout& sl, float cnorm, float* d_out, hipStream_t s);
+hipError_t launch_ablation_voxel(const SetGeom& sg, const InstGeom& ig, const uint8_t* set,
+                                 const SetLayout& sl, float cnorm, float* d_out, hipStream_t s);
+
 }  // namespace stkde

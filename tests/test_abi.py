@@ -1,5 +1,5 @@
 """Host-side checks of the C ABI that run without a GPU: the library loads,
-exports every entry point declared in include/stkde.h, and rejects invalid
+exports every entry point declared in include/*.h, and rejects invalid
 arguments on the host before anything is enqueued."""
 import ctypes
 import os
@@ -11,7 +11,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared_symbols():
-    src = open(os.path.join(ROOT, "include", "stkde.h")).read()
+    inc = os.path.join(ROOT, "include")
+    src = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(stkde_[a-z_]+)\s*\(", src)))
 
@@ -101,6 +102,28 @@ def test_compute_rejects_before_launch(L):
     assert lib.stkde_compute(h, fake, 10, fake, None, need, None, None) == -3
     assert lib.stkde_compute(h, fake, 10, fake, fake, need - 1, None, None) == -3
     assert lib.stkde_compute(h, fake, 10, fake, ctypes.c_void_p(0x10010), need, None, None) == -3
+
+
+def test_ablation_rejects_before_launch(L):
+    """The baselines validate like stkde_compute, and reject unknown methods."""
+    lib = L.lib()
+    p = L.Plan(L.Desc(gx=32, gy=32, gt=32, hs=3.0, ht=3.0))
+    need = p.workspace_bytes(10)
+    fake = ctypes.c_void_p(0x10000)
+    h = p.handle
+    for m in (0, 3, -1):
+        assert lib.stkde_ablation_compute(h, m, fake, 10, fake, fake, need, None) == -1
+        assert lib.stkde_ablation_accumulate(h, m, 10, fake, fake, need, None) == -1
+    for m in (L.ABLATION_SCATTER, L.ABLATION_VOXEL):
+        assert lib.stkde_ablation_compute(None, m, fake, 10, fake, fake, need, None) == -1
+        assert lib.stkde_ablation_compute(h, m, None, 10, fake, fake, need, None) == -1
+        assert lib.stkde_ablation_compute(h, m, fake, 10, None, fake, need, None) == -1
+        assert lib.stkde_ablation_compute(h, m, fake, 0, fake, fake, need, None) == -1
+        assert lib.stkde_ablation_compute(h, m, fake, 1 << 31, fake, fake, need, None) == -2
+        assert lib.stkde_ablation_compute(h, m, fake, 10, fake, fake, need - 1, None) == -3
+        assert lib.stkde_ablation_accumulate(h, m, 10, None, fake, need, None) == -1
+        assert lib.stkde_ablation_accumulate(h, m, 10, fake, None, need, None) == -3
+        assert lib.stkde_ablation_accumulate(h, m, 10, fake, fake, need - 1, None) == -3
 
 
 def test_oracle_and_library_share_no_code():
