@@ -12,6 +12,9 @@ Contents
   time in numpy so that the brute-force check does not share code with the C
   loops.
 * :func:`point_sums` -- per-point in-grid kernel sums and support counts.
+* :func:`pbsym_adaptive`, :func:`vb_voxels_adaptive`, :func:`point_sums_adaptive`,
+  :func:`vb_grid_numpy_adaptive` -- the same with a bandwidth pair per event
+  (the sample-point reading of the adaptive bandwidth of Sec. 8).
 
 Kernels follow the Epanechnikov reading of the garbled kernel formulas of
 Sec. 2.1: ks(u,v) = (2/pi)(1-u^2-v^2) on the open unit disc,
@@ -70,7 +73,16 @@ def _lib():
         lib.oracle_point_sums.argtypes = [P(_Grid), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_int]
-        for f in (lib.oracle_pbsym, lib.oracle_vb_voxels, lib.oracle_point_sums):
+        lib.oracle_pbsym_adaptive.argtypes = [P(_Grid), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                              ctypes.c_void_p, P(ctypes.c_int64), ctypes.c_int]
+        lib.oracle_vb_voxels_adaptive.argtypes = [P(_Grid), ctypes.c_void_p, ctypes.c_void_p,
+                                                  ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                                  ctypes.c_void_p, ctypes.c_int]
+        lib.oracle_point_sums_adaptive.argtypes = [P(_Grid), ctypes.c_void_p, ctypes.c_void_p,
+                                                   ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+        for f in (lib.oracle_pbsym, lib.oracle_vb_voxels, lib.oracle_point_sums, lib.oracle_pbsym_adaptive,
+                  lib.oracle_vb_voxels_adaptive, lib.oracle_point_sums_adaptive):
             f.restype = ctypes.c_int
         _LIB = lib
     return _LIB
@@ -172,3 +184,101 @@ def vb_grid_numpy(xyt, grid: Grid):
             ktv = np.where(np.abs(dt) <= grid.ht, 0.75 * (1.0 - w * w), 0.0)
             out[X, Y, :] = np.sum(ksv[:, None] * ktv, axis=0)
     return out / (n * grid.hs ** 2 * grid.ht)
+
+
+# ------------------------------------------------ per-event bandwidths
+def _bandwidths(hst, n):
+    h = np.ascontiguousarray(hst, dtype=np.float64)
+    if h.shape != (n, 2):
+        raise ValueError("bandwidths must be an (n, 2) array of (hs_i, ht_i)")
+    return h
+
+
+def pbsym_adaptive(xyt, hst, grid: Grid, nthreads=None):
+    """Alg. PB-SYM with a bandwidth pair per event (hst: (n, 2) of hs_i, ht_i
+    in domain units; grid.hs / grid.ht are not used).  Returns (density, evals)."""
+    pts = _points(xyt)
+    h = _bandwidths(hst, pts.shape[0])
+    out = np.empty((grid.gx, grid.gy, grid.gt), dtype=np.float64)
+    ev = ctypes.c_int64(0)
+    rc = _lib().oracle_pbsym_adaptive(ctypes.byref(grid._c()), pts.ctypes.data, h.ctypes.data,
+                                      pts.shape[0], out.ctypes.data, ctypes.byref(ev),
+                                      _threads(nthreads))
+    if rc != 0:
+        raise ValueError(f"oracle_pbsym_adaptive failed ({rc})")
+    return out, int(ev.value)
+
+
+def vb_voxels_adaptive(xyt, hst, grid: Grid, voxels, nthreads=None):
+    """Alg. VB with per-event bandwidths at the (m, 3) voxel list."""
+    pts = _points(xyt)
+    h = _bandwidths(hst, pts.shape[0])
+    vox = np.ascontiguousarray(voxels, dtype=np.int64).reshape(-1, 3)
+    out = np.empty(vox.shape[0], dtype=np.float64)
+    rc = _lib().oracle_vb_voxels_adaptive(ctypes.byref(grid._c()), pts.ctypes.data, h.ctypes.data,
+                                          pts.shape[0], vox.ctypes.data, vox.shape[0], out.ctypes.data,
+                                          _threads(nthreads))
+    if rc != 0:
+        raise ValueError(f"oracle_vb_voxels_adaptive failed ({rc})")
+    return out
+
+
+def point_sums_adaptive(xyt, hst, grid: Grid, nthreads=None):
+    """Per event, with its own bandwidths: (Ss, St, cs, ct) as :func:`point_sums`."""
+    pts = _points(xyt)
+    n = pts.shape[0]
+    h = _bandwidths(hst, n)
+    Ss = np.empty(n, np.float64)
+    St = np.empty(n, np.float64)
+    cs = np.empty(n, np.int64)
+    ct = np.empty(n, np.int64)
+    rc = _lib().oracle_point_sums_adaptive(ctypes.byref(grid._c()), pts.ctypes.data, h.ctypes.data, n,
+                                           Ss.ctypes.data, St.ctypes.data, cs.ctypes.data,
+                                           ct.ctypes.data, _threads(nthreads))
+    if rc != 0:
+        raise ValueError(f"oracle_point_sums_adaptive failed ({rc})")
+    return Ss, St, cs, ct
+
+
+def exact_mass_adaptive(xyt, hst, grid: Grid, nthreads=None):
+    """sum_i Ss(i) St(i) / (n hs_i^2 ht_i) * sres^2 tres: the grid's mass,
+    exact up to rounding (each event's clipping is a box)."""
+    Ss, St, _, _ = point_sums_adaptive(xyt, hst, grid, nthreads)
+    h = np.asarray(hst, dtype=np.float64)
+    ok = np.isfinite(h).all(axis=1) & (h[:, 0] > 0) & (h[:, 1] > 0)
+    w = np.zeros(len(h))
+    w[ok] = 1.0 / (h[ok, 0] ** 2 * h[ok, 1])
+    return float(np.sum(Ss * St * w) / len(h) * grid.sres ** 2 * grid.tres)
+
+
+def exact_evals_adaptive(xyt, hst, grid: Grid, nthreads=None):
+    """Exact number of in-grid (voxel, event) pairs inside the event's supports."""
+    _, _, cs, ct = point_sums_adaptive(xyt, hst, grid, nthreads)
+    return int(np.sum(cs * ct))
+
+
+def vb_grid_numpy_adaptive(xyt, hst, grid: Grid):
+    """Alg. VB with per-event bandwidths over a whole (tiny) grid, in numpy:
+    every voxel centre against every event, each term over hs_i^2 ht_i."""
+    pts = _points(xyt)
+    h = _bandwidths(hst, pts.shape[0])
+    n = pts.shape[0]
+    ok = np.all(np.isfinite(pts), axis=1) & np.all(np.isfinite(h), axis=1) & (h[:, 0] > 0) & (h[:, 1] > 0)
+    p, hs, ht = pts[ok], h[ok, 0], h[ok, 1]
+    out = np.zeros((grid.gx, grid.gy, grid.gt), dtype=np.float64)
+    ts = grid.t0 + (np.arange(grid.gt) + 0.5) * grid.tres
+    for X in range(grid.gx):
+        x = grid.x0 + (X + 0.5) * grid.sres
+        for Y in range(grid.gy):
+            y = grid.y0 + (Y + 0.5) * grid.sres
+            r2 = (p[:, 0] - x) ** 2 + (p[:, 1] - y) ** 2
+            inside = np.sqrt(r2) < hs
+            if not np.any(inside):
+                continue
+            ksv = (2.0 / np.pi) * (1.0 - r2[inside] / hs[inside] ** 2)
+            dt = ts[None, :] - p[inside, 2][:, None]
+            hti = ht[inside][:, None]
+            ktv = np.where(np.abs(dt) <= hti, 0.75 * (1.0 - (dt / hti) ** 2), 0.0)
+            wgt = 1.0 / (hs[inside] ** 2 * ht[inside])
+            out[X, Y, :] = np.sum((ksv * wgt)[:, None] * ktv, axis=0)
+    return out / n

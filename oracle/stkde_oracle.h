@@ -41,6 +41,22 @@ int oracle_vb_voxels(const oracle_grid* g, const double* xyt, int64_t n, const i
 int oracle_point_sums(const oracle_grid* g, const double* xyt, int64_t n, double* Ss, double* St,
                       int64_t* cs, int64_t* ct, int nthreads);
 
+/* Sample-point adaptive estimator (per-point bandwidths; the adaptive
+ * bandwidth named as future work in Sec. 8):
+ *
+ *   f(x,y,t) = 1/n * sum_i ks((x-xi)/hs_i, (y-yi)/hs_i) kt((t-ti)/ht_i) / (hs_i^2 ht_i)
+ *
+ * hst holds n pairs (hs_i, ht_i) in domain units, row-major.  A point whose
+ * pair is not finite and positive, or whose coordinates are not finite,
+ * contributes nothing but counts in n.  The grid's hs and ht are only
+ * validated, not used.  Same outputs as the fixed-bandwidth functions. */
+int oracle_pbsym_adaptive(const oracle_grid* g, const double* xyt, const double* hst, int64_t n,
+                          double* grid, int64_t* evals_out, int nthreads);
+int oracle_vb_voxels_adaptive(const oracle_grid* g, const double* xyt, const double* hst, int64_t n,
+                              const int64_t* vox, int64_t m, double* out, int nthreads);
+int oracle_point_sums_adaptive(const oracle_grid* g, const double* xyt, const double* hst, int64_t n,
+                               double* Ss, double* St, int64_t* cs, int64_t* ct, int nthreads);
+
 #ifdef __cplusplus
 }
 #endif
