@@ -78,9 +78,10 @@ def _traffic_from_profile(kernel_src_hash):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(inst, gpu_plan_fn, budget_s=20.0):
+def cpu_baseline(inst, gpu_plan_fn, budget_s=20.0, pairs=None):
     """Time the FP64 oracle on a bounded sample (the first k events of the
-    workload on the full grid), growing k until the run takes a few seconds
+    workload on the full grid, with their bandwidth pairs when the workload
+    has per-event bandwidths), growing k until the run takes a few seconds
     or covers the whole workload.  Also returns the GPU's max error against
     the oracle on that same sample."""
     import numpy as np
@@ -92,17 +93,21 @@ def cpu_baseline(inst, gpu_plan_fn, budget_s=20.0):
     k = max(1, n // 64)
     while True:
         t0 = time.perf_counter()
-        ref, evals = oracle.pbsym(inst.points[:k], g, nthreads=th)
+        if pairs is None:
+            ref, evals = oracle.pbsym(inst.points[:k], g, nthreads=th)
+        else:
+            ref, evals = oracle.pbsym_adaptive(inst.points[:k], pairs[:k], g, nthreads=th)
         dt = time.perf_counter() - t0
         _log(f"cpu oracle: {k} points, {evals} evals, {dt:.2f} s on {th} threads")
         if k >= n or dt * min(4, n / k) > budget_s:
             break
         k = min(n, k * 4)
-    gpu = gpu_plan_fn(inst.points[:k]).astype(np.float64)
+    gpu = gpu_plan_fn(k).astype(np.float64)
     err = float(np.max(np.abs(gpu - ref)) / max(np.max(np.abs(ref)), 1e-300))
     del ref
     sample = (f"first {k} of {n} events of the workload on the full {inst.gx}x{inst.gy}x{inst.gt} "
-              f"grid (FP64 grid zeroing + PB-SYM accumulation, IO excluded)")
+              f"grid (FP64 grid zeroing + PB-SYM accumulation"
+              f"{' with per-event bandwidths' if pairs is not None else ''}, IO excluded)")
     return {"value": evals / dt, "unit": "evals/s", "cores": th, "kind": "oracle",
             "sample": sample, "seconds": round(dt, 3), "evals": int(evals)}, err
 
@@ -385,6 +390,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="clustered-1M", choices=WORKLOADS)
     ap.add_argument("--plain", action="store_true", help="plain FP32 accumulation (no Kahan)")
+    ap.add_argument("--adaptive", action="store_true",
+                    help="per-event bandwidth pairs shrinking with the local event density "
+                         "(the workload's hs, ht are the largest)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--tile-t", type=int, default=0, help="tuning: time rows per tile (16/32)")
@@ -441,7 +449,12 @@ def main():
     inst = _instance(args.workload)
     n = inst.points.shape[0]
     kahan = not args.plain
-    flags = m.FLAG_MASS | (m.FLAG_KAHAN if kahan else 0)
+    flags = m.FLAG_MASS | (m.FLAG_KAHAN if kahan else 0) | (m.FLAG_ADAPTIVE if args.adaptive else 0)
+    pairs_np = None
+    if args.adaptive:
+        import workloads
+        pairs_np = workloads.adaptive_pairs(inst.points, inst.gx, inst.gy, inst.hs, inst.ht, inst.sres,
+                                            inst.x0, inst.y0)
     desc = m.Desc(gx=inst.gx, gy=inst.gy, gt=inst.gt, hs=inst.hs, ht=inst.ht, sres=inst.sres,
                   tres=inst.tres, x0=inst.x0, y0=inst.y0, t0=inst.t0, flags=flags)
     if args.tile_t or args.cell_xy or args.cell_t:
@@ -454,6 +467,12 @@ def main():
         tuning, tuning_src = None, "default"
     plan = m.Plan(desc, tuning)
     pts = torch.from_numpy(inst.points).to(dev)
+    pairs = torch.from_numpy(pairs_np).to(dev) if args.adaptive else None
+
+    def compute(p, o, st=None, w=None):
+        if args.adaptive:
+            return p.compute_adaptive_into(pts, pairs, o, stats=st, workspace=w)
+        return p.compute_into(pts, o, stats=st, workspace=w)
     out = torch.empty((inst.gx, inst.gy, inst.gt), dtype=torch.float32, device=dev)
     stats = torch.zeros(8, dtype=torch.float64, device=dev)
     ws = plan.workspace(n, dev)
@@ -462,9 +481,10 @@ def main():
          f"workspace {ws.numel() / 2**20:.1f} MiB, kahan={kahan}")
 
     # exact evaluation count (once, outside the timed region)
-    chk = m.Plan(m.Desc(**{**desc.__dict__, "flags": m.FLAG_POINT_STATS | m.FLAG_MASS}), tuning)
+    chk = m.Plan(m.Desc(**{**desc.__dict__, "flags": m.FLAG_POINT_STATS | m.FLAG_MASS
+                           | (flags & m.FLAG_ADAPTIVE)}), tuning)
     cstats = torch.zeros(8, dtype=torch.float64, device=dev)
-    chk.compute_into(pts, out, stats=cstats, workspace=ws)
+    compute(chk, out, cstats, ws)
     torch.cuda.synchronize()
     cs = cstats.cpu().numpy()
     evals = int(cs[2])
@@ -472,7 +492,7 @@ def main():
     _log(f"evals {evals}, point mass {cs[1]:.9f}, grid mass {cs[0]:.9f}")
 
     for _ in range(args.warmup):
-        plan.compute_into(pts, out, stats=stats, workspace=ws)
+        compute(plan, out, stats, ws)
     torch.cuda.synchronize()
     _log(f"warmup {args.warmup} done")
 
@@ -483,7 +503,7 @@ def main():
     t0 = time.perf_counter()
     for k in range(args.steps):
         ev[k][0].record(stream)
-        plan.compute_into(pts, out, stats=stats, workspace=ws)
+        compute(plan, out, stats, ws)
         ev[k][1].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -505,7 +525,10 @@ def main():
     gev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
     for k in range(reps):
         bev[k][0].record(stream)
-        plan.bin(pts, ws)
+        if args.adaptive:
+            plan.bin_adaptive(pts, pairs, ws)
+        else:
+            plan.bin(pts, ws)
         bev[k][1].record(stream)
         gev[k][0].record(stream)
         plan.accumulate(n, out, ws)
@@ -516,7 +539,7 @@ def main():
     _log(f"stage times: bin {bin_ms:.3f} ms, accumulation pass {pass_ms:.3f} ms")
 
     grid_bytes = inst.gx * inst.gy * inst.gt * 4
-    alg_bytes = grid_bytes + n * 24
+    alg_bytes = grid_bytes + n * (40 if args.adaptive else 24)  # points (and pairs) read once
     alg_flops = 2.0 * evals  # one multiply and one add per (voxel, point) pair
     # the binding roofline: HBM below the ridge point, FP32 matrix cores above it
     if alg_flops / alg_bytes < MFMA_F32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9):
@@ -528,7 +551,9 @@ def main():
     # the counters hold for the kernel source and work list they were taken on
     src = b"".join(open(os.path.join(ROOT, "paper_1705_09366_amd", "csrc", f), "rb").read()
                    for f in ("gather.hip", "pass.hip"))
-    traffic = _traffic_from_profile(hashlib.sha256(src).hexdigest())
+    # ... and for the workload they were taken on (the default run)
+    profiled = args.workload == "clustered-1M" and kahan and not args.adaptive and tuning_src.startswith("autotune")
+    traffic = _traffic_from_profile(hashlib.sha256(src).hexdigest()) if profiled else None
 
     value = evals / (ms_per_step * 1e-3)
     rec = {
@@ -546,6 +571,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": inst.name, "n": n, "grid": [inst.gx, inst.gy, inst.gt],
                    "hs": inst.hs, "ht": inst.ht, "accumulation": "kahan" if kahan else "plain",
+                   "bandwidths": "per-event (density-adaptive)" if args.adaptive else "fixed",
                    "evals": evals,
                    "tuning": ([tuning.tile_t, tuning.cell_xy, tuning.cell_t, tuning.split_share]
                               if tuning else [0, 0, 0, 0]),
@@ -558,14 +584,18 @@ def main():
     }
 
     if not args.no_cpu_baseline:
-        def gpu_sample(p):
+        def gpu_sample(k):
             sp = m.Plan(m.Desc(**{**desc.__dict__, "flags": flags & ~m.FLAG_MASS}), tuning)
-            o = sp(torch.from_numpy(np.ascontiguousarray(p)).to(dev))
+            xs = torch.from_numpy(np.ascontiguousarray(inst.points[:k])).to(dev)
+            if args.adaptive:
+                o = sp.compute_adaptive(xs, torch.from_numpy(np.ascontiguousarray(pairs_np[:k])).to(dev))
+            else:
+                o = sp(xs)
             torch.cuda.synchronize()
             r = o.cpu().numpy()
             sp.close()
             return r
-        cb, err = cpu_baseline(inst, gpu_sample, args.cpu_budget)
+        cb, err = cpu_baseline(inst, gpu_sample, args.cpu_budget, pairs_np)
         rec["cpu_baseline"] = cb
         rec["max_rel_err_vs_oracle"] = err
         _log(f"gpu vs oracle on the cpu sample: max rel err {err:.3e}")

@@ -63,7 +63,16 @@ enum {
     /* Fill d_stats[1..2] with the per-point FP64 mass and the exact number
      * of kernel evaluations (an extra pass over the points; see
      * stkde_compute). */
-    STKDE_FLAG_POINT_STATS = 8u
+    STKDE_FLAG_POINT_STATS = 8u,
+    /* Every point carries its own bandwidth pair (hs_i, ht_i): the
+     * sample-point reading of the bandwidth that adapts to the local density,
+     * named as future work in Sec. 8,
+     *   f = 1/n sum_i ks(./hs_i) kt(./ht_i) / (hs_i^2 ht_i).
+     * The desc's hs and ht are then the largest pairs the plan accepts (bins,
+     * tiles and loop bounds are sized by them).  Such a plan is computed with
+     * stkde_compute_adaptive / stkde_bin_adaptive, not with stkde_compute /
+     * stkde_bin, and cannot be a batch item. */
+    STKDE_FLAG_ADAPTIVE = 16u
 };
 
 /* Problem description (Sec. 2.1 and Table "Notations").  Lower-case values
@@ -146,10 +155,14 @@ stkde_status stkde_workspace_bytes(stkde_plan_t plan, int64_t n, size_t* bytes);
  *              evaluations the method performs,
  *          [3] number of points with a non-finite coordinate,
  *          [4] number of finite points whose cylinder misses the grid,
- *          [5..7] reserved (0).
+ *          [5] (STKDE_FLAG_ADAPTIVE) number of points with finite coordinates
+ *              whose bandwidth pair is not finite and positive or exceeds
+ *              the plan's hs / ht: they contribute nothing, count in n,
+ *          [6..7] reserved (0).
  *  stream  hipStream_t as void*.
  *
- * Errors: INVALID_ARG, TOO_LARGE, WORKSPACE, HIP. */
+ * Errors: INVALID_ARG (also for a plan with STKDE_FLAG_ADAPTIVE), TOO_LARGE,
+ * WORKSPACE, HIP. */
 stkde_status stkde_compute(stkde_plan_t plan, const double* d_xyt, int64_t n, float* d_out,
                            void* d_ws, size_t ws_bytes, double* d_stats, void* stream);
 
@@ -172,6 +185,28 @@ stkde_status stkde_bin(stkde_plan_t plan, const double* d_xyt, int64_t n, void* 
                        size_t ws_bytes, void* stream);
 stkde_status stkde_accumulate(stkde_plan_t plan, int64_t n, float* d_out, void* d_ws,
                               size_t ws_bytes, double* d_stats, void* stream);
+
+/* Per-point bandwidths (plans with STKDE_FLAG_ADAPTIVE; the estimator is
+ * given at that flag).  Arguments as stkde_compute / stkde_bin, plus
+ *
+ *  d_hst   device, n x 2 FP64, row-major (hs_i, ht_i) in domain units, one
+ *          pair per point of d_xyt.  Read only.  A pair that is not finite
+ *          and positive, or has hs_i > hs or ht_i > ht of the plan, drops its
+ *          point (it contributes nothing but counts in n) and is counted in
+ *          d_stats[5].  Pairs all equal to the plan's reproduce the grid of
+ *          stkde_compute on the plan without the flag (bit for bit where
+ *          that grid does not take the full-cover path).
+ *
+ * Each point's footprint and loop bounds use its own pair.  stkde_accumulate
+ * serves adaptive plans too (after stkde_bin_adaptive).  With
+ * STKDE_FLAG_POINT_STATS, d_stats[1..2] use the per-point pairs.
+ * The gather of such plans has no full-cover path.
+ * Errors: as stkde_compute; INVALID_ARG also for a plan without the flag. */
+stkde_status stkde_compute_adaptive(stkde_plan_t plan, const double* d_xyt, const double* d_hst, int64_t n,
+                                    float* d_out, void* d_ws, size_t ws_bytes, double* d_stats,
+                                    void* stream);
+stkde_status stkde_bin_adaptive(stkde_plan_t plan, const double* d_xyt, const double* d_hst, int64_t n,
+                                void* d_ws, size_t ws_bytes, void* stream);
 
 /* ---- binned point sets ---------------------------------------------------
  *

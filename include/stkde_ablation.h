@@ -48,7 +48,8 @@ enum {
  *          stkde_workspace_bytes(plan, n) bytes, 256-byte aligned; read only.
  *
  * Errors: INVALID_ARG (null pointer, n < 1, unknown method), TOO_LARGE,
- * WORKSPACE, HIP. */
+ * WORKSPACE, HIP; UNSUPPORTED for a plan with STKDE_FLAG_ADAPTIVE, or one
+ * whose footprint boxes or grid exceed 2^31 - 1 voxels. */
 stkde_status stkde_ablation_accumulate(stkde_plan_t plan, int32_t method, int64_t n, float* d_out,
                                        void* d_ws, size_t ws_bytes, void* stream);
 

@@ -32,6 +32,7 @@ STKDE_ERR_UNSUPPORTED = -5
 FLAG_KAHAN = 1
 FLAG_MASS = 4
 FLAG_POINT_STATS = 8
+FLAG_ADAPTIVE = 16
 
 EXPORTED = ("stkde_plan", "stkde_plan_destroy", "stkde_workspace_bytes", "stkde_compute",
             "stkde_bin", "stkde_accumulate", "stkde_status_string", "stkde_version",
@@ -39,7 +40,8 @@ EXPORTED = ("stkde_plan", "stkde_plan_destroy", "stkde_workspace_bytes", "stkde_
             "stkde_batch_plan", "stkde_batch_workspace_bytes", "stkde_batch_run",
             "stkde_batch_capture", "stkde_batch_replay", "stkde_batch_destroy",
             "stkde_plan_profile", "stkde_plan_profile_read",
-            "stkde_ablation_accumulate", "stkde_ablation_compute")
+            "stkde_ablation_accumulate", "stkde_ablation_compute",
+            "stkde_compute_adaptive", "stkde_bin_adaptive")
 
 # Baselines of include/stkde_ablation.h (benchmarks and tests only).
 ABLATION_SCATTER = 1
@@ -91,6 +93,12 @@ def lib():
                                     ctypes.c_void_p, ctypes.c_void_p]
         L.stkde_bin.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                 ctypes.c_size_t, ctypes.c_void_p]
+        L.stkde_compute_adaptive.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]
+        L.stkde_bin_adaptive.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t,
+                                         ctypes.c_void_p]
         L.stkde_accumulate.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                        ctypes.c_void_p]
@@ -300,6 +308,65 @@ class Plan:
         if st != STKDE_OK:
             raise StkdeError(st, "stkde_accumulate")
         return out
+
+    @staticmethod
+    def _check_pairs(points, pairs):
+        import torch
+        n = int(points.shape[0])
+        if pairs.dtype != torch.float64 or not pairs.is_cuda or tuple(pairs.shape) != (n, 2) \
+                or not pairs.is_contiguous():
+            raise ValueError("pairs must be a contiguous [n, 2] float64 CUDA tensor of (hs_i, ht_i)")
+
+    def compute_adaptive_into(self, points, pairs, out, stats=None, workspace=None, stream=None):
+        """Per-point bandwidths (plan with FLAG_ADAPTIVE): points [n, 3] and
+        pairs [n, 2] (hs_i, ht_i) float64 CUDA tensors; as :meth:`compute_into`."""
+        import torch
+        n = int(points.shape[0])
+        if points.dtype != torch.float64 or not points.is_cuda or points.dim() != 2 \
+                or points.shape[1] != 3 or not points.is_contiguous():
+            raise ValueError("points must be a contiguous [n, 3] float64 CUDA tensor")
+        self._check_pairs(points, pairs)
+        d = self.desc
+        if out.dtype != torch.float32 or not out.is_cuda or out.numel() != d.gx * d.gy * d.gt \
+                or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 CUDA tensor of gx*gy*gt elements")
+        if stats is not None and (stats.dtype != torch.float64 or stats.numel() < 8 or not stats.is_cuda):
+            raise ValueError("stats must be a float64 CUDA tensor of 8 elements")
+        ws = workspace if workspace is not None else self.workspace(n, points.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(points.device)
+        p, nb = self._ws_args(ws)
+        st = lib().stkde_compute_adaptive(self._h, ctypes.c_void_p(points.data_ptr()),
+                                          ctypes.c_void_p(pairs.data_ptr()), n,
+                                          ctypes.c_void_p(out.data_ptr()), p, nb,
+                                          ctypes.c_void_p(stats.data_ptr()) if stats is not None else None,
+                                          ctypes.c_void_p(stream.cuda_stream))
+        if st != STKDE_OK:
+            raise StkdeError(st, "stkde_compute_adaptive")
+        return out
+
+    def compute_adaptive(self, points, pairs, stats=None):
+        """The density grid with per-point bandwidths as a [gx, gy, gt] tensor."""
+        import torch
+        d = self.desc
+        out = torch.empty((d.gx, d.gy, d.gt), dtype=torch.float32, device=points.device)
+        return self.compute_adaptive_into(points, pairs, out, stats=stats)
+
+    def bin_adaptive(self, points, pairs, workspace, stream=None):
+        """Stage 1 with per-point bandwidths (stkde_bin_adaptive)."""
+        import torch
+        if points.dtype != torch.float64 or not points.is_cuda or points.dim() != 2 \
+                or points.shape[1] != 3 or not points.is_contiguous():
+            raise ValueError("points must be a contiguous [n, 3] float64 CUDA tensor")
+        self._check_pairs(points, pairs)
+        if stream is None:
+            stream = torch.cuda.current_stream(points.device)
+        p, nb = self._ws_args(workspace)
+        st = lib().stkde_bin_adaptive(self._h, ctypes.c_void_p(points.data_ptr()),
+                                      ctypes.c_void_p(pairs.data_ptr()), int(points.shape[0]), p, nb,
+                                      ctypes.c_void_p(stream.cuda_stream))
+        if st != STKDE_OK:
+            raise StkdeError(st, "stkde_bin_adaptive")
 
     def ablation_accumulate(self, method: int, n, out, workspace, stream=None):
         """Baseline accumulation (stkde_ablation_accumulate): ABLATION_SCATTER

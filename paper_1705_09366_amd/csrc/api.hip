@@ -68,7 +68,8 @@ constexpr int64_t kMaxDim = 65535;
 constexpr int32_t kMaxCells = 1 << 22;  // keys of at most 23 bits: <= 3 radix passes (<= 2 below 2^22 - 1 bins)
 constexpr int32_t kMaxBatch = 4096;
 constexpr double kSparseCandidates = 384.0;  // half the gather's survivor buffer
-constexpr uint32_t kKnownFlags = STKDE_FLAG_KAHAN | STKDE_FLAG_MASS | STKDE_FLAG_POINT_STATS;
+constexpr uint32_t kKnownFlags =
+    STKDE_FLAG_KAHAN | STKDE_FLAG_MASS | STKDE_FLAG_POINT_STATS | STKDE_FLAG_ADAPTIVE;
 
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
@@ -223,11 +224,13 @@ bool use_full(double hv, int32_t tile_t) { return tile_t <= 32 && hv >= stkde::k
 
 stkde::InstDev make_dev(const stkde::InstGeom& ig, const stkde::SetGeom& sg, const uint8_t* set_mem,
                         const stkde::SetLayout& sl, int64_t n_norm, int32_t ox, int32_t oy,
-                        int32_t ot, float* out, double* stats, bool mass, uint32_t split_share) {
+                        int32_t ot, float* out, double* stats, bool mass, uint32_t split_share,
+                        bool adaptive = false) {
     stkde::InstDev d{};
     d.cell_start = reinterpret_cast<const uint32_t*>(set_mem + sl.cell_start);
     d.recs = reinterpret_cast<const stkde::PointRec*>(set_mem + sl.recs);
     d.counters = reinterpret_cast<const unsigned long long*>(set_mem + sl.counters);
+    d.bw = adaptive ? reinterpret_cast<const float4*>(set_mem + sl.bw) : nullptr;
     d.out = out;
     d.stats = stats;
     d.tile_part = nullptr;
@@ -250,7 +253,7 @@ stkde::InstDev make_dev(const stkde::InstGeom& ig, const stkde::SetGeom& sg, con
     d.ntiles = ig.ntiles;
     d.tile_base = 0;
     d.flags = (mass && stats) ? stkde::kInstMass : 0u;
-    if (use_full(ig.hv, ig.tile_t)) d.flags |= stkde::kInstFull;
+    if (!adaptive && use_full(ig.hv, ig.tile_t)) d.flags |= stkde::kInstFull;
     d.inv_hv2 = ig.inv_hv2;
     d.inv_tv2 = ig.inv_tv2;
     d.cnorm = norm_const(ig.hs, ig.ht, n_norm);
@@ -273,7 +276,7 @@ struct ComputeLayout {
 
 ComputeLayout layout_compute(const stkde_plan_s* p, int64_t n) {
     ComputeLayout c{};
-    c.sl = stkde::layout_set(p->sg, n);
+    c.sl = stkde::layout_set(p->sg, n, (p->desc.flags & STKDE_FLAG_ADAPTIVE) != 0);
     c.so = stkde::layout_sort(n);
     c.pl = stkde::layout_pass(&p->ig, 1, p->ig.tile_t, (p->desc.flags & STKDE_FLAG_KAHAN) != 0);
     c.nblk_pts = (int32_t)((n + stkde::kStatBlock - 1) / stkde::kStatBlock);
@@ -387,16 +390,31 @@ stkde_status stkde_workspace_bytes(stkde_plan_t p, int64_t n, size_t* bytes) {
     return STKDE_OK;
 }
 
-stkde_status stkde_bin(stkde_plan_t p, const double* d_xyt, int64_t n, void* d_ws, size_t ws_bytes,
-                       void* stream) {
-    if (!d_xyt) return STKDE_ERR_INVALID_ARG;
+namespace {
+bool is_adaptive(stkde_plan_t p) { return (p->desc.flags & STKDE_FLAG_ADAPTIVE) != 0; }
+
+stkde_status bin_impl(stkde_plan_t p, const double* d_xyt, const double* d_hst, int64_t n, void* d_ws,
+                      size_t ws_bytes, void* stream) {
     Call c;
     const stkde_status st = check_common(p, n, d_ws, ws_bytes, stream, &c);
     if (st != STKDE_OK) return st;
-    if (stkde::launch_bin(p->sg, d_xyt, (int32_t)n, c.ws, c.L.sl, c.ws + c.L.shared, c.L.so, c.s) !=
-        hipSuccess)
+    if (stkde::launch_bin(p->sg, d_xyt, (int32_t)n, c.ws, c.L.sl, c.ws + c.L.shared, c.L.so, c.s,
+                          d_hst) != hipSuccess)
         return STKDE_ERR_HIP;
     return STKDE_OK;
+}
+}  // namespace
+
+stkde_status stkde_bin(stkde_plan_t p, const double* d_xyt, int64_t n, void* d_ws, size_t ws_bytes,
+                       void* stream) {
+    if (!p || !d_xyt || is_adaptive(p)) return STKDE_ERR_INVALID_ARG;
+    return bin_impl(p, d_xyt, nullptr, n, d_ws, ws_bytes, stream);
+}
+
+stkde_status stkde_bin_adaptive(stkde_plan_t p, const double* d_xyt, const double* d_hst, int64_t n,
+                                void* d_ws, size_t ws_bytes, void* stream) {
+    if (!p || !d_xyt || !d_hst || !is_adaptive(p)) return STKDE_ERR_INVALID_ARG;
+    return bin_impl(p, d_xyt, d_hst, n, d_ws, ws_bytes, stream);
 }
 
 stkde_status stkde_accumulate(stkde_plan_t p, int64_t n, float* d_out, void* d_ws, size_t ws_bytes,
@@ -406,8 +424,9 @@ stkde_status stkde_accumulate(stkde_plan_t p, int64_t n, float* d_out, void* d_w
     const stkde_status st = check_common(p, n, d_ws, ws_bytes, stream, &c);
     if (st != STKDE_OK) return st;
     const uint32_t fl = p->desc.flags;
+    const bool adapt = (fl & STKDE_FLAG_ADAPTIVE) != 0;
     stkde::InstDev d = make_dev(p->ig, p->sg, c.ws, c.L.sl, n, 0, 0, 0, d_out, d_stats,
-                                (fl & STKDE_FLAG_MASS) != 0, p->split_share);
+                                (fl & STKDE_FLAG_MASS) != 0, p->split_share, adapt);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (p->ev_used + 2 <= (int32_t)p->ev.size()) {
         e0 = p->ev[(size_t)p->ev_used];
@@ -417,28 +436,42 @@ stkde_status stkde_accumulate(stkde_plan_t p, int64_t n, float* d_out, void* d_w
     const int mode = acc_mode((fl & STKDE_FLAG_KAHAN) != 0, p->kahan_mode, n, p->desc, p->ig.Hs, p->ig.Ht,
                               p->ig.tile_t);
     if (stkde::launch_pass(&d, 1, c.ws + c.L.shared, c.L.pl, p->ig.tile_t, mode,
-                           use_full(p->ig.hv, p->ig.tile_t), c.s, e0, e1) != hipSuccess)
+                           !adapt && use_full(p->ig.hv, p->ig.tile_t), adapt, c.s, e0, e1) != hipSuccess)
         return STKDE_ERR_HIP;
     return STKDE_OK;
 }
 
-stkde_status stkde_compute(stkde_plan_t p, const double* d_xyt, int64_t n, float* d_out, void* d_ws,
-                           size_t ws_bytes, double* d_stats, void* stream) {
-    if (!p || !d_xyt || !d_out) return STKDE_ERR_INVALID_ARG;
+namespace {
+stkde_status compute_impl(stkde_plan_t p, const double* d_xyt, const double* d_hst, int64_t n,
+                          float* d_out, void* d_ws, size_t ws_bytes, double* d_stats, void* stream) {
     Call c;
     stkde_status st = check_common(p, n, d_ws, ws_bytes, stream, &c);
     if (st != STKDE_OK) return st;
-    st = stkde_bin(p, d_xyt, n, d_ws, ws_bytes, stream);
+    st = bin_impl(p, d_xyt, d_hst, n, d_ws, ws_bytes, stream);
     if (st != STKDE_OK) return st;
     st = stkde_accumulate(p, n, d_out, d_ws, ws_bytes, d_stats, stream);
     if (st != STKDE_OK) return st;
     if (d_stats && (p->desc.flags & STKDE_FLAG_POINT_STATS)) {
         double* part = reinterpret_cast<double*>(c.ws + c.L.shared);
-        if (stkde::launch_point_stats(p->ig, n, d_xyt, (int32_t)n, d_stats, part, c.L.nblk_pts, c.s) !=
-            hipSuccess)
+        if (stkde::launch_point_stats(p->ig, n, d_xyt, (int32_t)n, d_stats, part, c.L.nblk_pts, c.s,
+                                      d_hst) != hipSuccess)
             return STKDE_ERR_HIP;
     }
     return STKDE_OK;
+}
+}  // namespace
+
+stkde_status stkde_compute(stkde_plan_t p, const double* d_xyt, int64_t n, float* d_out, void* d_ws,
+                           size_t ws_bytes, double* d_stats, void* stream) {
+    if (!p || !d_xyt || !d_out || is_adaptive(p)) return STKDE_ERR_INVALID_ARG;
+    return compute_impl(p, d_xyt, nullptr, n, d_out, d_ws, ws_bytes, d_stats, stream);
+}
+
+stkde_status stkde_compute_adaptive(stkde_plan_t p, const double* d_xyt, const double* d_hst, int64_t n,
+                                    float* d_out, void* d_ws, size_t ws_bytes, double* d_stats,
+                                    void* stream) {
+    if (!p || !d_xyt || !d_hst || !d_out || !is_adaptive(p)) return STKDE_ERR_INVALID_ARG;
+    return compute_impl(p, d_xyt, d_hst, n, d_out, d_ws, ws_bytes, d_stats, stream);
 }
 
 // ---- binned sets ------------------------------------------------------------
@@ -502,7 +535,7 @@ stkde_status stkde_batch_plan(const stkde_item* items, int32_t count, stkde_batc
         if ((uintptr_t)it.d_set & 255u) return STKDE_ERR_INVALID_ARG;
         const stkde_desc& d = it.plan->desc;
         const stkde_desc& b = it.set->base;
-        if (d.flags & STKDE_FLAG_POINT_STATS) return STKDE_ERR_UNSUPPORTED;
+        if (d.flags & (STKDE_FLAG_POINT_STATS | STKDE_FLAG_ADAPTIVE)) return STKDE_ERR_UNSUPPORTED;
         if (!same_res(d.sres, b.sres) || !same_res(d.tres, b.tres)) return STKDE_ERR_INVALID_ARG;
         if (d.hs > b.hs || d.ht > b.ht) return STKDE_ERR_INVALID_ARG;
         if (it.ox < 0 || it.oy < 0 || it.ot < 0 || it.ox + d.gx > b.gx || it.oy + d.gy > b.gy ||
@@ -584,8 +617,8 @@ stkde_status batch_enqueue(stkde_batch_t b, uint8_t* ws, hipStream_t s) {
                                     (it.plan->desc.flags & STKDE_FLAG_MASS) != 0,
                                     it.plan->split_share));
         }
-        if (stkde::launch_pass(devs.data(), (int32_t)devs.size(), ws, g.pl, g.tile_t, g.mode, g.full, s) !=
-            hipSuccess)
+        if (stkde::launch_pass(devs.data(), (int32_t)devs.size(), ws, g.pl, g.tile_t, g.mode, g.full, false,
+                               s) != hipSuccess)
             return STKDE_ERR_HIP;
     }
     return STKDE_OK;
@@ -602,7 +635,7 @@ stkde_status stkde_batch_run(stkde_batch_t b, void* d_ws, size_t ws_bytes, void*
 stkde_status stkde_batch_capture(stkde_batch_t b, void* d_ws, size_t ws_bytes) {
     if (!b) return STKDE_ERR_INVALID_ARG;
     if (!d_ws || ws_bytes < b->ws_bytes || ((uintptr_t)d_ws & 255u)) return STKDE_ERR_WORKSPACE;
-    for (const auto& g : b->groups) stkde::prepare_gather(g.tile_t, g.mode, g.full);
+    for (const auto& g : b->groups) stkde::prepare_gather(g.tile_t, g.mode, g.full, false);
     hipStream_t cs = nullptr;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return STKDE_ERR_HIP;
     hipGraph_t graph = nullptr;
@@ -654,6 +687,7 @@ stkde_status stkde_ablation_accumulate(stkde_plan_t p, int32_t method, int64_t n
     Call c;
     const stkde_status st = check_common(p, n, d_ws, ws_bytes, stream, &c);
     if (st != STKDE_OK) return st;
+    if (is_adaptive(p)) return STKDE_ERR_UNSUPPORTED;
     // the scatter indexes a footprint box, the voxel gather its grid, in 32 bits
     const stkde::InstGeom& g = p->ig;
     const int64_t box = (int64_t)std::min<int64_t>(g.gx, 2 * (int64_t)g.Hs + 2) *
@@ -673,6 +707,7 @@ stkde_status stkde_ablation_compute(stkde_plan_t p, int32_t method, const double
                                     float* d_out, void* d_ws, size_t ws_bytes, void* stream) {
     if (!p || !d_xyt || !d_out || (method != STKDE_ABLATION_SCATTER && method != STKDE_ABLATION_VOXEL))
         return STKDE_ERR_INVALID_ARG;
+    if (is_adaptive(p)) return STKDE_ERR_UNSUPPORTED;
     stkde_status st = stkde_bin(p, d_xyt, n, d_ws, ws_bytes, stream);
     if (st != STKDE_OK) return st;
     return stkde_ablation_accumulate(p, method, n, d_out, d_ws, ws_bytes, stream);

@@ -39,11 +39,13 @@ __device__ inline int32_t floordiv(int32_t a, int32_t b) {
     return (a % b != 0 && (a < 0)) ? q - 1 : q;
 }
 
-// Voxel-space footprint of one point.  Column X is inside the disc when
+// Voxel-space footprint of one point with voxel bandwidths hv, tv (the
+// set's, or the point's own).  Column X is inside the disc when
 // |X + 1/2 - xr| < hv; row T is inside the window when |T + 1/2 - tr| <= tv.
 // The integer ranges below are those sets up to rows where the kernel value
 // is zero to rounding, clipped to the grid.
-__device__ inline Footprint footprint(const SetGeom& g, double x, double y, double t) {
+__device__ inline Footprint footprint(const SetGeom& g, double x, double y, double t, double hv,
+                                      double tv) {
     Footprint f;
     f.finite = isfinite(x) && isfinite(y) && isfinite(t);
     f.inside = false;
@@ -54,12 +56,12 @@ __device__ inline Footprint footprint(const SetGeom& g, double x, double y, doub
     f.fx = f.fy = f.ft = 0;
     if (!f.finite) return f;
     // reject far-away points before any conversion to integers
-    if (f.xr + g.hv < -1.0 || f.xr - g.hv > (double)g.gx + 1.0) return f;
-    if (f.yr + g.hv < -1.0 || f.yr - g.hv > (double)g.gy + 1.0) return f;
-    if (f.tr + g.tv < -1.0 || f.tr - g.tv > (double)g.gt + 1.0) return f;
-    const double xlo = floor(f.xr - g.hv - 0.5) + 1.0, xhi = ceil(f.xr + g.hv - 0.5) - 1.0;
-    const double ylo = floor(f.yr - g.hv - 0.5) + 1.0, yhi = ceil(f.yr + g.hv - 0.5) - 1.0;
-    const double tlo = ceil(f.tr - g.tv - 0.5), thi = floor(f.tr + g.tv - 0.5);
+    if (f.xr + hv < -1.0 || f.xr - hv > (double)g.gx + 1.0) return f;
+    if (f.yr + hv < -1.0 || f.yr - hv > (double)g.gy + 1.0) return f;
+    if (f.tr + tv < -1.0 || f.tr - tv > (double)g.gt + 1.0) return f;
+    const double xlo = floor(f.xr - hv - 0.5) + 1.0, xhi = ceil(f.xr + hv - 0.5) - 1.0;
+    const double ylo = floor(f.yr - hv - 0.5) + 1.0, yhi = ceil(f.yr + hv - 0.5) - 1.0;
+    const double tlo = ceil(f.tr - tv - 0.5), thi = floor(f.tr + tv - 0.5);
     f.xlo = (int32_t)fmax(xlo, 0.0);
     f.xhi = (int32_t)fmin(xhi, (double)(g.gx - 1));
     f.ylo = (int32_t)fmax(ylo, 0.0);
@@ -85,26 +87,47 @@ __global__ void k_zero_u64(unsigned long long* p, int count) {
     if (i < count) p[i] = 0ull;
 }
 
+// A point's voxel bandwidths: the set's, or its own pair (hs_i / sres,
+// ht_i / tres) when it carries one; false for a pair that is not finite and
+// positive or exceeds the set's (bins and tiles are sized by the set's).
+__device__ inline bool point_bandwidths(const SetGeom& g, const double* __restrict__ hst, int64_t i,
+                                        double* hv, double* tv) {
+    if (!hst) {
+        *hv = g.hv;
+        *tv = g.tv;
+        return true;
+    }
+    const double hs = hst[2 * (size_t)i], ht = hst[2 * (size_t)i + 1];
+    *hv = hs / g.sres;
+    *tv = ht / g.tres;
+    return isfinite(hs) && isfinite(ht) && hs > 0.0 && ht > 0.0 && *hv <= g.hv && *tv <= g.tv;
+}
+
 __global__ __launch_bounds__(kThreads) void k_transform(SetGeom g, const double* __restrict__ xyt,
-                                                        int32_t n, uint32_t* __restrict__ keys,
+                                                        const double* __restrict__ hst, int32_t n,
+                                                        uint32_t* __restrict__ keys,
                                                         uint32_t* __restrict__ vals,
                                                         unsigned long long* __restrict__ counters) {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    bool nonfinite = false, culled = false;
+    bool nonfinite = false, culled = false, badbw = false;
     if (i < n) {
+        double hv, tv;
+        const bool bw_ok = point_bandwidths(g, hst, i, &hv, &tv);
         const Footprint f = footprint(g, xyt[3 * (size_t)i], xyt[3 * (size_t)i + 1],
-                                      xyt[3 * (size_t)i + 2]);
+                                      xyt[3 * (size_t)i + 2], bw_ok ? hv : g.hv, bw_ok ? tv : g.tv);
         uint32_t key = (uint32_t)g.ncell;
         if (!f.finite) nonfinite = true;
+        else if (!bw_ok) badbw = true;
         else if (!f.inside) culled = true;
         else key = bin_key(g, f);
         keys[i] = key;
         vals[i] = (uint32_t)i;
     }
-    const unsigned long long mnf = __ballot(nonfinite), mcu = __ballot(culled);
+    const unsigned long long mnf = __ballot(nonfinite), mcu = __ballot(culled), mbw = __ballot(badbw);
     if ((threadIdx.x & 63) == 0) {
         if (mnf) atomicAdd(&counters[0], (unsigned long long)__popcll(mnf));
         if (mcu) atomicAdd(&counters[1], (unsigned long long)__popcll(mcu));
+        if (mbw) atomicAdd(&counters[2], (unsigned long long)__popcll(mbw));
     }
 }
 
@@ -263,17 +286,27 @@ __device__ inline uint32_t pack_tail(double v, float head) {
     return (uint32_t)__builtin_bit_cast(uint16_t, h);
 }
 
+// Per sorted point: its record, and with per-point bandwidths its terms
+// (1/hv_i^2, 1/tv_i^2, (hv^2 tv) / (hv_i^2 tv_i)): the weight carries the
+// point's own normalisation relative to the set's, which the store applies.
 __global__ __launch_bounds__(kThreads) void k_records(SetGeom g, const double* __restrict__ xyt,
+                                                      const double* __restrict__ hst,
                                                       const uint32_t* __restrict__ vals,
                                                       const uint32_t* __restrict__ cell_start,
-                                                      int32_t n, PointRec* __restrict__ recs) {
+                                                      int32_t n, PointRec* __restrict__ recs,
+                                                      float4* __restrict__ bw) {
     const int64_t s = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (s >= n) return;
     const int64_t nvalid = (int64_t)cell_start[g.ncell];
     if (s >= nvalid) return;
     const uint32_t i = vals[s];
+    double hv, tv;
+    (void)point_bandwidths(g, hst, i, &hv, &tv);  // valid: invalid pairs sort past nvalid
     const Footprint f = footprint(g, xyt[3 * (size_t)i], xyt[3 * (size_t)i + 1],
-                                  xyt[3 * (size_t)i + 2]);
+                                  xyt[3 * (size_t)i + 2], hv, tv);
+    if (hst)
+        bw[s] = make_float4((float)(1.0 / (hv * hv)), (float)(1.0 / (tv * tv)),
+                            (float)((g.hv * g.hv * g.tv) / (hv * hv * tv)), 0.0f);
     PointRec r;
     r.xh = (float)f.xr;
     r.yh = (float)f.yr;
@@ -298,12 +331,13 @@ namespace {
 size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 }  // namespace
 
-SetLayout layout_set(const SetGeom& g, int64_t n) {
+SetLayout layout_set(const SetGeom& g, int64_t n, bool adaptive) {
     SetLayout l{};
     size_t o = 0;
     l.cell_start = o; o = al256(o + ((size_t)g.ncell + 1) * 4);
     l.recs = o; o = al256(o + (size_t)n * sizeof(PointRec));
     l.counters = o; o = al256(o + 4 * 8);
+    l.bw = o; o = al256(o + (adaptive ? (size_t)n * sizeof(float4) : 0));
     l.total = o;
     return l;
 }
@@ -324,7 +358,8 @@ SortLayout layout_sort(int64_t n) {
 }
 
 hipError_t launch_bin(const SetGeom& g, const double* d_xyt, int32_t n, uint8_t* set,
-                      const SetLayout& sl, uint8_t* sort, const SortLayout& so, hipStream_t s) {
+                      const SetLayout& sl, uint8_t* sort, const SortLayout& so, hipStream_t s,
+                      const double* d_hst) {
     uint32_t* k0 = reinterpret_cast<uint32_t*>(sort + so.keys0);
     uint32_t* v0 = reinterpret_cast<uint32_t*>(sort + so.vals0);
     uint32_t* k1 = reinterpret_cast<uint32_t*>(sort + so.keys1);
@@ -336,7 +371,7 @@ hipError_t launch_bin(const SetGeom& g, const double* d_xyt, int32_t n, uint8_t*
     const int nb = (n + kThreads - 1) / kThreads;
 
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ctr, 4);
-    hipLaunchKernelGGL(k_transform, dim3(nb), dim3(kThreads), 0, s, g, d_xyt, n, k0, v0, ctr);
+    hipLaunchKernelGGL(k_transform, dim3(nb), dim3(kThreads), 0, s, g, d_xyt, d_hst, n, k0, v0, ctr);
 
     // keys are at most ncell (culled points): ceil(bits / 11) passes of equal digits
     const int bits = bits_for((uint32_t)g.ncell);
@@ -357,8 +392,9 @@ hipError_t launch_bin(const SetGeom& g, const double* d_xyt, int32_t n, uint8_t*
     }
     const int nc = (g.ncell + 1 + kThreads - 1) / kThreads;
     hipLaunchKernelGGL(k_cell_start, dim3(nc), dim3(kThreads), 0, s, k0, n, g.ncell, cs);
-    hipLaunchKernelGGL(k_records, dim3(nb), dim3(kThreads), 0, s, g, d_xyt, v0, cs, n,
-                       reinterpret_cast<PointRec*>(set + sl.recs));
+    hipLaunchKernelGGL(k_records, dim3(nb), dim3(kThreads), 0, s, g, d_xyt, d_hst, v0, cs, n,
+                       reinterpret_cast<PointRec*>(set + sl.recs),
+                       d_hst ? reinterpret_cast<float4*>(set + sl.bw) : nullptr);
     return hipGetLastError();
 }
 

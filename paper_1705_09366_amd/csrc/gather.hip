@@ -98,12 +98,16 @@ __device__ inline void kahan_fold(f32x4 (&sum)[CG], f32x4 (&comp)[CG], f32x4 (&p
 // spill outside the matrix-core loop; measured 4-7 % faster than three
 // workgroups).  With 768 survivors the LDS holds five workgroups where the
 // registers allow it.
-template <int TT, int MODE, bool FULL>
+// ADAPT: every record carries its own bandwidth terms (1/hv_i^2, 1/tv_i^2,
+// weight); they are staged beside the coordinates and enter the operands of
+// each point (the weight scales its Kt operand).
+template <int TT, int MODE, bool FULL, bool ADAPT>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_gather_items(
     const InstDev* __restrict__ descs, int32_t count, int32_t ntiles_total,
     const WorkItem* __restrict__ items, const uint32_t* __restrict__ bits,
     const uint32_t* __restrict__ sc, uint32_t* __restrict__ ctr, float* __restrict__ partials,
     float* __restrict__ kscratch) {
+    static_assert(!(FULL && ADAPT), "the full-cover path assumes one bandwidth pair");
     constexpr int NB = TT / 16;  // 16-row blocks per tile
     constexpr int CG = 4 * NB;   // accumulator blocks per wave
     // Kahan with the running (sum, compensation) in memory: this thread's
@@ -122,6 +126,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
     float2* const sY = sXYT + (kCap + 1);
     float2* const sT = sXYT + 2 * (kCap + 1);
     __shared__ uint8_t sQ[kCap];
+    // per-point bandwidth terms of the survivors (ADAPT only)
+    __shared__ float4 sB[ADAPT ? kCap + 1 : 1];
     // per-wave lists of survivor indices: the quadrant list, then (full-cover
     // path) the wave's share of the full-cover list, each padded to 8
     __shared__ uint16_t sL[kWaves][kCap + 16];
@@ -137,6 +143,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
         sX[kPad] = make_float2(-1.0e6f, 0.f);
         sY[kPad] = make_float2(-1.0e6f, 0.f);
         sT[kPad] = make_float2(-1.0e6f, 0.f);
+        if constexpr (ADAPT) sB[kPad] = make_float4(1.0f, 1.0f, 0.0f, 0.0f);
     }
 
     // this wave's quadrant: column groups gx in {gqx, gqx + 1}, gy in {gqy, gqy + 1}
@@ -242,24 +249,28 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                 }
                 int32_t nphase = 0;
 
-                // one group: operands from the coordinates of this lane's point,
-                // then all CG instructions
-                auto group = [&](const float2 cx, const float2 cy, const float2 ctt) {
+                // one group: operands from the coordinates (and, ADAPT, the
+                // bandwidth terms pb) of this lane's point, then all CG
+                // instructions
+                auto group = [&](const float2 cx, const float2 cy, const float2 ctt, const float4 pb) {
+                    const float ihv2 = ADAPT ? pb.x : inv_hv2;
+                    const float itv2 = ADAPT ? pb.y : inv_tv2;
                     float av[NB];
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
                         const float dt = ((rowc + 16.0f * b) - ctt.x) - ctt.y;
                         // the operands never exceed 1, so max(0, .) is a clamp to
                         // [0, 1], which folds into the producing instruction
-                        av[b] = __builtin_amdgcn_fmed3f(fmaf(-dt * dt, inv_tv2, 1.0f), 0.0f, 1.0f);
+                        av[b] = __builtin_amdgcn_fmed3f(fmaf(-dt * dt, itv2, 1.0f), 0.0f, 1.0f);
+                        if constexpr (ADAPT) av[b] *= pb.z;
                     }
                     float ux[2], uy[2];
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
                         const float dx = ((xc0 + 4.0f * h) - cx.x) - cx.y;
                         const float dy = ((yc0 + 4.0f * h) - cy.x) - cy.y;
-                        ux[h] = fmaf(-dx * dx, inv_hv2, 1.0f);
-                        uy[h] = dy * dy * inv_hv2;
+                        ux[h] = fmaf(-dx * dx, ihv2, 1.0f);
+                        uy[h] = dy * dy * ihv2;
                     }
 #pragma unroll
                     for (int g = 0; g < 4; ++g) {
@@ -305,6 +316,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                         const int32_t c = bb + tid;
                         bool surv = false;
                         PointRec r{};
+                        float4 pbw{};
                         uint32_t qm = 0;
                         if (c < cend) {
                             int32_t lo = 0, hi = nranges - 1;  // last range with sRP <= c
@@ -313,7 +325,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                                 if (sRP[mid] <= c) lo = mid;
                                 else hi = mid - 1;
                             }
-                            r = recs[sRB[lo] + (c - sRP[lo])];
+                            const int32_t ri = sRB[lo] + (c - sRP[lo]);
+                            r = recs[ri];
+                            if constexpr (ADAPT) pbw = D.bw[ri];
                             const int32_t xlo = (int32_t)(r.xb & 0xffffu) - BX0, xhi = (int32_t)(r.xb >> 16) - BX0;
                             const int32_t ylo = (int32_t)(r.yb & 0xffffu) - BY0, yhi = (int32_t)(r.yb >> 16) - BY0;
                             const int32_t tlo = (int32_t)(r.tb & 0xffffu), thi = (int32_t)(r.tb >> 16);
@@ -353,6 +367,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                             sX[s] = make_float2(r.xh - (float)BX0, half_lo(r.xl_yl));
                             sY[s] = make_float2(r.yh - (float)BY0, half_hi(r.xl_yl));
                             sT[s] = make_float2(r.th - (float)BT0, half_lo(r.tl));
+                            if constexpr (ADAPT) sB[s] = pbw;
                             sQ[s] = (uint8_t)qm;
                         }
                         count_s += add;
@@ -394,17 +409,20 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                     if (npairs > 0) {
                         int s = myL[kq];
                         float2 ax = sX[s], ay = sY[s], at = sT[s];
+                        float4 ab = ADAPT ? sB[s] : float4{};
                         for (int32_t pr = 0; pr < npairs; ++pr) {
                             s = myL[8 * pr + 4 + kq];
                             const float2 bx = sX[s], by = sY[s], bt = sT[s];
-                            group(ax, ay, at);
+                            const float4 bbw = ADAPT ? sB[s] : float4{};
+                            group(ax, ay, at, ab);
                             if (pr + 1 < npairs) {
                                 s = myL[8 * pr + 8 + kq];
                                 ax = sX[s];
                                 ay = sY[s];
                                 at = sT[s];
+                                if constexpr (ADAPT) ab = sB[s];
                             }
-                            group(bx, by, bt);
+                            group(bx, by, bt, bbw);
                         }
                     }
                     if constexpr (FULL) {
@@ -625,7 +643,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce_split(const InstDev* __rest
 // Workgroups of the persistent gather: compute units x resident workgroups
 // per compute unit, cached per device (memory-mode Kahan at most
 // kMemKahanGroups, the slots of its scratch).
-template <int TT, int MODE, bool FULL>
+template <int TT, int MODE, bool FULL, bool ADAPT>
 int resident_groups() {
     static_assert(!FULL || TT <= 32, "the full-cover sums of 64-row tiles do not fit the survivor LDS");
     static std::atomic<int> cache[kMaxDevices];
@@ -635,8 +653,8 @@ int resident_groups() {
     if (v > 0) return v;
     int ncu = 0, occ = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_gather_items<TT, MODE, FULL>, kThreads, 0) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_gather_items<TT, MODE, FULL, ADAPT>, kThreads,
+                                                     0) != hipSuccess)
         occ = 0;
     v = (ncu > 0 ? ncu : 256) * (occ > 0 ? occ : 1);
     if (MODE == kAccKahanMem && v > kMemKahanGroups) v = kMemKahanGroups;
@@ -644,36 +662,45 @@ int resident_groups() {
     return v;
 }
 
-template <int TT, int MODE, bool FULL>
+template <int TT, int MODE, bool FULL, bool ADAPT>
 void launch_items_t(const InstDev* d, int32_t count, const WorkItem* items, const uint32_t* bits,
                     const uint32_t* sc, uint32_t* ctr, float* partials, float* kscratch, int64_t T,
                     hipStream_t s) {
-    int64_t g = resident_groups<TT, MODE, FULL>();
+    int64_t g = resident_groups<TT, MODE, FULL, ADAPT>();
     const int64_t most = T + kPartSlots;  // items never exceed tiles + partial slots
     if (g > most) g = most;
     if (g < 1) g = 1;
-    hipLaunchKernelGGL((k_gather_items<TT, MODE, FULL>), dim3((uint32_t)g), dim3(kThreads), 0, s, d,
-                       count, (int32_t)T, items, bits, sc, ctr, partials, kscratch);
+    hipLaunchKernelGGL((k_gather_items<TT, MODE, FULL, ADAPT>), dim3((uint32_t)g), dim3(kThreads), 0, s,
+                       d, count, (int32_t)T, items, bits, sc, ctr, partials, kscratch);
 }
 
-// Calls f.template operator()<TT, MODE, FULL>() for the kernel variant of
-// (tile_t, mode, full); 64-row tiles are plain and without the full-cover path.
-template <typename F>
-void dispatch(int tile_t, int mode, bool full, F&& f) {
-    if (tile_t == 16) {
-        if (mode == kAccKahanReg) full ? f.template operator()<16, kAccKahanReg, true>()
-                                       : f.template operator()<16, kAccKahanReg, false>();
-        else if (mode == kAccKahanMem) full ? f.template operator()<16, kAccKahanMem, true>()
-                                            : f.template operator()<16, kAccKahanMem, false>();
-        else full ? f.template operator()<16, kAccPlain, true>() : f.template operator()<16, kAccPlain, false>();
-    } else if (tile_t == 32) {
-        if (mode == kAccKahanReg) full ? f.template operator()<32, kAccKahanReg, true>()
-                                       : f.template operator()<32, kAccKahanReg, false>();
-        else if (mode == kAccKahanMem) full ? f.template operator()<32, kAccKahanMem, true>()
-                                            : f.template operator()<32, kAccKahanMem, false>();
-        else full ? f.template operator()<32, kAccPlain, true>() : f.template operator()<32, kAccPlain, false>();
+// f.template operator()<TT, MODE, FULL, ADAPT>() for one (tile rows, mode):
+// per-point bandwidths never take the full-cover path, nor do 64-row tiles.
+template <int TT, int MODE, typename F>
+void dispatch_variant(bool full, bool adapt, F& f) {
+    if (adapt) {
+        f.template operator()<TT, MODE, false, true>();
+    } else if constexpr (TT <= 32) {
+        if (full) f.template operator()<TT, MODE, true, false>();
+        else f.template operator()<TT, MODE, false, false>();
     } else {
-        f.template operator()<64, kAccPlain, false>();
+        f.template operator()<TT, MODE, false, false>();
+    }
+}
+
+// The kernel variant of (tile_t, mode, full, adapt); 64-row tiles are plain.
+template <typename F>
+void dispatch(int tile_t, int mode, bool full, bool adapt, F&& f) {
+    if (tile_t == 16) {
+        if (mode == kAccKahanReg) dispatch_variant<16, kAccKahanReg>(full, adapt, f);
+        else if (mode == kAccKahanMem) dispatch_variant<16, kAccKahanMem>(full, adapt, f);
+        else dispatch_variant<16, kAccPlain>(full, adapt, f);
+    } else if (tile_t == 32) {
+        if (mode == kAccKahanReg) dispatch_variant<32, kAccKahanReg>(full, adapt, f);
+        else if (mode == kAccKahanMem) dispatch_variant<32, kAccKahanMem>(full, adapt, f);
+        else dispatch_variant<32, kAccPlain>(full, adapt, f);
+    } else {
+        dispatch_variant<64, kAccPlain>(full, adapt, f);
     }
 }
 
@@ -689,16 +716,17 @@ void launch_reduce_t(const InstDev* d, int32_t count, const uint32_t* top, const
 hipError_t launch_gather_items(const InstDev* d_desc, int32_t count, const WorkItem* d_items,
                                const uint32_t* d_bits, const uint32_t* d_scalars,
                                uint32_t* d_counters, float* d_partials, float* d_kscratch, int64_t T,
-                               int tile_t, int mode, bool full, hipStream_t s) {
-    dispatch(tile_t, mode, full, [&]<int TT, int M, bool F>() {
-        launch_items_t<TT, M, F>(d_desc, count, d_items, d_bits, d_scalars, d_counters, d_partials,
-                                 d_kscratch, T, s);
+                               int tile_t, int mode, bool full, bool adapt, hipStream_t s) {
+    dispatch(tile_t, mode, full, adapt, [&]<int TT, int M, bool F, bool A>() {
+        launch_items_t<TT, M, F, A>(d_desc, count, d_items, d_bits, d_scalars, d_counters, d_partials,
+                                    d_kscratch, T, s);
     });
     return hipGetLastError();
 }
 
-void prepare_gather(int tile_t, int mode, bool full) {
-    dispatch(tile_t, mode, full, []<int TT, int M, bool F>() { (void)resident_groups<TT, M, F>(); });
+void prepare_gather(int tile_t, int mode, bool full, bool adapt) {
+    dispatch(tile_t, mode, full, adapt,
+             []<int TT, int M, bool F, bool A>() { (void)resident_groups<TT, M, F, A>(); });
 }
 
 hipError_t launch_reduce_split(const InstDev* d_desc, int32_t count, const uint32_t* d_top,

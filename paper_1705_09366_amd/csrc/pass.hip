@@ -22,6 +22,7 @@ namespace {
 struct DescChunk {
     InstDev d[kDescChunk];
 };
+static_assert(sizeof(DescChunk) <= 4096, "descriptors must fit the kernel-argument space");
 
 size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -272,8 +273,8 @@ __global__ __launch_bounds__(256) void k_mass_chunks(const InstDev* __restrict__
 }
 
 // Per instance: stats[0] = grid mass (sum * sres^2 tres, or 0 without the
-// mass flag), [1], [2], [5..7] = 0, [3], [4] = the set's non-finite and
-// culled counts.
+// mass flag), [1], [2], [6], [7] = 0, [3], [4], [5] = the set's non-finite,
+// culled and invalid-bandwidth counts.
 __global__ __launch_bounds__(64) void k_finalize(const InstDev* __restrict__ descs,
                                                  const double* __restrict__ mid) {
     static_assert(kMassChunks == 64, "one wave per instance");
@@ -290,7 +291,7 @@ __global__ __launch_bounds__(64) void k_finalize(const InstDev* __restrict__ des
         st[2] = 0.0;
         st[3] = (double)D.counters[0];
         st[4] = (double)D.counters[1];
-        st[5] = 0.0;
+        st[5] = (double)D.counters[2];
         st[6] = 0.0;
         st[7] = 0.0;
     }
@@ -327,8 +328,8 @@ PassLayout layout_pass(const InstGeom* inst, int32_t count, int tile_t, bool kah
 }
 
 hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassLayout& pl,
-                       int tile_t, int mode, bool full, hipStream_t s, hipEvent_t ev_before,
-                       hipEvent_t ev_after) {
+                       int tile_t, int mode, bool full, bool adapt, hipStream_t s,
+                       hipEvent_t ev_before, hipEvent_t ev_after) {
     const bool kahan = mode != kAccPlain;
     InstDev* d_desc = reinterpret_cast<InstDev*>(pass + pl.desc);
     auto* inst_cost = reinterpret_cast<unsigned long long*>(pass + pl.inst_cost);
@@ -368,7 +369,7 @@ hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassL
     if (e != hipSuccess) return e;
     if (ev_before && (e = hipEventRecord(ev_before, s)) != hipSuccess) return e;
     e = launch_gather_items(d_desc, count, items, bits, sc, ctr, partials, kscratch, pl.T, tile_t, mode,
-                            full, s);
+                            full, adapt, s);
     if (e != hipSuccess) return e;
     if (ev_after && (e = hipEventRecord(ev_after, s)) != hipSuccess) return e;
     e = launch_reduce_split(d_desc, count, top, sc, partials, tile_t, kahan, s);

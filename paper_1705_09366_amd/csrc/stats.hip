@@ -9,7 +9,11 @@
 // evaluates those sums in FP64 with the support tests of Alg. VB / PB-SYM
 // written in domain units (spatial distance < hs via a square root, time
 // distance <= ht), in the same precision and the same form as the CPU
-// reference, so that the integer counts agree exactly.
+// reference, so that the integer counts agree exactly.  With per-point
+// bandwidths each point uses its own pair and loop bounds and its mass
+// carries (hs^2 ht) / (hs_i^2 ht_i) relative to the instance's pair; a
+// pair that binning drops (not finite and positive, or above the
+// instance's) contributes nothing here either.
 #include "stkde_internal.h"
 
 namespace stkde {
@@ -24,7 +28,8 @@ __device__ inline bool clip_rng(double v, double h, int32_t lo, int32_t hi, int3
 }
 
 __global__ __launch_bounds__(kStatBlock) void k_point_stats(InstGeom g, const double* __restrict__ xyt,
-                                                            int32_t n, double* __restrict__ part) {
+                                                            const double* __restrict__ hst, int32_t n,
+                                                            double* __restrict__ part) {
 #pragma clang fp contract(off)
     __shared__ double sm[kStatBlock];
     __shared__ double se[kStatBlock];
@@ -32,38 +37,51 @@ __global__ __launch_bounds__(kStatBlock) void k_point_stats(InstGeom g, const do
     double mass = 0.0, evals = 0.0;
     if (i < n) {
         const double xi = xyt[3 * (size_t)i], yi = xyt[3 * (size_t)i + 1], ti = xyt[3 * (size_t)i + 2];
-        if (isfinite(xi) && isfinite(yi) && isfinite(ti)) {
+        double hs = g.hs, ht = g.ht, Hs = g.Hs_d, Ht = g.Ht_d, wi = 1.0;
+        bool ok = true;
+        if (hst) {
+            hs = hst[2 * (size_t)i];
+            ht = hst[2 * (size_t)i + 1];
+            ok = isfinite(hs) && isfinite(ht) && hs > 0.0 && ht > 0.0 && hs / g.sres <= g.hv &&
+                 ht / g.tres <= g.tv;
+            if (ok) {
+                Hs = ceil(hs / g.sres);
+                Ht = ceil(ht / g.tres);
+                wi = (g.hs * g.hs * g.ht) / (hs * hs * ht);
+            }
+        }
+        if (ok && isfinite(xi) && isfinite(yi) && isfinite(ti)) {
             const double Xi = floor((xi - g.x0) / g.sres);
             const double Yi = floor((yi - g.y0) / g.sres);
             const double Ti = floor((ti - g.t0) / g.tres);
             int32_t xa, xb, ya, yb, ta, tb;
             double ss = 0.0, st = 0.0;
             long long cs = 0, ct = 0;
-            if (clip_rng(Xi, g.Hs_d, 0, g.gx, &xa, &xb) && clip_rng(Yi, g.Hs_d, 0, g.gy, &ya, &yb)) {
+            if (clip_rng(Xi, Hs, 0, g.gx, &xa, &xb) && clip_rng(Yi, Hs, 0, g.gy, &ya, &yb)) {
                 for (int32_t X = xa; X <= xb; ++X) {
                     const double x = g.x0 + ((double)X + 0.5) * g.sres;
                     for (int32_t Y = ya; Y <= yb; ++Y) {
                         const double y = g.y0 + ((double)Y + 0.5) * g.sres;
                         const double d = sqrt((xi - x) * (xi - x) + (yi - y) * (yi - y));
-                        if (d < g.hs) {
-                            const double u = (x - xi) / g.hs, v = (y - yi) / g.hs;
+                        if (d < hs) {
+                            const double u = (x - xi) / hs, v = (y - yi) / hs;
                             ss += (2.0 / 3.14159265358979323846) * (1.0 - u * u - v * v);
                             ++cs;
                         }
                     }
                 }
             }
-            if (clip_rng(Ti, g.Ht_d, 0, g.gt, &ta, &tb)) {
+            if (clip_rng(Ti, Ht, 0, g.gt, &ta, &tb)) {
                 for (int32_t T = ta; T <= tb; ++T) {
                     const double t = g.t0 + ((double)T + 0.5) * g.tres;
-                    if (fabs(ti - t) <= g.ht) {
-                        const double w = (t - ti) / g.ht;
+                    if (fabs(ti - t) <= ht) {
+                        const double w = (t - ti) / ht;
                         st += 0.75 * (1.0 - w * w);
                         ++ct;
                     }
                 }
             }
-            mass = ss * st;
+            mass = ss * st * wi;
             evals = (double)(cs * ct);
         }
     }
@@ -115,8 +133,9 @@ __global__ __launch_bounds__(1024) void k_stats_final(const double* __restrict__
 }  // namespace
 
 hipError_t launch_point_stats(const InstGeom& g, int64_t n_norm, const double* d_xyt, int32_t n,
-                              double* d_stats, double* part, int32_t nblk, hipStream_t s) {
-    hipLaunchKernelGGL(k_point_stats, dim3(nblk), dim3(kStatBlock), 0, s, g, d_xyt, n, part);
+                              double* d_stats, double* part, int32_t nblk, hipStream_t s,
+                              const double* d_hst) {
+    hipLaunchKernelGGL(k_point_stats, dim3(nblk), dim3(kStatBlock), 0, s, g, d_xyt, d_hst, n, part);
     const double scale = g.sres * g.sres * g.tres / ((double)n_norm * g.hs * g.hs * g.ht);
     hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(1024), 0, s, (const double*)part, nblk, scale,
                        d_stats);

@@ -73,7 +73,9 @@ struct InstGeom {
 struct alignas(16) InstDev {
     const uint32_t* cell_start;          // set: bin offsets
     const PointRec* recs;                // set: records in bin order
-    const unsigned long long* counters;  // set: non-finite, culled
+    const unsigned long long* counters;  // set: non-finite, culled, invalid bandwidth pairs
+    const float4* bw;                    // set: per record (1/hv_i^2, 1/tv_i^2, weight, 0) when
+                                         // its points carry their own bandwidths, else null
     float* out;                          // instance grid, [X][Y][T], T fastest
     double* stats;                       // optional 8 doubles, null for none
     double* tile_part;                   // pass scratch: ntiles * kWaves FP64 mass partials
@@ -154,10 +156,11 @@ constexpr int kCtrWords = 2 * kFetchLanes * kCtrStride;
 struct SetLayout {
     size_t cell_start;   // (ncell + 1) u32
     size_t recs;         // n PointRec
-    size_t counters;     // 4 x u64: non-finite, culled, 0, 0
+    size_t counters;     // 4 x u64: non-finite, culled, invalid bandwidth pairs, 0
+    size_t bw;           // n float4 (per-point bandwidths; 0 bytes without)
     size_t total;
 };
-SetLayout layout_set(const SetGeom& s, int64_t n);
+SetLayout layout_set(const SetGeom& s, int64_t n, bool adaptive = false);
 
 // ---- scratch of the binning radix sort --------------------------------------
 struct SortLayout {
@@ -247,32 +250,39 @@ __device__ inline uint32_t spatial_pos(const InstDev& D, uint32_t j) {
 }
 
 // ---- launchers (asynchronous on s; return the launch error) ---------------
-// Bin n points into set memory `set` using radix scratch `sort`.
+// Bin n points into set memory `set` using radix scratch `sort`.  d_hst
+// (n x 2 FP64 per-point bandwidths in domain units, or null) makes each
+// point's footprint and record terms its own; a pair that is not finite and
+// positive, or exceeds the set's bandwidths, drops the point (counted).
 hipError_t launch_bin(const SetGeom& g, const double* d_xyt, int32_t n, uint8_t* set,
-                      const SetLayout& sl, uint8_t* sort, const SortLayout& so, hipStream_t s);
+                      const SetLayout& sl, uint8_t* sort, const SortLayout& so, hipStream_t s,
+                      const double* d_hst = nullptr);
 // Work list, gather, split reduction, mass and statistics over `count`
 // instances.  The descriptors' tile_part and tile_base fields are filled in
 // here; every other field is the caller's.
 // ev_before / ev_after (may be null) are recorded on s right before and
 // right after the gather kernel.
-// full: use the gather's full-cover path (tile_t <= 32).
+// full: use the gather's full-cover path (tile_t <= 32); adapt: the
+// instances' sets carry per-point bandwidths (never with full).
 hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassLayout& pl,
-                       int tile_t, int mode, bool full, hipStream_t s,
+                       int tile_t, int mode, bool full, bool adapt, hipStream_t s,
                        hipEvent_t ev_before = nullptr, hipEvent_t ev_after = nullptr);
 // The gather proper (called by launch_pass).
 hipError_t launch_gather_items(const InstDev* d_desc, int32_t count, const WorkItem* d_items,
                                const uint32_t* d_bits, const uint32_t* d_scalars,
                                uint32_t* d_counters, float* d_partials, float* d_kscratch, int64_t T,
-                               int tile_t, int mode, bool full, hipStream_t s);
+                               int tile_t, int mode, bool full, bool adapt, hipStream_t s);
 // Query (and cache) the gather's launch size for the current device ahead of a
 // stream capture.
-void prepare_gather(int tile_t, int mode, bool full);
+void prepare_gather(int tile_t, int mode, bool full, bool adapt);
 hipError_t launch_reduce_split(const InstDev* d_desc, int32_t count, const uint32_t* d_top,
                                const uint32_t* d_scalars, const float* d_partials, int tile_t,
                                bool kahan, hipStream_t s);
-// d_stats[1], [2] from per-point FP64 sums of one instance (part: nblk x 4 doubles)
+// d_stats[1], [2] from per-point FP64 sums of one instance (part: nblk x 4
+// doubles); d_hst as for launch_bin (null: the instance's bandwidths).
 hipError_t launch_point_stats(const InstGeom& g, int64_t n_norm, const double* d_xyt, int32_t n,
-                              double* d_stats, double* part, int32_t nblk, hipStream_t s);
+                              double* d_stats, double* part, int32_t nblk, hipStream_t s,
+                              const double* d_hst = nullptr);
 
 // Baselines over a binned set on its own base grid (no window): a zero fill
 // then a point-parallel atomic scatter, or a voxel-parallel gather over bins.

@@ -199,6 +199,8 @@ def test_set_plan_validation(L):
     (dict(gx=48, gy=40, gt=48, hs=6.0, ht=4.0, sres=2.0), (0, 0, 0), -1),
     # point statistics are computed only by stkde_compute
     (dict(gx=96, gy=80, gt=48, hs=6.0, ht=4.0, flags=8), (0, 0, 0), -5),
+    # per-point bandwidths need their own binning
+    (dict(gx=96, gy=80, gt=48, hs=6.0, ht=4.0, flags=16), (0, 0, 0), -5),
 ])
 def test_batch_plan_validation(L, plan_kw, off, expect):
     s = _set(L)
@@ -243,3 +245,36 @@ def test_profile_api_host_checks(L):
     assert L.lib().stkde_plan_profile_read(plan.handle, None, 0, ctypes.byref(cnt)) == 0
     assert cnt.value == 0
     plan.close()
+
+
+def test_adaptive_entry_points_host_checks(L):
+    """Adaptive plans take the adaptive entry points only, and vice versa;
+    their workspace holds the per-point terms."""
+    lib = L.lib()
+    fixed = L.Plan(L.Desc(gx=32, gy=32, gt=32, hs=3.0, ht=3.0))
+    ad = L.Plan(L.Desc(gx=32, gy=32, gt=32, hs=3.0, ht=3.0, flags=L.FLAG_ADAPTIVE))
+    n = 1000
+    assert ad.workspace_bytes(n) >= fixed.workspace_bytes(n) + 16 * n
+    need = ad.workspace_bytes(n)
+    fake = ctypes.c_void_p(0x10000)
+    h, hf = ad.handle, fixed.handle
+    assert lib.stkde_compute(h, fake, n, fake, fake, need, None, None) == -1
+    assert lib.stkde_bin(h, fake, n, fake, need, None) == -1
+    assert lib.stkde_compute_adaptive(hf, fake, fake, n, fake, fake, need, None, None) == -1
+    assert lib.stkde_bin_adaptive(hf, fake, fake, n, fake, need, None) == -1
+    assert lib.stkde_compute_adaptive(h, fake, None, n, fake, fake, need, None, None) == -1
+    assert lib.stkde_compute_adaptive(h, None, fake, n, fake, fake, need, None, None) == -1
+    assert lib.stkde_compute_adaptive(h, fake, fake, n, None, fake, need, None, None) == -1
+    assert lib.stkde_compute_adaptive(h, fake, fake, 0, fake, fake, need, None, None) == -1
+    assert lib.stkde_compute_adaptive(h, fake, fake, 1 << 31, fake, fake, need, None, None) == -2
+    assert lib.stkde_compute_adaptive(h, fake, fake, n, fake, fake, need - 1, None, None) == -3
+    assert lib.stkde_bin_adaptive(h, fake, None, n, fake, need, None) == -1
+    assert lib.stkde_bin_adaptive(h, fake, fake, n, fake, need - 1, None) == -3
+    assert lib.stkde_ablation_compute(h, L.ABLATION_VOXEL, fake, n, fake, fake, need, None) == -5
+    assert lib.stkde_ablation_accumulate(h, L.ABLATION_SCATTER, n, fake, fake, need, None) == -5
+    # a set's base carries no flags
+    hs = ctypes.c_void_p()
+    d = L.Desc(gx=16, gy=16, gt=16, hs=2.0, ht=2.0, flags=L.FLAG_ADAPTIVE)
+    assert lib.stkde_set_plan(ctypes.byref(d._c()), None, 10, ctypes.byref(hs)) == -1
+    fixed.close()
+    ad.close()

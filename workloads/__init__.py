@@ -182,3 +182,26 @@ def small_random_case(seed: int, max_g: int = 40, max_n: int = 300):
     hi = np.array([x0 + gx * sres + 1.5 * hs, y0 + gy * sres + 1.5 * hs, t0 + gt * tres + 1.5 * ht])
     pts = lo + rng.uniform(0, 1, (n, 3)) * (hi - lo)
     return pts, dict(gx=gx, gy=gy, gt=gt, hs=hs, ht=ht, sres=sres, tres=tres, x0=x0, y0=y0, t0=t0)
+
+
+def adaptive_pairs(points: np.ndarray, gx: int, gy: int, hs: float, ht: float, sres: float = 1.0,
+                   x0: float = 0.0, y0: float = 0.0, block: int = 16, floor: float = 0.25) -> np.ndarray:
+    """Per-event bandwidth pairs that shrink where the events are dense (the
+    adaptive bandwidth of Sec. 8, read as one pair per event): a pilot count
+    c_i of the events in the event's block x block spatial cell (all times),
+    lambda_i = sqrt(g / c_i) with g the geometric mean of the pilot counts,
+    hs_i = hs * clip(lambda_i, floor, 1) and ht_i = ht * clip(sqrt(lambda_i),
+    sqrt(floor), 1).  The largest pairs are (hs, ht).  Returns (n, 2) float64."""
+    p = np.asarray(points, dtype=np.float64)
+    nbx = max(1, -(-gx // block))
+    nby = max(1, -(-gy // block))
+    cx = np.clip(np.floor((p[:, 0] - x0) / (sres * block)), 0, nbx - 1).astype(np.int64)
+    cy = np.clip(np.floor((p[:, 1] - y0) / (sres * block)), 0, nby - 1).astype(np.int64)
+    counts = np.bincount(cx * nby + cy, minlength=nbx * nby).astype(np.float64)
+    c = counts[cx * nby + cy]
+    g = float(np.exp(np.mean(np.log(c))))
+    lam = np.sqrt(g / c)
+    out = np.empty((len(p), 2))
+    out[:, 0] = hs * np.clip(lam, floor, 1.0)
+    out[:, 1] = ht * np.clip(np.sqrt(lam), np.sqrt(floor), 1.0)
+    return out
