@@ -46,11 +46,22 @@ def clustered(rng: np.random.Generator, k: int, n: int, gx: int, gy: int, gt: in
     * any coordinate that falls outside the grid is drawn again, so every
       point is inside the grid (footprints near the border are still clipped).
     """
+    mix = _mixture(rng, k, gx, gy, sigma_range)
+    return _mixture_events(rng, mix, n, gx, gy, gt, seasons, background)
+
+
+def _mixture(rng, k, gx, gy, sigma_range):
     mu = np.stack([rng.uniform(0.1 * gx, 0.9 * gx, k), rng.uniform(0.1 * gy, 0.9 * gy, k)], axis=1)
     sig = np.exp(rng.uniform(np.log(sigma_range[0]), np.log(sigma_range[1]), k))
     w = np.exp(rng.uniform(0.0, np.log(100.0), k))
     w /= w.sum()
-    comp = rng.choice(k, size=n, p=w)
+    return mu, sig, w
+
+
+def _mixture_events(rng, mix, n, gx, gy, gt, seasons, background, season_sigma=None):
+    mu, sig, w = mix
+    ssig = gt / 48.0 if season_sigma is None else season_sigma
+    comp = rng.choice(len(w), size=n, p=w)
     xy = np.empty((n, 2))
     todo = np.arange(n)
     while todo.size:
@@ -65,7 +76,7 @@ def clustered(rng: np.random.Generator, k: int, n: int, gx: int, gy: int, gt: in
         m = todo.size
         bg = rng.uniform(0.0, 1.0, m) < background
         j = rng.integers(0, seasons, m)
-        bump = (j + 0.5) * gt / seasons + rng.standard_normal(m) * (gt / 48.0)
+        bump = (j + 0.5) * gt / seasons + rng.standard_normal(m) * ssig
         cand = np.where(bg, rng.uniform(0.0, gt, m), bump)
         ok = (cand >= 0) & (cand < gt)
         t[todo[ok]] = cand[ok]
@@ -164,6 +175,49 @@ def config4_requests(count: int, seed_salt: int = 0):
         reqs.append(dict(set=s, gx=gx, gy=gy, gt=gt, x0=x0, y0=y0, t0=t0,
                          hs=float(rng.uniform(3, 40)), ht=float(rng.uniform(3, 40))))
     return reqs
+
+
+WORLD_EVENTS = 291_990_435
+
+
+def _world_chunk(args):
+    index, mix, m, gx, gy, gt = args
+    return _mixture_events(rng_for(5, salt=1 + index), mix, m, gx, gy, gt, 40, 0.2, season_sigma=10.0)
+
+
+def world_scale(resolution: str = "Hr", bandwidth: str = "Hb", n: int = WORLD_EVENTS,
+                chunk: int = 1 << 23, workers: int = 0) -> Instance:
+    """Stand-in for the paper's largest instances, the worldwide bird-spotting
+    set of Sec. 6.1 (291,990,435 events over 20 years at 3-day resolution;
+    Table tab:instance): grid 1781 x 3601 x 2435 at high resolution (60 GB of
+    FP32) or 357 x 721 x 2435 at low; bandwidths (Hs, Ht) = (10, 3) / (30, 5)
+    voxels at high resolution and (2, 3) / (6, 5) at low, as in that table.
+
+    Events: a 256-component Gaussian mixture in space (sigma log-uniform 3-150
+    voxels at high resolution, a fifth of that at low), 40 seasonal bumps in
+    time (two migrations a year, sigma 10 voxels = 30 days) with 20 % uniform
+    background.  Chunk c of ``chunk`` events comes from its own seeded stream,
+    so the events do not depend on how many worker processes draw them
+    (``workers`` > 1: a pool of freshly started processes that only run numpy)."""
+    hi = resolution == "Hr"
+    gx, gy, gt = (1781, 3601, 2435) if hi else (357, 721, 2435)
+    hs, ht = {("Hr", "Lb"): (10.0, 3.0), ("Hr", "Hb"): (30.0, 5.0),
+              ("Lr", "Lb"): (2.0, 3.0), ("Lr", "Hb"): (6.0, 5.0)}[(resolution, bandwidth)]
+    scale = 1.0 if hi else 0.2
+    mix = _mixture(rng_for(5), 256, gx, gy, (3.0 * scale, 150.0 * scale))
+    out = np.empty((n, 3), dtype=np.float64)
+    jobs = [(c, mix, min(chunk, n - b), gx, gy, gt) for c, b in enumerate(range(0, n, chunk))]
+    if workers > 1 and len(jobs) > 1:
+        import multiprocessing as mp
+        from concurrent.futures import ProcessPoolExecutor
+        with ProcessPoolExecutor(max_workers=min(workers, len(jobs)),
+                                 mp_context=mp.get_context("spawn")) as ex:
+            for (c, _, m, *_r), part in zip(jobs, ex.map(_world_chunk, jobs)):
+                out[c * chunk:c * chunk + m] = part
+    else:
+        for (c, _, m, *_r) in jobs:
+            out[c * chunk:c * chunk + m] = _world_chunk(jobs[c])
+    return Instance(f"world-{n}-{gx}x{gy}x{gt}-hs{hs:g}-ht{ht:g}", out, gx, gy, gt, hs, ht)
 
 
 def small_random_case(seed: int, max_g: int = 40, max_n: int = 300):
