@@ -512,8 +512,7 @@ def main():
         tuning, tuning_src = m.Tuning(args.tile_t, args.cell_xy, args.cell_t), "manual"
     elif args.tuning == "auto":
         from paper_1705_09366_amd import autotune
-        tuning = autotune.lookup(desc, n)
-        tuning_src = f"autotune {autotune.key(desc, n)}" if tuning else "default (no cache entry)"
+        tuning, tuning_src = autotune.resolve(desc, n)
     else:
         tuning, tuning_src = None, "default"
     plan = m.Plan(desc, tuning)

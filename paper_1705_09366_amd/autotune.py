@@ -89,6 +89,41 @@ def lookup(desc: Desc, n: int, cache: Optional[str] = None) -> Optional[Tuning]:
     return None
 
 
+def _parse_key(k: str):
+    """(hs bucket, ht bucket, density class, grid class, mode) of a cache key."""
+    _, hs, ht, d, g, mode = k.split("/")
+    return int(hs[2:]), int(ht[2:]), int(d[1:]), int(g[1:]), mode
+
+
+def resolve(desc: Desc, n: int, cache: Optional[str] = None, max_distance: float = 4.0):
+    """(tuning, source) for (desc, n): the entry of its own key; else the
+    nearest entry of the same accumulation mode, by |d hs bucket| +
+    |d ht bucket| + |d density class| + |d grid class| / 2 (ties: the first
+    key in sorted order), if within ``max_distance``; else (None, reason).
+    Deterministic, so results stay bitwise repeatable."""
+    t = lookup(desc, n, cache)
+    k = key(desc, n)
+    if t is not None:
+        return t, f"autotune {k}"
+    hs, ht, d, g, mode = _parse_key(k)
+    best, best_key = None, None
+    for path in (cache, os.environ.get("STKDE_TUNE_CACHE"), SHIPPED_CACHE):
+        entries = _load(path)
+        for ek in sorted(entries):
+            ehs, eht, ed, eg, emode = _parse_key(ek)
+            if emode != mode:
+                continue
+            dist = abs(ehs - hs) + abs(eht - ht) + abs(ed - d) + 0.5 * abs(eg - g)
+            if dist <= max_distance and (best is None or dist < best):
+                best, best_key = dist, ek
+        if best_key is not None:
+            tt, cxy, ct, ss = entries[best_key]["tuning"]
+            if (desc.flags & FLAG_KAHAN) and tt > 32:
+                tt = 32
+            return Tuning(tt, cxy, ct, ss), f"autotune nearest {best_key} (for {k})"
+    return None, f"default (no cache entry near {k})"
+
+
 def plan_for(desc: Desc, n: int, cache: Optional[str] = None) -> Plan:
     """A plan with the cached tuning for (desc, n), else the library's defaults."""
     return Plan(desc, lookup(desc, n, cache))

@@ -49,3 +49,32 @@ def test_shipped_cache_is_well_formed():
         assert ss == 0 or 64 <= ss <= 65536
         if k.endswith("/kahan"):
             assert tt <= 32
+
+
+def test_resolve_prefers_own_key_then_nearest(tmp_path):
+    import json
+    from paper_1705_09366_amd import Desc, FLAG_KAHAN, autotune
+    d = Desc(gx=1024, gy=1024, gt=256, hs=10.0, ht=7.0, flags=FLAG_KAHAN)
+    k = autotune.key(d, 1_000_000)
+    far = Desc(gx=1781, gy=3601, gt=2435, hs=30.0, ht=5.0, flags=FLAG_KAHAN)
+    kf = autotune.key(far, 291_990_435)
+    near_key = "gfx950/hs5/ht3/d5/g16/kahan"  # distance 0.5 from kf
+    other = "gfx950/hs5/ht3/d5/g17/plain"     # same place, other mode: never used
+    cache = {"version": autotune.CACHE_VERSION, "arch": "gfx950", "entries": {
+        k: {"tuning": [32, 24, 8, 0]},
+        near_key: {"tuning": [16, 16, 8, 512]},
+        other: {"tuning": [64, 16, 8, 0]}}}
+    path = tmp_path / "c.json"
+    path.write_text(json.dumps(cache))
+    t, src = autotune.resolve(d, 1_000_000, str(path))
+    assert (t.tile_t, t.cell_xy, t.cell_t) == (32, 24, 8) and src == f"autotune {k}"
+    t, src = autotune.resolve(far, 291_990_435, str(path))
+    assert (t.tile_t, t.cell_xy, t.cell_t, t.split_share) == (16, 16, 8, 512) and near_key in src
+    # the same answer every time
+    assert autotune.resolve(far, 291_990_435, str(path))[1] == src
+    # nothing within reach: the library default
+    tiny = Desc(gx=8, gy=8, gt=8, hs=1.0, ht=1.0, flags=FLAG_KAHAN)
+    empty = tmp_path / "e.json"
+    empty.write_text(json.dumps({**cache, "entries": {near_key: {"tuning": [16, 16, 8, 0]}}}))
+    t, src = autotune.resolve(tiny, 10, str(empty), max_distance=0.0)
+    assert t is None and src.startswith("default")
