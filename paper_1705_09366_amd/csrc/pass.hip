@@ -119,16 +119,80 @@ __device__ inline uint32_t block_scan(uint32_t v, uint32_t* ws, uint32_t* total)
     return pre + inc - v;
 }
 
+// Threshold class of the heaviest-first queue: the smallest class c >=
+// class(1) whose suffix count (tiles of class >= c) is at most kTopTiles.
+// Every workgroup of k_collect_heavy derives it from the histogram alone.
+__device__ inline uint32_t heavy_class(const uint32_t* __restrict__ hist, uint32_t* ws,
+                                       uint32_t* s_cls) {
+    const int tid = threadIdx.x;
+    constexpr int kPer = kCostClasses / 256;  // classes per thread, highest first
+    static_assert(kPer * 256 == kCostClasses, "whole classes per thread");
+    if (tid == 0) *s_cls = kCostClasses;
+    uint32_t h[kPer], sum = 0;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        h[u] = hist[kCostClasses - 1 - (kPer * tid + u)];
+        sum += h[u];
+    }
+    // exclusive scan over the 256 threads (classes above this thread's)
+    const int lane = tid & 63, w = tid >> 6;
+    uint32_t inc = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += v;
+    }
+    if (lane == 63) ws[w] = inc;
+    __syncthreads();
+    uint32_t above = inc - sum;
+    for (int k = 0; k < w; ++k) above += ws[k];
+    const uint32_t cmin = cost_class(1u);
+    uint32_t best = kCostClasses;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const uint32_t c = kCostClasses - 1 - (kPer * tid + u);
+        above += h[u];
+        if (c >= cmin && above <= (uint32_t)kTopTiles) best = c;
+    }
+    if (best < kCostClasses) atomicMin(s_cls, best);
+    __syncthreads();
+    return *s_cls;
+}
+
+// Collect the heavy tiles (those of the threshold class and above) into
+// heavy[] in any order; k_plan_items sorts them.
+__global__ __launch_bounds__(256) void k_collect_heavy(uint32_t T, const uint32_t* __restrict__ cost,
+                                                       const uint32_t* __restrict__ hist,
+                                                       unsigned long long* __restrict__ heavy,
+                                                       uint32_t* __restrict__ sc) {
+    __shared__ uint32_t ws[4];
+    __shared__ uint32_t s_cls;
+    const uint32_t cls = heavy_class(hist, ws, &s_cls);
+    constexpr int kU = 8;  // loads in flight per thread
+    const uint32_t j0 = blockIdx.x * (256u * kU) + threadIdx.x;
+    uint32_t cv[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const uint32_t j = j0 + 256u * u;
+        cv[u] = j < T ? cost[j] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        if (cv[u] != 0u && cost_class(cv[u]) >= cls) {
+            const uint32_t pos = atomicAdd(&sc[kScHeavyFound], 1u);  // < kTopTiles by the choice of cls
+            heavy[pos] = ((unsigned long long)(~cv[u]) << 32) | (j0 + 256u * u);
+        }
+    }
+}
+
 // The heaviest-first queue (one workgroup of 1024 threads):
-//  1. the heaviest cost classes holding at most kTopTiles tiles are taken,
-//     sorted by cost, descending (ties by tile), and flagged in the
-//     spatial queue's bitmask;
+//  1. the heavy tiles (k_collect_heavy) are sorted by cost, descending
+//     (ties by tile), and flagged in the spatial queue's bitmask;
 //  2. a taken tile whose cost exceeds max(kSplitFloor, its instance's total
 //     cost / its split share) is cut into up to kMaxParts equal candidate
 //     ranges, while partial slots last (costliest first).
 __global__ __launch_bounds__(1024) void k_plan_items(const InstDev* __restrict__ descs, int32_t count,
-                                                     uint32_t T, const uint32_t* __restrict__ cost,
-                                                     const uint32_t* __restrict__ hist,
+                                                     const unsigned long long* __restrict__ heavy,
                                                      const unsigned long long* __restrict__ inst_cost,
                                                      WorkItem* __restrict__ items,
                                                      uint32_t* __restrict__ top,
@@ -137,40 +201,12 @@ __global__ __launch_bounds__(1024) void k_plan_items(const InstDev* __restrict__
                                                      uint32_t* __restrict__ ctr, uint32_t nslots) {
     __shared__ unsigned long long keys[kTopTiles];
     __shared__ uint32_t ws[16];
-    __shared__ uint32_t s_cls, s_nh;
     const int tid = threadIdx.x;
-    static_assert(kCostClasses == 2 * 1024, "two cost classes per thread");
-
-    // ---- 1. threshold class: smallest class c >= class(1) whose suffix count
-    // (tiles of class >= c) is at most kTopTiles
-    if (tid == 0) {
-        s_cls = kCostClasses;
-        s_nh = 0;
-    }
-    const uint32_t chi = kCostClasses - 1 - 2 * tid, clo = chi - 1;
-    const uint32_t hhi = hist[chi], hlo = hist[clo];
-    uint32_t tot;
-    const uint32_t above = block_scan(hhi + hlo, ws, &tot);  // tiles of classes > chi
-    const uint32_t cmin = cost_class(1u);
-    if (chi >= cmin && above + hhi <= (uint32_t)kTopTiles) atomicMin(&s_cls, chi);
-    if (clo >= cmin && above + hhi + hlo <= (uint32_t)kTopTiles) atomicMin(&s_cls, clo);
-    __syncthreads();
-    const uint32_t cls = s_cls;
-
-    // collect the heavy tiles (in any order: they are sorted next)
-    for (uint32_t j = (uint32_t)tid; j < T; j += 1024u) {
-        const uint32_t c = cost[j];
-        if (c != 0u && cost_class(c) >= cls) {
-            const uint32_t pos = atomicAdd(&s_nh, 1u);
-            keys[pos] = ((unsigned long long)(~c) << 32) | j;
-        }
-    }
-    __syncthreads();
-    const uint32_t nh = s_nh;  // <= kTopTiles by the choice of cls
+    const uint32_t nh = sc[kScHeavyFound];  // <= kTopTiles
     // bitonic sort of the heavy keys, ascending: cost descending, then tile.
     // One key per thread; exchanges with partners in the same wave go through
     // lane shuffles, the others through LDS.
-    unsigned long long key = (uint32_t)tid < nh ? keys[tid] : ~0ull;
+    unsigned long long key = (uint32_t)tid < nh ? heavy[tid] : ~0ull;
     if (nh > 1) {
         for (int k = 2; k <= kTopTiles; k <<= 1) {
             for (int jj = k >> 1; jj > 0; jj >>= 1) {
@@ -315,6 +351,7 @@ PassLayout layout_pass(const InstGeom* inst, int32_t count, int tile_t, bool kah
     l.bits = o; o = al256(o + ((size_t)T + 31) / 32 * 4);
     l.scalars = o; o = al256(o + (size_t)kScCount * 4);
     l.counters = o; o = al256(o + (size_t)kCtrWords * 4);
+    l.heavy = o; o = al256(o + (size_t)kTopTiles * 8);
     l.top = o; o = al256(o + (size_t)kTopTiles * 16);
     l.items = o; o = al256(o + (size_t)kTopTiles * kMaxParts * sizeof(WorkItem));
     l.partials = o; o = al256(o + (size_t)kPartSlots * kTileXY * kTileXY * tile_t * 4);
@@ -361,10 +398,12 @@ hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassL
     const uint32_t T = (uint32_t)pl.T;
     hipLaunchKernelGGL(k_tile_cost, dim3((T + 255) / 256), dim3(256), 0, s, (const InstDev*)d_desc,
                        count, T, tile_t, cost, hist, inst_cost, bits);
-    hipLaunchKernelGGL(k_plan_items, dim3(1), dim3(1024), 0, s, (const InstDev*)d_desc, count, T,
-                       (const uint32_t*)cost, (const uint32_t*)hist,
-                       (const unsigned long long*)inst_cost, items, top, bits, sc, ctr,
-                       (uint32_t)kPartSlots);
+    auto* heavy = reinterpret_cast<unsigned long long*>(pass + pl.heavy);
+    hipLaunchKernelGGL(k_collect_heavy, dim3((T + 2047) / 2048), dim3(256), 0, s, T, (const uint32_t*)cost,
+                       (const uint32_t*)hist, heavy, sc);
+    hipLaunchKernelGGL(k_plan_items, dim3(1), dim3(1024), 0, s, (const InstDev*)d_desc, count,
+                       (const unsigned long long*)heavy, (const unsigned long long*)inst_cost, items, top,
+                       bits, sc, ctr, (uint32_t)kPartSlots);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev_before && (e = hipEventRecord(ev_before, s)) != hipSuccess) return e;

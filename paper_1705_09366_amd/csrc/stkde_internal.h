@@ -147,6 +147,7 @@ constexpr int kCtrStride = 64;  // u32
 constexpr int kScHeavyItems = 0;  // items in the heaviest-first queue
 constexpr int kScSplit = 1;       // split tiles
 constexpr int kScHeavyTiles = 2;  // tiles in the heaviest-first queue
+constexpr int kScHeavyFound = 3;  // heavy tiles collected (before sorting)
 constexpr int kScCount = 8;
 // Counters (u32 offsets into PassLayout::counters): queue q, lane k at
 // (q * kFetchLanes + k) * kCtrStride.
@@ -179,6 +180,7 @@ struct PassLayout {
     size_t bits;         // ceil(T / 32) u32: spatial-queue positions taken by the heavy queue
     size_t scalars;      // kScCount u32
     size_t counters;     // kCtrWords u32: the queues' fetch counters
+    size_t heavy;        // kTopTiles u64 keys of the heavy tiles, in collection order
     size_t top;          // kTopTiles x 4 u32 split tiles: tile, parts, slot0, candidates
     size_t items;        // kTopTiles * kMaxParts WorkItem (the heaviest-first queue)
     size_t partials;     // kPartSlots x 16 x 16 x tile_t FP32
