@@ -606,9 +606,17 @@ __global__ __launch_bounds__(kThreads) void k_reduce_split(const InstDev* __rest
 #pragma unroll
         for (int r = 0; r < TT; r += 4) {
             f32x4 s = f32x4{0.f, 0.f, 0.f, 0.f}, c = f32x4{0.f, 0.f, 0.f, 0.f};
-            for (uint32_t p = 0; p < parts; ++p) {
-                const f32x4 v = *reinterpret_cast<const f32x4*>(
-                    partials + ((size_t)(slot0 + p) * (kTileXY * kTileXY) + tid) * TT + r);
+            // every part's values in flight at once, then added in part order
+            f32x4 pv[kMaxParts];
+#pragma unroll
+            for (int p = 0; p < kMaxParts; ++p)
+                pv[p] = (uint32_t)p < parts ? *reinterpret_cast<const f32x4*>(
+                                                  partials + ((size_t)(slot0 + p) * (kTileXY * kTileXY) + tid) * TT + r)
+                                            : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int p = 0; p < kMaxParts; ++p) {
+                if ((uint32_t)p >= parts) break;
+                const f32x4 v = pv[p];
                 if constexpr (KAHAN) {
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
@@ -623,11 +631,17 @@ __global__ __launch_bounds__(kThreads) void k_reduce_split(const InstDev* __rest
             }
             const f32x4 o = s * D.cnorm;
             if (col_ok) {
+                if ((gtI & 3) == 0 && T0 + r + 3 < gtI) {
+                    *reinterpret_cast<f32x4*>(col + T0 + r) = o;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    if (T0 + r + e < gtI) {
-                        col[T0 + r + e] = o[e];
-                        msum += (double)o[e];
+                    for (int e = 0; e < 4; ++e) msum += (double)o[e];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        if (T0 + r + e < gtI) {
+                            col[T0 + r + e] = o[e];
+                            msum += (double)o[e];
+                        }
                     }
                 }
             }
