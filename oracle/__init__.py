@@ -35,13 +35,19 @@ class _Grid(ctypes.Structure):
     _fields_ = [("gx", ctypes.c_int64), ("gy", ctypes.c_int64), ("gt", ctypes.c_int64),
                 ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("t0", ctypes.c_double),
                 ("sres", ctypes.c_double), ("tres", ctypes.c_double),
-                ("hs", ctypes.c_double), ("ht", ctypes.c_double)]
+                ("hs", ctypes.c_double), ("ht", ctypes.c_double),
+                ("kernel", ctypes.c_int32), ("corner", ctypes.c_int32)]
+
+
+KERNEL_EPANECHNIKOV, KERNEL_QUARTIC, KERNEL_GAUSSIAN, KERNEL_PRINTED = 0, 1, 2, 3
 
 
 @dataclass(frozen=True)
 class Grid:
     """Discretised domain (Sec. 2.1): gx x gy x gt voxels of sres x sres x tres
-    with voxel (0,0,0) cornered at (x0, y0, t0), and bandwidths hs, ht."""
+    with voxel (0,0,0) cornered at (x0, y0, t0), bandwidths hs, ht, the kernel
+    pair (KERNEL_*, see stkde_oracle.h) and where voxels are sampled (centre,
+    or lower corner with ``corner``)."""
     gx: int
     gy: int
     gt: int
@@ -52,10 +58,12 @@ class Grid:
     x0: float = 0.0
     y0: float = 0.0
     t0: float = 0.0
+    kernel: int = KERNEL_EPANECHNIKOV
+    corner: bool = False
 
     def _c(self):
         return _Grid(self.gx, self.gy, self.gt, self.x0, self.y0, self.t0,
-                     self.sres, self.tres, self.hs, self.ht)
+                     self.sres, self.tres, self.hs, self.ht, int(self.kernel), int(bool(self.corner)))
 
 
 def _lib():
@@ -158,6 +166,30 @@ def exact_evals(xyt, grid: Grid, nthreads=None):
     return int(np.sum(cs * ct))
 
 
+def _np_ks(kernel, u, v):
+    """Spatial factor of each pair on u^2 + v^2 < 1 (numpy; see stkde_oracle.h)."""
+    r2 = u * u + v * v
+    if kernel == KERNEL_QUARTIC:
+        return 3.0 / np.pi * (1.0 - r2) ** 2
+    if kernel == KERNEL_GAUSSIAN:
+        return np.exp(-2.0 * r2) / (np.pi / 2.0 * (1.0 - np.exp(-2.0)))
+    if kernel == KERNEL_PRINTED:
+        return np.pi / 2.0 * (1.0 - u) ** 2 * (1.0 - v) ** 2
+    return (2.0 / np.pi) * (1.0 - r2)
+
+
+def _np_kt(kernel, w):
+    """Temporal factor of each pair on |w| <= 1 (numpy)."""
+    import math
+    if kernel == KERNEL_QUARTIC:
+        return 15.0 / 16.0 * (1.0 - w * w) ** 2
+    if kernel == KERNEL_GAUSSIAN:
+        return np.exp(-2.0 * w * w) / (math.sqrt(math.pi / 2.0) * math.erf(math.sqrt(2.0)))
+    if kernel == KERNEL_PRINTED:
+        return 0.75 * (1.0 - w) ** 2
+    return 0.75 * (1.0 - w * w)
+
+
 def vb_grid_numpy(xyt, grid: Grid):
     """Alg. VB over the whole grid, vectorised over points with numpy.  For
     tiny grids only (it holds a points x voxels-row temporary)."""
@@ -165,10 +197,11 @@ def vb_grid_numpy(xyt, grid: Grid):
     fin = np.all(np.isfinite(pts), axis=1)
     n = pts.shape[0]
     p = pts[fin]
+    off = 0.0 if grid.corner else 0.5
     out = np.zeros((grid.gx, grid.gy, grid.gt), dtype=np.float64)
-    xs = grid.x0 + (np.arange(grid.gx) + 0.5) * grid.sres
-    ys = grid.y0 + (np.arange(grid.gy) + 0.5) * grid.sres
-    ts = grid.t0 + (np.arange(grid.gt) + 0.5) * grid.tres
+    xs = grid.x0 + (np.arange(grid.gx) + off) * grid.sres
+    ys = grid.y0 + (np.arange(grid.gy) + off) * grid.sres
+    ts = grid.t0 + (np.arange(grid.gt) + off) * grid.tres
     for X, x in enumerate(xs):
         for Y, y in enumerate(ys):
             d = np.sqrt((p[:, 0] - x) ** 2 + (p[:, 1] - y) ** 2)
@@ -178,10 +211,10 @@ def vb_grid_numpy(xyt, grid: Grid):
             q = p[ins]
             u = (x - q[:, 0]) / grid.hs
             v = (y - q[:, 1]) / grid.hs
-            ksv = (2.0 / np.pi) * (1.0 - u * u - v * v)
+            ksv = _np_ks(grid.kernel, u, v)
             dt = ts[None, :] - q[:, 2][:, None]
             w = dt / grid.ht
-            ktv = np.where(np.abs(dt) <= grid.ht, 0.75 * (1.0 - w * w), 0.0)
+            ktv = np.where(np.abs(dt) <= grid.ht, _np_kt(grid.kernel, np.clip(w, -1.0, 1.0)), 0.0)
             out[X, Y, :] = np.sum(ksv[:, None] * ktv, axis=0)
     return out / (n * grid.hs ** 2 * grid.ht)
 
@@ -266,19 +299,20 @@ def vb_grid_numpy_adaptive(xyt, hst, grid: Grid):
     ok = np.all(np.isfinite(pts), axis=1) & np.all(np.isfinite(h), axis=1) & (h[:, 0] > 0) & (h[:, 1] > 0)
     p, hs, ht = pts[ok], h[ok, 0], h[ok, 1]
     out = np.zeros((grid.gx, grid.gy, grid.gt), dtype=np.float64)
-    ts = grid.t0 + (np.arange(grid.gt) + 0.5) * grid.tres
+    off = 0.0 if grid.corner else 0.5
+    ts = grid.t0 + (np.arange(grid.gt) + off) * grid.tres
     for X in range(grid.gx):
-        x = grid.x0 + (X + 0.5) * grid.sres
+        x = grid.x0 + (X + off) * grid.sres
         for Y in range(grid.gy):
-            y = grid.y0 + (Y + 0.5) * grid.sres
+            y = grid.y0 + (Y + off) * grid.sres
             r2 = (p[:, 0] - x) ** 2 + (p[:, 1] - y) ** 2
             inside = np.sqrt(r2) < hs
             if not np.any(inside):
                 continue
-            ksv = (2.0 / np.pi) * (1.0 - r2[inside] / hs[inside] ** 2)
+            ksv = _np_ks(grid.kernel, (x - p[inside, 0]) / hs[inside], (y - p[inside, 1]) / hs[inside])
             dt = ts[None, :] - p[inside, 2][:, None]
             hti = ht[inside][:, None]
-            ktv = np.where(np.abs(dt) <= hti, 0.75 * (1.0 - (dt / hti) ** 2), 0.0)
+            ktv = np.where(np.abs(dt) <= hti, _np_kt(grid.kernel, np.clip(dt / hti, -1.0, 1.0)), 0.0)
             wgt = 1.0 / (hs[inside] ** 2 * ht[inside])
             out[X, Y, :] = np.sum((ksv * wgt)[:, None] * ktv, axis=0)
     return out / n

@@ -18,6 +18,9 @@
  *   ks(u,v) = (2/pi) (1 - u^2 - v^2)   where sqrt(u^2+v^2) < 1, else 0
  *   kt(w)   = (3/4)  (1 - w^2)         where |w| <= 1,          else 0
  *
+ * Other separable kernel pairs (quartic, truncated Gaussian, the pair as
+ * printed) are selected by oracle_grid.kernel; stkde_oracle.h defines them.
+ *
  * The strict "<" in space and "<=" in time follow the tests written in the
  * VB and PB-SYM algorithms (Sec. 2.2 and Sec. 3.2).  Both kernels vanish on
  * their support boundary, so the choice only changes which pairs are counted
@@ -26,7 +29,8 @@
  * Voxels (Sec. 2.1, discretisation; Table "Notations"): the grid has
  * Gx x Gy x Gt voxels of size sres x sres x tres whose corner (0,0,0) sits at
  * the domain origin (x0,y0,t0).  A voxel is sampled at its centre,
- * x = x0 + (X + 1/2) sres, and likewise in y and t.  The output grid is
+ * x = x0 + (X + 1/2) sres, and likewise in y and t (or, with
+ * oracle_grid.corner, at its lower corner x0 + X sres).  The output grid is
  * indexed stkde[X][Y][T], T fastest.  Hs = ceil(hs/sres) and Ht = ceil(ht/tres)
  * are the bandwidths in voxels; they only bound loops.
  *
@@ -66,6 +70,57 @@ static double kt_epan(double w) {
     return 0.75 * (1.0 - w * w);
 }
 
+/* The other pairs of stkde_oracle.h, each called only inside its support. */
+static double ks_quartic(double u, double v) {
+    const double e = 1.0 - u * u - v * v;
+    return (3.0 / ORACLE_PI) * e * e;
+}
+
+static double kt_quartic(double w) {
+    const double e = 1.0 - w * w;
+    return (15.0 / 16.0) * e * e;
+}
+
+static double ks_gauss(double u, double v) {
+    return exp(-2.0 * (u * u + v * v)) / (0.5 * ORACLE_PI * (1.0 - exp(-2.0)));
+}
+
+static double kt_gauss(double w) {
+    return exp(-2.0 * w * w) / (sqrt(0.5 * ORACLE_PI) * erf(sqrt(2.0)));
+}
+
+static double ks_printed(double u, double v) {
+    return (ORACLE_PI / 2.0) * (1.0 - u) * (1.0 - u) * (1.0 - v) * (1.0 - v);
+}
+
+static double kt_printed(double w) {
+    return 0.75 * (1.0 - w) * (1.0 - w);
+}
+
+static double ks_of(int32_t kernel, double u, double v) {
+    switch (kernel) {
+    case ORACLE_KERNEL_QUARTIC: return ks_quartic(u, v);
+    case ORACLE_KERNEL_GAUSSIAN: return ks_gauss(u, v);
+    case ORACLE_KERNEL_PRINTED: return ks_printed(u, v);
+    default: return ks_epan(u, v);
+    }
+}
+
+static double kt_of(int32_t kernel, double w) {
+    switch (kernel) {
+    case ORACLE_KERNEL_QUARTIC: return kt_quartic(w);
+    case ORACLE_KERNEL_GAUSSIAN: return kt_gauss(w);
+    case ORACLE_KERNEL_PRINTED: return kt_printed(w);
+    default: return kt_epan(w);
+    }
+}
+
+/* Where a voxel is sampled, in voxels from its lower corner (Sec. 2.1 leaves
+ * it open; the centre is the default reading). */
+static double sample_offset(const oracle_grid* g) {
+    return g->corner ? 0.0 : 0.5;
+}
+
 static int check_desc(const oracle_grid* g, int64_t n) {
     if (!g) return -1;
     if (n < 1) return -1;
@@ -73,6 +128,7 @@ static int check_desc(const oracle_grid* g, int64_t n) {
     if (!(g->sres > 0.0) || !(g->tres > 0.0) || !(g->hs > 0.0) || !(g->ht > 0.0)) return -1;
     if (!isfinite(g->sres) || !isfinite(g->tres) || !isfinite(g->hs) || !isfinite(g->ht)) return -1;
     if (!isfinite(g->x0) || !isfinite(g->y0) || !isfinite(g->t0)) return -1;
+    if (g->kernel < 0 || g->kernel > ORACLE_KERNEL_PRINTED || (g->corner != 0 && g->corner != 1)) return -1;
     return 0;
 }
 
@@ -140,13 +196,13 @@ int oracle_pbsym(const oracle_grid* g, const double* xyt, int64_t n, double* gri
                 /* Spatial invariant Ks[X][Y] over the box, normalisation folded
                  * in (second loop nest of Alg. PB-SYM). */
                 for (int64_t X = Xa; X <= Xb; ++X) {
-                    const double x = g->x0 + ((double)X + 0.5) * g->sres;
+                    const double x = g->x0 + ((double)X + sample_offset(g)) * g->sres;
                     for (int64_t Y = Ya; Y <= Yb; ++Y) {
-                        const double y = g->y0 + ((double)Y + 0.5) * g->sres;
+                        const double y = g->y0 + ((double)Y + sample_offset(g)) * g->sres;
                         const int64_t k = (X - Xa) * ny + (Y - Ya);
                         const double d = sqrt((xi - x) * (xi - x) + (yi - y) * (yi - y));
                         if (d < g->hs) {
-                            Ks[k] = ks_epan((x - xi) / g->hs, (y - yi) / g->hs) * norm;
+                            Ks[k] = ks_of(g->kernel, (x - xi) / g->hs, (y - yi) / g->hs) * norm;
                             ins[k] = 1;
                         } else {
                             Ks[k] = 0.0;
@@ -157,9 +213,9 @@ int oracle_pbsym(const oracle_grid* g, const double* xyt, int64_t n, double* gri
                 /* Temporal invariant Kt[T] over the window (third loop). */
                 int64_t cnt_t = 0;
                 for (int64_t T = Ta; T <= Tb; ++T) {
-                    const double t = g->t0 + ((double)T + 0.5) * g->tres;
+                    const double t = g->t0 + ((double)T + sample_offset(g)) * g->tres;
                     if (fabs(ti - t) <= g->ht) {
-                        Kt[T - Ta] = kt_epan((t - ti) / g->ht);
+                        Kt[T - Ta] = kt_of(g->kernel, (t - ti) / g->ht);
                         int_[T - Ta] = 1;
                         ++cnt_t;
                     } else {
@@ -207,15 +263,15 @@ int oracle_vb_voxels(const oracle_grid* g, const double* xyt, int64_t n, const i
     const double denom = (double)n * g->hs * g->hs * g->ht;
 #pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1)
     for (int64_t j = 0; j < m; ++j) {
-        const double x = g->x0 + ((double)vox[3 * j] + 0.5) * g->sres;
-        const double y = g->y0 + ((double)vox[3 * j + 1] + 0.5) * g->sres;
-        const double t = g->t0 + ((double)vox[3 * j + 2] + 0.5) * g->tres;
+        const double x = g->x0 + ((double)vox[3 * j] + sample_offset(g)) * g->sres;
+        const double y = g->y0 + ((double)vox[3 * j + 1] + sample_offset(g)) * g->sres;
+        const double t = g->t0 + ((double)vox[3 * j + 2] + sample_offset(g)) * g->tres;
         double sum = 0.0;
         for (int64_t i = 0; i < n; ++i) {
             const double xi = xyt[3 * i], yi = xyt[3 * i + 1], ti = xyt[3 * i + 2];
             if (!isfinite(xi) || !isfinite(yi) || !isfinite(ti)) continue;
             if (sqrt((xi - x) * (xi - x) + (yi - y) * (yi - y)) < g->hs && fabs(ti - t) <= g->ht)
-                sum += ks_epan((x - xi) / g->hs, (y - yi) / g->hs) * kt_epan((t - ti) / g->ht);
+                sum += ks_of(g->kernel, (x - xi) / g->hs, (y - yi) / g->hs) * kt_of(g->kernel, (t - ti) / g->ht);
         }
         out[j] = sum / denom;
     }
@@ -247,11 +303,11 @@ int oracle_point_sums(const oracle_grid* g, const double* xyt, int64_t n, double
             const int okt = clip_range(voxel_of(ti, g->t0, g->tres), Ht, 0, g->gt, &Ta, &Tb);
             if (okx && oky) {
                 for (int64_t X = Xa; X <= Xb; ++X) {
-                    const double x = g->x0 + ((double)X + 0.5) * g->sres;
+                    const double x = g->x0 + ((double)X + sample_offset(g)) * g->sres;
                     for (int64_t Y = Ya; Y <= Yb; ++Y) {
-                        const double y = g->y0 + ((double)Y + 0.5) * g->sres;
+                        const double y = g->y0 + ((double)Y + sample_offset(g)) * g->sres;
                         if (sqrt((xi - x) * (xi - x) + (yi - y) * (yi - y)) < g->hs) {
-                            ss += ks_epan((x - xi) / g->hs, (y - yi) / g->hs);
+                            ss += ks_of(g->kernel, (x - xi) / g->hs, (y - yi) / g->hs);
                             ++ns;
                         }
                     }
@@ -259,9 +315,9 @@ int oracle_point_sums(const oracle_grid* g, const double* xyt, int64_t n, double
             }
             if (okt) {
                 for (int64_t T = Ta; T <= Tb; ++T) {
-                    const double t = g->t0 + ((double)T + 0.5) * g->tres;
+                    const double t = g->t0 + ((double)T + sample_offset(g)) * g->tres;
                     if (fabs(ti - t) <= g->ht) {
-                        st += kt_epan((t - ti) / g->ht);
+                        st += kt_of(g->kernel, (t - ti) / g->ht);
                         ++nt;
                     }
                 }
@@ -356,13 +412,13 @@ int oracle_pbsym_adaptive(const oracle_grid* g, const double* xyt, const double*
                 if (!clip_range_d(voxel_of(ti, g->t0, g->tres), Ht, 0, Gt, &Ta, &Tb)) continue;
                 const int64_t ny = Yb - Ya + 1, nt = Tb - Ta + 1;
                 for (int64_t X = Xa; X <= Xb; ++X) {
-                    const double x = g->x0 + ((double)X + 0.5) * g->sres;
+                    const double x = g->x0 + ((double)X + sample_offset(g)) * g->sres;
                     for (int64_t Y = Ya; Y <= Yb; ++Y) {
-                        const double y = g->y0 + ((double)Y + 0.5) * g->sres;
+                        const double y = g->y0 + ((double)Y + sample_offset(g)) * g->sres;
                         const int64_t k = (X - Xa) * ny + (Y - Ya);
                         const double d = sqrt((xi - x) * (xi - x) + (yi - y) * (yi - y));
                         if (d < hs) {
-                            Ks[k] = ks_epan((x - xi) / hs, (y - yi) / hs) * norm;
+                            Ks[k] = ks_of(g->kernel, (x - xi) / hs, (y - yi) / hs) * norm;
                             ins[k] = 1;
                         } else {
                             Ks[k] = 0.0;
@@ -372,9 +428,9 @@ int oracle_pbsym_adaptive(const oracle_grid* g, const double* xyt, const double*
                 }
                 int64_t cnt_t = 0;
                 for (int64_t T = Ta; T <= Tb; ++T) {
-                    const double t = g->t0 + ((double)T + 0.5) * g->tres;
+                    const double t = g->t0 + ((double)T + sample_offset(g)) * g->tres;
                     if (fabs(ti - t) <= ht) {
-                        Kt[T - Ta] = kt_epan((t - ti) / ht);
+                        Kt[T - Ta] = kt_of(g->kernel, (t - ti) / ht);
                         ++cnt_t;
                     } else {
                         Kt[T - Ta] = 0.0;
@@ -414,16 +470,16 @@ int oracle_vb_voxels_adaptive(const oracle_grid* g, const double* xyt, const dou
     if (nthreads < 1) nthreads = 1;
 #pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1)
     for (int64_t j = 0; j < m; ++j) {
-        const double x = g->x0 + ((double)vox[3 * j] + 0.5) * g->sres;
-        const double y = g->y0 + ((double)vox[3 * j + 1] + 0.5) * g->sres;
-        const double t = g->t0 + ((double)vox[3 * j + 2] + 0.5) * g->tres;
+        const double x = g->x0 + ((double)vox[3 * j] + sample_offset(g)) * g->sres;
+        const double y = g->y0 + ((double)vox[3 * j + 1] + sample_offset(g)) * g->sres;
+        const double t = g->t0 + ((double)vox[3 * j + 2] + sample_offset(g)) * g->tres;
         double sum = 0.0;
         for (int64_t i = 0; i < n; ++i) {
             if (!adaptive_event_ok(xyt, hst, i)) continue;
             const double xi = xyt[3 * i], yi = xyt[3 * i + 1], ti = xyt[3 * i + 2];
             const double hs = hst[2 * i], ht = hst[2 * i + 1];
             if (sqrt((xi - x) * (xi - x) + (yi - y) * (yi - y)) < hs && fabs(ti - t) <= ht)
-                sum += ks_epan((x - xi) / hs, (y - yi) / hs) * kt_epan((t - ti) / ht) / (hs * hs * ht);
+                sum += ks_of(g->kernel, (x - xi) / hs, (y - yi) / hs) * kt_of(g->kernel, (t - ti) / ht) / (hs * hs * ht);
         }
         out[j] = sum / (double)n;
     }
@@ -451,11 +507,11 @@ int oracle_point_sums_adaptive(const oracle_grid* g, const double* xyt, const do
             const int okt = clip_range_d(voxel_of(ti, g->t0, g->tres), Ht, 0, g->gt, &Ta, &Tb);
             if (okx && oky) {
                 for (int64_t X = Xa; X <= Xb; ++X) {
-                    const double x = g->x0 + ((double)X + 0.5) * g->sres;
+                    const double x = g->x0 + ((double)X + sample_offset(g)) * g->sres;
                     for (int64_t Y = Ya; Y <= Yb; ++Y) {
-                        const double y = g->y0 + ((double)Y + 0.5) * g->sres;
+                        const double y = g->y0 + ((double)Y + sample_offset(g)) * g->sres;
                         if (sqrt((xi - x) * (xi - x) + (yi - y) * (yi - y)) < hs) {
-                            ss += ks_epan((x - xi) / hs, (y - yi) / hs);
+                            ss += ks_of(g->kernel, (x - xi) / hs, (y - yi) / hs);
                             ++ns;
                         }
                     }
@@ -463,9 +519,9 @@ int oracle_point_sums_adaptive(const oracle_grid* g, const double* xyt, const do
             }
             if (okt) {
                 for (int64_t T = Ta; T <= Tb; ++T) {
-                    const double t = g->t0 + ((double)T + 0.5) * g->tres;
+                    const double t = g->t0 + ((double)T + sample_offset(g)) * g->tres;
                     if (fabs(ti - t) <= ht) {
-                        st += kt_epan((t - ti) / ht);
+                        st += kt_of(g->kernel, (t - ti) / ht);
                         ++nt;
                     }
                 }

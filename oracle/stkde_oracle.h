@@ -23,7 +23,24 @@ typedef struct {
     double x0, y0, t0;     /* domain coordinate of the corner of voxel (0,0,0) */
     double sres, tres;     /* voxel size in space and time */
     double hs, ht;         /* spatial and temporal bandwidths, domain units */
+    int32_t kernel;        /* ORACLE_KERNEL_*: the separable kernel pair */
+    int32_t corner;        /* 0: sample voxels at their centres; 1: at their lower corners */
 } oracle_grid;
+
+/* Kernel pairs.  Sec. 2.1 prints one pair (garbled: ORACLE_KERNEL_PRINTED is
+ * it taken literally) and the method needs only a product of a spatial and a
+ * temporal factor; the others are unit-integral pairs on the same supports
+ * (disc u^2 + v^2 < 1, window |w| <= 1):
+ *   EPANECHNIKOV  (2/pi)(1 - u^2 - v^2)      x  (3/4)(1 - w^2)          (the default reading)
+ *   QUARTIC       (3/pi)(1 - u^2 - v^2)^2    x  (15/16)(1 - w^2)^2
+ *   GAUSSIAN      exp(-2(u^2 + v^2)) / Zs    x  exp(-2 w^2) / Zt         (sigma = half the bandwidth,
+ *                 Zs = (pi/2)(1 - e^-2), Zt = sqrt(pi/2) erf(sqrt 2): normalised on the support)
+ *   PRINTED       (pi/2)(1 - u)^2 (1 - v)^2  x  (3/4)(1 - w)^2          (as printed; not normalised)
+ * with u = (x - x_i)/hs, v = (y - y_i)/hs, w = (t - t_i)/ht. */
+#define ORACLE_KERNEL_EPANECHNIKOV 0
+#define ORACLE_KERNEL_QUARTIC 1
+#define ORACLE_KERNEL_GAUSSIAN 2
+#define ORACLE_KERNEL_PRINTED 3
 
 /* Alg. PB-SYM (Sec. 3.2) in FP64.  grid: gx*gy*gt doubles, overwritten.
  * evals_out (optional): number of (voxel, point) pairs that pass both

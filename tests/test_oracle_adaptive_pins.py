@@ -176,8 +176,8 @@ _MUTANTS = [
     ("normalisation by the grid's pair", "const double norm = 1.0 / ((double)n * hs * hs * ht);",
      "const double norm = 1.0 / ((double)n * g->hs * g->hs * g->ht);"),
     ("support by the grid's hs", "if (d < hs) {", "if (d < g->hs) {"),
-    ("kt scaled by the grid's ht", "Kt[T - Ta] = kt_epan((t - ti) / ht);",
-     "Kt[T - Ta] = kt_epan((t - ti) / g->ht);"),
+    ("kt scaled by the grid's ht", "Kt[T - Ta] = kt_of(g->kernel, (t - ti) / ht);",
+     "Kt[T - Ta] = kt_of(g->kernel, (t - ti) / g->ht);"),
     ("short loop bound", "const double Hs = ceil(hs / g->sres), Ht = ceil(ht / g->tres);\n"
      "                const double norm",
      "const double Hs = floor(hs / g->sres), Ht = ceil(ht / g->tres);\n"

@@ -282,10 +282,7 @@ _MUTANTS = [
      "return (1.0 - u * u - v * v);"),
     ("sign in kt", "return 0.75 * (1.0 - w * w);", "return 0.75 * (1.0 + w * w);"),
     ("transposed Y", "grid + (X * Gy + Y) * Gt + Ta", "grid + (Y * Gx + X) * Gt + Ta"),
-    ("corner sampling", "const double t = g->t0 + ((double)T + 0.5) * g->tres;\n"
-     "                    if (fabs(ti - t) <= g->ht) {\n                        Kt[",
-     "const double t = g->t0 + ((double)T) * g->tres;\n"
-     "                    if (fabs(ti - t) <= g->ht) {\n                        Kt["),
+    ("corner sampling", "return g->corner ? 0.0 : 0.5;", "return 0.0;"),
     ("short loop bound", "const int64_t Hs = (int64_t)ceil(g->hs / g->sres);\n"
      "    const int64_t Ht = (int64_t)ceil(g->ht / g->tres);\n    const double norm",
      "const int64_t Hs = (int64_t)floor(g->hs / g->sres);\n"
