@@ -37,6 +37,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 MFMA_F32_PEAK_TFLOPS = 157.3  # dense FP32 matrix-core peak of MI355X
+KERNELS = ("epanechnikov", "quartic", "gaussian", "printed")
 WORKLOADS = ("clustered-1M", "clustered-200k-hs50", "uniform-10k", "world-Hr-Hb", "world-Hr-Lb",
              "world-Lr-Hb", "world-Lr-Lb")
 
@@ -85,7 +86,7 @@ def _traffic_from_profile(kernel_src_hash):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(inst, gpu_plan_fn, budget_s=20.0, pairs=None):
+def cpu_baseline(inst, gpu_plan_fn, budget_s=20.0, pairs=None, kernel=0, corner=False):
     """Time the FP64 oracle on a bounded sample (the first k events of the
     workload on the full grid, with their bandwidth pairs when the workload
     has per-event bandwidths), growing k until the run takes a few seconds
@@ -94,7 +95,8 @@ def cpu_baseline(inst, gpu_plan_fn, budget_s=20.0, pairs=None):
     import numpy as np
     import oracle
     g = oracle.Grid(gx=inst.gx, gy=inst.gy, gt=inst.gt, hs=inst.hs, ht=inst.ht,
-                    sres=inst.sres, tres=inst.tres, x0=inst.x0, y0=inst.y0, t0=inst.t0)
+                    sres=inst.sres, tres=inst.tres, x0=inst.x0, y0=inst.y0, t0=inst.t0,
+                    kernel=kernel, corner=corner)
     n = inst.points.shape[0]
     th = _cpu_threads()
     k = max(1, n // 64)
@@ -119,7 +121,7 @@ def cpu_baseline(inst, gpu_plan_fn, budget_s=20.0, pairs=None):
             "sample": sample, "seconds": round(dt, 3), "evals": int(evals)}, err
 
 
-def cpu_baseline_window(inst, out, budget_s=20.0):
+def cpu_baseline_window(inst, out, budget_s=20.0, kernel=0, corner=False):
     """The FP64 oracle on a bounded sample of a grid too large for host memory
     in FP64: a window of the grid (all times, a square in space around the
     densest spatial cell) with the events that can reach it, the window
@@ -144,7 +146,8 @@ def cpu_baseline_window(inst, out, budget_s=20.0):
         sel = ((p[:, 0] > x0 - reach) & (p[:, 0] < x0 + wx + reach) &
                (p[:, 1] > y0 - reach) & (p[:, 1] < y0 + wy + reach))
         sub = np.ascontiguousarray(p[sel])
-        g = oracle.Grid(gx=wx, gy=wy, gt=inst.gt, hs=inst.hs, ht=inst.ht, x0=float(x0), y0=float(y0))
+        g = oracle.Grid(gx=wx, gy=wy, gt=inst.gt, hs=inst.hs, ht=inst.ht, x0=float(x0), y0=float(y0),
+                        kernel=kernel, corner=corner)
         t0 = time.perf_counter()
         ref, evals = oracle.pbsym(sub, g, nthreads=th)
         dt = time.perf_counter() - t0
@@ -441,6 +444,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="clustered-1M", choices=WORKLOADS)
     ap.add_argument("--plain", action="store_true", help="plain FP32 accumulation (no Kahan)")
+    ap.add_argument("--kernel", default="epanechnikov", choices=KERNELS,
+                    help="kernel pair (Epanechnikov is the default reading of Sec. 2.1)")
+    ap.add_argument("--corner", action="store_true", help="sample voxels at their lower corners")
     ap.add_argument("--adaptive", action="store_true",
                     help="per-event bandwidth pairs shrinking with the local event density "
                          "(the workload's hs, ht are the largest)")
@@ -500,7 +506,9 @@ def main():
     inst = _instance(args.workload)
     n = inst.points.shape[0]
     kahan = not args.plain
-    flags = m.FLAG_MASS | (m.FLAG_KAHAN if kahan else 0) | (m.FLAG_ADAPTIVE if args.adaptive else 0)
+    kern = KERNELS.index(args.kernel)
+    flags = m.FLAG_MASS | (m.FLAG_KAHAN if kahan else 0) | (m.FLAG_ADAPTIVE if args.adaptive else 0) \
+        | m.kernel_flag(kern) | (m.FLAG_CORNER if args.corner else 0)
     pairs_np = None
     if args.adaptive:
         import workloads
@@ -602,7 +610,8 @@ def main():
     src = b"".join(open(os.path.join(ROOT, "paper_1705_09366_amd", "csrc", f), "rb").read()
                    for f in ("gather.hip", "pass.hip"))
     # ... and for the workload they were taken on (the default run)
-    profiled = args.workload == "clustered-1M" and kahan and not args.adaptive and tuning_src.startswith("autotune")
+    profiled = (args.workload == "clustered-1M" and kahan and not args.adaptive and kern == 0 and not args.corner
+                and tuning_src.startswith("autotune"))
     traffic = _traffic_from_profile(hashlib.sha256(src).hexdigest()) if profiled else None
 
     value = evals / (ms_per_step * 1e-3)
@@ -622,6 +631,7 @@ def main():
         "config": {"workload": inst.name, "n": n, "grid": [inst.gx, inst.gy, inst.gt],
                    "hs": inst.hs, "ht": inst.ht, "accumulation": "kahan" if kahan else "plain",
                    "bandwidths": "per-event (density-adaptive)" if args.adaptive else "fixed",
+                   "kernel": args.kernel, "sampling": "corner" if args.corner else "centre",
                    "evals": evals,
                    "tuning": ([tuning.tile_t, tuning.cell_xy, tuning.cell_t, tuning.split_share]
                               if tuning else [0, 0, 0, 0]),
@@ -634,7 +644,7 @@ def main():
     }
 
     if not args.no_cpu_baseline and args.workload.startswith("world-"):
-        cb, err = cpu_baseline_window(inst, out, args.cpu_budget)
+        cb, err = cpu_baseline_window(inst, out, args.cpu_budget, kern, args.corner)
         rec["cpu_baseline"] = cb
         rec["max_rel_err_vs_oracle"] = err
         _log(f"gpu vs oracle on the window: max rel err {err:.3e}")
@@ -650,7 +660,7 @@ def main():
             r = o.cpu().numpy()
             sp.close()
             return r
-        cb, err = cpu_baseline(inst, gpu_sample, args.cpu_budget, pairs_np)
+        cb, err = cpu_baseline(inst, gpu_sample, args.cpu_budget, pairs_np, kern, args.corner)
         rec["cpu_baseline"] = cb
         rec["max_rel_err_vs_oracle"] = err
         _log(f"gpu vs oracle on the cpu sample: max rel err {err:.3e}")

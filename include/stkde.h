@@ -72,8 +72,37 @@ enum {
      * tiles and loop bounds are sized by them).  Such a plan is computed with
      * stkde_compute_adaptive / stkde_bin_adaptive, not with stkde_compute /
      * stkde_bin, and cannot be a batch item. */
-    STKDE_FLAG_ADAPTIVE = 16u
+    STKDE_FLAG_ADAPTIVE = 16u,
+    /* Sample voxel (X, Y, T) at its lower corner (x0 + X sres, y0 + Y sres,
+     * t0 + T tres) instead of its centre (Sec. 2.1 leaves the sampling point
+     * open).  Not for batch items. */
+    STKDE_FLAG_CORNER = 32u
 };
+
+/* Kernel pair, in bits 8..11 of stkde_desc.flags (STKDE_FLAG_KERNEL(k)).
+ * PB-SYM needs only a product of a spatial and a temporal factor (Sec. 3.2).
+ * With u = (x - x_i)/hs, v = (y - y_i)/hs, w = (t - t_i)/ht, on the supports
+ * u^2 + v^2 < 1 and |w| <= 1 (zero outside):
+ *   EPANECHNIKOV (default)  ks = (2/pi)(1 - u^2 - v^2),    kt = (3/4)(1 - w^2)
+ *   QUARTIC                 ks = (3/pi)(1 - u^2 - v^2)^2,  kt = (15/16)(1 - w^2)^2
+ *   GAUSSIAN                ks = exp(-2(u^2 + v^2)) / Zs,  kt = exp(-2 w^2) / Zt
+ *                           (sigma = half the bandwidth, truncated at it and
+ *                           normalised on the support: Zs = (pi/2)(1 - e^-2),
+ *                           Zt = sqrt(pi/2) erf(sqrt 2))
+ *   PRINTED                 ks = (pi/2)(1 - u)^2 (1 - v)^2, kt = (3/4)(1 - w)^2
+ *                           (the pair exactly as Sec. 2.1 prints it; not
+ *                           normalised: an interior point carries mass 37 pi^2 / 24)
+ * Pairs other than EPANECHNIKOV: no per-point bandwidths (UNSUPPORTED), no
+ * batch items, at most 32 time rows per tile (a larger tile_t is lowered). */
+enum {
+    STKDE_KERNEL_EPANECHNIKOV = 0,
+    STKDE_KERNEL_QUARTIC = 1,
+    STKDE_KERNEL_GAUSSIAN = 2,
+    STKDE_KERNEL_PRINTED = 3
+};
+#define STKDE_KERNEL_SHIFT 8
+#define STKDE_KERNEL_MASK 0xf00u
+#define STKDE_FLAG_KERNEL(k) ((uint32_t)(k) << STKDE_KERNEL_SHIFT)
 
 /* Problem description (Sec. 2.1 and Table "Notations").  Lower-case values
  * are in domain units; the grid is gx x gy x gt voxels of sres x sres x tres

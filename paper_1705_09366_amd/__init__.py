@@ -33,6 +33,14 @@ FLAG_KAHAN = 1
 FLAG_MASS = 4
 FLAG_POINT_STATS = 8
 FLAG_ADAPTIVE = 16
+FLAG_CORNER = 32
+# Kernel pairs (include/stkde.h): flags |= kernel_flag(KERNEL_*)
+KERNEL_EPANECHNIKOV, KERNEL_QUARTIC, KERNEL_GAUSSIAN, KERNEL_PRINTED = 0, 1, 2, 3
+
+
+def kernel_flag(kernel: int) -> int:
+    """The desc flag bits that select a kernel pair."""
+    return (int(kernel) & 0xF) << 8
 
 EXPORTED = ("stkde_plan", "stkde_plan_destroy", "stkde_workspace_bytes", "stkde_compute",
             "stkde_bin", "stkde_accumulate", "stkde_status_string", "stkde_version",

@@ -68,8 +68,20 @@ constexpr int64_t kMaxDim = 65535;
 constexpr int32_t kMaxCells = 1 << 22;  // keys of at most 23 bits: <= 3 radix passes (<= 2 below 2^22 - 1 bins)
 constexpr int32_t kMaxBatch = 4096;
 constexpr double kSparseCandidates = 384.0;  // half the gather's survivor buffer
-constexpr uint32_t kKnownFlags =
-    STKDE_FLAG_KAHAN | STKDE_FLAG_MASS | STKDE_FLAG_POINT_STATS | STKDE_FLAG_ADAPTIVE;
+constexpr uint32_t kKnownFlags = STKDE_FLAG_KAHAN | STKDE_FLAG_MASS | STKDE_FLAG_POINT_STATS |
+                                  STKDE_FLAG_ADAPTIVE | STKDE_FLAG_CORNER | STKDE_KERNEL_MASK;
+
+int kernel_of(const stkde_desc& d) { return (int)((d.flags & STKDE_KERNEL_MASK) >> STKDE_KERNEL_SHIFT); }
+
+// Sampling at lower corners is sampling at centres of the grid whose origin
+// sits half a voxel lower: every stage works on that grid.
+double origin_shift(const stkde_desc& d, double res) { return (d.flags & STKDE_FLAG_CORNER) ? 0.5 * res : 0.0; }
+
+// Pairs that are not zero on their support boundary test membership near it
+// in FP64, from coordinates the binned set then keeps.
+bool exact_support(const stkde_desc& d) {
+    return kernel_of(d) == STKDE_KERNEL_GAUSSIAN || kernel_of(d) == STKDE_KERNEL_PRINTED;
+}
 
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
@@ -84,6 +96,7 @@ stkde_status check_desc(const stkde_desc* d) {
         return STKDE_ERR_INVALID_ARG;
     if (!isfinite(d->x0) || !isfinite(d->y0) || !isfinite(d->t0)) return STKDE_ERR_INVALID_ARG;
     if (d->flags & ~kKnownFlags) return STKDE_ERR_INVALID_ARG;
+    if (kernel_of(*d) > STKDE_KERNEL_PRINTED) return STKDE_ERR_INVALID_ARG;
     const uint64_t nvox = (uint64_t)d->gx * (uint64_t)d->gy * (uint64_t)d->gt;
     if (nvox > ((uint64_t)1 << 40)) return STKDE_ERR_TOO_LARGE;  // 4 TiB of FP32
     if (!(d->hs / d->sres < 1e9) || !(d->ht / d->tres < 1e9)) return STKDE_ERR_TOO_LARGE;
@@ -128,9 +141,9 @@ void make_set_geom(const stkde_desc& d, int32_t cell_xy, int32_t cell_t, int32_t
     g.gx = (int32_t)d.gx;
     g.gy = (int32_t)d.gy;
     g.gt = (int32_t)d.gt;
-    g.x0 = d.x0;
-    g.y0 = d.y0;
-    g.t0 = d.t0;
+    g.x0 = d.x0 - origin_shift(d, d.sres);
+    g.y0 = d.y0 - origin_shift(d, d.sres);
+    g.t0 = d.t0 - origin_shift(d, d.tres);
     g.sres = d.sres;
     g.tres = d.tres;
     g.hv = d.hs / d.sres;
@@ -164,13 +177,14 @@ stkde_status make_inst_geom(const stkde_desc& d, const stkde_desc& base, int32_t
     g.gx = (int32_t)d.gx;
     g.gy = (int32_t)d.gy;
     g.gt = (int32_t)d.gt;
-    g.x0 = d.x0;
-    g.y0 = d.y0;
-    g.t0 = d.t0;
+    g.x0 = d.x0 - origin_shift(d, d.sres);
+    g.y0 = d.y0 - origin_shift(d, d.sres);
+    g.t0 = d.t0 - origin_shift(d, d.tres);
     g.sres = d.sres;
     g.tres = d.tres;
     g.hs = d.hs;
     g.ht = d.ht;
+    g.kernel = kernel_of(d);
     g.hv = d.hs / d.sres;
     g.tv = d.ht / d.tres;
     g.Hs = cap_hs(g.hv, base);
@@ -213,10 +227,17 @@ int acc_mode(bool kahan, int32_t requested, int64_t n, const stkde_desc& base, i
     return est <= kSparseCandidates ? stkde::kAccKahanMem : stkde::kAccKahanReg;
 }
 
-// (2/pi) (3/4) / (n hs^2 ht): the constants of both kernels and the
-// estimator's normalisation, rounded once to FP32 at the store.
-float norm_const(double hs, double ht, int64_t n) {
-    return (float)((2.0 / 3.14159265358979323846) * 0.75 / ((double)n * hs * hs * ht));
+// The constant factors of the kernel pair times 1/(n hs^2 ht), rounded
+// once to FP32 at the store: (2/pi)(3/4) for Epanechnikov, (3/pi)(15/16)
+// quartic, 1/(Zs Zt) for the truncated Gaussian (Zs = (pi/2)(1 - e^-2),
+// Zt = sqrt(pi/2) erf(sqrt 2)), (pi/2)(3/4) for the pair as printed.
+float norm_const(double hs, double ht, int64_t n, int kernel = 0) {
+    const double pi = 3.14159265358979323846;
+    double c = (2.0 / pi) * 0.75;
+    if (kernel == STKDE_KERNEL_QUARTIC) c = (3.0 / pi) * (15.0 / 16.0);
+    if (kernel == STKDE_KERNEL_GAUSSIAN) c = 1.0 / ((0.5 * pi * (1.0 - exp(-2.0))) * (sqrt(0.5 * pi) * erf(sqrt(2.0))));
+    if (kernel == STKDE_KERNEL_PRINTED) c = (0.5 * pi) * 0.75;
+    return (float)(c / ((double)n * hs * hs * ht));
 }
 
 // The gather's full-cover path pays off when discs are large against a tile.
@@ -253,10 +274,17 @@ stkde::InstDev make_dev(const stkde::InstGeom& ig, const stkde::SetGeom& sg, con
     d.ntiles = ig.ntiles;
     d.tile_base = 0;
     d.flags = (mass && stats) ? stkde::kInstMass : 0u;
-    if (!adaptive && use_full(ig.hv, ig.tile_t)) d.flags |= stkde::kInstFull;
+    if (!adaptive && ig.kernel == stkde::kKernelEpan && use_full(ig.hv, ig.tile_t)) d.flags |= stkde::kInstFull;
     d.inv_hv2 = ig.inv_hv2;
     d.inv_tv2 = ig.inv_tv2;
-    d.cnorm = norm_const(ig.hs, ig.ht, n_norm);
+    d.inv_hv = (float)(1.0 / ig.hv);
+    d.inv_tv = (float)(1.0 / ig.tv);
+    d.hv64 = ig.hv;
+    d.tv64 = ig.tv;
+    d.x64 = (ig.kernel == stkde::kKernelGauss || ig.kernel == stkde::kKernelPrinted)
+                ? reinterpret_cast<const double*>(set_mem + sl.x64)
+                : nullptr;
+    d.cnorm = norm_const(ig.hs, ig.ht, n_norm, ig.kernel);
     d.split_share = split_share;
     return d;
 }
@@ -276,7 +304,7 @@ struct ComputeLayout {
 
 ComputeLayout layout_compute(const stkde_plan_s* p, int64_t n) {
     ComputeLayout c{};
-    c.sl = stkde::layout_set(p->sg, n, (p->desc.flags & STKDE_FLAG_ADAPTIVE) != 0);
+    c.sl = stkde::layout_set(p->sg, n, (p->desc.flags & STKDE_FLAG_ADAPTIVE) != 0, exact_support(p->desc));
     c.so = stkde::layout_sort(n);
     c.pl = stkde::layout_pass(&p->ig, 1, p->ig.tile_t, (p->desc.flags & STKDE_FLAG_KAHAN) != 0);
     c.nblk_pts = (int32_t)((n + stkde::kStatBlock - 1) / stkde::kStatBlock);
@@ -334,8 +362,11 @@ stkde_status stkde_plan(const stkde_desc* d, const stkde_tuning* tun, stkde_plan
     if (st != STKDE_OK) return st;
     int32_t tile_t = tun && tun->tile_t ? tun->tile_t : default_tile_t(d->ht / d->tres);
     // compensated accumulation holds three accumulator sets; with 64-row
-    // tiles that would leave one wave per SIMD
-    if ((d->flags & STKDE_FLAG_KAHAN) && tile_t > 32) tile_t = 32;
+    // tiles that would leave one wave per SIMD (the other kernel pairs have
+    // 16- and 32-row gathers only)
+    if (((d->flags & STKDE_FLAG_KAHAN) || kernel_of(*d) != STKDE_KERNEL_EPANECHNIKOV) && tile_t > 32) tile_t = 32;
+    if (kernel_of(*d) != STKDE_KERNEL_EPANECHNIKOV && (d->flags & STKDE_FLAG_ADAPTIVE))
+        return STKDE_ERR_UNSUPPORTED;
     stkde_plan_s tmp;
     tmp.desc = *d;
     tmp.split_share = tun && tun->split_share ? (uint32_t)tun->split_share : stkde::kBalanceItems;
@@ -399,7 +430,7 @@ stkde_status bin_impl(stkde_plan_t p, const double* d_xyt, const double* d_hst, 
     const stkde_status st = check_common(p, n, d_ws, ws_bytes, stream, &c);
     if (st != STKDE_OK) return st;
     if (stkde::launch_bin(p->sg, d_xyt, (int32_t)n, c.ws, c.L.sl, c.ws + c.L.shared, c.L.so, c.s,
-                          d_hst) != hipSuccess)
+                          d_hst, exact_support(p->desc)) != hipSuccess)
         return STKDE_ERR_HIP;
     return STKDE_OK;
 }
@@ -433,10 +464,13 @@ stkde_status stkde_accumulate(stkde_plan_t p, int64_t n, float* d_out, void* d_w
         e1 = p->ev[(size_t)p->ev_used + 1];
         p->ev_used += 2;
     }
-    const int mode = acc_mode((fl & STKDE_FLAG_KAHAN) != 0, p->kahan_mode, n, p->desc, p->ig.Hs, p->ig.Ht,
-                              p->ig.tile_t);
-    if (stkde::launch_pass(&d, 1, c.ws + c.L.shared, c.L.pl, p->ig.tile_t, mode,
-                           !adapt && use_full(p->ig.hv, p->ig.tile_t), adapt, c.s, e0, e1) != hipSuccess)
+    const int kf = p->ig.kernel;
+    int mode = acc_mode((fl & STKDE_FLAG_KAHAN) != 0, p->kahan_mode, n, p->desc, p->ig.Hs, p->ig.Ht,
+                        p->ig.tile_t);
+    if (kf != stkde::kKernelEpan && mode == stkde::kAccKahanReg) mode = stkde::kAccKahanMem;  // same bits
+    const bool full = !adapt && kf == stkde::kKernelEpan && use_full(p->ig.hv, p->ig.tile_t);
+    if (stkde::launch_pass(&d, 1, c.ws + c.L.shared, c.L.pl, p->ig.tile_t, mode, full, adapt, kf, c.s, e0,
+                           e1) != hipSuccess)
         return STKDE_ERR_HIP;
     return STKDE_OK;
 }
@@ -535,7 +569,8 @@ stkde_status stkde_batch_plan(const stkde_item* items, int32_t count, stkde_batc
         if ((uintptr_t)it.d_set & 255u) return STKDE_ERR_INVALID_ARG;
         const stkde_desc& d = it.plan->desc;
         const stkde_desc& b = it.set->base;
-        if (d.flags & (STKDE_FLAG_POINT_STATS | STKDE_FLAG_ADAPTIVE)) return STKDE_ERR_UNSUPPORTED;
+        if (d.flags & (STKDE_FLAG_POINT_STATS | STKDE_FLAG_ADAPTIVE | STKDE_FLAG_CORNER | STKDE_KERNEL_MASK))
+            return STKDE_ERR_UNSUPPORTED;
         if (!same_res(d.sres, b.sres) || !same_res(d.tres, b.tres)) return STKDE_ERR_INVALID_ARG;
         if (d.hs > b.hs || d.ht > b.ht) return STKDE_ERR_INVALID_ARG;
         if (it.ox < 0 || it.oy < 0 || it.ot < 0 || it.ox + d.gx > b.gx || it.oy + d.gy > b.gy ||
@@ -618,7 +653,7 @@ stkde_status batch_enqueue(stkde_batch_t b, uint8_t* ws, hipStream_t s) {
                                     it.plan->split_share));
         }
         if (stkde::launch_pass(devs.data(), (int32_t)devs.size(), ws, g.pl, g.tile_t, g.mode, g.full, false,
-                               s) != hipSuccess)
+                               stkde::kKernelEpan, s) != hipSuccess)
             return STKDE_ERR_HIP;
     }
     return STKDE_OK;
@@ -635,7 +670,7 @@ stkde_status stkde_batch_run(stkde_batch_t b, void* d_ws, size_t ws_bytes, void*
 stkde_status stkde_batch_capture(stkde_batch_t b, void* d_ws, size_t ws_bytes) {
     if (!b) return STKDE_ERR_INVALID_ARG;
     if (!d_ws || ws_bytes < b->ws_bytes || ((uintptr_t)d_ws & 255u)) return STKDE_ERR_WORKSPACE;
-    for (const auto& g : b->groups) stkde::prepare_gather(g.tile_t, g.mode, g.full, false);
+    for (const auto& g : b->groups) stkde::prepare_gather(g.tile_t, g.mode, g.full, false, stkde::kKernelEpan);
     hipStream_t cs = nullptr;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return STKDE_ERR_HIP;
     hipGraph_t graph = nullptr;
@@ -687,7 +722,7 @@ stkde_status stkde_ablation_accumulate(stkde_plan_t p, int32_t method, int64_t n
     Call c;
     const stkde_status st = check_common(p, n, d_ws, ws_bytes, stream, &c);
     if (st != STKDE_OK) return st;
-    if (is_adaptive(p)) return STKDE_ERR_UNSUPPORTED;
+    if (is_adaptive(p) || p->ig.kernel != stkde::kKernelEpan) return STKDE_ERR_UNSUPPORTED;
     // the scatter indexes a footprint box, the voxel gather its grid, in 32 bits
     const stkde::InstGeom& g = p->ig;
     const int64_t box = (int64_t)std::min<int64_t>(g.gx, 2 * (int64_t)g.Hs + 2) *
@@ -707,7 +742,7 @@ stkde_status stkde_ablation_compute(stkde_plan_t p, int32_t method, const double
                                     float* d_out, void* d_ws, size_t ws_bytes, void* stream) {
     if (!p || !d_xyt || !d_out || (method != STKDE_ABLATION_SCATTER && method != STKDE_ABLATION_VOXEL))
         return STKDE_ERR_INVALID_ARG;
-    if (is_adaptive(p)) return STKDE_ERR_UNSUPPORTED;
+    if (is_adaptive(p) || p->ig.kernel != stkde::kKernelEpan) return STKDE_ERR_UNSUPPORTED;
     stkde_status st = stkde_bin(p, d_xyt, n, d_ws, ws_bytes, stream);
     if (st != STKDE_OK) return st;
     return stkde_ablation_accumulate(p, method, n, d_out, d_ws, ws_bytes, stream);

@@ -294,7 +294,7 @@ __global__ __launch_bounds__(kThreads) void k_records(SetGeom g, const double* _
                                                       const uint32_t* __restrict__ vals,
                                                       const uint32_t* __restrict__ cell_start,
                                                       int32_t n, PointRec* __restrict__ recs,
-                                                      float4* __restrict__ bw) {
+                                                      float4* __restrict__ bw, double* __restrict__ x64) {
     const int64_t s = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (s >= n) return;
     const int64_t nvalid = (int64_t)cell_start[g.ncell];
@@ -307,6 +307,11 @@ __global__ __launch_bounds__(kThreads) void k_records(SetGeom g, const double* _
     if (hst)
         bw[s] = make_float4((float)(1.0 / (hv * hv)), (float)(1.0 / (tv * tv)),
                             (float)((g.hv * g.hv * g.tv) / (hv * hv * tv)), 0.0f);
+    if (x64) {
+        x64[3 * s] = f.xr;
+        x64[3 * s + 1] = f.yr;
+        x64[3 * s + 2] = f.tr;
+    }
     PointRec r;
     r.xh = (float)f.xr;
     r.yh = (float)f.yr;
@@ -331,13 +336,14 @@ namespace {
 size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 }  // namespace
 
-SetLayout layout_set(const SetGeom& g, int64_t n, bool adaptive) {
+SetLayout layout_set(const SetGeom& g, int64_t n, bool adaptive, bool exact) {
     SetLayout l{};
     size_t o = 0;
     l.cell_start = o; o = al256(o + ((size_t)g.ncell + 1) * 4);
     l.recs = o; o = al256(o + (size_t)n * sizeof(PointRec));
     l.counters = o; o = al256(o + 4 * 8);
     l.bw = o; o = al256(o + (adaptive ? (size_t)n * sizeof(float4) : 0));
+    l.x64 = o; o = al256(o + (exact ? (size_t)n * 3 * sizeof(double) : 0));
     l.total = o;
     return l;
 }
@@ -359,7 +365,7 @@ SortLayout layout_sort(int64_t n) {
 
 hipError_t launch_bin(const SetGeom& g, const double* d_xyt, int32_t n, uint8_t* set,
                       const SetLayout& sl, uint8_t* sort, const SortLayout& so, hipStream_t s,
-                      const double* d_hst) {
+                      const double* d_hst, bool exact) {
     uint32_t* k0 = reinterpret_cast<uint32_t*>(sort + so.keys0);
     uint32_t* v0 = reinterpret_cast<uint32_t*>(sort + so.vals0);
     uint32_t* k1 = reinterpret_cast<uint32_t*>(sort + so.keys1);
@@ -394,7 +400,8 @@ hipError_t launch_bin(const SetGeom& g, const double* d_xyt, int32_t n, uint8_t*
     hipLaunchKernelGGL(k_cell_start, dim3(nc), dim3(kThreads), 0, s, k0, n, g.ncell, cs);
     hipLaunchKernelGGL(k_records, dim3(nb), dim3(kThreads), 0, s, g, d_xyt, d_hst, v0, cs, n,
                        reinterpret_cast<PointRec*>(set + sl.recs),
-                       d_hst ? reinterpret_cast<float4*>(set + sl.bw) : nullptr);
+                       d_hst ? reinterpret_cast<float4*>(set + sl.bw) : nullptr,
+                       exact ? reinterpret_cast<double*>(set + sl.x64) : nullptr);
     return hipGetLastError();
 }
 

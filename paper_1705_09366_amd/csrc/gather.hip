@@ -68,6 +68,10 @@ constexpr int kCap = 768;  // survivors held in LDS between matrix-core phases
 constexpr uint32_t kFullFlag = 0x10u;      // survivor mask: disc covers the whole tile
 constexpr float kFullMargin = 0.99998f;    // largest a + b at a tile corner for that
 constexpr int kMaxDevices = 64;
+// Pairs that are not zero on their support boundary decide membership near it
+// in FP64: within this band of the FP32 test (|1 - u^2 - v^2| or |w^2 - 1|),
+// far wider than its rounding, the record's FP64 coordinates are read.
+constexpr float kExactBand = 1.0e-4f;
 
 __device__ inline float half_lo(uint32_t v) {
     return (float)__builtin_bit_cast(_Float16, (uint16_t)(v & 0xffffu));
@@ -75,6 +79,68 @@ __device__ inline float half_lo(uint32_t v) {
 
 __device__ inline float half_hi(uint32_t v) {
     return (float)__builtin_bit_cast(_Float16, (uint16_t)(v >> 16));
+}
+
+// Matrix-core operands of each kernel pair, without its constant factors
+// (applied at the store).  e = 1 - u^2 - v^2 for the (point, column), so the
+// disc is e > 0; dt, dx, dy are voxel minus point offsets in voxels.
+//   Epanechnikov  Kt' = 1 - w^2,        Ks' = e            (both clamped at 0;
+//                 the operands never exceed 1, so max(0, .) is a clamp to [0, 1],
+//                 which folds into the producing instruction)
+//   quartic       Kt' = (1 - w^2)^2,    Ks' = e^2
+//   Gaussian      Kt' = exp(-2 w^2),    Ks' = exp(-2 u^2) exp(-2 v^2)   on the supports
+//   as printed    Kt' = (1 - w)^2,      Ks' = (1 - u)^2 (1 - v)^2        on the supports
+template <int KF>
+__device__ inline float kt_operand(float dt, float inv_tv2, float inv_tv) {
+    if constexpr (KF == kKernelEpan) {
+        return __builtin_amdgcn_fmed3f(fmaf(-dt * dt, inv_tv2, 1.0f), 0.0f, 1.0f);
+    } else if constexpr (KF == kKernelQuartic) {
+        const float e = __builtin_amdgcn_fmed3f(fmaf(-dt * dt, inv_tv2, 1.0f), 0.0f, 1.0f);
+        return e * e;
+    } else if constexpr (KF == kKernelGauss) {
+        const float w2 = dt * dt * inv_tv2;
+        return w2 <= 1.0f ? __builtin_amdgcn_exp2f(-2.0f * 1.44269504088896340736f * w2) : 0.0f;
+    } else {
+        const float w = dt * inv_tv;
+        return dt * dt * inv_tv2 <= 1.0f ? (1.0f - w) * (1.0f - w) : 0.0f;
+    }
+}
+
+// The per-axis factor of a multiplicatively separable spatial operand (1
+// for the additive ones).
+template <int KF>
+__device__ inline float ks_factor(float d, float inv_hv2, float inv_hv) {
+    if constexpr (KF == kKernelGauss) {
+        return __builtin_amdgcn_exp2f(-2.0f * 1.44269504088896340736f * (d * d * inv_hv2));
+    } else if constexpr (KF == kKernelPrinted) {
+        const float u = d * inv_hv;
+        return (1.0f - u) * (1.0f - u);
+    } else {
+        return 1.0f;
+    }
+}
+
+// Value of the temporal operand ignoring the support (pairs tested exactly).
+template <int KF>
+__device__ inline float kt_value(float dt, float inv_tv2, float inv_tv) {
+    if constexpr (KF == kKernelGauss) {
+        return __builtin_amdgcn_exp2f(-2.0f * 1.44269504088896340736f * (dt * dt * inv_tv2));
+    } else {
+        const float w = dt * inv_tv;
+        return (1.0f - w) * (1.0f - w);
+    }
+}
+
+template <int KF>
+__device__ inline float ks_operand(float e, float fx, float fy) {
+    if constexpr (KF == kKernelEpan) {
+        return __builtin_amdgcn_fmed3f(e, 0.0f, 1.0f);
+    } else if constexpr (KF == kKernelQuartic) {
+        const float c = __builtin_amdgcn_fmed3f(e, 0.0f, 1.0f);
+        return c * c;
+    } else {
+        return e > 0.0f ? fx * fy : 0.0f;
+    }
 }
 
 // (sum, comp) += pass by Kahan's rule; pass is cleared.
@@ -101,15 +167,32 @@ __device__ inline void kahan_fold(f32x4 (&sum)[CG], f32x4 (&comp)[CG], f32x4 (&p
 // ADAPT: every record carries its own bandwidth terms (1/hv_i^2, 1/tv_i^2,
 // weight); they are staged beside the coordinates and enter the operands of
 // each point (the weight scales its Kt operand).
-template <int TT, int MODE, bool FULL, bool ADAPT>
+// KF: the kernel pair (kKernel*); its constants are applied at the store.
+// FP64 support tests of one (record, column) and one (record, row), in base
+// voxels with the sampling point at +1/2 (products and sums rounded as
+// written, without contraction).
+__device__ inline bool exact_disc(const double* __restrict__ x64, uint32_t ri, int32_t X, int32_t Y,
+                                  double hv) {
+    const double dx = __dadd_rn((double)X + 0.5, -x64[3 * (size_t)ri]);
+    const double dy = __dadd_rn((double)Y + 0.5, -x64[3 * (size_t)ri + 1]);
+    return __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)) < __dmul_rn(hv, hv);
+}
+
+__device__ inline bool exact_window(const double* __restrict__ x64, uint32_t ri, int32_t T, double tv) {
+    return fabs(__dadd_rn((double)T + 0.5, -x64[3 * (size_t)ri + 2])) <= tv;
+}
+
+template <int TT, int MODE, bool FULL, bool ADAPT, int KF>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_gather_items(
     const InstDev* __restrict__ descs, int32_t count, int32_t ntiles_total,
     const WorkItem* __restrict__ items, const uint32_t* __restrict__ bits,
     const uint32_t* __restrict__ sc, uint32_t* __restrict__ ctr, float* __restrict__ partials,
     float* __restrict__ kscratch) {
     static_assert(!(FULL && ADAPT), "the full-cover path assumes one bandwidth pair");
+    static_assert(KF == kKernelEpan || (!FULL && !ADAPT), "other pairs: no full-cover path, one pair");
     constexpr int NB = TT / 16;  // 16-row blocks per tile
     constexpr int CG = 4 * NB;   // accumulator blocks per wave
+    constexpr bool EXACT = KF == kKernelGauss || KF == kKernelPrinted;
     // Kahan with the running (sum, compensation) in memory: this thread's
     // slot of kscratch, sum of block k at [k], compensation at [CG + k]
     f32x4* __restrict__ kslot =
@@ -128,6 +211,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
     __shared__ uint8_t sQ[kCap];
     // per-point bandwidth terms of the survivors (ADAPT only)
     __shared__ float4 sB[ADAPT ? kCap + 1 : 1];
+    // record index of each survivor (pairs with exact support tests only)
+    __shared__ uint32_t sI[EXACT ? kCap + 1 : 1];
     // per-wave lists of survivor indices: the quadrant list, then (full-cover
     // path) the wave's share of the full-cover list, each padded to 8
     __shared__ uint16_t sL[kWaves][kCap + 16];
@@ -144,6 +229,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
         sY[kPad] = make_float2(-1.0e6f, 0.f);
         sT[kPad] = make_float2(-1.0e6f, 0.f);
         if constexpr (ADAPT) sB[kPad] = make_float4(1.0f, 1.0f, 0.0f, 0.0f);
+        if constexpr (EXACT) sI[kPad] = 0u;  // never read: the pad is far from every boundary
     }
 
     // this wave's quadrant: column groups gx in {gqx, gqx + 1}, gy in {gqy, gqy + 1}
@@ -192,6 +278,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                 const int32_t inst = find_inst(descs, count, it.tile);
                 const InstDev& D = descs[inst];
                 const float inv_hv2 = D.inv_hv2, inv_tv2 = D.inv_tv2;
+                const float inv_hv = D.inv_hv, inv_tv = D.inv_tv;
 
                 const int32_t tile = (int32_t)(it.tile - (uint32_t)D.tile_base);
                 const int32_t tx = tile % D.ntx;
@@ -252,29 +339,46 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                 // one group: operands from the coordinates (and, ADAPT, the
                 // bandwidth terms pb) of this lane's point, then all CG
                 // instructions
-                auto group = [&](const float2 cx, const float2 cy, const float2 ctt, const float4 pb) {
+                auto group = [&](const float2 cx, const float2 cy, const float2 ctt, const float4 pb,
+                                 const uint32_t ri) {
                     const float ihv2 = ADAPT ? pb.x : inv_hv2;
                     const float itv2 = ADAPT ? pb.y : inv_tv2;
                     float av[NB];
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
                         const float dt = ((rowc + 16.0f * b) - ctt.x) - ctt.y;
-                        // the operands never exceed 1, so max(0, .) is a clamp to
-                        // [0, 1], which folds into the producing instruction
-                        av[b] = __builtin_amdgcn_fmed3f(fmaf(-dt * dt, itv2, 1.0f), 0.0f, 1.0f);
+                        if constexpr (EXACT) {
+                            const float w2 = dt * dt * itv2;
+                            bool in = w2 <= 1.0f;
+                            if (fabsf(w2 - 1.0f) < kExactBand)
+                                in = exact_window(D.x64, ri, BT0 + 16 * b + (lane & 15), D.tv64);
+                            av[b] = in ? kt_value<KF>(dt, itv2, inv_tv) : 0.0f;
+                        } else {
+                            av[b] = kt_operand<KF>(dt, itv2, inv_tv);
+                        }
                         if constexpr (ADAPT) av[b] *= pb.z;
                     }
-                    float ux[2], uy[2];
+                    float ux[2], uy[2], fx[2], fy[2];
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
                         const float dx = ((xc0 + 4.0f * h) - cx.x) - cx.y;
                         const float dy = ((yc0 + 4.0f * h) - cy.x) - cy.y;
                         ux[h] = fmaf(-dx * dx, ihv2, 1.0f);
                         uy[h] = dy * dy * ihv2;
+                        fx[h] = ks_factor<KF>(dx, ihv2, inv_hv);
+                        fy[h] = ks_factor<KF>(dy, ihv2, inv_hv);
                     }
 #pragma unroll
                     for (int g = 0; g < 4; ++g) {
-                        const float ks = __builtin_amdgcn_fmed3f(ux[g & 1] - uy[g >> 1], 0.0f, 1.0f);
+                        float ks = ks_operand<KF>(ux[g & 1] - uy[g >> 1], fx[g & 1], fy[g >> 1]);
+                        if constexpr (EXACT) {
+                            const float e = ux[g & 1] - uy[g >> 1];
+                            if (fabsf(e) < kExactBand) {
+                                const int32_t X = BX0 + 4 * gqx + 4 * (g & 1) + (lane & 3);
+                                const int32_t Y = BY0 + 4 * gqy + 4 * (g >> 1) + ((lane >> 2) & 3);
+                                ks = exact_disc(D.x64, ri, X, Y, D.hv64) ? fx[g & 1] * fy[g >> 1] : 0.0f;
+                            }
+                        }
 #pragma unroll
                         for (int b = 0; b < NB; ++b)
                             acc[g * NB + b] =
@@ -317,7 +421,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                         bool surv = false;
                         PointRec r{};
                         float4 pbw{};
-                        uint32_t qm = 0;
+                        uint32_t qm = 0, rix = 0;
                         if (c < cend) {
                             int32_t lo = 0, hi = nranges - 1;  // last range with sRP <= c
                             while (lo < hi) {
@@ -326,6 +430,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                                 else hi = mid - 1;
                             }
                             const int32_t ri = sRB[lo] + (c - sRP[lo]);
+                            rix = (uint32_t)ri;
                             r = recs[ri];
                             if constexpr (ADAPT) pbw = D.bw[ri];
                             const int32_t xlo = (int32_t)(r.xb & 0xffffu) - BX0, xhi = (int32_t)(r.xb >> 16) - BX0;
@@ -368,6 +473,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                             sY[s] = make_float2(r.yh - (float)BY0, half_hi(r.xl_yl));
                             sT[s] = make_float2(r.th - (float)BT0, half_lo(r.tl));
                             if constexpr (ADAPT) sB[s] = pbw;
+                            if constexpr (EXACT) sI[s] = rix;
                             sQ[s] = (uint8_t)qm;
                         }
                         count_s += add;
@@ -410,19 +516,22 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                         int s = myL[kq];
                         float2 ax = sX[s], ay = sY[s], at = sT[s];
                         float4 ab = ADAPT ? sB[s] : float4{};
+                        uint32_t ai = EXACT ? sI[s] : 0u;
                         for (int32_t pr = 0; pr < npairs; ++pr) {
                             s = myL[8 * pr + 4 + kq];
                             const float2 bx = sX[s], by = sY[s], bt = sT[s];
                             const float4 bbw = ADAPT ? sB[s] : float4{};
-                            group(ax, ay, at, ab);
+                            const uint32_t bi = EXACT ? sI[s] : 0u;
+                            group(ax, ay, at, ab, ai);
                             if (pr + 1 < npairs) {
                                 s = myL[8 * pr + 8 + kq];
                                 ax = sX[s];
                                 ay = sY[s];
                                 at = sT[s];
                                 if constexpr (ADAPT) ab = sB[s];
+                                if constexpr (EXACT) ai = sI[s];
                             }
-                            group(bx, by, bt, bbw);
+                            group(bx, by, bt, bbw, bi);
                         }
                     }
                     if constexpr (FULL) {
@@ -657,7 +766,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce_split(const InstDev* __rest
 // Workgroups of the persistent gather: compute units x resident workgroups
 // per compute unit, cached per device (memory-mode Kahan at most
 // kMemKahanGroups, the slots of its scratch).
-template <int TT, int MODE, bool FULL, bool ADAPT>
+template <int TT, int MODE, bool FULL, bool ADAPT, int KF>
 int resident_groups() {
     static_assert(!FULL || TT <= 32, "the full-cover sums of 64-row tiles do not fit the survivor LDS");
     static std::atomic<int> cache[kMaxDevices];
@@ -667,8 +776,8 @@ int resident_groups() {
     if (v > 0) return v;
     int ncu = 0, occ = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_gather_items<TT, MODE, FULL, ADAPT>, kThreads,
-                                                     0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_gather_items<TT, MODE, FULL, ADAPT, KF>,
+                                                     kThreads, 0) != hipSuccess)
         occ = 0;
     v = (ncu > 0 ? ncu : 256) * (occ > 0 ? occ : 1);
     if (MODE == kAccKahanMem && v > kMemKahanGroups) v = kMemKahanGroups;
@@ -676,35 +785,54 @@ int resident_groups() {
     return v;
 }
 
-template <int TT, int MODE, bool FULL, bool ADAPT>
+template <int TT, int MODE, bool FULL, bool ADAPT, int KF>
 void launch_items_t(const InstDev* d, int32_t count, const WorkItem* items, const uint32_t* bits,
                     const uint32_t* sc, uint32_t* ctr, float* partials, float* kscratch, int64_t T,
                     hipStream_t s) {
-    int64_t g = resident_groups<TT, MODE, FULL, ADAPT>();
+    int64_t g = resident_groups<TT, MODE, FULL, ADAPT, KF>();
     const int64_t most = T + kPartSlots;  // items never exceed tiles + partial slots
     if (g > most) g = most;
     if (g < 1) g = 1;
-    hipLaunchKernelGGL((k_gather_items<TT, MODE, FULL, ADAPT>), dim3((uint32_t)g), dim3(kThreads), 0, s,
-                       d, count, (int32_t)T, items, bits, sc, ctr, partials, kscratch);
+    hipLaunchKernelGGL((k_gather_items<TT, MODE, FULL, ADAPT, KF>), dim3((uint32_t)g), dim3(kThreads), 0,
+                       s, d, count, (int32_t)T, items, bits, sc, ctr, partials, kscratch);
 }
 
-// f.template operator()<TT, MODE, FULL, ADAPT>() for one (tile rows, mode):
-// per-point bandwidths never take the full-cover path, nor do 64-row tiles.
+// f.template operator()<TT, MODE, FULL, ADAPT, KF>() for one (tile rows,
+// mode) of the Epanechnikov pair: per-point bandwidths never take the
+// full-cover path, nor do 64-row tiles.
 template <int TT, int MODE, typename F>
 void dispatch_variant(bool full, bool adapt, F& f) {
     if (adapt) {
-        f.template operator()<TT, MODE, false, true>();
+        f.template operator()<TT, MODE, false, true, kKernelEpan>();
     } else if constexpr (TT <= 32) {
-        if (full) f.template operator()<TT, MODE, true, false>();
-        else f.template operator()<TT, MODE, false, false>();
+        if (full) f.template operator()<TT, MODE, true, false, kKernelEpan>();
+        else f.template operator()<TT, MODE, false, false, kKernelEpan>();
     } else {
-        f.template operator()<TT, MODE, false, false>();
+        f.template operator()<TT, MODE, false, false, kKernelEpan>();
     }
 }
 
-// The kernel variant of (tile_t, mode, full, adapt); 64-row tiles are plain.
+// The other pairs: 16- or 32-row tiles, plain or compensated (scratch form;
+// the register form performs the same operations), one bandwidth pair.
+template <int KF, typename F>
+void dispatch_pair(int tile_t, int mode, F& f) {
+    const bool kahan = mode != kAccPlain;
+    if (tile_t == 16) {
+        kahan ? f.template operator()<16, kAccKahanMem, false, false, KF>()
+              : f.template operator()<16, kAccPlain, false, false, KF>();
+    } else {
+        kahan ? f.template operator()<32, kAccKahanMem, false, false, KF>()
+              : f.template operator()<32, kAccPlain, false, false, KF>();
+    }
+}
+
+// The kernel variant of (tile_t, mode, full, adapt, kernel pair); 64-row
+// tiles are plain.
 template <typename F>
-void dispatch(int tile_t, int mode, bool full, bool adapt, F&& f) {
+void dispatch(int tile_t, int mode, bool full, bool adapt, int kf, F&& f) {
+    if (kf == kKernelQuartic) return dispatch_pair<kKernelQuartic>(tile_t, mode, f);
+    if (kf == kKernelGauss) return dispatch_pair<kKernelGauss>(tile_t, mode, f);
+    if (kf == kKernelPrinted) return dispatch_pair<kKernelPrinted>(tile_t, mode, f);
     if (tile_t == 16) {
         if (mode == kAccKahanReg) dispatch_variant<16, kAccKahanReg>(full, adapt, f);
         else if (mode == kAccKahanMem) dispatch_variant<16, kAccKahanMem>(full, adapt, f);
@@ -730,17 +858,17 @@ void launch_reduce_t(const InstDev* d, int32_t count, const uint32_t* top, const
 hipError_t launch_gather_items(const InstDev* d_desc, int32_t count, const WorkItem* d_items,
                                const uint32_t* d_bits, const uint32_t* d_scalars,
                                uint32_t* d_counters, float* d_partials, float* d_kscratch, int64_t T,
-                               int tile_t, int mode, bool full, bool adapt, hipStream_t s) {
-    dispatch(tile_t, mode, full, adapt, [&]<int TT, int M, bool F, bool A>() {
-        launch_items_t<TT, M, F, A>(d_desc, count, d_items, d_bits, d_scalars, d_counters, d_partials,
-                                    d_kscratch, T, s);
+                               int tile_t, int mode, bool full, bool adapt, int kf, hipStream_t s) {
+    dispatch(tile_t, mode, full, adapt, kf, [&]<int TT, int M, bool F, bool A, int K>() {
+        launch_items_t<TT, M, F, A, K>(d_desc, count, d_items, d_bits, d_scalars, d_counters, d_partials,
+                                       d_kscratch, T, s);
     });
     return hipGetLastError();
 }
 
-void prepare_gather(int tile_t, int mode, bool full, bool adapt) {
-    dispatch(tile_t, mode, full, adapt,
-             []<int TT, int M, bool F, bool A>() { (void)resident_groups<TT, M, F, A>(); });
+void prepare_gather(int tile_t, int mode, bool full, bool adapt, int kf) {
+    dispatch(tile_t, mode, full, adapt, kf,
+             []<int TT, int M, bool F, bool A, int K>() { (void)resident_groups<TT, M, F, A, K>(); });
 }
 
 hipError_t launch_reduce_split(const InstDev* d_desc, int32_t count, const uint32_t* d_top,

@@ -19,6 +19,27 @@
 namespace stkde {
 namespace {
 
+// The kernel pairs in FP64, each evaluated only inside its support
+// (u = (x - x_i)/hs, v = (y - y_i)/hs, w = (t - t_i)/ht).
+__device__ inline double spatial_kernel(int32_t kernel, double u, double v) {
+    const double r2 = u * u + v * v;
+    switch (kernel) {
+    case kKernelQuartic: return (3.0 / 3.14159265358979323846) * (1.0 - r2) * (1.0 - r2);
+    case kKernelGauss: return exp(-2.0 * r2) / (0.5 * 3.14159265358979323846 * (1.0 - exp(-2.0)));
+    case kKernelPrinted: return (0.5 * 3.14159265358979323846) * (1.0 - u) * (1.0 - u) * (1.0 - v) * (1.0 - v);
+    default: return (2.0 / 3.14159265358979323846) * (1.0 - u * u - v * v);
+    }
+}
+
+__device__ inline double temporal_kernel(int32_t kernel, double w) {
+    switch (kernel) {
+    case kKernelQuartic: return 0.9375 * (1.0 - w * w) * (1.0 - w * w);
+    case kKernelGauss: return exp(-2.0 * w * w) / (sqrt(0.5 * 3.14159265358979323846) * erf(sqrt(2.0)));
+    case kKernelPrinted: return 0.75 * (1.0 - w) * (1.0 - w);
+    default: return 0.75 * (1.0 - w * w);
+    }
+}
+
 __device__ inline bool clip_rng(double v, double h, int32_t lo, int32_t hi, int32_t* a, int32_t* b) {
     const double da = v - h, db = v + h;
     if (db < (double)lo || da > (double)(hi - 1)) return false;
@@ -65,7 +86,7 @@ __global__ __launch_bounds__(kStatBlock) void k_point_stats(InstGeom g, const do
                         const double d = sqrt((xi - x) * (xi - x) + (yi - y) * (yi - y));
                         if (d < hs) {
                             const double u = (x - xi) / hs, v = (y - yi) / hs;
-                            ss += (2.0 / 3.14159265358979323846) * (1.0 - u * u - v * v);
+                            ss += spatial_kernel(g.kernel, u, v);
                             ++cs;
                         }
                     }
@@ -76,7 +97,7 @@ __global__ __launch_bounds__(kStatBlock) void k_point_stats(InstGeom g, const do
                     const double t = g.t0 + ((double)T + 0.5) * g.tres;
                     if (fabs(ti - t) <= ht) {
                         const double w = (t - ti) / ht;
-                        st += 0.75 * (1.0 - w * w);
+                        st += temporal_kernel(g.kernel, w);
                         ++ct;
                     }
                 }

@@ -67,6 +67,7 @@ struct InstGeom {
     double hv, tv;            // voxel bandwidths
     double Hs_d, Ht_d;        // ceil(hv), ceil(tv) uncapped (loop bounds of the statistics)
     float inv_hv2, inv_tv2;   // 1/hv^2, 1/tv^2 (FP32)
+    int32_t kernel;           // kKernel*: the kernel pair
 };
 
 // Per-instance descriptor the device work list refers to (pass scratch copy).
@@ -76,6 +77,9 @@ struct alignas(16) InstDev {
     const unsigned long long* counters;  // set: non-finite, culled, invalid bandwidth pairs
     const float4* bw;                    // set: per record (1/hv_i^2, 1/tv_i^2, weight, 0) when
                                          // its points carry their own bandwidths, else null
+    const double* x64;                   // set: per record its FP64 voxel coordinates (xr, yr, tr)
+                                         // for the exact support tests of the pairs that are not
+                                         // zero on their boundary, else null
     float* out;                          // instance grid, [X][Y][T], T fastest
     double* stats;                       // optional 8 doubles, null for none
     double* tile_part;                   // pass scratch: ntiles * kWaves FP64 mass partials
@@ -87,8 +91,15 @@ struct alignas(16) InstDev {
     int32_t ntx, nty, ntiles, tile_base; // instance tiles; first global tile index
     uint32_t flags;                      // kInstMass, kInstFull
     float inv_hv2, inv_tv2, cnorm;
+    float inv_hv, inv_tv;                // 1/hv, 1/tv (the pair as printed is odd in u, v, w)
+    double hv64, tv64;                   // hv, tv in FP64 (exact support tests)
     uint32_t split_share;                // split tiles above total cost / split_share
 };
+// Kernel pairs (the public STKDE_KERNEL_* values).
+constexpr int kKernelEpan = 0;
+constexpr int kKernelQuartic = 1;
+constexpr int kKernelGauss = 2;
+constexpr int kKernelPrinted = 3;
 constexpr uint32_t kInstMass = 1u;
 constexpr uint32_t kInstFull = 2u;  // use the full-cover path (in a kernel that has it)
 
@@ -159,9 +170,10 @@ struct SetLayout {
     size_t recs;         // n PointRec
     size_t counters;     // 4 x u64: non-finite, culled, invalid bandwidth pairs, 0
     size_t bw;           // n float4 (per-point bandwidths; 0 bytes without)
+    size_t x64;          // n x 3 FP64 voxel coordinates (exact support tests; 0 bytes without)
     size_t total;
 };
-SetLayout layout_set(const SetGeom& s, int64_t n, bool adaptive = false);
+SetLayout layout_set(const SetGeom& s, int64_t n, bool adaptive = false, bool exact = false);
 
 // ---- scratch of the binning radix sort --------------------------------------
 struct SortLayout {
@@ -258,25 +270,26 @@ __device__ inline uint32_t spatial_pos(const InstDev& D, uint32_t j) {
 // positive, or exceeds the set's bandwidths, drops the point (counted).
 hipError_t launch_bin(const SetGeom& g, const double* d_xyt, int32_t n, uint8_t* set,
                       const SetLayout& sl, uint8_t* sort, const SortLayout& so, hipStream_t s,
-                      const double* d_hst = nullptr);
+                      const double* d_hst = nullptr, bool exact = false);
 // Work list, gather, split reduction, mass and statistics over `count`
 // instances.  The descriptors' tile_part and tile_base fields are filled in
 // here; every other field is the caller's.
 // ev_before / ev_after (may be null) are recorded on s right before and
 // right after the gather kernel.
 // full: use the gather's full-cover path (tile_t <= 32); adapt: the
-// instances' sets carry per-point bandwidths (never with full).
+// instances' sets carry per-point bandwidths (never with full); kf: the
+// kernel pair (other than Epanechnikov: neither full nor adapt, tile_t <= 32).
 hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassLayout& pl,
-                       int tile_t, int mode, bool full, bool adapt, hipStream_t s,
+                       int tile_t, int mode, bool full, bool adapt, int kf, hipStream_t s,
                        hipEvent_t ev_before = nullptr, hipEvent_t ev_after = nullptr);
 // The gather proper (called by launch_pass).
 hipError_t launch_gather_items(const InstDev* d_desc, int32_t count, const WorkItem* d_items,
                                const uint32_t* d_bits, const uint32_t* d_scalars,
                                uint32_t* d_counters, float* d_partials, float* d_kscratch, int64_t T,
-                               int tile_t, int mode, bool full, bool adapt, hipStream_t s);
+                               int tile_t, int mode, bool full, bool adapt, int kf, hipStream_t s);
 // Query (and cache) the gather's launch size for the current device ahead of a
 // stream capture.
-void prepare_gather(int tile_t, int mode, bool full, bool adapt);
+void prepare_gather(int tile_t, int mode, bool full, bool adapt, int kf);
 hipError_t launch_reduce_split(const InstDev* d_desc, int32_t count, const uint32_t* d_top,
                                const uint32_t* d_scalars, const float* d_partials, int tile_t,
                                bool kahan, hipStream_t s);

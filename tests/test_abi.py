@@ -201,6 +201,9 @@ def test_set_plan_validation(L):
     (dict(gx=96, gy=80, gt=48, hs=6.0, ht=4.0, flags=8), (0, 0, 0), -5),
     # per-point bandwidths need their own binning
     (dict(gx=96, gy=80, gt=48, hs=6.0, ht=4.0, flags=16), (0, 0, 0), -5),
+    # corner sampling and kernel pairs other than the default: single grids only
+    (dict(gx=96, gy=80, gt=48, hs=6.0, ht=4.0, flags=32), (0, 0, 0), -5),
+    (dict(gx=96, gy=80, gt=48, hs=6.0, ht=4.0, flags=1 << 8), (0, 0, 0), -5),
 ])
 def test_batch_plan_validation(L, plan_kw, off, expect):
     s = _set(L)
@@ -278,3 +281,24 @@ def test_adaptive_entry_points_host_checks(L):
     assert lib.stkde_set_plan(ctypes.byref(d._c()), None, 10, ctypes.byref(hs)) == -1
     fixed.close()
     ad.close()
+
+
+def test_kernel_pair_and_corner_host_checks(L):
+    lib = L.lib()
+    for k in range(4):
+        p = L.Plan(L.Desc(gx=32, gy=32, gt=32, hs=3.0, ht=3.0, flags=L.kernel_flag(k) | L.FLAG_CORNER))
+        p.close()
+    for k in (4, 9, 15):
+        with pytest.raises(L.StkdeError) as e:
+            L.Plan(L.Desc(gx=32, gy=32, gt=32, hs=3.0, ht=3.0, flags=L.kernel_flag(k)))
+        assert e.value.status == L.STKDE_ERR_INVALID_ARG
+    with pytest.raises(L.StkdeError) as e:
+        L.Plan(L.Desc(gx=32, gy=32, gt=32, hs=3.0, ht=3.0, flags=L.kernel_flag(L.KERNEL_QUARTIC) | L.FLAG_ADAPTIVE))
+    assert e.value.status == L.STKDE_ERR_UNSUPPORTED
+    # corner sampling with per-point bandwidths is fine
+    L.Plan(L.Desc(gx=32, gy=32, gt=32, hs=3.0, ht=3.0, flags=L.FLAG_CORNER | L.FLAG_ADAPTIVE)).close()
+    p = L.Plan(L.Desc(gx=32, gy=32, gt=32, hs=3.0, ht=3.0, flags=L.kernel_flag(L.KERNEL_GAUSSIAN)))
+    need = p.workspace_bytes(10)
+    fake = ctypes.c_void_p(0x10000)
+    assert lib.stkde_ablation_compute(p.handle, L.ABLATION_SCATTER, fake, 10, fake, fake, need, None) == -5
+    p.close()
