@@ -183,7 +183,8 @@ __device__ inline bool exact_window(const double* __restrict__ x64, uint32_t ri,
 }
 
 template <int TT, int MODE, bool FULL, bool ADAPT, int KF>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_gather_items(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
+    (MODE == kAccKahanReg || FULL || ADAPT || TT == 64) ? 4 : 6, 8))) void k_gather_items(
     const InstDev* __restrict__ descs, int32_t count, int32_t ntiles_total,
     const WorkItem* __restrict__ items, const uint32_t* __restrict__ bits,
     const uint32_t* __restrict__ sc, uint32_t* __restrict__ ctr, float* __restrict__ partials,
