@@ -65,7 +65,11 @@ namespace {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kCap = 768;  // survivors held in LDS between matrix-core phases
-constexpr uint32_t kFullFlag = 0x10u;      // survivor mask: disc covers the whole tile
+// Survivor mask: bits 0..3 the quadrants its footprint box meets but its disc
+// does not cover (full-cover kernels: covers every column centre, with a
+// margin), bits 4..7 the quadrants it covers; all four covered = the whole
+// tile.
+constexpr uint32_t kCoverAll = 0xF0u;
 constexpr float kFullMargin = 0.99998f;    // largest a + b at a tile corner for that
 constexpr int kMaxDevices = 64;
 // Pairs that are not zero on their support boundary decide membership near it
@@ -216,7 +220,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
     __shared__ uint32_t sI[EXACT ? kCap + 1 : 1];
     // per-wave lists of survivor indices: the quadrant list, then (full-cover
     // path) the wave's share of the full-cover list, each padded to 8
-    __shared__ uint16_t sL[kWaves][kCap + 16];
+    __shared__ uint16_t sL[kWaves][kCap + 24];
     __shared__ int32_t sRB[kMaxRanges];
     __shared__ int32_t sRP[kMaxRanges + 1];
     __shared__ int32_t sWC[kWaves];
@@ -395,6 +399,29 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                     fa[b] = f32x4{0.f, 0.f, 0.f, 0.f};
                     fb[b] = f32x4{0.f, 0.f, 0.f, 0.f};
                 }
+                // quadrant-cover group (a disc covering this wave's quadrant but
+                // not the tile): one instruction per row block, its 16 columns
+                // the quadrant's 8 x-columns (B = a - 1) and 8 y-columns (B = b)
+                f32x4 fq[FULL ? NB : 1];
+#pragma unroll
+                for (int b = 0; b < (FULL ? NB : 1); ++b) fq[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+                const float qx0 = (float)(8 * (wave & 1) + (lane & 7)) + 0.5f;
+                const float qy0 = (float)(8 * (wave >> 1) + (lane & 7)) + 0.5f;
+                const bool qxcol = (lane & 15) < 8;
+                auto group_quad = [&](const float2 cx, const float2 cy, const float2 ctt) {
+                    float av[NB];
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        const float dt = ((rowc + 16.0f * b) - ctt.x) - ctt.y;
+                        av[b] = __builtin_amdgcn_fmed3f(fmaf(-dt * dt, inv_tv2, 1.0f), 0.0f, 1.0f);
+                    }
+                    const float dx = (qx0 - cx.x) - cx.y;
+                    const float dy = (qy0 - cy.x) - cy.y;
+                    const float bq = qxcol ? fmaf(dx * dx, inv_hv2, -1.0f) : dy * dy * inv_hv2;
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+                        fq[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[b], bq, fq[b], 0, 0, 0);
+                };
                 auto group_full = [&](const float2 cx, const float2 cy, const float2 ctt) {
                     float av[NB];
 #pragma unroll
@@ -444,15 +471,22 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                                 qm = (uint32_t)(x0 && y0) | ((uint32_t)(x1 && y0) << 1) |
                                      ((uint32_t)(x0 && y1) << 2) | ((uint32_t)(x1 && y1) << 3);
                                 if (FULL && (D.flags & kInstFull)) {
-                                    // the disc covers every column centre of the tile
-                                    // (its farthest corner with a margin): the
-                                    // spatial kernel is then 1 - a(x) - b(y) on the
-                                    // whole tile, separable in x and y
+                                    // quadrants whose every column centre the disc
+                                    // covers (farthest corner, with a margin): the
+                                    // spatial kernel is 1 - a(x) - b(y) there,
+                                    // separable in x and y
                                     const float px = (r.xh - (float)BX0) + half_lo(r.xl_yl);
                                     const float py = (r.yh - (float)BY0) + half_hi(r.xl_yl);
-                                    const float dxm = fmaxf(fabsf(0.5f - px), fabsf(15.5f - px));
-                                    const float dym = fmaxf(fabsf(0.5f - py), fabsf(15.5f - py));
-                                    if ((dxm * dxm + dym * dym) * inv_hv2 <= kFullMargin) qm = kFullFlag;
+                                    uint32_t qc = 0;
+#pragma unroll
+                                    for (int q = 0; q < 4; ++q) {
+                                        const float xa = 8.0f * (q & 1) + 0.5f, ya = 8.0f * (q >> 1) + 0.5f;
+                                        const float dxm = fmaxf(fabsf(xa - px), fabsf(xa + 7.0f - px));
+                                        const float dym = fmaxf(fabsf(ya - py), fabsf(ya + 7.0f - py));
+                                        if (((qm >> q) & 1u) && (dxm * dxm + dym * dym) * inv_hv2 <= kFullMargin)
+                                            qc |= 1u << q;
+                                    }
+                                    qm = (qm & ~qc) | (qc << 4);
                                 }
                             }
                             surv = qm != 0;
@@ -495,12 +529,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                     if (lane < ((8 - (nw & 7)) & 7)) myL[nw + lane] = (uint16_t)kPad;
                     const int32_t npairs = (nw + 7) >> 3;
                     // full-cover survivors, dealt to the waves in groups of 4 by rank
-                    int32_t nfull = 0, nf = 0;
+                    int32_t nfull = 0, nf = 0, nq = 0;
                     uint16_t* const myF = myL + 8 * npairs;
+                    uint16_t* myQ = myF;
                     if constexpr (FULL) {
                         for (int32_t base = 0; base < count_s; base += 64) {
                             const int32_t s = base + lane;
-                            const bool isf = s < count_s && (sQ[s] & kFullFlag);
+                            const bool isf = s < count_s && sQ[s] == kCoverAll;
                             const unsigned long long fm = __ballot(isf);
                             const int32_t rk = nfull + __popcll(fm & lt);
                             const bool mine = isf && ((rk >> 2) & 3) == wave;
@@ -510,6 +545,20 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                             nfull += __popcll(fm);
                         }
                         if (lane < ((8 - (nf & 7)) & 7)) myF[nf + lane] = (uint16_t)kPad;
+                        // this wave's quadrant-cover survivors
+                        myQ = myF + ((nf + 7) & ~7);
+                        for (int32_t base = 0; base < count_s; base += 64) {
+                            const int32_t s = base + lane;
+                            bool mine = false;
+                            if (s < count_s) {
+                                const uint32_t q = sQ[s];
+                                mine = q != kCoverAll && ((q >> (4 + wave)) & 1u);
+                            }
+                            const unsigned long long bm = __ballot(mine);
+                            if (mine) myQ[nq + __popcll(bm & lt)] = (uint16_t)s;
+                            nq += __popcll(bm);
+                        }
+                        if (lane < ((8 - (nq & 7)) & 7)) myQ[nq + lane] = (uint16_t)kPad;
                     }
 
                     // ---- matrix-core accumulation, two groups per iteration ---------
@@ -552,6 +601,39 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                                 }
                                 group_full(bx, by, bt);
                             }
+                        }
+                        const int32_t nqp = (nq + 7) >> 3;
+                        if (nqp > 0) {
+                            int s = myQ[kq];
+                            float2 ax = sX[s], ay = sY[s], at = sT[s];
+                            for (int32_t pr = 0; pr < nqp; ++pr) {
+                                s = myQ[8 * pr + 4 + kq];
+                                const float2 bx = sX[s], by = sY[s], bt = sT[s];
+                                group_quad(ax, ay, at);
+                                if (pr + 1 < nqp) {
+                                    s = myQ[8 * pr + 8 + kq];
+                                    ax = sX[s];
+                                    ay = sY[s];
+                                    at = sT[s];
+                                }
+                                group_quad(bx, by, bt);
+                            }
+                            // acc -= (sum Kt (a - 1))[T][x] + (sum Kt b)[T][y]: lane
+                            // (k, j) of a column group reads row group k's entries of
+                            // its x column and of its y column
+#pragma unroll
+                            for (int g = 0; g < 4; ++g) {
+                                const int sx = (lane & 48) | (4 * (g & 1) + (lane & 3));
+                                const int sy = (lane & 48) | (8 + 4 * (g >> 1) + ((lane >> 2) & 3));
+#pragma unroll
+                                for (int b = 0; b < NB; ++b) {
+#pragma unroll
+                                    for (int e = 0; e < 4; ++e)
+                                        acc[g * NB + b][e] -= __shfl(fq[b][e], sx, 64) + __shfl(fq[b][e], sy, 64);
+                                }
+                            }
+#pragma unroll
+                            for (int b = 0; b < NB; ++b) fq[b] = f32x4{0.f, 0.f, 0.f, 0.f};
                         }
                         if (nfull > 0) {
                             // add -(sum Kt (a - 1))[T][X] - (sum Kt b)[T][Y] of the
