@@ -220,7 +220,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
     __shared__ uint32_t sI[EXACT ? kCap + 1 : 1];
     // per-wave lists of survivor indices: the quadrant list, then (full-cover
     // path) the wave's share of the full-cover list, each padded to 8
-    __shared__ uint16_t sL[kWaves][kCap + 24];
+    __shared__ uint16_t sL[kWaves][kCap + 8];
+    // full-cover kernels: each wave's share of the tile-cover survivors and its
+    // quadrant-cover survivors (one scan fills all three lists)
+    __shared__ uint16_t sF[FULL ? kWaves : 1][FULL ? kCap / 4 + 8 : 1];
+    __shared__ uint16_t sQL[FULL ? kWaves : 1][FULL ? kCap + 8 : 1];
     __shared__ int32_t sRB[kMaxRanges];
     __shared__ int32_t sRP[kMaxRanges + 1];
     __shared__ int32_t sWC[kWaves];
@@ -477,15 +481,20 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                                     // separable in x and y
                                     const float px = (r.xh - (float)BX0) + half_lo(r.xl_yl);
                                     const float py = (r.yh - (float)BY0) + half_hi(r.xl_yl);
+                                    // farthest column centre per axis and quadrant half
+                                    float ax2[2], ay2[2];
+#pragma unroll
+                                    for (int h = 0; h < 2; ++h) {
+                                        const float ex = fmaxf(fabsf(8.0f * h + 0.5f - px), fabsf(8.0f * h + 7.5f - px));
+                                        const float ey = fmaxf(fabsf(8.0f * h + 0.5f - py), fabsf(8.0f * h + 7.5f - py));
+                                        ax2[h] = ex * ex;
+                                        ay2[h] = ey * ey;
+                                    }
                                     uint32_t qc = 0;
 #pragma unroll
-                                    for (int q = 0; q < 4; ++q) {
-                                        const float xa = 8.0f * (q & 1) + 0.5f, ya = 8.0f * (q >> 1) + 0.5f;
-                                        const float dxm = fmaxf(fabsf(xa - px), fabsf(xa + 7.0f - px));
-                                        const float dym = fmaxf(fabsf(ya - py), fabsf(ya + 7.0f - py));
-                                        if (((qm >> q) & 1u) && (dxm * dxm + dym * dym) * inv_hv2 <= kFullMargin)
+                                    for (int q = 0; q < 4; ++q)
+                                        if (((qm >> q) & 1u) && (ax2[q & 1] + ay2[q >> 1]) * inv_hv2 <= kFullMargin)
                                             qc |= 1u << q;
-                                    }
                                     qm = (qm & ~qc) | (qc << 4);
                                 }
                             }
@@ -516,48 +525,39 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                         __syncthreads();  // sWC is rewritten by the next round
                     }
 
-                    // ---- this wave's list: survivors meeting its quadrant -----------
-                    int32_t nw = 0;
+                    // ---- this wave's lists, in one scan of the survivors: those
+                    // meeting its quadrant; (full-cover kernels) its share of
+                    // those covering the tile, dealt to the waves in groups of 4
+                    // by rank; and those covering its quadrant only --------------
+                    int32_t nw = 0, nfull = 0, nf = 0, nq = 0;
                     for (int32_t base = 0; base < count_s; base += 64) {
                         const int32_t s = base + lane;
-                        const bool mine = s < count_s && ((sQ[s] >> wave) & 1u);
+                        const uint32_t q = s < count_s ? (uint32_t)sQ[s] : 0u;
+                        const bool mine = (q >> wave) & 1u;
                         const unsigned long long bm = __ballot(mine);
                         if (mine) myL[nw + __popcll(bm & lt)] = (uint16_t)s;
                         nw += __popcll(bm);
+                        if constexpr (FULL) {
+                            const bool isf = q == kCoverAll;
+                            const unsigned long long fm = __ballot(isf);
+                            const int32_t rk = nfull + __popcll(fm & lt);
+                            const bool minef = isf && ((rk >> 2) & 3) == wave;
+                            const bool mineq = !isf && ((q >> (4 + wave)) & 1u);
+                            const unsigned long long bf = __ballot(minef), bq = __ballot(mineq);
+                            if (minef) sF[wave][nf + __popcll(bf & lt)] = (uint16_t)s;
+                            if (mineq) sQL[wave][nq + __popcll(bq & lt)] = (uint16_t)s;
+                            nf += __popcll(bf);
+                            nq += __popcll(bq);
+                            nfull += __popcll(fm);
+                        }
                     }
                     // pad to a whole number of pairs of groups
                     if (lane < ((8 - (nw & 7)) & 7)) myL[nw + lane] = (uint16_t)kPad;
                     const int32_t npairs = (nw + 7) >> 3;
-                    // full-cover survivors, dealt to the waves in groups of 4 by rank
-                    int32_t nfull = 0, nf = 0, nq = 0;
-                    uint16_t* const myF = myL + 8 * npairs;
-                    uint16_t* myQ = myF;
+                    uint16_t* const myF = FULL ? sF[wave] : myL;
+                    uint16_t* const myQ = FULL ? sQL[wave] : myL;
                     if constexpr (FULL) {
-                        for (int32_t base = 0; base < count_s; base += 64) {
-                            const int32_t s = base + lane;
-                            const bool isf = s < count_s && sQ[s] == kCoverAll;
-                            const unsigned long long fm = __ballot(isf);
-                            const int32_t rk = nfull + __popcll(fm & lt);
-                            const bool mine = isf && ((rk >> 2) & 3) == wave;
-                            const unsigned long long bm = __ballot(mine);
-                            if (mine) myF[nf + __popcll(bm & lt)] = (uint16_t)s;
-                            nf += __popcll(bm);
-                            nfull += __popcll(fm);
-                        }
                         if (lane < ((8 - (nf & 7)) & 7)) myF[nf + lane] = (uint16_t)kPad;
-                        // this wave's quadrant-cover survivors
-                        myQ = myF + ((nf + 7) & ~7);
-                        for (int32_t base = 0; base < count_s; base += 64) {
-                            const int32_t s = base + lane;
-                            bool mine = false;
-                            if (s < count_s) {
-                                const uint32_t q = sQ[s];
-                                mine = q != kCoverAll && ((q >> (4 + wave)) & 1u);
-                            }
-                            const unsigned long long bm = __ballot(mine);
-                            if (mine) myQ[nq + __popcll(bm & lt)] = (uint16_t)s;
-                            nq += __popcll(bm);
-                        }
                         if (lane < ((8 - (nq & 7)) & 7)) myQ[nq + lane] = (uint16_t)kPad;
                     }
 
