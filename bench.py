@@ -26,6 +26,7 @@ Prints ONE JSON line:
                    workload, on this host's cores
 """
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -44,6 +45,20 @@ WORKLOADS = ("clustered-1M", "clustered-200k-hs50", "uniform-10k", "world-Hr-Hb"
 
 def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _operand_form(inst, tuning, kahan, adaptive, kern):
+    """Matrix-core operands of the gather, by the library's rule: two FP16
+    terms for the Epanechnikov pair with one bandwidth pair, no full-cover
+    path (hs / sres < 14) and 16- or 32-row tiles, unless the tuning asks for
+    FP32."""
+    import math
+    tt = tuning.tile_t if tuning and tuning.tile_t else (32 if math.ceil(inst.ht / inst.tres) <= 12 else 16)
+    if kahan or kern != 0:
+        tt = min(tt, 32)
+    fp32 = (tuning is not None and tuning.operand_form == 1) or adaptive or kern != 0 or tt > 32 \
+        or inst.hs / inst.sres >= 14.0
+    return "fp32" if fp32 else "fp16 hi+lo, fp32 accumulate"
 
 
 def _instance(name):
@@ -450,6 +465,8 @@ def main():
     ap.add_argument("--adaptive", action="store_true",
                     help="per-event bandwidth pairs shrinking with the local event density "
                          "(the workload's hs, ht are the largest)")
+    ap.add_argument("--fp32-operands", action="store_true",
+                    help="FP32 matrix-core operands in the gather (default: two FP16 terms where it has them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--tile-t", type=int, default=0, help="tuning: time rows per tile (16/32)")
@@ -523,6 +540,9 @@ def main():
         tuning, tuning_src = autotune.resolve(desc, n)
     else:
         tuning, tuning_src = None, "default"
+    if args.fp32_operands:
+        tuning = dataclasses.replace(tuning or m.Tuning(), operand_form=1)
+    operands = _operand_form(inst, tuning, kahan, args.adaptive, kern)
     plan = m.Plan(desc, tuning)
     pts = torch.from_numpy(inst.points).to(dev)
     pairs = torch.from_numpy(pairs_np).to(dev) if args.adaptive else None
@@ -611,7 +631,7 @@ def main():
                    for f in ("gather.hip", "pass.hip"))
     # ... and for the workload they were taken on (the default run)
     profiled = (args.workload == "clustered-1M" and kahan and not args.adaptive and kern == 0 and not args.corner
-                and tuning_src.startswith("autotune"))
+                and tuning_src.startswith("autotune") and not args.fp32_operands)
     traffic = _traffic_from_profile(hashlib.sha256(src).hexdigest()) if profiled else None
 
     value = evals / (ms_per_step * 1e-3)
@@ -632,7 +652,7 @@ def main():
                    "hs": inst.hs, "ht": inst.ht, "accumulation": "kahan" if kahan else "plain",
                    "bandwidths": "per-event (density-adaptive)" if args.adaptive else "fixed",
                    "kernel": args.kernel, "sampling": "corner" if args.corner else "centre",
-                   "evals": evals,
+                   "operands": operands, "evals": evals,
                    "tuning": ([tuning.tile_t, tuning.cell_xy, tuning.cell_t, tuning.split_share]
                               if tuning else [0, 0, 0, 0]),
                    "tuning_source": tuning_src},

@@ -118,10 +118,11 @@ typedef struct {
 /* Optional tuning of one plan.  Zero fields mean "library default".
  * tile_t must be 0, 16, 32 or 64 (64 is reduced to 32 under STKDE_FLAG_KAHAN);
  * cell_xy and cell_t in [4, 256]; split_share 0 or in [64, 65536]; kahan_mode
- * 0, 1 or 2.  The plan may enlarge the bins beyond these values when a tile
- * would otherwise read more bin rows than the gather supports.  Tuning
- * changes the summation order, so results differ between tunings in the last
- * bits -- except kahan_mode, whose settings give identical results. */
+ * 0, 1 or 2; operand_form 0 or 1.  The plan may enlarge the bins beyond these
+ * values when a tile would otherwise read more bin rows than the gather
+ * supports.  Tuning changes the summation order, so results differ between
+ * tunings in the last bits -- except kahan_mode, whose settings give
+ * identical results. */
 typedef struct {
     int32_t tile_t;      /* voxel rows in time per output tile (16, 32 or 64) */
     int32_t cell_xy;     /* bin edge in x and y, voxels */
@@ -133,6 +134,13 @@ typedef struct {
                             compensation) pair lives: 1 registers, 2 a per-workgroup
                             scratch slot touched only by tiles that take more
                             than one pass; 0 picks by the expected points per tile */
+    int32_t operand_form; /* matrix-core operands of the gather: 0 (default) two
+                             FP16 terms each (hi + lo, 22 significant bits; the
+                             product as hi*hi + hi*lo + lo*hi with FP32
+                             accumulation) where the gather has that form -- the
+                             Epanechnikov pair, one bandwidth pair, no full-cover
+                             path (hs / sres < 14), 16- or 32-row tiles -- and FP32
+                             elsewhere; 1 FP32 everywhere */
 } stkde_tuning;
 
 typedef struct stkde_plan_s* stkde_plan_t;

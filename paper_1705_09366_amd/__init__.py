@@ -72,7 +72,7 @@ class _Desc(ctypes.Structure):
 class _Tuning(ctypes.Structure):
     _fields_ = [("tile_t", ctypes.c_int32), ("cell_xy", ctypes.c_int32),
                 ("cell_t", ctypes.c_int32), ("split_share", ctypes.c_int32),
-                ("kahan_mode", ctypes.c_int32)]
+                ("kahan_mode", ctypes.c_int32), ("operand_form", ctypes.c_int32)]
 
 
 class _Item(ctypes.Structure):
@@ -171,16 +171,19 @@ class Desc:
 @dataclass(frozen=True)
 class Tuning:
     """Tuning of one plan (0 = library default): time rows per tile, bin
-    edges, the split share of the work list, and where compensated
-    accumulation keeps its running pair (1 registers, 2 memory)."""
+    edges, the split share of the work list, where compensated accumulation
+    keeps its running pair (1 registers, 2 memory), and the matrix-core
+    operands (0 two FP16 terms where the gather has that form, 1 FP32)."""
     tile_t: int = 0
     cell_xy: int = 0
     cell_t: int = 0
     split_share: int = 0
     kahan_mode: int = 0
+    operand_form: int = 0
 
     def _c(self):
-        return _Tuning(self.tile_t, self.cell_xy, self.cell_t, self.split_share, self.kahan_mode)
+        return _Tuning(self.tile_t, self.cell_xy, self.cell_t, self.split_share, self.kahan_mode,
+                       self.operand_form)
 
 
 class Plan:

@@ -21,6 +21,7 @@ struct stkde_plan_s {
     stkde_desc desc;
     uint32_t split_share;
     int32_t kahan_mode;  // 0 automatic, else kAccKahanReg / kAccKahanMem
+    int32_t operand_form;  // 0 two-term FP16 where the gather has it, 1 FP32
     stkde::InstGeom ig;  // the plan's grid as an instance of its own set
     stkde::SetGeom sg;   // binning of the plan's own points
     // gather timing (stkde_plan_profile): event pairs, filled in order
@@ -51,6 +52,7 @@ struct stkde_batch_s {
         bool kahan;
         int mode;  // accumulation mode of the gather (kAcc*)
         bool full; // full-cover path
+        bool h16;  // two-term FP16 operands
         std::vector<int32_t> idx;
         std::vector<stkde::InstGeom> geo;
         stkde::PassLayout pl;
@@ -112,6 +114,7 @@ stkde_status check_tuning(const stkde_tuning* t) {
     if (t->split_share != 0 && (t->split_share < 64 || t->split_share > 65536))
         return STKDE_ERR_INVALID_ARG;
     if (t->kahan_mode < 0 || t->kahan_mode > 2) return STKDE_ERR_INVALID_ARG;
+    if (t->operand_form < 0 || t->operand_form > 1) return STKDE_ERR_INVALID_ARG;
     return STKDE_OK;
 }
 
@@ -243,6 +246,13 @@ float norm_const(double hs, double ht, int64_t n, int kernel = 0) {
 // The gather's full-cover path pays off when discs are large against a tile.
 bool use_full(double hv, int32_t tile_t) { return tile_t <= 32 && hv >= stkde::kFullMinHv; }
 
+// Two-term FP16 matrix-core operands: the gathers of the Epanechnikov pair with
+// one bandwidth pair, no full-cover path and 16- or 32-row tiles have them,
+// unless the plan's tuning asks for FP32 operands.
+bool use_h16(int kf, bool adapt, bool full, int32_t tile_t, int32_t operand_form) {
+    return kf == stkde::kKernelEpan && !adapt && !full && tile_t <= 32 && operand_form == 0;
+}
+
 stkde::InstDev make_dev(const stkde::InstGeom& ig, const stkde::SetGeom& sg, const uint8_t* set_mem,
                         const stkde::SetLayout& sl, int64_t n_norm, int32_t ox, int32_t oy,
                         int32_t ot, float* out, double* stats, bool mass, uint32_t split_share,
@@ -371,6 +381,7 @@ stkde_status stkde_plan(const stkde_desc* d, const stkde_tuning* tun, stkde_plan
     tmp.desc = *d;
     tmp.split_share = tun && tun->split_share ? (uint32_t)tun->split_share : stkde::kBalanceItems;
     tmp.kahan_mode = tun ? tun->kahan_mode : 0;
+    tmp.operand_form = tun ? tun->operand_form : 0;
     make_set_geom(*d, tun ? tun->cell_xy : 0, tun ? tun->cell_t : 0, tile_t, &tmp.sg);
     st = make_inst_geom(*d, *d, tile_t, &tmp.ig);
     if (st != STKDE_OK) return st;
@@ -469,8 +480,10 @@ stkde_status stkde_accumulate(stkde_plan_t p, int64_t n, float* d_out, void* d_w
                         p->ig.tile_t);
     if (kf != stkde::kKernelEpan && mode == stkde::kAccKahanReg) mode = stkde::kAccKahanMem;  // same bits
     const bool full = !adapt && kf == stkde::kKernelEpan && use_full(p->ig.hv, p->ig.tile_t);
-    if (stkde::launch_pass(&d, 1, c.ws + c.L.shared, c.L.pl, p->ig.tile_t, mode, full, adapt, kf, c.s, e0,
-                           e1) != hipSuccess)
+    const bool h16 = use_h16(kf, adapt, full, p->ig.tile_t, p->operand_form);
+    if (h16 && mode == stkde::kAccKahanReg) mode = stkde::kAccKahanMem;
+    if (stkde::launch_pass(&d, 1, c.ws + c.L.shared, c.L.pl, p->ig.tile_t, mode, full, adapt, kf, h16, c.s,
+                           e0, e1) != hipSuccess)
         return STKDE_ERR_HIP;
     return STKDE_OK;
 }
@@ -598,34 +611,41 @@ stkde_status stkde_batch_plan(const stkde_item* items, int32_t count, stkde_batc
                                    it.set->n, it.set->base, geo[(size_t)i].Hs, geo[(size_t)i].Ht,
                                    geo[(size_t)i].tile_t);
     }
-    // one pass per (tile rows, plain or compensated); the pass takes the
-    // register form of Kahan if any of its grids expects dense tiles (both
-    // forms give the same bits) and the kernel with the full-cover path if
-    // any of its grids uses it (the path is switched per grid)
+    // one pass per (tile rows, plain or compensated, operand form); an FP32
+    // pass takes the register form of Kahan if any of its grids expects dense
+    // tiles (both forms give the same bits) and the kernel with the
+    // full-cover path if any of its grids uses it (the path is switched per
+    // grid); a grid takes the same kernel as alone
     const int tts[3] = {16, 32, 64};
     for (int kahan = 0; kahan < 2; ++kahan) {
         for (int tt : tts) {
-            stkde_batch_s::Group g;
-            g.tile_t = tt;
-            g.kahan = kahan != 0;
-            g.mode = g.kahan ? stkde::kAccKahanMem : stkde::kAccPlain;
-            g.full = false;
-            for (int32_t i = 0; i < count; ++i) {
-                if ((mode[(size_t)i] != stkde::kAccPlain) == g.kahan && geo[(size_t)i].tile_t == tt) {
-                    g.idx.push_back(i);
-                    g.geo.push_back(geo[(size_t)i]);
-                    if (mode[(size_t)i] == stkde::kAccKahanReg) g.mode = stkde::kAccKahanReg;
-                    if (use_full(geo[(size_t)i].hv, tt)) g.full = true;
+            for (int h16 = 0; h16 < 2; ++h16) {
+                stkde_batch_s::Group g;
+                g.tile_t = tt;
+                g.kahan = kahan != 0;
+                g.h16 = h16 != 0;
+                g.mode = g.kahan ? stkde::kAccKahanMem : stkde::kAccPlain;
+                g.full = false;
+                for (int32_t i = 0; i < count; ++i) {
+                    const bool fi = use_full(geo[(size_t)i].hv, tt);
+                    const bool hi = use_h16(stkde::kKernelEpan, false, fi, tt, items[i].plan->operand_form);
+                    if ((mode[(size_t)i] != stkde::kAccPlain) == g.kahan && geo[(size_t)i].tile_t == tt &&
+                        hi == g.h16) {
+                        g.idx.push_back(i);
+                        g.geo.push_back(geo[(size_t)i]);
+                        if (mode[(size_t)i] == stkde::kAccKahanReg && !g.h16) g.mode = stkde::kAccKahanReg;
+                        if (fi) g.full = true;
+                    }
                 }
+                if (g.idx.empty()) continue;
+                g.pl = stkde::layout_pass(g.geo.data(), (int32_t)g.geo.size(), tt, g.kahan);
+                if (g.pl.T > 0x7fffffffLL) {
+                    delete bt;
+                    return STKDE_ERR_TOO_LARGE;
+                }
+                bt->ws_bytes = std::max(bt->ws_bytes, g.pl.total);
+                bt->groups.push_back(std::move(g));
             }
-            if (g.idx.empty()) continue;
-            g.pl = stkde::layout_pass(g.geo.data(), (int32_t)g.geo.size(), tt, g.kahan);
-            if (g.pl.T > 0x7fffffffLL) {
-                delete bt;
-                return STKDE_ERR_TOO_LARGE;
-            }
-            bt->ws_bytes = std::max(bt->ws_bytes, g.pl.total);
-            bt->groups.push_back(std::move(g));
         }
     }
     *out = bt;
@@ -653,7 +673,7 @@ stkde_status batch_enqueue(stkde_batch_t b, uint8_t* ws, hipStream_t s) {
                                     it.plan->split_share));
         }
         if (stkde::launch_pass(devs.data(), (int32_t)devs.size(), ws, g.pl, g.tile_t, g.mode, g.full, false,
-                               stkde::kKernelEpan, s) != hipSuccess)
+                               stkde::kKernelEpan, g.h16, s) != hipSuccess)
             return STKDE_ERR_HIP;
     }
     return STKDE_OK;
@@ -670,7 +690,8 @@ stkde_status stkde_batch_run(stkde_batch_t b, void* d_ws, size_t ws_bytes, void*
 stkde_status stkde_batch_capture(stkde_batch_t b, void* d_ws, size_t ws_bytes) {
     if (!b) return STKDE_ERR_INVALID_ARG;
     if (!d_ws || ws_bytes < b->ws_bytes || ((uintptr_t)d_ws & 255u)) return STKDE_ERR_WORKSPACE;
-    for (const auto& g : b->groups) stkde::prepare_gather(g.tile_t, g.mode, g.full, false, stkde::kKernelEpan);
+    for (const auto& g : b->groups)
+        stkde::prepare_gather(g.tile_t, g.mode, g.full, false, stkde::kKernelEpan, g.h16);
     hipStream_t cs = nullptr;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return STKDE_ERR_HIP;
     hipGraph_t graph = nullptr;

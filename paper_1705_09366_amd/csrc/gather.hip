@@ -55,6 +55,22 @@
 // With compensated accumulation each matrix-core phase (up to kCap points)
 // accumulates into a fresh pass accumulator that is then added into
 // (sum, compensation) by Kahan's rule; within a pass the sum is plain FP32.
+//
+// Two-term FP16 operands (variant H16: the Epanechnikov pair, one bandwidth
+// pair, no full-cover path, 16- or 32-row tiles).  The FP32 operands above
+// are built the same way, then each is written as hi + lo with hi its FP16
+// truncation and lo the FP16 truncation of the exact remainder, and the
+// product as hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_f16 (32 points per
+// instruction, FP32 accumulation) -- the splitting scheme of Markidis et al.
+// (2018) and Ootomo and Yokota (2022) for FP32 products on half-precision
+// matrix units.  Each operand keeps 22 significant bits (truncation error
+// below 2^-21 of its value; below 2^-24 absolute where lo falls in FP16's
+// subnormal range, which the matrix cores honour), the dropped lo*lo term is
+// below 2^-20 of the product, so a product is low by less than 2^-19 of
+// itself, and all products are non-negative, so every voxel's sum is too,
+// beyond its FP32 accumulation error.  The three instructions cost 3/16 of
+// the FP32 form's matrix-core time per point; operand construction (VALU)
+// bounds the loop instead.
 #include <atomic>
 
 #include "stkde_internal.h"
@@ -64,7 +80,11 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kCap = 768;  // survivors held in LDS between matrix-core phases
+// survivors held in LDS between matrix-core phases: FP32-operand kernels, and
+// two-term FP16 kernels (at most four workgroups per compute unit, as their
+// registers allow; fewer phases, so fewer Kahan folds and scratch round trips)
+constexpr int kCapF32 = 768;
+constexpr int kCapH16 = 1152;
 // Survivor mask: bits 0..3 the quadrants its footprint box meets but its disc
 // does not cover (full-cover kernels: covers every column centre, with a
 // margin), bits 4..7 the quadrants it covers; all four covered = the whole
@@ -84,6 +104,26 @@ __device__ inline float half_lo(uint32_t v) {
 __device__ inline float half_hi(uint32_t v) {
     return (float)__builtin_bit_cast(_Float16, (uint16_t)(v >> 16));
 }
+
+typedef _Float16 h16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// x = hi + lo + e and y likewise, hi and lo packed FP16 pairs (x in the low
+// halves): hi truncates x to FP16, lo truncates the remainder x - hi, which
+// is exact in FP32.  The remainder is one mixed-precision FMA per value,
+// -hi * 1 + x with hi read as FP16 (the compiler does not select it here).
+__device__ inline void split_pair(float x, float y, uint32_t& hi, uint32_t& lo) {
+    hi = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(x, y));
+    float rx, ry;
+    asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(rx) : "v"(hi), "v"(x));
+    asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(ry) : "v"(hi), "v"(y));
+    lo = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(rx, ry));
+}
+
+// Position of list entry p in a two-term FP16 kernel's wave list: within each
+// group of 32, element j of lane group k (k = lane / 16) is entry 4 j + k, and
+// lane group k reads its 8 elements as one 16-byte word.
+__device__ inline int32_t h16_slot(int32_t p) { return (p & ~31) | ((p & 3) << 3) | ((p & 31) >> 2); }
 
 // Matrix-core operands of each kernel pair, without its constant factors
 // (applied at the store).  e = 1 - u^2 - v^2 for the (point, column), so the
@@ -186,15 +226,20 @@ __device__ inline bool exact_window(const double* __restrict__ x64, uint32_t ri,
     return fabs(__dadd_rn((double)T + 0.5, -x64[3 * (size_t)ri + 2])) <= tv;
 }
 
-template <int TT, int MODE, bool FULL, bool ADAPT, int KF>
+// H16: two-term FP16 operands (see the header).
+template <int TT, int MODE, bool FULL, bool ADAPT, int KF, bool H16>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
-    (MODE == kAccKahanReg || FULL || ADAPT || TT == 64) ? 4 : 6, 8))) void k_gather_items(
+    (MODE == kAccKahanReg || FULL || ADAPT || TT == 64 || H16) ? 4 : 6, 8))) void k_gather_items(
     const InstDev* __restrict__ descs, int32_t count, int32_t ntiles_total,
     const WorkItem* __restrict__ items, const uint32_t* __restrict__ bits,
     const uint32_t* __restrict__ sc, uint32_t* __restrict__ ctr, float* __restrict__ partials,
     float* __restrict__ kscratch) {
     static_assert(!(FULL && ADAPT), "the full-cover path assumes one bandwidth pair");
     static_assert(KF == kKernelEpan || (!FULL && !ADAPT), "other pairs: no full-cover path, one pair");
+    static_assert(!H16 || (KF == kKernelEpan && !FULL && !ADAPT && TT <= 32 && MODE != kAccKahanReg),
+                  "two-term FP16 operands: Epanechnikov, one pair, no full-cover path, 16/32 rows");
+    constexpr int kCap = H16 ? kCapH16 : kCapF32;
+    constexpr int kLPad = H16 ? 32 : 8;  // wave lists are padded to this many entries
     constexpr int NB = TT / 16;  // 16-row blocks per tile
     constexpr int CG = 4 * NB;   // accumulator blocks per wave
     constexpr bool EXACT = KF == kKernelGauss || KF == kKernelPrinted;
@@ -218,9 +263,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
     __shared__ float4 sB[ADAPT ? kCap + 1 : 1];
     // record index of each survivor (pairs with exact support tests only)
     __shared__ uint32_t sI[EXACT ? kCap + 1 : 1];
-    // per-wave lists of survivor indices: the quadrant list, then (full-cover
-    // path) the wave's share of the full-cover list, each padded to 8
-    __shared__ uint16_t sL[kWaves][kCap + 8];
+    // per-wave lists of survivor indices meeting the wave's quadrant, padded to
+    // kLPad (two-term FP16 kernels: in h16_slot order)
+    __shared__ __align__(16) uint16_t sL[kWaves][kCap + kLPad];
     // full-cover kernels: each wave's share of the tile-cover survivors and its
     // quadrant-cover survivors (one scan fills all three lists)
     __shared__ uint16_t sF[FULL ? kWaves : 1][FULL ? kCap / 4 + 8 : 1];
@@ -444,6 +489,76 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                     }
                 };
 
+                // two-term FP16 group of 32 list entries from `base`, nv of them valid:
+                // lane group k = lane / 16 supplies points 4 j + k (j = 0..7) as the
+                // eight elements of its operands; pairs of elements holding only
+                // padding in every lane group are zero without being computed
+                auto group16 = [&](const int32_t base, const int32_t nv) {
+                    const int32_t npv = (nv + 7) >> 3;
+                    u32x4 ah[NB], al[NB], bh[4], bl[4];
+                    const uint4 ix = *reinterpret_cast<const uint4*>(myL + base + 8 * kq);
+                    const uint32_t ixa[4] = {ix.x, ix.y, ix.z, ix.w};
+#pragma unroll
+                    for (int jp = 0; jp < 4; ++jp) {
+                        if (jp > 0 && jp >= npv) {
+#pragma unroll
+                            for (int b = 0; b < NB; ++b) ah[b][jp] = al[b][jp] = 0u;
+#pragma unroll
+                            for (int g = 0; g < 4; ++g) bh[g][jp] = bl[g][jp] = 0u;
+                            continue;
+                        }
+                        float kt[2][NB], ks[2][4];
+#pragma unroll
+                        for (int jj = 0; jj < 2; ++jj) {
+                            const int s = jj == 0 ? (int)(ixa[jp] & 0xffffu) : (int)(ixa[jp] >> 16);
+                            const float2 cx = sX[s], cy = sY[s], ct = sT[s];
+#pragma unroll
+                            for (int b = 0; b < NB; ++b) {
+                                const float dt = ((rowc + 16.0f * b) - ct.x) - ct.y;
+                                kt[jj][b] = kt_operand<kKernelEpan>(dt, inv_tv2, inv_tv);
+                            }
+                            float ux[2], uy[2];
+#pragma unroll
+                            for (int h = 0; h < 2; ++h) {
+                                const float dx = ((xc0 + 4.0f * h) - cx.x) - cx.y;
+                                const float dy = ((yc0 + 4.0f * h) - cy.x) - cy.y;
+                                ux[h] = fmaf(-dx * dx, inv_hv2, 1.0f);
+                                uy[h] = dy * dy * inv_hv2;
+                            }
+#pragma unroll
+                            for (int g = 0; g < 4; ++g)
+                                ks[jj][g] = ks_operand<kKernelEpan>(ux[g & 1] - uy[g >> 1], 1.0f, 1.0f);
+                        }
+#pragma unroll
+                        for (int b = 0; b < NB; ++b) {
+                            uint32_t h, l;
+                            split_pair(kt[0][b], kt[1][b], h, l);
+                            ah[b][jp] = h;
+                            al[b][jp] = l;
+                        }
+#pragma unroll
+                        for (int g = 0; g < 4; ++g) {
+                            uint32_t h, l;
+                            split_pair(ks[0][g], ks[1][g], h, l);
+                            bh[g][jp] = h;
+                            bl[g][jp] = l;
+                        }
+                    }
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+#pragma unroll
+                        for (int b = 0; b < NB; ++b) {
+                            const h16x8 Ah = __builtin_bit_cast(h16x8, ah[b]), Al = __builtin_bit_cast(h16x8, al[b]);
+                            const h16x8 Bh = __builtin_bit_cast(h16x8, bh[g]), Bl = __builtin_bit_cast(h16x8, bl[g]);
+                            f32x4 a = acc[g * NB + b];
+                            a = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ah, Bh, a, 0, 0, 0);
+                            a = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ah, Bl, a, 0, 0, 0);
+                            a = __builtin_amdgcn_mfma_f32_16x16x32_f16(Al, Bh, a, 0, 0, 0);
+                            acc[g * NB + b] = a;
+                        }
+                    }
+                };
+
                 int32_t bb = (int32_t)min(it.cbeg, (uint32_t)cend);
                 while (bb < cend) {
                     // ---- stage: fill the survivor list ------------------------------
@@ -535,7 +650,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                         const uint32_t q = s < count_s ? (uint32_t)sQ[s] : 0u;
                         const bool mine = (q >> wave) & 1u;
                         const unsigned long long bm = __ballot(mine);
-                        if (mine) myL[nw + __popcll(bm & lt)] = (uint16_t)s;
+                        if (mine) {
+                            const int32_t p = nw + __popcll(bm & lt);
+                            myL[H16 ? h16_slot(p) : p] = (uint16_t)s;
+                        }
                         nw += __popcll(bm);
                         if constexpr (FULL) {
                             const bool isf = q == kCoverAll;
@@ -551,9 +669,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                             nfull += __popcll(fm);
                         }
                     }
-                    // pad to a whole number of pairs of groups
-                    if (lane < ((8 - (nw & 7)) & 7)) myL[nw + lane] = (uint16_t)kPad;
-                    const int32_t npairs = (nw + 7) >> 3;
+                    // pad to a whole number of pairs of groups (FP32 operands) or of
+                    // 32-point groups (two-term FP16)
+                    if (lane < ((kLPad - (nw & (kLPad - 1))) & (kLPad - 1))) {
+                        const int32_t p = nw + lane;
+                        myL[H16 ? h16_slot(p) : p] = (uint16_t)kPad;
+                    }
+                    const int32_t npairs = H16 ? 0 : (nw + 7) >> 3;
+                    if constexpr (H16) {
+                        for (int32_t base = 0; base < nw; base += 32) group16(base, min(32, nw - base));
+                    }
                     uint16_t* const myF = FULL ? sF[wave] : myL;
                     uint16_t* const myQ = FULL ? sQL[wave] : myL;
                     if constexpr (FULL) {
@@ -849,7 +974,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce_split(const InstDev* __rest
 // Workgroups of the persistent gather: compute units x resident workgroups
 // per compute unit, cached per device (memory-mode Kahan at most
 // kMemKahanGroups, the slots of its scratch).
-template <int TT, int MODE, bool FULL, bool ADAPT, int KF>
+template <int TT, int MODE, bool FULL, bool ADAPT, int KF, bool H16>
 int resident_groups() {
     static_assert(!FULL || TT <= 32, "the full-cover sums of 64-row tiles do not fit the survivor LDS");
     static std::atomic<int> cache[kMaxDevices];
@@ -859,7 +984,7 @@ int resident_groups() {
     if (v > 0) return v;
     int ncu = 0, occ = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_gather_items<TT, MODE, FULL, ADAPT, KF>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_gather_items<TT, MODE, FULL, ADAPT, KF, H16>,
                                                      kThreads, 0) != hipSuccess)
         occ = 0;
     v = (ncu > 0 ? ncu : 256) * (occ > 0 ? occ : 1);
@@ -868,30 +993,37 @@ int resident_groups() {
     return v;
 }
 
-template <int TT, int MODE, bool FULL, bool ADAPT, int KF>
+template <int TT, int MODE, bool FULL, bool ADAPT, int KF, bool H16>
 void launch_items_t(const InstDev* d, int32_t count, const WorkItem* items, const uint32_t* bits,
                     const uint32_t* sc, uint32_t* ctr, float* partials, float* kscratch, int64_t T,
                     hipStream_t s) {
-    int64_t g = resident_groups<TT, MODE, FULL, ADAPT, KF>();
+    int64_t g = resident_groups<TT, MODE, FULL, ADAPT, KF, H16>();
     const int64_t most = T + kPartSlots;  // items never exceed tiles + partial slots
     if (g > most) g = most;
     if (g < 1) g = 1;
-    hipLaunchKernelGGL((k_gather_items<TT, MODE, FULL, ADAPT, KF>), dim3((uint32_t)g), dim3(kThreads), 0,
+    hipLaunchKernelGGL((k_gather_items<TT, MODE, FULL, ADAPT, KF, H16>), dim3((uint32_t)g), dim3(kThreads), 0,
                        s, d, count, (int32_t)T, items, bits, sc, ctr, partials, kscratch);
 }
 
-// f.template operator()<TT, MODE, FULL, ADAPT, KF>() for one (tile rows,
-// mode) of the Epanechnikov pair: per-point bandwidths never take the
-// full-cover path, nor do 64-row tiles.
+// f.template operator()<TT, MODE, FULL, ADAPT, KF, H16>() for one (tile
+// rows, mode) of the Epanechnikov pair: per-point bandwidths never take the
+// full-cover path, nor do 64-row tiles; two-term FP16 operands are the
+// kernels without either of them, 16 or 32 rows, plain or scratch-form
+// Kahan (the caller maps the register form to the scratch form).
 template <int TT, int MODE, typename F>
-void dispatch_variant(bool full, bool adapt, F& f) {
+void dispatch_variant(bool full, bool adapt, bool h16, F& f) {
     if (adapt) {
-        f.template operator()<TT, MODE, false, true, kKernelEpan>();
+        f.template operator()<TT, MODE, false, true, kKernelEpan, false>();
     } else if constexpr (TT <= 32) {
-        if (full) f.template operator()<TT, MODE, true, false, kKernelEpan>();
-        else f.template operator()<TT, MODE, false, false, kKernelEpan>();
+        if (full) f.template operator()<TT, MODE, true, false, kKernelEpan, false>();
+        else if constexpr (MODE != kAccKahanReg) {
+            if (h16) f.template operator()<TT, MODE, false, false, kKernelEpan, true>();
+            else f.template operator()<TT, MODE, false, false, kKernelEpan, false>();
+        } else {
+            f.template operator()<TT, MODE, false, false, kKernelEpan, false>();
+        }
     } else {
-        f.template operator()<TT, MODE, false, false, kKernelEpan>();
+        f.template operator()<TT, MODE, false, false, kKernelEpan, false>();
     }
 }
 
@@ -901,31 +1033,31 @@ template <int KF, typename F>
 void dispatch_pair(int tile_t, int mode, F& f) {
     const bool kahan = mode != kAccPlain;
     if (tile_t == 16) {
-        kahan ? f.template operator()<16, kAccKahanMem, false, false, KF>()
-              : f.template operator()<16, kAccPlain, false, false, KF>();
+        kahan ? f.template operator()<16, kAccKahanMem, false, false, KF, false>()
+              : f.template operator()<16, kAccPlain, false, false, KF, false>();
     } else {
-        kahan ? f.template operator()<32, kAccKahanMem, false, false, KF>()
-              : f.template operator()<32, kAccPlain, false, false, KF>();
+        kahan ? f.template operator()<32, kAccKahanMem, false, false, KF, false>()
+              : f.template operator()<32, kAccPlain, false, false, KF, false>();
     }
 }
 
-// The kernel variant of (tile_t, mode, full, adapt, kernel pair); 64-row
-// tiles are plain.
+// The kernel variant of (tile_t, mode, full, adapt, kernel pair, operand
+// form); 64-row tiles are plain.
 template <typename F>
-void dispatch(int tile_t, int mode, bool full, bool adapt, int kf, F&& f) {
+void dispatch(int tile_t, int mode, bool full, bool adapt, int kf, bool h16, F&& f) {
     if (kf == kKernelQuartic) return dispatch_pair<kKernelQuartic>(tile_t, mode, f);
     if (kf == kKernelGauss) return dispatch_pair<kKernelGauss>(tile_t, mode, f);
     if (kf == kKernelPrinted) return dispatch_pair<kKernelPrinted>(tile_t, mode, f);
     if (tile_t == 16) {
-        if (mode == kAccKahanReg) dispatch_variant<16, kAccKahanReg>(full, adapt, f);
-        else if (mode == kAccKahanMem) dispatch_variant<16, kAccKahanMem>(full, adapt, f);
-        else dispatch_variant<16, kAccPlain>(full, adapt, f);
+        if (mode == kAccKahanReg) dispatch_variant<16, kAccKahanReg>(full, adapt, h16, f);
+        else if (mode == kAccKahanMem) dispatch_variant<16, kAccKahanMem>(full, adapt, h16, f);
+        else dispatch_variant<16, kAccPlain>(full, adapt, h16, f);
     } else if (tile_t == 32) {
-        if (mode == kAccKahanReg) dispatch_variant<32, kAccKahanReg>(full, adapt, f);
-        else if (mode == kAccKahanMem) dispatch_variant<32, kAccKahanMem>(full, adapt, f);
-        else dispatch_variant<32, kAccPlain>(full, adapt, f);
+        if (mode == kAccKahanReg) dispatch_variant<32, kAccKahanReg>(full, adapt, h16, f);
+        else if (mode == kAccKahanMem) dispatch_variant<32, kAccKahanMem>(full, adapt, h16, f);
+        else dispatch_variant<32, kAccPlain>(full, adapt, h16, f);
     } else {
-        dispatch_variant<64, kAccPlain>(full, adapt, f);
+        dispatch_variant<64, kAccPlain>(full, adapt, h16, f);
     }
 }
 
@@ -941,17 +1073,18 @@ void launch_reduce_t(const InstDev* d, int32_t count, const uint32_t* top, const
 hipError_t launch_gather_items(const InstDev* d_desc, int32_t count, const WorkItem* d_items,
                                const uint32_t* d_bits, const uint32_t* d_scalars,
                                uint32_t* d_counters, float* d_partials, float* d_kscratch, int64_t T,
-                               int tile_t, int mode, bool full, bool adapt, int kf, hipStream_t s) {
-    dispatch(tile_t, mode, full, adapt, kf, [&]<int TT, int M, bool F, bool A, int K>() {
-        launch_items_t<TT, M, F, A, K>(d_desc, count, d_items, d_bits, d_scalars, d_counters, d_partials,
-                                       d_kscratch, T, s);
+                               int tile_t, int mode, bool full, bool adapt, int kf, bool h16,
+                               hipStream_t s) {
+    dispatch(tile_t, mode, full, adapt, kf, h16, [&]<int TT, int M, bool F, bool A, int K, bool H>() {
+        launch_items_t<TT, M, F, A, K, H>(d_desc, count, d_items, d_bits, d_scalars, d_counters, d_partials,
+                                          d_kscratch, T, s);
     });
     return hipGetLastError();
 }
 
-void prepare_gather(int tile_t, int mode, bool full, bool adapt, int kf) {
-    dispatch(tile_t, mode, full, adapt, kf,
-             []<int TT, int M, bool F, bool A, int K>() { (void)resident_groups<TT, M, F, A, K>(); });
+void prepare_gather(int tile_t, int mode, bool full, bool adapt, int kf, bool h16) {
+    dispatch(tile_t, mode, full, adapt, kf, h16,
+             []<int TT, int M, bool F, bool A, int K, bool H>() { (void)resident_groups<TT, M, F, A, K, H>(); });
 }
 
 hipError_t launch_reduce_split(const InstDev* d_desc, int32_t count, const uint32_t* d_top,

@@ -365,7 +365,7 @@ PassLayout layout_pass(const InstGeom* inst, int32_t count, int tile_t, bool kah
 }
 
 hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassLayout& pl,
-                       int tile_t, int mode, bool full, bool adapt, int kf, hipStream_t s,
+                       int tile_t, int mode, bool full, bool adapt, int kf, bool h16, hipStream_t s,
                        hipEvent_t ev_before, hipEvent_t ev_after) {
     const bool kahan = mode != kAccPlain;
     InstDev* d_desc = reinterpret_cast<InstDev*>(pass + pl.desc);
@@ -408,7 +408,7 @@ hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassL
     if (e != hipSuccess) return e;
     if (ev_before && (e = hipEventRecord(ev_before, s)) != hipSuccess) return e;
     e = launch_gather_items(d_desc, count, items, bits, sc, ctr, partials, kscratch, pl.T, tile_t, mode,
-                            full, adapt, kf, s);
+                            full, adapt, kf, h16, s);
     if (e != hipSuccess) return e;
     if (ev_after && (e = hipEventRecord(ev_after, s)) != hipSuccess) return e;
     e = launch_reduce_split(d_desc, count, top, sc, partials, tile_t, kahan, s);

@@ -278,18 +278,21 @@ hipError_t launch_bin(const SetGeom& g, const double* d_xyt, int32_t n, uint8_t*
 // right after the gather kernel.
 // full: use the gather's full-cover path (tile_t <= 32); adapt: the
 // instances' sets carry per-point bandwidths (never with full); kf: the
-// kernel pair (other than Epanechnikov: neither full nor adapt, tile_t <= 32).
+// kernel pair (other than Epanechnikov: neither full nor adapt, tile_t <= 32);
+// h16: two-term FP16 matrix-core operands (Epanechnikov, neither full nor
+// adapt, tile_t <= 32, mode not kAccKahanReg; ignored elsewhere).
 hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassLayout& pl,
-                       int tile_t, int mode, bool full, bool adapt, int kf, hipStream_t s,
+                       int tile_t, int mode, bool full, bool adapt, int kf, bool h16, hipStream_t s,
                        hipEvent_t ev_before = nullptr, hipEvent_t ev_after = nullptr);
 // The gather proper (called by launch_pass).
 hipError_t launch_gather_items(const InstDev* d_desc, int32_t count, const WorkItem* d_items,
                                const uint32_t* d_bits, const uint32_t* d_scalars,
                                uint32_t* d_counters, float* d_partials, float* d_kscratch, int64_t T,
-                               int tile_t, int mode, bool full, bool adapt, int kf, hipStream_t s);
+                               int tile_t, int mode, bool full, bool adapt, int kf, bool h16,
+                               hipStream_t s);
 // Query (and cache) the gather's launch size for the current device ahead of a
 // stream capture.
-void prepare_gather(int tile_t, int mode, bool full, bool adapt, int kf);
+void prepare_gather(int tile_t, int mode, bool full, bool adapt, int kf, bool h16);
 hipError_t launch_reduce_split(const InstDev* d_desc, int32_t count, const uint32_t* d_top,
                                const uint32_t* d_scalars, const float* d_partials, int tile_t,
                                bool kahan, hipStream_t s);

@@ -69,12 +69,14 @@ def test_tuning_validation(L):
     d = L.Desc(gx=16, gy=16, gt=16, hs=2.0, ht=2.0)
     for bad in (L.Tuning(tile_t=8), L.Tuning(cell_xy=2), L.Tuning(cell_t=2), L.Tuning(cell_xy=512),
                 L.Tuning(split_share=63), L.Tuning(split_share=65537), L.Tuning(split_share=-1),
-                L.Tuning(kahan_mode=3), L.Tuning(kahan_mode=-1)):
+                L.Tuning(kahan_mode=3), L.Tuning(kahan_mode=-1), L.Tuning(operand_form=2),
+                L.Tuning(operand_form=-1)):
         with pytest.raises(L.StkdeError):
             L.Plan(d, bad)
     L.Plan(d, L.Tuning(tile_t=16, cell_xy=32, cell_t=8)).close()
     L.Plan(d, L.Tuning(split_share=64)).close()
     L.Plan(d, L.Tuning(kahan_mode=2)).close()
+    L.Plan(d, L.Tuning(operand_form=1)).close()
     L.Plan(d, L.Tuning(split_share=65536)).close()
 
 

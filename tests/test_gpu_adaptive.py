@@ -98,10 +98,12 @@ def test_equal_pairs_are_the_fixed_path_bitwise(torch_cuda, flags, tile_t):
     import paper_1705_09366_amd as m
     pts, g = workloads.small_random_case(77, max_g=90, max_n=600)
     g.update(gx=83, gy=57, gt=45)
-    tun = m.Tuning(tile_t=tile_t)
+    # per-point bandwidths take FP32 operands: compare with the fixed path's
+    # FP32 form
+    tun = m.Tuning(tile_t=tile_t, operand_form=1)
     pairs = np.tile([g["hs"], g["ht"]], (len(pts), 1))
     _say(f"equal pairs flags={flags} tile_t={tile_t}")
-    a, _ = _run(torch_cuda, pts, pairs, g, flags=flags, tuning=tun)
+    a, _ = _run(torch_cuda, pts, pairs, g, flags=flags, tuning=m.Tuning(tile_t=tile_t))
     plan = m.Plan(_desc(g, flags), tun)
     b = plan(torch_cuda.from_numpy(pts).cuda()).cpu().numpy()
     plan.close()

@@ -252,11 +252,14 @@ def test_radix_digit_widths(torch_cuda, grid, cells):
     assert st[0] == pytest.approx(st[1], rel=1e-6)
 
 
+@pytest.mark.parametrize("operand_form", [0, 1])
 @pytest.mark.parametrize("split_share", [0, 65536])
-def test_kahan_modes_identical(torch_cuda, split_share):
+def test_kahan_modes_identical(torch_cuda, split_share, operand_form):
     """Compensated accumulation with its running pair in registers or in the
     per-workgroup scratch slot performs the same operations: identical bits,
-    also for tiles that take many passes (a dense pile) and for split parts."""
+    also for tiles that take many passes (a dense pile) and for split parts
+    (FP32 operands; two-term FP16 operands have the scratch form only, which
+    a register-form request selects)."""
     import paper_1705_09366_amd as m
     rng = np.random.default_rng(41)
     g = dict(gx=48, gy=48, gt=40, hs=6.0, ht=5.0)
@@ -265,9 +268,10 @@ def test_kahan_modes_identical(torch_cuda, split_share):
     res = []
     for mode in (1, 2):
         for tt in (16, 32):
-            _say(f"kahan mode {mode} tile_t {tt} split_share {split_share}")
+            _say(f"kahan mode {mode} tile_t {tt} split_share {split_share} operand_form {operand_form}")
             out, st = _run(torch_cuda, pts, g, flags=1 | 4,
-                           tuning=m.Tuning(tile_t=tt, split_share=split_share, kahan_mode=mode))
+                           tuning=m.Tuning(tile_t=tt, split_share=split_share, kahan_mode=mode,
+                                           operand_form=operand_form))
             res.append((mode, tt, out, st))
     ref, _ = oracle.pbsym(pts, _grid(g))
     for mode, tt, out, st in res:
