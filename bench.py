@@ -537,7 +537,7 @@ def main():
         tuning, tuning_src = m.Tuning(args.tile_t, args.cell_xy, args.cell_t), "manual"
     elif args.tuning == "auto":
         from paper_1705_09366_amd import autotune
-        tuning, tuning_src = autotune.resolve(desc, n)
+        tuning, tuning_src = autotune.resolve(desc, n, fp32=args.fp32_operands)
     else:
         tuning, tuning_src = None, "default"
     if args.fp32_operands:

@@ -11,9 +11,11 @@ strategy for an instance from its shape; this is the measured form of that
 choice for the one strategy implemented here.  Entries are keyed by the
 device architecture, the bandwidths in voxels (power-of-two buckets of
 hs/sres and ht/tres), a density class (mean number of points whose cylinder
-covers a voxel, in powers of 4), a grid-size class (voxels in powers of 4)
-and the accumulation mode; each entry
-stores the fastest measured tuning.  A lookup is deterministic: a given
+covers a voxel, in powers of 4), a grid-size class (voxels in powers of 4),
+the accumulation mode and the gather's matrix-core operand form (keys of
+gathers with FP32 operands -- the other kernel pairs, per-point bandwidths,
+or operand_form = 1 -- end in "/fp32"; their costs differ enough to want
+other bins); each entry stores the fastest measured tuning.  A lookup is deterministic: a given
 description always resolves to the same pinned tuning, so results stay
 bitwise repeatable.
 
@@ -30,7 +32,9 @@ import sys
 import time
 from typing import Dict, List, Optional, Tuple
 
-from . import Desc, Plan, Tuning, FLAG_KAHAN
+from . import Desc, Plan, Tuning, FLAG_ADAPTIVE, FLAG_KAHAN
+
+_KERNEL_MASK = 0xF00
 
 ARCH = "gfx950"
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -60,10 +64,18 @@ def grid_class(desc: Desc) -> int:
     return int(round(math.log2(float(desc.gx * desc.gy * desc.gt)) / 2.0))
 
 
-def key(desc: Desc, n: int) -> str:
+def fp32_operands(desc: Desc, fp32: bool = False) -> bool:
+    """Whether the plan's gather takes FP32 matrix-core operands whatever its
+    shape: asked for (operand_form = 1), another kernel pair, or per-point
+    bandwidths."""
+    return bool(fp32 or (desc.flags & _KERNEL_MASK) or (desc.flags & FLAG_ADAPTIVE))
+
+
+def key(desc: Desc, n: int, fp32: bool = False) -> str:
     mode = "kahan" if desc.flags & FLAG_KAHAN else "plain"
     return (f"{ARCH}/hs{_bucket(desc.hs / desc.sres)}/ht{_bucket(desc.ht / desc.tres)}"
-            f"/d{density_class(desc, n)}/g{grid_class(desc)}/{mode}")
+            f"/d{density_class(desc, n)}/g{grid_class(desc)}/{mode}"
+            + ("/fp32" if fp32_operands(desc, fp32) else ""))
 
 
 def _load(path: str) -> Dict:
@@ -76,51 +88,57 @@ def _load(path: str) -> Dict:
     return data.get("entries", {})
 
 
-def lookup(desc: Desc, n: int, cache: Optional[str] = None) -> Optional[Tuning]:
-    """The pinned tuning for (desc, n), or None when no cache covers it."""
-    k = key(desc, n)
+def _tuning(e, desc: Desc, fp32: bool) -> Tuning:
+    tt, cxy, ct, ss = e["tuning"]
+    if (desc.flags & FLAG_KAHAN) and tt > 32:
+        tt = 32
+    return Tuning(tt, cxy, ct, ss, 0, 1 if fp32 else 0)
+
+
+def lookup(desc: Desc, n: int, cache: Optional[str] = None, fp32: bool = False) -> Optional[Tuning]:
+    """The pinned tuning for (desc, n), or None when no cache covers it
+    (fp32: for a plan with FP32 operands, which the tuning then asks for)."""
+    k = key(desc, n, fp32)
     for path in (cache, os.environ.get("STKDE_TUNE_CACHE"), SHIPPED_CACHE):
         e = _load(path).get(k)
         if e is not None:
-            tt, cxy, ct, ss = e["tuning"]
-            if (desc.flags & FLAG_KAHAN) and tt > 32:
-                tt = 32
-            return Tuning(tt, cxy, ct, ss)
+            return _tuning(e, desc, fp32)
     return None
 
 
 def _parse_key(k: str):
-    """(hs bucket, ht bucket, density class, grid class, mode) of a cache key."""
-    _, hs, ht, d, g, mode = k.split("/")
-    return int(hs[2:]), int(ht[2:]), int(d[1:]), int(g[1:]), mode
+    """(hs bucket, ht bucket, density class, grid class, mode, operand form) of
+    a cache key."""
+    parts = k.split("/")
+    _, hs, ht, d, g, mode = parts[:6]
+    form = parts[6] if len(parts) > 6 else "default"
+    return int(hs[2:]), int(ht[2:]), int(d[1:]), int(g[1:]), mode, form
 
 
-def resolve(desc: Desc, n: int, cache: Optional[str] = None, max_distance: float = 4.0):
+def resolve(desc: Desc, n: int, cache: Optional[str] = None, max_distance: float = 4.0,
+            fp32: bool = False):
     """(tuning, source) for (desc, n): the entry of its own key; else the
-    nearest entry of the same accumulation mode, by |d hs bucket| +
-    |d ht bucket| + |d density class| + |d grid class| / 2 (ties: the first
-    key in sorted order), if within ``max_distance``; else (None, reason).
-    Deterministic, so results stay bitwise repeatable."""
-    t = lookup(desc, n, cache)
-    k = key(desc, n)
+    nearest entry of the same accumulation mode and operand form, by
+    |d hs bucket| + |d ht bucket| + |d density class| + |d grid class| / 2
+    (ties: the first key in sorted order), if within ``max_distance``; else
+    (None, reason).  Deterministic, so results stay bitwise repeatable."""
+    t = lookup(desc, n, cache, fp32)
+    k = key(desc, n, fp32)
     if t is not None:
         return t, f"autotune {k}"
-    hs, ht, d, g, mode = _parse_key(k)
+    hs, ht, d, g, mode, form = _parse_key(k)
     best, best_key = None, None
     for path in (cache, os.environ.get("STKDE_TUNE_CACHE"), SHIPPED_CACHE):
         entries = _load(path)
         for ek in sorted(entries):
-            ehs, eht, ed, eg, emode = _parse_key(ek)
-            if emode != mode:
+            ehs, eht, ed, eg, emode, eform = _parse_key(ek)
+            if emode != mode or eform != form:
                 continue
             dist = abs(ehs - hs) + abs(eht - ht) + abs(ed - d) + 0.5 * abs(eg - g)
             if dist <= max_distance and (best is None or dist < best):
                 best, best_key = dist, ek
         if best_key is not None:
-            tt, cxy, ct, ss = entries[best_key]["tuning"]
-            if (desc.flags & FLAG_KAHAN) and tt > 32:
-                tt = 32
-            return Tuning(tt, cxy, ct, ss), f"autotune nearest {best_key} (for {k})"
+            return _tuning(entries[best_key], desc, fp32), f"autotune nearest {best_key} (for {k})"
     return None, f"default (no cache entry near {k})"
 
 
@@ -156,9 +174,10 @@ def candidates_tile(desc: Desc) -> List[int]:
     return [16, 32] if desc.flags & FLAG_KAHAN else [16, 32, 64]
 
 
-def tune(points, desc: Desc, reps: int = 5, log=None) -> Tuple[Tuning, float, List]:
+def tune(points, desc: Desc, reps: int = 5, log=None, operand_form: int = 0) -> Tuple[Tuning, float, List]:
     """Coordinate search: tile rows with default bins, then bin edges, then
     the split share; returns (best tuning, its ms, every measurement)."""
+    of = operand_form
     table = []
 
     def run(t: Tuning) -> float:
@@ -173,13 +192,13 @@ def tune(points, desc: Desc, reps: int = 5, log=None) -> Tuple[Tuning, float, Li
             log(f"  {t}: {ms:.3f} ms")
         return ms
 
-    default_ms = measure(points, desc, None, reps)
+    default_ms = measure(points, desc, Tuning(operand_form=of), reps)
     table.append(([0, 0, 0, 0], default_ms))
     if log:
         log(f"  library default: {default_ms:.3f} ms")
     best, best_ms = None, math.inf
     for tt in candidates_tile(desc):
-        t = Tuning(tt, 0, 0, 0)
+        t = Tuning(tt, 0, 0, 0, 0, of)
         ms = run(t)
         if ms < best_ms:
             best, best_ms = t, ms
@@ -188,12 +207,12 @@ def tune(points, desc: Desc, reps: int = 5, log=None) -> Tuple[Tuning, float, Li
                         for d in (max(8, 4 * math.ceil(tv / 2)), max(8, 4 * math.ceil(tv / 4)))
                         if c <= 256 and d <= 256})
     for cxy, ct in cell_opts:
-        t = Tuning(best.tile_t, cxy, ct, 0)
+        t = Tuning(best.tile_t, cxy, ct, 0, 0, of)
         ms = run(t)
         if ms < best_ms:
             best, best_ms = t, ms
     for ss in (512, 8192):
-        t = Tuning(best.tile_t, best.cell_xy, best.cell_t, ss)
+        t = Tuning(best.tile_t, best.cell_xy, best.cell_t, ss, 0, of)
         ms = run(t)
         if ms < best_ms:
             best, best_ms = t, ms
@@ -216,17 +235,18 @@ def tuning_workloads():
                        Desc(gx=gx, gy=gy, gt=gt, hs=hs, ht=ht))
 
 
-def build_cache(path: str, kahan_modes=(True, False), reps: int = 5, log=print):
-    """Tune every synthetic workload and write the cache (fastest per key)."""
+def build_cache(path: str, kahan_modes=(True, False), reps: int = 5, log=print, forms=(0, 1)):
+    """Tune every synthetic workload and write the cache (fastest per key),
+    for each operand form in ``forms`` (0 the default, 1 FP32)."""
     import torch
     entries: Dict[str, Dict] = {}
     for name, pts, d0 in tuning_workloads():
         dev_pts = torch.from_numpy(pts).cuda()
-        for kahan in kahan_modes:
+        for kahan, form in ((k_, f_) for k_ in kahan_modes for f_ in forms):
             desc = Desc(**{**d0.__dict__, "flags": FLAG_KAHAN if kahan else 0})
-            k = key(desc, len(pts))
-            log(f"[tune] {name} kahan={kahan} -> {k}")
-            best, ms, table = tune(dev_pts, desc, reps, log)
+            k = key(desc, len(pts), fp32=form == 1)
+            log(f"[tune] {name} kahan={kahan} operand_form={form} -> {k}")
+            best, ms, table = tune(dev_pts, desc, reps, log, form)
             base = table[0][1]  # the library's default tuning
             prev = entries.get(k)
             # a key seen twice keeps the tuning with the larger gain

@@ -47,8 +47,9 @@ def test_shipped_cache_is_well_formed():
         tt, cxy, ct, ss = e["tuning"]
         assert tt in (16, 32, 64) and (cxy == 0 or 4 <= cxy <= 256) and (ct == 0 or 4 <= ct <= 256)
         assert ss == 0 or 64 <= ss <= 65536
-        if k.endswith("/kahan"):
+        if "/kahan" in k:
             assert tt <= 32
+        assert k.count("/") == 5 or k.endswith("/fp32")
 
 
 def test_resolve_prefers_own_key_then_nearest(tmp_path):
@@ -78,3 +79,38 @@ def test_resolve_prefers_own_key_then_nearest(tmp_path):
     empty.write_text(json.dumps({**cache, "entries": {near_key: {"tuning": [16, 16, 8, 0]}}}))
     t, src = autotune.resolve(tiny, 10, str(empty), max_distance=0.0)
     assert t is None and src.startswith("default")
+
+
+def test_operand_form_keys_are_separate(tmp_path):
+    """Gathers with FP32 operands (asked for, another kernel pair, per-point
+    bandwidths) have keys of their own and never take the default form's
+    entries, also through the nearest-entry search."""
+    from paper_1705_09366_amd import FLAG_ADAPTIVE, kernel_flag
+    d = Desc(gx=1024, gy=1024, gt=256, hs=10.0, ht=7.0, flags=FLAG_KAHAN)
+    k = autotune.key(d, 1_000_000)
+    assert k == "gfx950/hs4/ht3/d2/g14/kahan"
+    assert autotune.key(d, 1_000_000, fp32=True) == k + "/fp32"
+    for fl in (kernel_flag(1), kernel_flag(3), FLAG_ADAPTIVE):
+        dq = Desc(**{**d.__dict__, "flags": FLAG_KAHAN | fl})
+        assert autotune.key(dq, 1_000_000) == k + "/fp32"
+    # a grid class the shipped cache does not cover, so that only this cache answers
+    big = Desc(gx=4096, gy=4096, gt=1024, hs=10.0, ht=7.0, flags=FLAG_KAHAN)
+    kb = autotune.key(big, 4_000_000)
+    kb_near_fp32 = autotune.key(big, 16_000_000, fp32=True)  # one density class away
+    assert kb_near_fp32 != kb + "/fp32"
+    path = tmp_path / "c.json"
+    path.write_text(json.dumps({"version": 1, "arch": "gfx950", "entries": {
+        kb: {"tuning": [32, 24, 8, 512]}, kb_near_fp32: {"tuning": [32, 16, 8, 0]}}}))
+    t, src = autotune.resolve(big, 4_000_000, str(path))
+    assert (t.tile_t, t.cell_xy, t.operand_form) == (32, 24, 0) and src.endswith(kb)
+    t, src = autotune.resolve(big, 4_000_000, str(path), fp32=True)
+    assert (t.cell_xy, t.operand_form) == (16, 1) and f"nearest {kb_near_fp32}" in src
+    bq = Desc(**{**big.__dict__, "flags": FLAG_KAHAN | kernel_flag(2)})
+    t, src = autotune.resolve(bq, 4_000_000, str(path))
+    assert t.cell_xy == 16 and "/fp32" in src
+    # an FP32-form cache alone never serves a default-form plan
+    only = tmp_path / "o.json"
+    only.write_text(json.dumps({"version": 1, "arch": "gfx950", "entries": {
+        kb_near_fp32: {"tuning": [32, 16, 8, 0]}}}))
+    t, src = autotune.resolve(big, 4_000_000, str(only))
+    assert t is None or "/fp32" not in src
