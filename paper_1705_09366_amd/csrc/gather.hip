@@ -30,14 +30,14 @@
 //   setup   the bin rows (t, y) whose bins can hold points reaching the tile
 //           become a list of candidate ranges in LDS;
 //   stage   256 candidates at a time, one per thread: test the point's
-//           clipped footprint box against the tile and append the survivors'
-//           tile-local coordinates to an LDS list, together with the set of
-//           4 x 4 column groups and 16-row blocks its cylinder touches (a
-//           disc-versus-group test); repeat until the list is nearly full or
-//           the candidates are exhausted;
+//           clipped footprint box against the tile, and its disc against the
+//           tile's four 8 x 8 quadrants, and append the survivors' tile-local
+//           coordinates to an LDS list, together with the set of quadrants
+//           its disc reaches; repeat until the list is nearly full or the
+//           candidates are exhausted;
 //   lists   each wave owns an 8 x 8 quadrant (four 4 x 4 column groups) x
 //           TT/16 blocks of 16 rows as matrix-core accumulators, and keeps,
-//           in list order, the survivors whose footprint box meets its
+//           in list order, the survivors whose disc reaches its
 //           quadrant;
 //   mma     per group of 4 consecutive survivors of its list, each lane
 //           builds its matrix-core operands in registers -- the Kt entries
@@ -91,6 +91,10 @@ constexpr int kCapH16 = 1152;
 // tile.
 constexpr uint32_t kCoverAll = 0xF0u;
 constexpr float kFullMargin = 0.99998f;    // largest a + b at a tile corner for that
+// A quadrant whose nearest column centre lies farther than the disc's radius
+// (beyond 1.0001 hv^2, after moving the point 0.001 voxel closer) holds no
+// evaluation of the point: its FP32 operands there are 0 by a wide margin.
+constexpr float kCullMargin = 1.0001f;
 constexpr int kMaxDevices = 64;
 // Pairs that are not zero on their support boundary decide membership near it
 // in FP64: within this band of the FP32 test (|1 - u^2 - v^2| or |w^2 - 1|),
@@ -589,13 +593,29 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                                 const bool y0 = ylo <= 7 && yhi >= 0, y1 = ylo <= 15 && yhi >= 8;
                                 qm = (uint32_t)(x0 && y0) | ((uint32_t)(x1 && y0) << 1) |
                                      ((uint32_t)(x0 && y1) << 2) | ((uint32_t)(x1 && y1) << 3);
+                                // of those, the quadrants the disc reaches: nearest column
+                                // centre per axis and quadrant half
+                                const float px = (r.xh - (float)BX0) + half_lo(r.xl_yl);
+                                const float py = (r.yh - (float)BY0) + half_hi(r.xl_yl);
+                                {
+                                    const float ihv2p = ADAPT ? pbw.x : inv_hv2;
+                                    float nx2[2], ny2[2];
+#pragma unroll
+                                    for (int h = 0; h < 2; ++h) {
+                                        const float ex = fmaxf(fabsf(px - (8.0f * h + 4.0f)) - 3.501f, 0.0f);
+                                        const float ey = fmaxf(fabsf(py - (8.0f * h + 4.0f)) - 3.501f, 0.0f);
+                                        nx2[h] = ex * ex;
+                                        ny2[h] = ey * ey;
+                                    }
+#pragma unroll
+                                    for (int q = 0; q < 4; ++q)
+                                        if ((nx2[q & 1] + ny2[q >> 1]) * ihv2p > kCullMargin) qm &= ~(1u << q);
+                                }
                                 if (FULL && (D.flags & kInstFull)) {
                                     // quadrants whose every column centre the disc
                                     // covers (farthest corner, with a margin): the
                                     // spatial kernel is 1 - a(x) - b(y) there,
                                     // separable in x and y
-                                    const float px = (r.xh - (float)BX0) + half_lo(r.xl_yl);
-                                    const float py = (r.yh - (float)BY0) + half_hi(r.xl_yl);
                                     // farthest column centre per axis and quadrant half
                                     float ax2[2], ay2[2];
 #pragma unroll
