@@ -137,10 +137,11 @@ typedef struct {
     int32_t operand_form; /* matrix-core operands of the gather: 0 (default) two
                              FP16 terms each (hi + lo, 22 significant bits; the
                              product as hi*hi + hi*lo + lo*hi with FP32
-                             accumulation) where the gather has that form -- the
-                             Epanechnikov pair, one bandwidth pair, no full-cover
-                             path (hs / sres < 14), 16- or 32-row tiles -- and FP32
-                             elsewhere; 1 FP32 everywhere */
+                             accumulation) where the gather has that form -- one
+                             bandwidth pair, no full-cover path (which only the
+                             Epanechnikov pair takes, from hs / sres >= 14), 16-
+                             or 32-row tiles -- and FP32 elsewhere; 1 FP32
+                             everywhere */
 } stkde_tuning;
 
 typedef struct stkde_plan_s* stkde_plan_t;

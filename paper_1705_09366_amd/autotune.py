@@ -13,9 +13,9 @@ device architecture, the bandwidths in voxels (power-of-two buckets of
 hs/sres and ht/tres), a density class (mean number of points whose cylinder
 covers a voxel, in powers of 4), a grid-size class (voxels in powers of 4),
 the accumulation mode and the gather's matrix-core operand form (keys of
-gathers with FP32 operands -- the other kernel pairs, per-point bandwidths,
-or operand_form = 1 -- end in "/fp32"; their costs differ enough to want
-other bins); each entry stores the fastest measured tuning.  A lookup is deterministic: a given
+gathers with FP32 operands -- per-point bandwidths, or operand_form = 1 --
+end in "/fp32"; their costs differ enough to want other bins); each entry
+stores the fastest measured tuning.  A lookup is deterministic: a given
 description always resolves to the same pinned tuning, so results stay
 bitwise repeatable.
 
@@ -33,8 +33,6 @@ import time
 from typing import Dict, List, Optional, Tuple
 
 from . import Desc, Plan, Tuning, FLAG_ADAPTIVE, FLAG_KAHAN
-
-_KERNEL_MASK = 0xF00
 
 ARCH = "gfx950"
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -66,9 +64,8 @@ def grid_class(desc: Desc) -> int:
 
 def fp32_operands(desc: Desc, fp32: bool = False) -> bool:
     """Whether the plan's gather takes FP32 matrix-core operands whatever its
-    shape: asked for (operand_form = 1), another kernel pair, or per-point
-    bandwidths."""
-    return bool(fp32 or (desc.flags & _KERNEL_MASK) or (desc.flags & FLAG_ADAPTIVE))
+    shape: asked for (operand_form = 1) or per-point bandwidths."""
+    return bool(fp32 or (desc.flags & FLAG_ADAPTIVE))
 
 
 def key(desc: Desc, n: int, fp32: bool = False) -> str:

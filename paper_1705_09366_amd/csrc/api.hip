@@ -246,11 +246,12 @@ float norm_const(double hs, double ht, int64_t n, int kernel = 0) {
 // The gather's full-cover path pays off when discs are large against a tile.
 bool use_full(double hv, int32_t tile_t) { return tile_t <= 32 && hv >= stkde::kFullMinHv; }
 
-// Two-term FP16 matrix-core operands: the gathers of the Epanechnikov pair with
-// one bandwidth pair, no full-cover path and 16- or 32-row tiles have them,
+// Two-term FP16 matrix-core operands: the gathers with one bandwidth pair, no
+// full-cover path and 16- or 32-row tiles have them (every kernel pair),
 // unless the plan's tuning asks for FP32 operands.
 bool use_h16(int kf, bool adapt, bool full, int32_t tile_t, int32_t operand_form) {
-    return kf == stkde::kKernelEpan && !adapt && !full && tile_t <= 32 && operand_form == 0;
+    (void)kf;
+    return !adapt && !full && tile_t <= 32 && operand_form == 0;
 }
 
 stkde::InstDev make_dev(const stkde::InstGeom& ig, const stkde::SetGeom& sg, const uint8_t* set_mem,

@@ -240,8 +240,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
     float* __restrict__ kscratch) {
     static_assert(!(FULL && ADAPT), "the full-cover path assumes one bandwidth pair");
     static_assert(KF == kKernelEpan || (!FULL && !ADAPT), "other pairs: no full-cover path, one pair");
-    static_assert(!H16 || (KF == kKernelEpan && !FULL && !ADAPT && TT <= 32 && MODE != kAccKahanReg),
-                  "two-term FP16 operands: Epanechnikov, one pair, no full-cover path, 16/32 rows");
+    static_assert(!H16 || (!FULL && !ADAPT && TT <= 32 && MODE != kAccKahanReg),
+                  "two-term FP16 operands: one bandwidth pair, no full-cover path, 16/32 rows");
     constexpr int kCap = H16 ? kCapH16 : kCapF32;
     constexpr int kLPad = H16 ? 32 : 8;  // wave lists are padded to this many entries
     constexpr int NB = TT / 16;  // 16-row blocks per tile
@@ -397,11 +397,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                 // one group: operands from the coordinates (and, ADAPT, the
                 // bandwidth terms pb) of this lane's point, then all CG
                 // instructions
-                auto group = [&](const float2 cx, const float2 cy, const float2 ctt, const float4 pb,
-                                 const uint32_t ri) {
+                // this lane's operands for one point: the Kt entries of its row in
+                // every block (av) and the Ks entries of its column in every
+                // column group (ks)
+                auto operands = [&](const float2 cx, const float2 cy, const float2 ctt, const float4 pb,
+                                    const uint32_t ri, float (&av)[NB], float (&kso)[4]) {
                     const float ihv2 = ADAPT ? pb.x : inv_hv2;
                     const float itv2 = ADAPT ? pb.y : inv_tv2;
-                    float av[NB];
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
                         const float dt = ((rowc + 16.0f * b) - ctt.x) - ctt.y;
@@ -437,10 +439,19 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                                 ks = exact_disc(D.x64, ri, X, Y, D.hv64) ? fx[g & 1] * fy[g >> 1] : 0.0f;
                             }
                         }
+                        kso[g] = ks;
+                    }
+                };
+                auto group = [&](const float2 cx, const float2 cy, const float2 ctt, const float4 pb,
+                                 const uint32_t ri) {
+                    float av[NB], ks[4];
+                    operands(cx, cy, ctt, pb, ri, av, ks);
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
 #pragma unroll
                         for (int b = 0; b < NB; ++b)
                             acc[g * NB + b] =
-                                __builtin_amdgcn_mfma_f32_16x16x4f32(av[b], ks, acc[g * NB + b], 0, 0, 0);
+                                __builtin_amdgcn_mfma_f32_16x16x4f32(av[b], ks[g], acc[g * NB + b], 0, 0, 0);
                     }
                 };
 
@@ -515,23 +526,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
                         for (int jj = 0; jj < 2; ++jj) {
                             const int s = jj == 0 ? (int)(ixa[jp] & 0xffffu) : (int)(ixa[jp] >> 16);
-                            const float2 cx = sX[s], cy = sY[s], ct = sT[s];
-#pragma unroll
-                            for (int b = 0; b < NB; ++b) {
-                                const float dt = ((rowc + 16.0f * b) - ct.x) - ct.y;
-                                kt[jj][b] = kt_operand<kKernelEpan>(dt, inv_tv2, inv_tv);
-                            }
-                            float ux[2], uy[2];
-#pragma unroll
-                            for (int h = 0; h < 2; ++h) {
-                                const float dx = ((xc0 + 4.0f * h) - cx.x) - cx.y;
-                                const float dy = ((yc0 + 4.0f * h) - cy.x) - cy.y;
-                                ux[h] = fmaf(-dx * dx, inv_hv2, 1.0f);
-                                uy[h] = dy * dy * inv_hv2;
-                            }
-#pragma unroll
-                            for (int g = 0; g < 4; ++g)
-                                ks[jj][g] = ks_operand<kKernelEpan>(ux[g & 1] - uy[g >> 1], 1.0f, 1.0f);
+                            operands(sX[s], sY[s], sT[s], float4{}, EXACT ? sI[s] : 0u, kt[jj], ks[jj]);
                         }
 #pragma unroll
                         for (int b = 0; b < NB; ++b) {
@@ -1049,25 +1044,30 @@ void dispatch_variant(bool full, bool adapt, bool h16, F& f) {
 
 // The other pairs: 16- or 32-row tiles, plain or compensated (scratch form;
 // the register form performs the same operations), one bandwidth pair.
-template <int KF, typename F>
-void dispatch_pair(int tile_t, int mode, F& f) {
+template <int KF, bool H, typename F>
+void dispatch_pair_form(int tile_t, int mode, F& f) {
     const bool kahan = mode != kAccPlain;
     if (tile_t == 16) {
-        kahan ? f.template operator()<16, kAccKahanMem, false, false, KF, false>()
-              : f.template operator()<16, kAccPlain, false, false, KF, false>();
+        kahan ? f.template operator()<16, kAccKahanMem, false, false, KF, H>()
+              : f.template operator()<16, kAccPlain, false, false, KF, H>();
     } else {
-        kahan ? f.template operator()<32, kAccKahanMem, false, false, KF, false>()
-              : f.template operator()<32, kAccPlain, false, false, KF, false>();
+        kahan ? f.template operator()<32, kAccKahanMem, false, false, KF, H>()
+              : f.template operator()<32, kAccPlain, false, false, KF, H>();
     }
+}
+template <int KF, typename F>
+void dispatch_pair(int tile_t, int mode, bool h16, F& f) {
+    if (h16) dispatch_pair_form<KF, true>(tile_t, mode, f);
+    else dispatch_pair_form<KF, false>(tile_t, mode, f);
 }
 
 // The kernel variant of (tile_t, mode, full, adapt, kernel pair, operand
 // form); 64-row tiles are plain.
 template <typename F>
 void dispatch(int tile_t, int mode, bool full, bool adapt, int kf, bool h16, F&& f) {
-    if (kf == kKernelQuartic) return dispatch_pair<kKernelQuartic>(tile_t, mode, f);
-    if (kf == kKernelGauss) return dispatch_pair<kKernelGauss>(tile_t, mode, f);
-    if (kf == kKernelPrinted) return dispatch_pair<kKernelPrinted>(tile_t, mode, f);
+    if (kf == kKernelQuartic) return dispatch_pair<kKernelQuartic>(tile_t, mode, h16, f);
+    if (kf == kKernelGauss) return dispatch_pair<kKernelGauss>(tile_t, mode, h16, f);
+    if (kf == kKernelPrinted) return dispatch_pair<kKernelPrinted>(tile_t, mode, h16, f);
     if (tile_t == 16) {
         if (mode == kAccKahanReg) dispatch_variant<16, kAccKahanReg>(full, adapt, h16, f);
         else if (mode == kAccKahanMem) dispatch_variant<16, kAccKahanMem>(full, adapt, h16, f);

@@ -82,17 +82,19 @@ def test_resolve_prefers_own_key_then_nearest(tmp_path):
 
 
 def test_operand_form_keys_are_separate(tmp_path):
-    """Gathers with FP32 operands (asked for, another kernel pair, per-point
-    bandwidths) have keys of their own and never take the default form's
-    entries, also through the nearest-entry search."""
+    """Gathers with FP32 operands (asked for, per-point bandwidths) have keys
+    of their own and never take the default form's entries, also through the
+    nearest-entry search."""
     from paper_1705_09366_amd import FLAG_ADAPTIVE, kernel_flag
     d = Desc(gx=1024, gy=1024, gt=256, hs=10.0, ht=7.0, flags=FLAG_KAHAN)
     k = autotune.key(d, 1_000_000)
     assert k == "gfx950/hs4/ht3/d2/g14/kahan"
     assert autotune.key(d, 1_000_000, fp32=True) == k + "/fp32"
-    for fl in (kernel_flag(1), kernel_flag(3), FLAG_ADAPTIVE):
+    dq = Desc(**{**d.__dict__, "flags": FLAG_KAHAN | FLAG_ADAPTIVE})
+    assert autotune.key(dq, 1_000_000) == k + "/fp32"
+    for fl in (kernel_flag(1), kernel_flag(3)):  # the other pairs have two-term operands too
         dq = Desc(**{**d.__dict__, "flags": FLAG_KAHAN | fl})
-        assert autotune.key(dq, 1_000_000) == k + "/fp32"
+        assert autotune.key(dq, 1_000_000) == k
     # a grid class the shipped cache does not cover, so that only this cache answers
     big = Desc(gx=4096, gy=4096, gt=1024, hs=10.0, ht=7.0, flags=FLAG_KAHAN)
     kb = autotune.key(big, 4_000_000)
@@ -105,7 +107,7 @@ def test_operand_form_keys_are_separate(tmp_path):
     assert (t.tile_t, t.cell_xy, t.operand_form) == (32, 24, 0) and src.endswith(kb)
     t, src = autotune.resolve(big, 4_000_000, str(path), fp32=True)
     assert (t.cell_xy, t.operand_form) == (16, 1) and f"nearest {kb_near_fp32}" in src
-    bq = Desc(**{**big.__dict__, "flags": FLAG_KAHAN | kernel_flag(2)})
+    bq = Desc(**{**big.__dict__, "flags": FLAG_KAHAN | FLAG_ADAPTIVE})
     t, src = autotune.resolve(bq, 4_000_000, str(path))
     assert t.cell_xy == 16 and "/fp32" in src
     # an FP32-form cache alone never serves a default-form plan

@@ -1,7 +1,7 @@
 """GPU parity of the gather's two matrix-core operand forms against the FP64
 oracle, through the C ABI: two FP16 terms per operand (hi + lo, the default
-where the gather has that form: Epanechnikov pair, one bandwidth pair, no
-full-cover path, 16- or 32-row tiles) and FP32 (tuning operand_form = 1).
+where the gather has that form: one bandwidth pair, no full-cover path, 16-
+or 32-row tiles, every kernel pair) and FP32 (tuning operand_form = 1).
 
 Both forms meet the bar of every other path, max |gpu - oracle| <= 1e-5
 max(oracle).  Because every product in the sum is non-negative, the
@@ -96,6 +96,25 @@ def test_random_cases(torch_cuda, seed, form):
     _check(gpu, ref, per_voxel=True)
     assert int(st[2]) == evals
     assert st[0] == pytest.approx(st[1], rel=1e-5, abs=1e-300)
+
+
+@pytest.mark.parametrize("form", [0, 1], ids=["fp16x2", "fp32"])
+@pytest.mark.parametrize("kernel", [1, 2, 3], ids=["quartic", "gaussian", "printed"])
+def test_other_pairs_both_forms(torch_cuda, kernel, form):
+    """The other kernel pairs (operands up to 16 for the printed pair, exact
+    support tests near the boundary for the Gaussian and printed pairs) in
+    both forms, with the per-voxel bound."""
+    import paper_1705_09366_amd as m
+    for seed in range(3):
+        pts, g = workloads.small_random_case(2300 + 10 * kernel + seed, max_g=70, max_n=700)
+        tt = (16, 32)[seed % 2]
+        grid = Grid(gx=g["gx"], gy=g["gy"], gt=g["gt"], hs=g["hs"], ht=g["ht"], sres=g["sres"], tres=g["tres"],
+                    x0=g["x0"], y0=g["y0"], t0=g["t0"], kernel=kernel)
+        ref, evals = oracle.pbsym(pts, grid)
+        _say(f"pair {kernel} operand_form={form} seed={seed} tile_t={tt} n={len(pts)}")
+        gpu, st = _run(torch_cuda, pts, g, 1 | 4 | 8 | m.kernel_flag(kernel), m.Tuning(tile_t=tt, operand_form=form))
+        _check(gpu, ref, per_voxel=True)
+        assert int(st[2]) == evals
 
 
 @pytest.mark.parametrize("hv,tv", [(0.3, 0.4), (0.75, 9.0), (3.3, 0.6), (13.9, 2.2), (9.5, 15.0)])
