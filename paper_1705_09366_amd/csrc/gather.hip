@@ -558,27 +558,39 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                     }
                 };
 
+                // record (and bandwidth terms) of candidate c, if any
+                auto fetch = [&](const int32_t c, PointRec& r, uint32_t& rix, float4& pbw) {
+                    if (c < cend) {
+                        int32_t lo = 0, hi = nranges - 1;  // last range with sRP <= c
+                        while (lo < hi) {
+                            const int32_t mid = (lo + hi + 1) >> 1;
+                            if (sRP[mid] <= c) lo = mid;
+                            else hi = mid - 1;
+                        }
+                        const int32_t ri = sRB[lo] + (c - sRP[lo]);
+                        rix = (uint32_t)ri;
+                        r = recs[ri];
+                        if constexpr (ADAPT) pbw = D.bw[ri];
+                    }
+                };
                 int32_t bb = (int32_t)min(it.cbeg, (uint32_t)cend);
                 while (bb < cend) {
-                    // ---- stage: fill the survivor list ------------------------------
+                    // ---- stage: fill the survivor list; each round's records are
+                    // loaded during the round before it ----------------------------
                     int32_t count_s = 0;
+                    PointRec rn{};
+                    float4 pbn{};
+                    uint32_t rin = 0;
+                    fetch(bb + tid, rn, rin, pbn);
                     while (bb < cend && count_s <= kCap - kThreads) {
                         const int32_t c = bb + tid;
                         bool surv = false;
-                        PointRec r{};
-                        float4 pbw{};
-                        uint32_t qm = 0, rix = 0;
+                        const PointRec r = rn;
+                        const float4 pbw = pbn;
+                        const uint32_t rix = rin;
+                        fetch(bb + kThreads + tid, rn, rin, pbn);
+                        uint32_t qm = 0;
                         if (c < cend) {
-                            int32_t lo = 0, hi = nranges - 1;  // last range with sRP <= c
-                            while (lo < hi) {
-                                const int32_t mid = (lo + hi + 1) >> 1;
-                                if (sRP[mid] <= c) lo = mid;
-                                else hi = mid - 1;
-                            }
-                            const int32_t ri = sRB[lo] + (c - sRP[lo]);
-                            rix = (uint32_t)ri;
-                            r = recs[ri];
-                            if constexpr (ADAPT) pbw = D.bw[ri];
                             const int32_t xlo = (int32_t)(r.xb & 0xffffu) - BX0, xhi = (int32_t)(r.xb >> 16) - BX0;
                             const int32_t ylo = (int32_t)(r.yb & 0xffffu) - BY0, yhi = (int32_t)(r.yb >> 16) - BY0;
                             const int32_t tlo = (int32_t)(r.tb & 0xffffu), thi = (int32_t)(r.tb >> 16);
