@@ -75,14 +75,24 @@ def key(desc: Desc, n: int, fp32: bool = False) -> str:
             + ("/fp32" if fp32_operands(desc, fp32) else ""))
 
 
+_LOADED: Dict[Tuple[str, int, int], Dict] = {}
+
+
 def _load(path: str) -> Dict:
+    """The entries of a cache file (parsed once per file version: a server
+    looks up every request)."""
     if not path or not os.path.exists(path):
         return {}
-    with open(path) as f:
-        data = json.load(f)
-    if data.get("version") != CACHE_VERSION or data.get("arch") != ARCH:
-        return {}
-    return data.get("entries", {})
+    st = os.stat(path)
+    k = (os.path.abspath(path), st.st_mtime_ns, st.st_size)
+    entries = _LOADED.get(k)
+    if entries is None:
+        with open(path) as f:
+            data = json.load(f)
+        ok = data.get("version") == CACHE_VERSION and data.get("arch") == ARCH
+        entries = data.get("entries", {}) if ok else {}
+        _LOADED[k] = entries
+    return entries
 
 
 def _tuning(e, desc: Desc, fp32: bool) -> Tuning:
