@@ -309,13 +309,25 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
         for (uint32_t lane_off = 0; lane_off < (uint32_t)kFetchLanes; ++lane_off) {
             const uint32_t k = (home + lane_off) % kFetchLanes;
             uint32_t* c = ctr + (q * kFetchLanes + k) * kCtrStride;
+            // spatial queue: after the set-up of a tile that takes one phase, the
+            // next position of this counter is taken at once, so that the
+            // atomic's latency is hidden behind the tile's work (taking it
+            // early for longer tiles costs more in balance than it saves)
+            bool pend = false;
+            uint32_t pnext = 0;
             for (;;) {
                 if (tid == 0) {
-                    // a counter only grows: when even a stale value shows it
-                    // exhausted it is, and the atomic can be skipped
-                    const uint32_t seen = __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    sIdx = (k + kFetchLanes * seen >= qlen) ? 0xffffffffu
-                                                            : k + kFetchLanes * atomicAdd(c, 1u);
+                    uint32_t v;
+                    if (pend) {
+                        v = pnext;
+                        pend = false;
+                    } else {
+                        // a counter only grows: when even a stale value shows it
+                        // exhausted it is, and the atomic can be skipped
+                        const uint32_t seen = __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        v = (k + kFetchLanes * seen >= qlen) ? 0xffffffffu : k + kFetchLanes * atomicAdd(c, 1u);
+                    }
+                    sIdx = v;
                 }
                 __syncthreads();
                 const uint32_t idx = __builtin_amdgcn_readfirstlane(sIdx);
@@ -374,6 +386,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                 __syncthreads();
                 const int32_t total = sRP[nranges];
                 const int32_t cend = it.cend == kAll ? total : min((int32_t)it.cend, total);
+                if (q == 1 && tid == 0 && total <= kCap) {
+                    pend = true;
+                    pnext = k + kFetchLanes * atomicAdd(c, 1u);
+                }
                 const PointRec* __restrict__ recs = D.recs;
 
                 // ---- accumulators: [column group q][row block b].  acc is the
