@@ -334,12 +334,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                 __syncthreads();  // sIdx is rewritten by the next fetch
                 if (idx >= qlen) break;
                 WorkItem it;
+                // spatial queue: every tile in spatial order, minus those the
+                // heaviest-first queue took (tested after the set-up, so that the
+                // mask's load overlaps the set-up's)
+                uint32_t taken = 0;
                 if (q == 0) {
                     it = items[idx];
                 } else {
-                    // spatial queue: every tile in spatial order, minus those the
-                    // heaviest-first queue took
-                    if ((bits[idx >> 5] >> (idx & 31)) & 1u) continue;
+                    taken = (bits[idx >> 5] >> (idx & 31)) & 1u;
                     it.tile = spatial_tile(descs[find_inst(descs, count, idx)], idx);
                     it.cbeg = 0;
                     it.cend = kAll;
@@ -384,6 +386,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                     if (lane == nranges - 1) sRP[nranges] = inc;
                 }
                 __syncthreads();
+                if (taken) continue;
                 const int32_t total = sRP[nranges];
                 const int32_t cend = it.cend == kAll ? total : min((int32_t)it.cend, total);
                 if (q == 1 && tid == 0 && total <= kCap) {
