@@ -488,9 +488,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU sharding of the output slabs "
-              "is a design (see the sharding section of the design notes), not an implemented "
-              "path. Run with --gpus 1.", file=sys.stderr, flush=True)
+        print("bench.py: the library runs on one GPU; sharding the output into per-GPU slabs is "
+              "not implemented. Run with --gpus 1.", file=sys.stderr, flush=True)
         sys.exit(2)
 
     import numpy as np

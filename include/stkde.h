@@ -48,7 +48,7 @@ typedef enum {
     STKDE_ERR_TOO_LARGE = -2,   /* a size overflows the library's index types */
     STKDE_ERR_WORKSPACE = -3,   /* workspace missing or smaller than stkde_workspace_bytes() */
     STKDE_ERR_HIP = -4,         /* a HIP runtime call failed (now or in earlier async work) */
-    STKDE_ERR_UNSUPPORTED = -5  /* a valid request this build does not handle */
+    STKDE_ERR_UNSUPPORTED = -5  /* a valid request the library does not handle */
 } stkde_status;
 
 /* Flags of stkde_desc.flags. */
