@@ -266,18 +266,17 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     }
 }
 
-// cell_start[c] = lower_bound(sorted keys, c) for c in [0, ncell].
+// cell_start[c] = lower_bound(sorted keys, c) for c in [0, ncell]: sorted
+// position s (0 <= s <= n) is the lower bound of the cells in
+// (key[s - 1], key[s]] (key[-1] = -1, key[n] = ncell), so each cell is written
+// once, by the position that starts it.
 __global__ void k_cell_start(const uint32_t* __restrict__ keys, int32_t n, int32_t ncell,
                              uint32_t* __restrict__ cell_start) {
-    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c > ncell) return;
-    int32_t lo = 0, hi = n;
-    while (lo < hi) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (keys[mid] < (uint32_t)c) lo = mid + 1;
-        else hi = mid;
-    }
-    cell_start[c] = (uint32_t)lo;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s > n) return;
+    const int64_t lo = s == 0 ? -1 : (int64_t)keys[s - 1];
+    const int64_t hi = s == n ? (int64_t)ncell : (int64_t)keys[s];
+    for (int64_t c = lo + 1; c <= hi; ++c) cell_start[c] = (uint32_t)s;
 }
 
 // FP16 bit pattern of the tail v - head (|tail| <= half an FP32 ulp of v).
@@ -396,8 +395,8 @@ hipError_t launch_bin(const SetGeom& g, const double* d_xyt, int32_t n, uint8_t*
         std::swap(k0, k1);
         std::swap(v0, v1);
     }
-    const int nc = (g.ncell + 1 + kThreads - 1) / kThreads;
-    hipLaunchKernelGGL(k_cell_start, dim3(nc), dim3(kThreads), 0, s, k0, n, g.ncell, cs);
+    hipLaunchKernelGGL(k_cell_start, dim3((uint32_t)(((int64_t)n + kThreads) / kThreads)), dim3(kThreads), 0, s, k0,
+                       n, g.ncell, cs);
     hipLaunchKernelGGL(k_records, dim3(nb), dim3(kThreads), 0, s, g, d_xyt, d_hst, v0, cs, n,
                        reinterpret_cast<PointRec*>(set + sl.recs),
                        d_hst ? reinterpret_cast<float4*>(set + sl.bw) : nullptr,

@@ -72,11 +72,23 @@ __global__ __launch_bounds__(256) void k_tile_cost(const InstDev* __restrict__ d
         const int32_t ty = rest % D.nty;
         const int32_t tt = rest / D.nty;
         const TileBins b = tile_bins(D, tx * kTileXY + D.ox, ty * kTileXY + D.oy, tt * rows + D.ot, rows);
-        for (int32_t cz = b.ct0; cz <= b.ct1; ++cz) {
-            for (int32_t cy = b.cy0; cy <= b.cy1; ++cy) {
-                const int32_t row = (cz * D.ncy + cy) * D.ncx;
-                c += D.cell_start[row + b.cx1 + 1] - D.cell_start[row + b.cx0];
+        // bin rows in batches of 8, each batch's 16 offsets loaded together
+        const int32_t nyr = b.cy1 - b.cy0 + 1;
+        const int32_t nrows = nyr * (b.ct1 - b.ct0 + 1);
+        for (int32_t r0 = 0; r0 < nrows; r0 += 8) {
+            uint32_t hi[8], lo[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                hi[u] = lo[u] = 0u;
+                const int32_t r = r0 + u;
+                if (r < nrows) {
+                    const int32_t row = ((b.ct0 + r / nyr) * D.ncy + (b.cy0 + r % nyr)) * D.ncx;
+                    hi[u] = D.cell_start[row + b.cx1 + 1];
+                    lo[u] = D.cell_start[row + b.cx0];
+                }
             }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) c += hi[u] - lo[u];
         }
         cost[j] = c;
         atomicAdd(&h[cost_class(c)], 1u);
