@@ -124,6 +124,16 @@ __device__ inline void split_pair(float x, float y, uint32_t& hi, uint32_t& lo) 
     lo = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(rx, ry));
 }
 
+// Value of v in lane ^ 8 (a rotation by 8 within each row of 16 lanes) and
+// in lane ^ 2 (a permutation within each group of 4 lanes).
+__device__ inline float dpp_xor8(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x128, 0xf, 0xf, false));
+}
+
+__device__ inline float dpp_xor2(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x4e, 0xf, 0xf, false));
+}
+
 // Position of list entry p in a two-term FP16 kernel's wave list: within each
 // group of 32, element j of lane group k (k = lane / 16) is entry 4 j + k, and
 // lane group k reads its 8 elements as one 16-byte word.
@@ -300,6 +310,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
     const float rowc = (float)(lane & 15) + 0.5f;
     const float xc0 = (float)(4 * gqx + (lane & 3)) + 0.5f;
     const float yc0 = (float)(4 * gqy + ((lane >> 2) & 3)) + 0.5f;
+    // Which columns a lane's column-group slots hold.  Slot g holds tile-local
+    // column (colx(g), coly(g)).  In the two-term kernels the x half and the y
+    // half of slot 0 differ per lane (swx, swy), so that of the two x offsets
+    // of a Ks column a lane computes one and takes the other from lane ^ 8, and
+    // likewise the y offset from lane ^ 2: both lanes hold the same point, and
+    // lane ^ 8 (lane ^ 2) has the same x (y) with the other half.
+    const int swx = H16 ? (lane >> 3) & 1 : 0;
+    const int swy = H16 ? (lane >> 1) & 1 : 0;
+    auto colx = [&](int g) { return 4 * gqx + 4 * ((g & 1) ^ swx) + (lane & 3); };
+    auto coly = [&](int g) { return 4 * gqy + 4 * ((g >> 1) ^ swy) + ((lane >> 2) & 3); };
+    const float xcs = xc0 + 4.0f * (float)swx, ycs = yc0 + 4.0f * (float)swy;
     uint16_t* myL = sL[wave];
 
     const uint32_t T = (uint32_t)ntiles_total;
@@ -437,24 +458,43 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                         }
                         if constexpr (ADAPT) av[b] *= pb.z;
                     }
+                    // ux = 1 - dx^2/hv^2 and dy^2 of the two x and two y offsets
+                    // of this lane's columns, e = ux - dy^2/hv^2
                     float ux[2], uy[2], fx[2], fy[2];
+                    if constexpr (H16) {
+                        const float dx = (xcs - cx.x) - cx.y;
+                        const float dy = (ycs - cy.x) - cy.y;
+                        ux[0] = fmaf(-dx * dx, ihv2, 1.0f);
+                        uy[0] = dy * dy;
+                        ux[1] = dpp_xor8(ux[0]);
+                        uy[1] = dpp_xor2(uy[0]);
+                        fx[0] = ks_factor<KF>(dx, ihv2, inv_hv);
+                        fy[0] = ks_factor<KF>(dy, ihv2, inv_hv);
+                        if constexpr (EXACT) {
+                            fx[1] = dpp_xor8(fx[0]);
+                            fy[1] = dpp_xor2(fy[0]);
+                        } else {
+                            fx[1] = fy[1] = 1.0f;
+                        }
+                    } else {
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const float dx = ((xc0 + 4.0f * h) - cx.x) - cx.y;
-                        const float dy = ((yc0 + 4.0f * h) - cy.x) - cy.y;
-                        ux[h] = fmaf(-dx * dx, ihv2, 1.0f);
-                        uy[h] = dy * dy * ihv2;
-                        fx[h] = ks_factor<KF>(dx, ihv2, inv_hv);
-                        fy[h] = ks_factor<KF>(dy, ihv2, inv_hv);
+                        for (int h = 0; h < 2; ++h) {
+                            const float dx = ((xc0 + 4.0f * h) - cx.x) - cx.y;
+                            const float dy = ((yc0 + 4.0f * h) - cy.x) - cy.y;
+                            ux[h] = fmaf(-dx * dx, ihv2, 1.0f);
+                            uy[h] = dy * dy;
+                            fx[h] = ks_factor<KF>(dx, ihv2, inv_hv);
+                            fy[h] = ks_factor<KF>(dy, ihv2, inv_hv);
+                        }
                     }
 #pragma unroll
                     for (int g = 0; g < 4; ++g) {
-                        float ks = ks_operand<KF>(ux[g & 1] - uy[g >> 1], fx[g & 1], fy[g >> 1]);
+                        const float e = fmaf(-uy[g >> 1], ihv2, ux[g & 1]);
+                        float ks = ks_operand<KF>(e, fx[g & 1], fy[g >> 1]);
                         if constexpr (EXACT) {
-                            const float e = ux[g & 1] - uy[g >> 1];
                             if (fabsf(e) < kExactBand) {
-                                const int32_t X = BX0 + 4 * gqx + 4 * (g & 1) + (lane & 3);
-                                const int32_t Y = BY0 + 4 * gqy + 4 * (g >> 1) + ((lane >> 2) & 3);
+                                const int32_t X = BX0 + colx(g);
+                                const int32_t Y = BY0 + coly(g);
                                 ks = exact_disc(D.x64, ri, X, Y, D.hv64) ? fx[g & 1] * fy[g >> 1] : 0.0f;
                             }
                         }
@@ -833,8 +873,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                             __syncthreads();
 #pragma unroll
                             for (int g = 0; g < 4; ++g) {
-                                const int32_t lx = 4 * gqx + 4 * (g & 1) + (lane & 3);
-                                const int32_t ly = 4 * gqy + 4 * (g >> 1) + ((lane >> 2) & 3);
+                                const int32_t lx = colx(g), ly = coly(g);
 #pragma unroll
                                 for (int b = 0; b < NB; ++b) {
                                     const f32x4 sa = *reinterpret_cast<const f32x4*>(W + (0 * NB + b) * 256 + lx * 16 + t4);
@@ -892,8 +931,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                     float* P = partials + (size_t)it.slot * (kTileXY * kTileXY * TT);
 #pragma unroll
                     for (int g = 0; g < 4; ++g) {
-                        const int32_t lx = 4 * gqx + 4 * (g & 1) + (lane & 3);
-                        const int32_t ly = 4 * gqy + 4 * (g >> 1) + ((lane >> 2) & 3);
+                        const int32_t lx = colx(g), ly = coly(g);
 #pragma unroll
                         for (int b = 0; b < NB; ++b)
                             *reinterpret_cast<f32x4*>(P + (lx * kTileXY + ly) * TT + 16 * b + 4 * (lane >> 4)) =
@@ -909,8 +947,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                 const bool vec = (gtI & 3) == 0;
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
-                    const int32_t X = X0 + 4 * gqx + 4 * (g & 1) + (lane & 3);
-                    const int32_t Y = Y0 + 4 * gqy + 4 * (g >> 1) + ((lane >> 2) & 3);
+                    const int32_t X = X0 + colx(g);
+                    const int32_t Y = Y0 + coly(g);
                     if (X >= gxI || Y >= gyI) continue;
                     float* col = out + ((size_t)X * gyI + Y) * gtI;
 #pragma unroll
