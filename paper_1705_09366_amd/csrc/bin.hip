@@ -10,8 +10,8 @@
 //      passes.
 //      This is the device form of the per-subdomain point lists that the
 //      paper's domain decompositions build on the host (Sec. 4.2, Sec. 5.1).
-//   3. bin offsets: cell_start[c] = first sorted position with key >= c.
-//   4. records: per sorted point, the 32-byte PointRec (voxel-space
+//   3. bin offsets, cell_start[c] = first sorted position with key >= c, and
+//      (same kernel) per sorted point the 32-byte PointRec (voxel-space
 //      coordinates as FP32 head + FP16 tail, and the clipped footprint box).
 // The bin offsets, records and counters form the *binned set*, which stays
 // valid for any number of later density computations on the base grid or a
@@ -144,14 +144,22 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restr
                                                          uint32_t* __restrict__ hist,
                                                          int32_t nblk) {
     __shared__ uint32_t cnt[kMaxBuckets];
-    for (int d = threadIdx.x; d < nbuck; d += kThreads) cnt[d] = 0;
-    __syncthreads();
-    const uint32_t mask = (uint32_t)nbuck - 1u;
+    // every key of this thread is loaded before the first count, so that the
+    // loads are in flight together
     const int32_t base = blockIdx.x * kSortTile;
+    uint32_t kr[kSortItems];
 #pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
         const int32_t i = base + it * kThreads + threadIdx.x;
-        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & mask], 1u);
+        kr[it] = i < n ? keys[i] : 0u;
+    }
+    for (int d = threadIdx.x; d < nbuck; d += kThreads) cnt[d] = 0;
+    __syncthreads();
+    const uint32_t mask = (uint32_t)nbuck - 1u;
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        const int32_t i = base + it * kThreads + threadIdx.x;
+        if (i < n) atomicAdd(&cnt[(kr[it] >> shift) & mask], 1u);
     }
     __syncthreads();
     for (int d = threadIdx.x; d < nbuck; d += kThreads) hist[(size_t)d * nblk + blockIdx.x] = cnt[d];
@@ -221,23 +229,29 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int nbuck = 1 << dbits;
     const uint32_t mask = (uint32_t)nbuck - 1u;
+    // every key and value of this thread is loaded up front, so that the
+    // loads are in flight together rather than one round at a time
+    const int32_t base = blockIdx.x * kSortTile;
+    uint32_t kr[kSortItems], vr[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const int32_t i = base + r * kThreads + tid;
+        kr[r] = i < n ? kin[i] : 0u;
+        vr[r] = i < n ? vin[i] : 0u;
+    }
     for (int d = tid; d < nbuck; d += kThreads) {
         off[d] = hist[(size_t)d * nblk + blockIdx.x];
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) wcnt[w][d] = 0;
     }
     __syncthreads();
-    const int32_t base = blockIdx.x * kSortTile;
     const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const int32_t i = base + r * kThreads + tid;
         const bool valid = i < n;
-        uint32_t key = 0, val = 0, d = 0;
-        if (valid) {
-            key = kin[i];
-            val = vin[i];
-            d = (key >> shift) & mask;
-        }
+        const uint32_t key = kr[r], val = vr[r];
+        const uint32_t d = valid ? (key >> shift) & mask : 0u;
         unsigned long long peers = __ballot(valid);
         for (int b = 0; b < dbits; ++b) {
             const unsigned long long bb = __ballot((d >> b) & 1u);
@@ -266,43 +280,51 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     }
 }
 
-// cell_start[c] = lower_bound(sorted keys, c) for c in [0, ncell]: sorted
-// position s (0 <= s <= n) is the lower bound of the cells in
-// (key[s - 1], key[s]] (key[-1] = -1, key[n] = ncell), so each cell is written
-// once, by the position that starts it.
-__global__ void k_cell_start(const uint32_t* __restrict__ keys, int32_t n, int32_t ncell,
-                             uint32_t* __restrict__ cell_start) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s > n) return;
-    const int64_t lo = s == 0 ? -1 : (int64_t)keys[s - 1];
-    const int64_t hi = s == n ? (int64_t)ncell : (int64_t)keys[s];
-    for (int64_t c = lo + 1; c <= hi; ++c) cell_start[c] = (uint32_t)s;
-}
-
 // FP16 bit pattern of the tail v - head (|tail| <= half an FP32 ulp of v).
 __device__ inline uint32_t pack_tail(double v, float head) {
     const _Float16 h = (_Float16)(float)(v - (double)head);
     return (uint32_t)__builtin_bit_cast(uint16_t, h);
 }
 
-// Per sorted point: its record, and with per-point bandwidths its terms
-// (1/hv_i^2, 1/tv_i^2, (hv^2 tv) / (hv_i^2 tv_i)): the weight carries the
-// point's own normalisation relative to the set's, which the store applies.
-__global__ __launch_bounds__(kThreads) void k_records(SetGeom g, const double* __restrict__ xyt,
-                                                      const double* __restrict__ hst,
-                                                      const uint32_t* __restrict__ vals,
-                                                      const uint32_t* __restrict__ cell_start,
-                                                      int32_t n, PointRec* __restrict__ recs,
-                                                      float4* __restrict__ bw, double* __restrict__ x64) {
+// Per sorted position s in [0, n]:
+//  - bin offsets: cell_start[c] = lower_bound(sorted keys, c) for c in
+//    [0, ncell]; s is the lower bound of the cells in (key[s - 1], key[s]]
+//    (key[-1] = -1, key[n] = ncell), so each cell is written once, by the
+//    position that starts it;
+//  - for a valid point (s below n minus the points the transform counted as
+//    non-finite, culled or with an invalid bandwidth pair, which sort last):
+//    its record, and with per-point bandwidths its terms (1/hv_i^2,
+//    1/tv_i^2, (hv^2 tv) / (hv_i^2 tv_i)): the weight carries the point's own
+//    normalisation relative to the set's, which the store applies.
+// vals is a permutation of [0, n), so the point's coordinates are loaded
+// before its validity is known and the loads are in flight together.
+__global__ __launch_bounds__(kThreads) void k_offsets_records(
+    SetGeom g, const double* __restrict__ xyt, const double* __restrict__ hst,
+    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+    const unsigned long long* __restrict__ counters, int32_t n, uint32_t* __restrict__ cell_start,
+    PointRec* __restrict__ recs, float4* __restrict__ bw, double* __restrict__ x64) {
     const int64_t s = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (s >= n) return;
-    const int64_t nvalid = (int64_t)cell_start[g.ncell];
+    if (s > n) return;
+    // clamped positions, so that every load is unconditional (n > 0)
+    const int64_t sp = s > 0 ? s - 1 : 0, sc = s < n ? s : (int64_t)n - 1;
+    uint32_t kp = 0, kc = 0, i = 0;
+    double x = 0.0, y = 0.0, t = 0.0;
+    if (n > 0) {
+        kp = keys[sp];
+        kc = keys[sc];
+        i = vals[sc];
+        x = xyt[3 * (size_t)i];
+        y = xyt[3 * (size_t)i + 1];
+        t = xyt[3 * (size_t)i + 2];
+    }
+    const int64_t nvalid = (int64_t)n - (int64_t)(counters[0] + counters[1] + counters[2]);
+    const int64_t lo = s == 0 ? -1 : (int64_t)kp;
+    const int64_t hi = s == n ? (int64_t)g.ncell : (int64_t)kc;
+    for (int64_t c = lo + 1; c <= hi; ++c) cell_start[c] = (uint32_t)s;
     if (s >= nvalid) return;
-    const uint32_t i = vals[s];
     double hv, tv;
     (void)point_bandwidths(g, hst, i, &hv, &tv);  // valid: invalid pairs sort past nvalid
-    const Footprint f = footprint(g, xyt[3 * (size_t)i], xyt[3 * (size_t)i + 1],
-                                  xyt[3 * (size_t)i + 2], hv, tv);
+    const Footprint f = footprint(g, x, y, t, hv, tv);
     if (hst)
         bw[s] = make_float4((float)(1.0 / (hv * hv)), (float)(1.0 / (tv * tv)),
                             (float)((g.hv * g.hv * g.tv) / (hv * hv * tv)), 0.0f);
@@ -395,10 +417,8 @@ hipError_t launch_bin(const SetGeom& g, const double* d_xyt, int32_t n, uint8_t*
         std::swap(k0, k1);
         std::swap(v0, v1);
     }
-    hipLaunchKernelGGL(k_cell_start, dim3((uint32_t)(((int64_t)n + kThreads) / kThreads)), dim3(kThreads), 0, s, k0,
-                       n, g.ncell, cs);
-    hipLaunchKernelGGL(k_records, dim3(nb), dim3(kThreads), 0, s, g, d_xyt, d_hst, v0, cs, n,
-                       reinterpret_cast<PointRec*>(set + sl.recs),
+    hipLaunchKernelGGL(k_offsets_records, dim3((uint32_t)(((int64_t)n + kThreads) / kThreads)), dim3(kThreads), 0,
+                       s, g, d_xyt, d_hst, k0, v0, ctr, n, cs, reinterpret_cast<PointRec*>(set + sl.recs),
                        d_hst ? reinterpret_cast<float4*>(set + sl.bw) : nullptr,
                        exact ? reinterpret_cast<double*>(set + sl.x64) : nullptr);
     return hipGetLastError();
