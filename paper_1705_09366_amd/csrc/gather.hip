@@ -311,13 +311,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
     const float xc0 = (float)(4 * gqx + (lane & 3)) + 0.5f;
     const float yc0 = (float)(4 * gqy + ((lane >> 2) & 3)) + 0.5f;
     // Which columns a lane's column-group slots hold.  Slot g holds tile-local
-    // column (colx(g), coly(g)).  In the two-term kernels the x half and the y
-    // half of slot 0 differ per lane (swx, swy), so that of the two x offsets
-    // of a Ks column a lane computes one and takes the other from lane ^ 8, and
-    // likewise the y offset from lane ^ 2: both lanes hold the same point, and
-    // lane ^ 8 (lane ^ 2) has the same x (y) with the other half.
-    const int swx = H16 ? (lane >> 3) & 1 : 0;
-    const int swy = H16 ? (lane >> 1) & 1 : 0;
+    // column (colx(g), coly(g)); the x half and the y half of slot 0 differ per
+    // lane (swx, swy), so that of the two x offsets of a Ks column a lane
+    // computes one and takes the other from lane ^ 8, and likewise the y
+    // offset from lane ^ 2: in both operand forms the 16 lanes of a row hold
+    // one point, and lane ^ 8 (lane ^ 2) has the same x (y) with the other
+    // half.
+    const int swx = (lane >> 3) & 1;
+    const int swy = (lane >> 1) & 1;
     auto colx = [&](int g) { return 4 * gqx + 4 * ((g & 1) ^ swx) + (lane & 3); };
     auto coly = [&](int g) { return 4 * gqy + 4 * ((g >> 1) ^ swy) + ((lane >> 2) & 3); };
     const float xcs = xc0 + 4.0f * (float)swx, ycs = yc0 + 4.0f * (float)swy;
@@ -461,7 +462,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                     // ux = 1 - dx^2/hv^2 and dy^2 of the two x and two y offsets
                     // of this lane's columns, e = ux - dy^2/hv^2
                     float ux[2], uy[2], fx[2], fy[2];
-                    if constexpr (H16) {
+                    {
                         const float dx = (xcs - cx.x) - cx.y;
                         const float dy = (ycs - cy.x) - cy.y;
                         ux[0] = fmaf(-dx * dx, ihv2, 1.0f);
@@ -475,16 +476,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                             fy[1] = dpp_xor2(fy[0]);
                         } else {
                             fx[1] = fy[1] = 1.0f;
-                        }
-                    } else {
-#pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            const float dx = ((xc0 + 4.0f * h) - cx.x) - cx.y;
-                            const float dy = ((yc0 + 4.0f * h) - cy.x) - cy.y;
-                            ux[h] = fmaf(-dx * dx, ihv2, 1.0f);
-                            uy[h] = dy * dy;
-                            fx[h] = ks_factor<KF>(dx, ihv2, inv_hv);
-                            fy[h] = ks_factor<KF>(dy, ihv2, inv_hv);
                         }
                     }
 #pragma unroll
@@ -834,8 +825,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                             // its x column and of its y column
 #pragma unroll
                             for (int g = 0; g < 4; ++g) {
-                                const int sx = (lane & 48) | (4 * (g & 1) + (lane & 3));
-                                const int sy = (lane & 48) | (8 + 4 * (g >> 1) + ((lane >> 2) & 3));
+                                const int sx = (lane & 48) | (colx(g) - 4 * gqx);
+                                const int sy = (lane & 48) | (8 + coly(g) - 4 * gqy);
 #pragma unroll
                                 for (int b = 0; b < NB; ++b) {
 #pragma unroll
