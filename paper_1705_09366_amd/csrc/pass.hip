@@ -72,23 +72,30 @@ __global__ __launch_bounds__(256) void k_tile_cost(const InstDev* __restrict__ d
         const int32_t ty = rest % D.nty;
         const int32_t tt = rest / D.nty;
         const TileBins b = tile_bins(D, tx * kTileXY + D.ox, ty * kTileXY + D.oy, tt * rows + D.ot, rows);
-        // bin rows in batches of 8, each batch's 16 offsets loaded together
+        // bin rows (t, y) in batches of 16, each batch's 32 offsets loaded
+        // together; (ct, cy) walks the rows with y fastest
         const int32_t nyr = b.cy1 - b.cy0 + 1;
         const int32_t nrows = nyr * (b.ct1 - b.ct0 + 1);
-        for (int32_t r0 = 0; r0 < nrows; r0 += 8) {
-            uint32_t hi[8], lo[8];
+        int32_t ct = b.ct0, cy = b.cy0;
+        for (int32_t r0 = 0; r0 < nrows; r0 += 16) {
+            uint32_t hi[16], lo[16];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < 16; ++u) {
                 hi[u] = lo[u] = 0u;
-                const int32_t r = r0 + u;
-                if (r < nrows) {
-                    const int32_t row = ((b.ct0 + r / nyr) * D.ncy + (b.cy0 + r % nyr)) * D.ncx;
+                if (r0 + u < nrows) {
+                    const int32_t row = (ct * D.ncy + cy) * D.ncx;
                     hi[u] = D.cell_start[row + b.cx1 + 1];
                     lo[u] = D.cell_start[row + b.cx0];
+                    if (cy == b.cy1) {
+                        cy = b.cy0;
+                        ++ct;
+                    } else {
+                        ++cy;
+                    }
                 }
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) c += hi[u] - lo[u];
+            for (int u = 0; u < 16; ++u) c += hi[u] - lo[u];
         }
         cost[j] = c;
         atomicAdd(&h[cost_class(c)], 1u);
@@ -179,7 +186,7 @@ __global__ __launch_bounds__(256) void k_collect_heavy(uint32_t T, const uint32_
                                                        uint32_t* __restrict__ sc) {
     __shared__ uint32_t ws[4];
     __shared__ uint32_t s_cls;
-    const uint32_t cls = heavy_class(hist, ws, &s_cls);
+    // the costs are loaded first, so that their loads overlap the threshold's
     constexpr int kU = 8;  // loads in flight per thread
     const uint32_t j0 = blockIdx.x * (256u * kU) + threadIdx.x;
     uint32_t cv[kU];
@@ -188,6 +195,7 @@ __global__ __launch_bounds__(256) void k_collect_heavy(uint32_t T, const uint32_
         const uint32_t j = j0 + 256u * u;
         cv[u] = j < T ? cost[j] : 0u;
     }
+    const uint32_t cls = heavy_class(hist, ws, &s_cls);
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
         if (cv[u] != 0u && cost_class(cv[u]) >= cls) {
