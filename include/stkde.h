@@ -125,7 +125,8 @@ typedef struct {
  * identical results. */
 typedef struct {
     int32_t tile_t;      /* voxel rows in time per output tile (16, 32 or 64) */
-    int32_t cell_xy;     /* bin edge in x and y, voxels */
+    int32_t cell_xy;     /* bin edge in y, voxels; x bins are 8 voxels wide (at
+                            most cell_xy), widened only to bound the bin count */
     int32_t cell_t;      /* bin edge in t, voxels */
     int32_t split_share; /* a tile costlier than 1/split_share of its grid's total
                             candidate count (and than 2048 candidates) is split

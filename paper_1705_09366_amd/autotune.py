@@ -2,7 +2,7 @@
 
 What it searches, per plan (stkde_tuning):
   tile_t       time rows of an output tile (16, 32; 64 without Kahan),
-  cell_xy, ct  bin edges of the binning (library default = bandwidth-sized),
+  cell_xy, ct  bin edges in y and t (library default = bandwidth-sized; x bins are narrower),
   split_share  the work list's split threshold (a tile costlier than
                1/split_share of its grid's candidates is cut into parts).
 

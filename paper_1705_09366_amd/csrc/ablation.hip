@@ -79,8 +79,8 @@ __global__ __launch_bounds__(256) void k_voxel_gather(const PointRec* __restrict
     const size_t rest = v / sg.gt;
     const int32_t Y = (int32_t)(rest % sg.gy);
     const int32_t X = (int32_t)(rest / sg.gy);
-    const int32_t cx0 = clamp_i32(floordiv_i(X - Hs - 1, sg.cxy), 0, sg.ncx - 1);
-    const int32_t cx1 = clamp_i32(floordiv_i(X + Hs + 1, sg.cxy), 0, sg.ncx - 1);
+    const int32_t cx0 = clamp_i32(floordiv_i(X - Hs - 1, sg.cx), 0, sg.ncx - 1);
+    const int32_t cx1 = clamp_i32(floordiv_i(X + Hs + 1, sg.cx), 0, sg.ncx - 1);
     const int32_t cy0 = clamp_i32(floordiv_i(Y - Hs - 1, sg.cxy), 0, sg.ncy - 1);
     const int32_t cy1 = clamp_i32(floordiv_i(Y + Hs + 1, sg.cxy), 0, sg.ncy - 1);
     const int32_t ct0 = clamp_i32(floordiv_i(T - Ht - 1, sg.ct), 0, sg.nct - 1);

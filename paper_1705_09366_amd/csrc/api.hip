@@ -67,6 +67,7 @@ struct stkde_batch_s {
 namespace {
 
 constexpr int64_t kMaxDim = 65535;
+constexpr int32_t kXBin = 8;           // x bin edge in voxels (see make_set_geom)
 constexpr int32_t kMaxCells = 1 << 22;  // keys of at most 23 bits: <= 3 radix passes (<= 2 below 2^22 - 1 bins)
 constexpr int32_t kMaxBatch = 4096;
 constexpr double kSparseCandidates = 384.0;  // half the gather's survivor buffer
@@ -135,9 +136,12 @@ int64_t ranges_needed(const stkde::SetGeom& g, int32_t Hs, int32_t Ht, int32_t r
     return (ny < g.ncy ? ny : g.ncy) * (nt < g.nct ? nt : g.nct);
 }
 
-// Bins about as wide as the bandwidth (the paper's bandwidth-sized blocks of
-// points, Sec. 4.2 and Sec. 5.1): a tile then reads a few bin rows, and few of
-// the candidates it reads miss it.
+// Bins about as wide as the bandwidth in y and t (the paper's bandwidth-sized
+// blocks of points, Sec. 4.2 and Sec. 5.1): a tile then reads a few bin rows.
+// Within a row (t, y) a tile reads one contiguous run of x bins, so narrow x
+// bins cost no extra ranges and cut the candidates that miss the tile in x:
+// x bins are kXBin voxels wide (at most the y edge), widened only to keep the
+// bin count within kMaxCells.
 void make_set_geom(const stkde_desc& d, int32_t cell_xy, int32_t cell_t, int32_t rows,
                    stkde::SetGeom* out) {
     stkde::SetGeom g{};
@@ -154,8 +158,9 @@ void make_set_geom(const stkde_desc& d, int32_t cell_xy, int32_t cell_t, int32_t
     const int32_t Hs = cap_hs(g.hv, d), Ht = cap_ht(g.tv, d);
     g.cxy = cell_xy ? cell_xy : (int32_t)fmin(256.0, fmax(16.0, 8.0 * ceil(Hs / 8.0)));
     g.ct = cell_t ? cell_t : (int32_t)fmin(256.0, fmax(8.0, 4.0 * ceil(Ht / 4.0)));
+    g.cx = g.cxy < kXBin ? g.cxy : kXBin;
     for (;;) {
-        g.ncx = ceil_div(d.gx, g.cxy);
+        g.ncx = ceil_div(d.gx, g.cx);
         g.ncy = ceil_div(d.gy, g.cxy);
         g.nct = ceil_div(d.gt, g.ct);
         const int64_t nc = (int64_t)g.ncx * g.ncy * g.nct;
@@ -166,7 +171,12 @@ void make_set_geom(const stkde_desc& d, int32_t cell_xy, int32_t cell_t, int32_t
             g.ncell = (int32_t)nc;
             break;
         }
+        // too many bins: first widen the x bins back towards the y edge; else
         // grow the dimension that contributes more bin rows
+        if (nc > kMaxCells && g.cx < g.cxy) {
+            g.cx = 2 * g.cx < g.cxy ? 2 * g.cx : g.cxy;
+            continue;
+        }
         if ((ry >= rt && g.cxy < 65536) || g.ct >= 65536) g.cxy *= 2;
         else g.ct *= 2;
     }
@@ -275,6 +285,7 @@ stkde::InstDev make_dev(const stkde::InstGeom& ig, const stkde::SetGeom& sg, con
     d.ot = ot;
     d.Hs = ig.Hs;
     d.Ht = ig.Ht;
+    d.cx = sg.cx;
     d.cxy = sg.cxy;
     d.ct = sg.ct;
     d.ncx = sg.ncx;

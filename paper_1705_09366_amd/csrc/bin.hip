@@ -3,7 +3,7 @@
 // Stages (all deterministic; atomics appear only in integer counters whose
 // final values do not depend on order):
 //   1. transform: FP64 point -> voxel coordinates, support footprint clipped
-//      to the grid, bin key.  Points whose footprint misses the grid, and
+//      to the grid, bin key (bins narrow in x, bandwidth-sized in y and t).  Points whose footprint misses the grid, and
 //      points with a non-finite coordinate, get the key `ncell`, which sorts
 //      after every bin and is never visited.
 //   2. stable LSD radix sort of (key, index) with 8- to 11-bit digits, 1-3
@@ -76,7 +76,7 @@ __device__ inline Footprint footprint(const SetGeom& g, double x, double y, doub
 }
 
 __device__ inline uint32_t bin_key(const SetGeom& g, const Footprint& f) {
-    const int32_t cx = clamp_i(floordiv(f.fx, g.cxy), 0, g.ncx - 1);
+    const int32_t cx = clamp_i(floordiv(f.fx, g.cx), 0, g.ncx - 1);
     const int32_t cy = clamp_i(floordiv(f.fy, g.cxy), 0, g.ncy - 1);
     const int32_t ct = clamp_i(floordiv(f.ft, g.ct), 0, g.nct - 1);
     return (uint32_t)((ct * g.ncy + cy) * g.ncx + cx);
@@ -258,7 +258,9 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
             peers &= ((d >> b) & 1u) ? bb : ~bb;
         }
         const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
-        if (valid && rank == 0) wcnt[wv][d] = (uint32_t)__popcll(peers);
+        const bool lead = valid && rank == 0;  // one lane per (wave, digit) present
+        const uint32_t cnt = (uint32_t)__popcll(peers);
+        if (lead) wcnt[wv][d] = cnt;
         __syncthreads();
         if (valid) {
             uint32_t pos = off[d] + rank;
@@ -266,17 +268,15 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
             kout[pos] = key;
             vout[pos] = val;
         }
-        __syncthreads();
-        for (int dd = tid; dd < nbuck; dd += kThreads) {
-            uint32_t add = 0;
-#pragma unroll
-            for (int w = 0; w < kWaves; ++w) {
-                add += wcnt[w][dd];
-                wcnt[w][dd] = 0;
-            }
-            off[dd] += add;
+        __syncthreads();  // off and wcnt of this round are read
+        // only the digits present move: each leader adds its wave's count and
+        // clears its own entry (the next round's entries of other waves are
+        // other rows; its own wave's come after this in program order, and
+        // they are read only after the next round's first barrier)
+        if (lead) {
+            atomicAdd(&off[d], cnt);
+            wcnt[wv][d] = 0;
         }
-        __syncthreads();
     }
 }
 
@@ -304,9 +304,10 @@ __global__ __launch_bounds__(kThreads) void k_offsets_records(
     const unsigned long long* __restrict__ counters, int32_t n, uint32_t* __restrict__ cell_start,
     PointRec* __restrict__ recs, float4* __restrict__ bw, double* __restrict__ x64) {
     const int64_t s = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (s > n) return;
+    const int lane = threadIdx.x & 63;
+    const bool act = s <= n;  // every lane stays for the wave's shared cell writes
     // clamped positions, so that every load is unconditional (n > 0)
-    const int64_t sp = s > 0 ? s - 1 : 0, sc = s < n ? s : (int64_t)n - 1;
+    const int64_t sp = s > 0 ? (s <= n ? s - 1 : (int64_t)n - 1) : 0, sc = s < n ? s : (int64_t)n - 1;
     uint32_t kp = 0, kc = 0, i = 0;
     double x = 0.0, y = 0.0, t = 0.0;
     if (n > 0) {
@@ -318,10 +319,21 @@ __global__ __launch_bounds__(kThreads) void k_offsets_records(
         t = xyt[3 * (size_t)i + 2];
     }
     const int64_t nvalid = (int64_t)n - (int64_t)(counters[0] + counters[1] + counters[2]);
-    const int64_t lo = s == 0 ? -1 : (int64_t)kp;
-    const int64_t hi = s == n ? (int64_t)g.ncell : (int64_t)kc;
-    for (int64_t c = lo + 1; c <= hi; ++c) cell_start[c] = (uint32_t)s;
-    if (s >= nvalid) return;
+    // cells (lo, hi] start at s; runs of empty bins can be long, so runs of
+    // more than two cells are written by the whole wave, 64 cells a step
+    const int32_t lo = !act ? 0 : (s == 0 ? -1 : (int32_t)kp);
+    const int32_t hi = !act ? 0 : (s == n ? g.ncell : (int32_t)kc);
+    const bool wide = hi - lo > 2;
+    if (!wide) {
+        for (int32_t c = lo + 1; c <= hi; ++c) cell_start[c] = (uint32_t)s;
+    }
+    for (unsigned long long m = __ballot(wide); m != 0ull; m &= m - 1ull) {
+        const int src = __builtin_ctzll(m);
+        const int32_t wlo = __shfl(lo, src, 64), whi = __shfl(hi, src, 64);
+        const uint32_t ws = (uint32_t)__shfl((int32_t)s, src, 64);
+        for (int32_t c = wlo + 1 + lane; c <= whi; c += 64) cell_start[c] = ws;
+    }
+    if (!act || s >= nvalid) return;
     double hv, tv;
     (void)point_bandwidths(g, hst, i, &hv, &tv);  // valid: invalid pairs sort past nvalid
     const Footprint f = footprint(g, x, y, t, hv, tv);

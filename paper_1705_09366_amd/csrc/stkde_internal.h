@@ -46,7 +46,7 @@ static_assert(sizeof(PointRec) == 32, "record layout");
 // Binning geometry of a point set.
 struct SetGeom {
     int32_t gx, gy, gt;       // base grid
-    int32_t cxy, ct;          // bin edge in x/y and in t (voxels)
+    int32_t cx, cxy, ct;      // bin edge in x, in y, and in t (voxels)
     int32_t ncx, ncy, nct;    // bins per axis
     int32_t ncell;            // ncx * ncy * nct
     double x0, y0, t0;
@@ -87,7 +87,7 @@ struct alignas(16) InstDev {
     int32_t gx, gy, gt;                  // instance grid
     int32_t ox, oy, ot;                  // its voxel (0,0,0) in the set's base grid
     int32_t Hs, Ht;                      // instance loop bounds
-    int32_t cxy, ct, ncx, ncy, nct;      // set bins
+    int32_t cx, cxy, ct, ncx, ncy, nct;  // set bins (edges in x, y, t; bins per axis)
     int32_t ntx, nty, ntiles, tile_base; // instance tiles; first global tile index
     uint32_t flags;                      // kInstMass, kInstFull
     float inv_hv2, inv_tv2, cnorm;
@@ -235,8 +235,8 @@ struct TileBins {
 __device__ inline TileBins tile_bins(const InstDev& D, int32_t bx0, int32_t by0, int32_t bt0,
                                      int32_t rows) {
     TileBins b;
-    b.cx0 = clamp_i32(floordiv_i(bx0 - D.Hs - 1, D.cxy), 0, D.ncx - 1);
-    b.cx1 = clamp_i32(floordiv_i(bx0 + kTileXY - 1 + D.Hs + 1, D.cxy), 0, D.ncx - 1);
+    b.cx0 = clamp_i32(floordiv_i(bx0 - D.Hs - 1, D.cx), 0, D.ncx - 1);
+    b.cx1 = clamp_i32(floordiv_i(bx0 + kTileXY - 1 + D.Hs + 1, D.cx), 0, D.ncx - 1);
     b.cy0 = clamp_i32(floordiv_i(by0 - D.Hs - 1, D.cxy), 0, D.ncy - 1);
     b.cy1 = clamp_i32(floordiv_i(by0 + kTileXY - 1 + D.Hs + 1, D.cxy), 0, D.ncy - 1);
     b.ct0 = clamp_i32(floordiv_i(bt0 - D.Ht - 1, D.ct), 0, D.nct - 1);
