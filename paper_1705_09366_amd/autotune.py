@@ -182,8 +182,8 @@ def candidates_tile(desc: Desc) -> List[int]:
 
 
 def tune(points, desc: Desc, reps: int = 5, log=None, operand_form: int = 0) -> Tuple[Tuning, float, List]:
-    """Coordinate search: tile rows with default bins, then bin edges, then
-    the split share; returns (best tuning, its ms, every measurement)."""
+    """Search: every (tile rows, bin edges) pair, then the split share of
+    the best; returns (best tuning, its ms, every measurement)."""
     of = operand_form
     table = []
 
@@ -203,21 +203,20 @@ def tune(points, desc: Desc, reps: int = 5, log=None, operand_form: int = 0) -> 
     table.append(([0, 0, 0, 0], default_ms))
     if log:
         log(f"  library default: {default_ms:.3f} ms")
+    hv, tv = desc.hs / desc.sres, desc.ht / desc.tres
+    # y edges around the bandwidth (x bins are narrow whatever the y edge);
+    # t edges of 8 voxels and about a half and a quarter of the window
+    cell_opts = sorted({(c, d) for c in (12, 16, 20, 24, max(16, 8 * math.ceil(hv / 4)))
+                        for d in (8, max(8, 4 * math.ceil(tv / 2)), max(8, 4 * math.ceil(tv / 4)))
+                        if c <= 256 and d <= 256})
+    # tile rows and bin edges together (the best edges depend on the rows)
     best, best_ms = None, math.inf
     for tt in candidates_tile(desc):
-        t = Tuning(tt, 0, 0, 0, 0, of)
-        ms = run(t)
-        if ms < best_ms:
-            best, best_ms = t, ms
-    hv, tv = desc.hs / desc.sres, desc.ht / desc.tres
-    cell_opts = sorted({(c, d) for c in (16, max(16, 8 * math.ceil(hv / 4)))
-                        for d in (max(8, 4 * math.ceil(tv / 2)), max(8, 4 * math.ceil(tv / 4)))
-                        if c <= 256 and d <= 256})
-    for cxy, ct in cell_opts:
-        t = Tuning(best.tile_t, cxy, ct, 0, 0, of)
-        ms = run(t)
-        if ms < best_ms:
-            best, best_ms = t, ms
+        for cxy, ct in [(0, 0)] + cell_opts:
+            t = Tuning(tt, cxy, ct, 0, 0, of)
+            ms = run(t)
+            if ms < best_ms:
+                best, best_ms = t, ms
     for ss in (512, 8192):
         t = Tuning(best.tile_t, best.cell_xy, best.cell_t, ss, 0, of)
         ms = run(t)
@@ -242,16 +241,21 @@ def tuning_workloads():
                        Desc(gx=gx, gy=gy, gt=gt, hs=hs, ht=ht))
 
 
-def build_cache(path: str, kahan_modes=(True, False), reps: int = 5, log=print, forms=(0, 1)):
+def build_cache(path: str, kahan_modes=(True, False), reps: int = 5, log=print, forms=(0, 1),
+                merge: Optional[str] = None):
     """Tune every synthetic workload and write the cache (fastest per key),
-    for each operand form in ``forms`` (0 the default, 1 FP32)."""
+    for each operand form in ``forms`` (0 the default, 1 FP32).  With
+    ``merge``, the entries of that cache whose keys this run does not tune
+    are kept."""
     import torch
     entries: Dict[str, Dict] = {}
+    tuned = set()
     for name, pts, d0 in tuning_workloads():
         dev_pts = torch.from_numpy(pts).cuda()
         for kahan, form in ((k_, f_) for k_ in kahan_modes for f_ in forms):
             desc = Desc(**{**d0.__dict__, "flags": FLAG_KAHAN if kahan else 0})
             k = key(desc, len(pts), fp32=form == 1)
+            tuned.add(k)
             log(f"[tune] {name} kahan={kahan} operand_form={form} -> {k}")
             best, ms, table = tune(dev_pts, desc, reps, log, form)
             base = table[0][1]  # the library's default tuning
@@ -263,6 +267,10 @@ def build_cache(path: str, kahan_modes=(True, False), reps: int = 5, log=print, 
                               "ms": ms, "gain": gain, "workload": name, "default_ms": base}
         del dev_pts
         torch.cuda.empty_cache()
+    if merge:
+        for k, e in _load(merge).items():
+            if k not in tuned:
+                entries[k] = e
     data = {"version": CACHE_VERSION, "arch": ARCH,
             "made": time.strftime("%Y-%m-%d"), "entries": entries}
     with open(path, "w") as f:
@@ -275,6 +283,11 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser(description="tune the gather on this GPU")
     ap.add_argument("--build-cache", metavar="PATH", required=True)
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--kahan-only", action="store_true", help="tune the compensated keys only")
+    ap.add_argument("--forms", default="0,1", help="operand forms to tune (0 two-term, 1 FP32)")
+    ap.add_argument("--merge", metavar="PATH", help="keep this cache's entries for keys not tuned")
     a = ap.parse_args()
     sys.path.insert(0, os.path.dirname(HERE))
-    build_cache(a.build_cache, reps=a.reps, log=lambda m: print(m, flush=True))
+    build_cache(a.build_cache, kahan_modes=(True,) if a.kahan_only else (True, False), reps=a.reps,
+                log=lambda m: print(m, flush=True), forms=tuple(int(f) for f in a.forms.split(",")),
+                merge=a.merge)
