@@ -86,9 +86,21 @@ def _cpu_threads():
     return n
 
 
-def _traffic_from_profile(kernel_src_hash):
+def profiled_sources_hash():
+    """SHA-256 of what shapes the gather's launches and memory traffic: every
+    source file of the library (sorted by name) and the tuning cache."""
+    csrc = os.path.join(ROOT, "paper_1705_09366_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    h.update(open(os.path.join(ROOT, "paper_1705_09366_amd", "tuned_gfx950.json"), "rb").read())
+    return h.hexdigest()
+
+
+def _traffic_from_profile(sources_hash):
     """HBM bytes per launch of the gather kernel from a committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
+    counter summary, if it was taken on the current sources and tunings."""
     path = os.path.join(ROOT, "profiles", "gather_clustered1M_pmc.json")
     if not os.path.exists(path):
         return None
@@ -96,7 +108,7 @@ def _traffic_from_profile(kernel_src_hash):
         rec = json.load(open(path))
     except Exception:
         return None
-    if rec.get("gather_src_sha256") != kernel_src_hash:
+    if rec.get("src_sha256") != sources_hash:
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -625,13 +637,11 @@ def main():
     else:
         bound, unit, peak = "mfma", "TFLOP/s", MFMA_F32_PEAK_TFLOPS
         achieved = alg_flops / (gather_ms * 1e-3) / 1e12
-    # the counters hold for the kernel source and work list they were taken on
-    src = b"".join(open(os.path.join(ROOT, "paper_1705_09366_amd", "csrc", f), "rb").read()
-                   for f in ("gather.hip", "pass.hip"))
-    # ... and for the workload they were taken on (the default run)
+    # the counters hold for the sources and tunings they were taken on, and
+    # for the workload they were taken on (the default run)
     profiled = (args.workload == "clustered-1M" and kahan and not args.adaptive and kern == 0 and not args.corner
                 and tuning_src.startswith("autotune") and not args.fp32_operands)
-    traffic = _traffic_from_profile(hashlib.sha256(src).hexdigest()) if profiled else None
+    traffic = _traffic_from_profile(profiled_sources_hash()) if profiled else None
 
     value = evals / (ms_per_step * 1e-3)
     rec = {
