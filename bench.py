@@ -482,7 +482,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--tile-t", type=int, default=0, help="tuning: time rows per tile (16/32)")
-    ap.add_argument("--cell-xy", type=int, default=0, help="tuning: bin edge in x, y")
+    ap.add_argument("--cell-xy", type=int, default=0, help="tuning: bin edge in y (x bins are narrower)")
     ap.add_argument("--cell-t", type=int, default=0, help="tuning: bin edge in t")
     ap.add_argument("--tuning", default="auto", choices=("auto", "default"),
                     help="auto: the autotune cache's pinned tuning for the workload (when it has "

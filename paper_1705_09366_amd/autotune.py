@@ -229,12 +229,14 @@ def tuning_workloads():
     """Synthetic workloads spanning the benchmark bandwidths and densities
     (yielded one at a time): clustered sets (the benchmark generator with
     other seeds) on 256^2 x 64, 512^2 x 365 and 1024^2 x 256 grids,
-    hs 3..50, ht 2..30 voxels, n 20k..1M."""
+    hs 3..50, ht 2..30 voxels (ht about 0.6 hs, and the short windows of
+    the world-scale pairs, hs 10 / ht 3 and hs 30 / ht 5), n 20k..1M."""
     import workloads
     rng = workloads.rng_for(90)
     shapes = [(256, 256, 64), (512, 512, 365), (1024, 1024, 256)]
     for gx, gy, gt in shapes:
-        for hs, ht in ((3.0, 2.0), (5.0, 4.0), (10.0, 7.0), (20.0, 14.0), (30.0, 20.0), (50.0, 30.0)):
+        for hs, ht in ((3.0, 2.0), (5.0, 4.0), (10.0, 7.0), (20.0, 14.0), (30.0, 20.0), (50.0, 30.0),
+                       (10.0, 3.0), (30.0, 5.0)):
             for n in (20_000, 200_000, 1_000_000):
                 pts = workloads.clustered(rng, 64 if n >= 200_000 else 16, n, gx, gy, gt)
                 yield (f"tune-{n}-{gx}x{gy}x{gt}-hs{hs:g}-ht{ht:g}", pts,
