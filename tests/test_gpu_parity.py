@@ -227,10 +227,12 @@ def test_full_size_sampled(torch_cuda, which, flags):
 
 
 @pytest.mark.parametrize("grid,cells", [
-    ((96, 80, 40), (16, 8)),       # few bins: one 8-bit pass
+    ((64, 80, 40), (16, 8)),       # 8 x 5 x 5 bins (x bins 8 voxels): one 8-bit pass
     ((512, 512, 64), (4, 4)),      # 2^18 bins: 19-bit keys, two 10-bit passes
     ((512, 512, 256), (4, 4)),     # 2^20 bins: 21-bit keys, two 11-bit passes
     ((1024, 1024, 256), (4, 4)),   # 2^22 bins: 23-bit keys, three 8-bit passes
+    ((2048, 2048, 68), (4, 4)),    # 4.5M bins with 4-voxel x bins: x bins widen to 8,
+                                   # 2.2M bins, 22-bit keys, two 11-bit passes
 ])
 def test_radix_digit_widths(torch_cuda, grid, cells):
     """Small bins force keys of 7 to 23 bits through every digit width of the
