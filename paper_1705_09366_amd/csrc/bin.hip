@@ -3,9 +3,10 @@
 // Stages (all deterministic; atomics appear only in integer counters whose
 // final values do not depend on order):
 //   1. transform: FP64 point -> voxel coordinates, support footprint clipped
-//      to the grid, bin key (bins narrow in x, bandwidth-sized in y and t).  Points whose footprint misses the grid, and
-//      points with a non-finite coordinate, get the key `ncell`, which sorts
-//      after every bin and is never visited.
+//      to the grid, bin key (bins narrow in x, bandwidth-sized in y and t).
+//      Points whose footprint misses the grid, and points with a non-finite
+//      coordinate, get the key `ncell`, which sorts after every bin and is
+//      never visited.
 //   2. stable LSD radix sort of (key, index) with 8- to 11-bit digits, 1-3
 //      passes.
 //      This is the device form of the per-subdomain point lists that the
