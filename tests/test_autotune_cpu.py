@@ -116,3 +116,25 @@ def test_operand_form_keys_are_separate(tmp_path):
         kb_near_fp32: {"tuning": [32, 16, 8, 0]}}}))
     t, src = autotune.resolve(big, 4_000_000, str(only))
     assert t is None or "/fp32" not in src
+
+
+def test_tune_searches_rows_and_bins_together(monkeypatch):
+    """The best (tile rows, bin edges) pair is found even where the best rows
+    with default bins differ from the best rows overall."""
+    d = Desc(gx=512, gy=512, gt=365, hs=50.0, ht=30.0, flags=FLAG_KAHAN)
+
+    def fake_measure(points, desc, t, reps=5):
+        if t.tile_t == 0:
+            return 10.0
+        if (t.tile_t, t.cell_xy, t.cell_t) == (16, 20, 8):
+            return 7.0
+        # 32-row tiles win with the default bins and with every other edge pair
+        return {16: 9.0, 32: 8.0}[t.tile_t] + (0.5 if t.cell_xy else 0.0)
+
+    monkeypatch.setattr(autotune, "measure", fake_measure)
+    best, ms, table = autotune.tune(None, d)
+    assert (best.tile_t, best.cell_xy, best.cell_t, best.split_share) == (16, 20, 8, 0)
+    assert ms == 7.0
+    # every pair was measured: both row counts with the default and each edge pair
+    measured = {tuple(e[0][:3]) for e in table}
+    assert (32, 0, 0) in measured and (16, 20, 8) in measured and (32, 20, 8) in measured
