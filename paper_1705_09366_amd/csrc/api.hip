@@ -68,7 +68,7 @@ namespace {
 
 constexpr int64_t kMaxDim = 65535;
 constexpr int32_t kXBin = 8;           // x bin edge in voxels (see make_set_geom)
-constexpr int32_t kMaxCells = 1 << 22;  // keys of at most 23 bits: <= 3 radix passes (<= 2 below 2^22 - 1 bins)
+constexpr int32_t kMaxCells = 1 << 22;  // keys of at most 23 bits: <= 3 radix passes (<= 2 below 2^22 - 2 bins)
 constexpr int32_t kMaxBatch = 4096;
 constexpr double kSparseCandidates = 384.0;  // half the gather's survivor buffer
 constexpr uint32_t kKnownFlags = STKDE_FLAG_KAHAN | STKDE_FLAG_MASS | STKDE_FLAG_POINT_STATS |
@@ -271,7 +271,6 @@ stkde::InstDev make_dev(const stkde::InstGeom& ig, const stkde::SetGeom& sg, con
     stkde::InstDev d{};
     d.cell_start = reinterpret_cast<const uint32_t*>(set_mem + sl.cell_start);
     d.recs = reinterpret_cast<const stkde::PointRec*>(set_mem + sl.recs);
-    d.counters = reinterpret_cast<const unsigned long long*>(set_mem + sl.counters);
     d.bw = adaptive ? reinterpret_cast<const float4*>(set_mem + sl.bw) : nullptr;
     d.out = out;
     d.stats = stats;

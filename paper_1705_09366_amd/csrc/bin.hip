@@ -1,12 +1,11 @@
 // bin.hip -- binning of points into space-time bins on the device.
 //
-// Stages (all deterministic; atomics appear only in integer counters whose
-// final values do not depend on order):
+// Stages (all deterministic):
 //   1. transform: FP64 point -> voxel coordinates, support footprint clipped
 //      to the grid, bin key (bins narrow in x, bandwidth-sized in y and t).
-//      Points whose footprint misses the grid, and points with a non-finite
-//      coordinate, get the key `ncell`, which sorts after every bin and is
-//      never visited.
+//      Points whose footprint misses the grid, with an invalid bandwidth
+//      pair or with a non-finite coordinate get keys ncell + 0, 1, 2, which
+//      sort after every bin and are never visited.
 //   2. stable LSD radix sort of (key, index) with 8- to 11-bit digits, 1-3
 //      passes.
 //      This is the device form of the per-subdomain point lists that the
@@ -14,7 +13,7 @@
 //   3. bin offsets, cell_start[c] = first sorted position with key >= c, and
 //      (same kernel) per sorted point the 32-byte PointRec (voxel-space
 //      coordinates as FP32 head + FP16 tail, and the clipped footprint box).
-// The bin offsets, records and counters form the *binned set*, which stays
+// The bin offsets and records form the *binned set*, which stays
 // valid for any number of later density computations on the base grid or a
 // window of it with bandwidths up to the set's; the sort buffers are scratch.
 #include <utility>
@@ -83,11 +82,6 @@ __device__ inline uint32_t bin_key(const SetGeom& g, const Footprint& f) {
     return (uint32_t)((ct * g.ncy + cy) * g.ncx + cx);
 }
 
-__global__ void k_zero_u64(unsigned long long* p, int count) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) p[i] = 0ull;
-}
-
 // A point's voxel bandwidths: the set's, or its own pair (hs_i / sres,
 // ht_i / tres) when it carries one; false for a pair that is not finite and
 // positive or exceeds the set's (bins and tiles are sized by the set's).
@@ -107,28 +101,20 @@ __device__ inline bool point_bandwidths(const SetGeom& g, const double* __restri
 __global__ __launch_bounds__(kThreads) void k_transform(SetGeom g, const double* __restrict__ xyt,
                                                         const double* __restrict__ hst, int32_t n,
                                                         uint32_t* __restrict__ keys,
-                                                        uint32_t* __restrict__ vals,
-                                                        unsigned long long* __restrict__ counters) {
+                                                        uint32_t* __restrict__ vals) {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    bool nonfinite = false, culled = false, badbw = false;
     if (i < n) {
         double hv, tv;
         const bool bw_ok = point_bandwidths(g, hst, i, &hv, &tv);
         const Footprint f = footprint(g, xyt[3 * (size_t)i], xyt[3 * (size_t)i + 1],
                                       xyt[3 * (size_t)i + 2], bw_ok ? hv : g.hv, bw_ok ? tv : g.tv);
-        uint32_t key = (uint32_t)g.ncell;
-        if (!f.finite) nonfinite = true;
-        else if (!bw_ok) badbw = true;
-        else if (!f.inside) culled = true;
+        uint32_t key;
+        if (!f.finite) key = (uint32_t)(g.ncell + kKeyNonFinite);
+        else if (!bw_ok) key = (uint32_t)(g.ncell + kKeyBadBw);
+        else if (!f.inside) key = (uint32_t)(g.ncell + kKeyCulled);
         else key = bin_key(g, f);
         keys[i] = key;
         vals[i] = (uint32_t)i;
-    }
-    const unsigned long long mnf = __ballot(nonfinite), mcu = __ballot(culled), mbw = __ballot(badbw);
-    if ((threadIdx.x & 63) == 0) {
-        if (mnf) atomicAdd(&counters[0], (unsigned long long)__popcll(mnf));
-        if (mcu) atomicAdd(&counters[1], (unsigned long long)__popcll(mcu));
-        if (mbw) atomicAdd(&counters[2], (unsigned long long)__popcll(mbw));
     }
 }
 
@@ -289,20 +275,20 @@ __device__ inline uint32_t pack_tail(double v, float head) {
 
 // Per sorted position s in [0, n]:
 //  - bin offsets: cell_start[c] = lower_bound(sorted keys, c) for c in
-//    [0, ncell]; s is the lower bound of the cells in (key[s - 1], key[s]]
-//    (key[-1] = -1, key[n] = ncell), so each cell is written once, by the
-//    position that starts it;
-//  - for a valid point (s below n minus the points the transform counted as
-//    non-finite, culled or with an invalid bandwidth pair, which sort last):
-//    its record, and with per-point bandwidths its terms (1/hv_i^2,
+//    [0, ncell + kKeySentinels]; s is the lower bound of the cells in
+//    (key[s - 1], key[s]] (key[-1] = -1, key[n] = ncell + kKeySentinels),
+//    so each cell is written once, by the position that starts it (the
+//    offsets past ncell count the points that are never visited);
+//  - for a valid point (key below ncell): its record, and with per-point
+//    bandwidths its terms (1/hv_i^2,
 //    1/tv_i^2, (hv^2 tv) / (hv_i^2 tv_i)): the weight carries the point's own
 //    normalisation relative to the set's, which the store applies.
 // vals is a permutation of [0, n), so the point's coordinates are loaded
 // before its validity is known and the loads are in flight together.
 __global__ __launch_bounds__(kThreads) void k_offsets_records(
     SetGeom g, const double* __restrict__ xyt, const double* __restrict__ hst,
-    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
-    const unsigned long long* __restrict__ counters, int32_t n, uint32_t* __restrict__ cell_start,
+    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, int32_t n,
+    uint32_t* __restrict__ cell_start,
     PointRec* __restrict__ recs, float4* __restrict__ bw, double* __restrict__ x64) {
     const int64_t s = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     const int lane = threadIdx.x & 63;
@@ -319,11 +305,10 @@ __global__ __launch_bounds__(kThreads) void k_offsets_records(
         y = xyt[3 * (size_t)i + 1];
         t = xyt[3 * (size_t)i + 2];
     }
-    const int64_t nvalid = (int64_t)n - (int64_t)(counters[0] + counters[1] + counters[2]);
     // cells (lo, hi] start at s; runs of empty bins can be long, so runs of
     // more than two cells are written by the whole wave, 64 cells a step
     const int32_t lo = !act ? 0 : (s == 0 ? -1 : (int32_t)kp);
-    const int32_t hi = !act ? 0 : (s == n ? g.ncell : (int32_t)kc);
+    const int32_t hi = !act ? 0 : (s == n ? g.ncell + kKeySentinels : (int32_t)kc);
     const bool wide = hi - lo > 2;
     if (!wide) {
         for (int32_t c = lo + 1; c <= hi; ++c) cell_start[c] = (uint32_t)s;
@@ -334,9 +319,9 @@ __global__ __launch_bounds__(kThreads) void k_offsets_records(
         const uint32_t ws = (uint32_t)__shfl((int32_t)s, src, 64);
         for (int32_t c = wlo + 1 + lane; c <= whi; c += 64) cell_start[c] = ws;
     }
-    if (!act || s >= nvalid) return;
+    if (!act || s == n || kc >= (uint32_t)g.ncell) return;
     double hv, tv;
-    (void)point_bandwidths(g, hst, i, &hv, &tv);  // valid: invalid pairs sort past nvalid
+    (void)point_bandwidths(g, hst, i, &hv, &tv);  // valid: invalid pairs sort past the bins
     const Footprint f = footprint(g, x, y, t, hv, tv);
     if (hst)
         bw[s] = make_float4((float)(1.0 / (hv * hv)), (float)(1.0 / (tv * tv)),
@@ -373,9 +358,8 @@ size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 SetLayout layout_set(const SetGeom& g, int64_t n, bool adaptive, bool exact) {
     SetLayout l{};
     size_t o = 0;
-    l.cell_start = o; o = al256(o + ((size_t)g.ncell + 1) * 4);
+    l.cell_start = o; o = al256(o + ((size_t)g.ncell + kKeySentinels + 1) * 4);
     l.recs = o; o = al256(o + (size_t)n * sizeof(PointRec));
-    l.counters = o; o = al256(o + 4 * 8);
     l.bw = o; o = al256(o + (adaptive ? (size_t)n * sizeof(float4) : 0));
     l.x64 = o; o = al256(o + (exact ? (size_t)n * 3 * sizeof(double) : 0));
     l.total = o;
@@ -407,14 +391,12 @@ hipError_t launch_bin(const SetGeom& g, const double* d_xyt, int32_t n, uint8_t*
     uint32_t* hist = reinterpret_cast<uint32_t*>(sort + so.hist);
     uint32_t* totals = reinterpret_cast<uint32_t*>(sort + so.totals);
     uint32_t* cs = reinterpret_cast<uint32_t*>(set + sl.cell_start);
-    unsigned long long* ctr = reinterpret_cast<unsigned long long*>(set + sl.counters);
     const int nb = (n + kThreads - 1) / kThreads;
 
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ctr, 4);
-    hipLaunchKernelGGL(k_transform, dim3(nb), dim3(kThreads), 0, s, g, d_xyt, d_hst, n, k0, v0, ctr);
+    hipLaunchKernelGGL(k_transform, dim3(nb), dim3(kThreads), 0, s, g, d_xyt, d_hst, n, k0, v0);
 
-    // keys are at most ncell (culled points): ceil(bits / 11) passes of equal digits
-    const int bits = bits_for((uint32_t)g.ncell);
+    // keys are at most ncell + 2 (non-finite points): ceil(bits / 11) passes of equal digits
+    const int bits = bits_for((uint32_t)(g.ncell + kKeySentinels - 1));
     const int passes = bits <= 8 ? 1 : (bits + kMaxDigitBits - 1) / kMaxDigitBits;
     const int dbits = bits <= 8 ? 8 : (bits + passes - 1) / passes;
     const int nbuck = 1 << dbits;
@@ -431,7 +413,7 @@ hipError_t launch_bin(const SetGeom& g, const double* d_xyt, int32_t n, uint8_t*
         std::swap(v0, v1);
     }
     hipLaunchKernelGGL(k_offsets_records, dim3((uint32_t)(((int64_t)n + kThreads) / kThreads)), dim3(kThreads), 0,
-                       s, g, d_xyt, d_hst, k0, v0, ctr, n, cs, reinterpret_cast<PointRec*>(set + sl.recs),
+                       s, g, d_xyt, d_hst, k0, v0, n, cs, reinterpret_cast<PointRec*>(set + sl.recs),
                        d_hst ? reinterpret_cast<float4*>(set + sl.bw) : nullptr,
                        exact ? reinterpret_cast<double*>(set + sl.x64) : nullptr);
     return hipGetLastError();

@@ -345,9 +345,11 @@ __global__ __launch_bounds__(64) void k_finalize(const InstDev* __restrict__ des
         st[0] = (D.flags & kInstMass) ? v * D.mass_scale : 0.0;
         st[1] = 0.0;
         st[2] = 0.0;
-        st[3] = (double)D.counters[0];
-        st[4] = (double)D.counters[1];
-        st[5] = (double)D.counters[2];
+        // the set's points that are never visited, from the offsets of their keys
+        const uint32_t* cs = D.cell_start + (size_t)D.ncx * D.ncy * D.nct;
+        st[3] = (double)(cs[kKeyNonFinite + 1] - cs[kKeyNonFinite]);
+        st[4] = (double)(cs[kKeyCulled + 1] - cs[kKeyCulled]);
+        st[5] = (double)(cs[kKeyBadBw + 1] - cs[kKeyBadBw]);
         st[6] = 0.0;
         st[7] = 0.0;
     }

@@ -44,6 +44,11 @@ struct alignas(16) PointRec {
 static_assert(sizeof(PointRec) == 32, "record layout");
 
 // Binning geometry of a point set.
+// Keys of the points that are never visited sort after every bin: culled
+// (footprint off the grid) ncell + 0, invalid bandwidth pair ncell + 1,
+// non-finite coordinate ncell + 2.  Their bin offsets give their counts.
+constexpr int32_t kKeyCulled = 0, kKeyBadBw = 1, kKeyNonFinite = 2, kKeySentinels = 3;
+
 struct SetGeom {
     int32_t gx, gy, gt;       // base grid
     int32_t cx, cxy, ct;      // bin edge in x, in y, and in t (voxels)
@@ -74,7 +79,6 @@ struct InstGeom {
 struct alignas(16) InstDev {
     const uint32_t* cell_start;          // set: bin offsets
     const PointRec* recs;                // set: records in bin order
-    const unsigned long long* counters;  // set: non-finite, culled, invalid bandwidth pairs
     const float4* bw;                    // set: per record (1/hv_i^2, 1/tv_i^2, weight, 0) when
                                          // its points carry their own bandwidths, else null
     const double* x64;                   // set: per record its FP64 voxel coordinates (xr, yr, tr)
@@ -166,9 +170,8 @@ constexpr int kCtrWords = 2 * kFetchLanes * kCtrStride;
 
 // ---- set memory (caller-owned, persistent) --------------------------------
 struct SetLayout {
-    size_t cell_start;   // (ncell + 1) u32
+    size_t cell_start;   // (ncell + kKeySentinels + 1) u32
     size_t recs;         // n PointRec
-    size_t counters;     // 4 x u64: non-finite, culled, invalid bandwidth pairs, 0
     size_t bw;           // n float4 (per-point bandwidths; 0 bytes without)
     size_t x64;          // n x 3 FP64 voxel coordinates (exact support tests; 0 bytes without)
     size_t total;
