@@ -199,3 +199,36 @@ def test_clustered_1m_sampled(torch_cuda, flags):
         assert int(st[2]) == oracle.exact_evals_adaptive(inst.points, pairs, _grid(g))
         assert st[0] == pytest.approx(m_pts, rel=1e-5)
     assert st[3] == 0 and st[5] == 0
+
+
+def test_every_invalid_kind_counted_together(torch_cuda):
+    """Non-finite coordinates, footprints that hold no sample point (here: off
+    the grid) and invalid pairs in one call: each kind gets its own count (a
+    non-finite point whose pair is also invalid counts as non-finite) and the
+    grid matches the oracle on the rest."""
+    _, g = workloads.small_random_case(95, max_g=40, max_n=120)
+    rng = np.random.default_rng(6)
+    # every other point well inside the grid, so that only those below are culled
+    lo = np.array([g["x0"], g["y0"], g["t0"]])
+    span = np.array([g["gx"] * g["sres"], g["gy"] * g["sres"], g["gt"] * g["tres"]])
+    pts = lo + rng.uniform(0.1, 0.9, (48, 3)) * span
+    # pairs whose windows and discs always hold a sample centre (a point whose
+    # footprint holds none is culled too): half-widths of at least 0.6 voxel
+    assert g["ht"] / g["tres"] >= 0.8 and g["hs"] / g["sres"] >= 0.8
+    pairs = _pairs(rng, len(pts), g, lo=0.75)
+    far = 1e6 * max(g["sres"], g["tres"])
+    pts[1, 0] = np.nan
+    pts[4, 2] = np.inf
+    pts[2] = [g["x0"] - far, g["y0"], g["t0"]]
+    pts[6] = [g["x0"], g["y0"] + far, g["t0"]]
+    pts[9] = [g["x0"], g["y0"], g["t0"] - far]
+    pairs[7] = [np.nan, g["ht"]]
+    pairs[10] = [g["hs"], -1.0]
+    pairs[4] = [0.0, g["ht"]]  # non-finite point and invalid pair
+    ref_pairs = pairs.copy()
+    ref_pairs[[7, 10, 4]] = np.nan
+    ref, evals = oracle.pbsym_adaptive(pts, ref_pairs, _grid(g))
+    gpu, st = _run(torch_cuda, pts, pairs, g, flags=4 | 8)
+    _check_close(gpu, ref)
+    assert (int(st[3]), int(st[4]), int(st[5])) == (2, 3, 2)
+    assert int(st[2]) == evals
