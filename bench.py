@@ -113,13 +113,12 @@ def _traffic_from_profile(sources_hash):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(inst, gpu_plan_fn, budget_s=20.0, pairs=None, kernel=0, corner=False):
+def cpu_baseline(inst, budget_s=20.0, pairs=None, kernel=0, corner=False):
     """Time the FP64 oracle on a bounded sample (the first k events of the
     workload on the full grid, with their bandwidth pairs when the workload
     has per-event bandwidths), growing k until the run takes a few seconds
-    or covers the whole workload.  Also returns the GPU's max error against
-    the oracle on that same sample."""
-    import numpy as np
+    or covers the whole workload.  Returns the record, the oracle's grid and
+    k (the caller compares the GPU on the same sample)."""
     import oracle
     g = oracle.Grid(gx=inst.gx, gy=inst.gy, gt=inst.gt, hs=inst.hs, ht=inst.ht,
                     sres=inst.sres, tres=inst.tres, x0=inst.x0, y0=inst.y0, t0=inst.t0,
@@ -138,14 +137,13 @@ def cpu_baseline(inst, gpu_plan_fn, budget_s=20.0, pairs=None, kernel=0, corner=
         if k >= n or dt * min(4, n / k) > budget_s:
             break
         k = min(n, k * 4)
-    gpu = gpu_plan_fn(k).astype(np.float64)
-    err = float(np.max(np.abs(gpu - ref)) / max(np.max(np.abs(ref)), 1e-300))
-    del ref
     sample = (f"first {k} of {n} events of the workload on the full {inst.gx}x{inst.gy}x{inst.gt} "
               f"grid (FP64 grid zeroing + PB-SYM accumulation"
               f"{' with per-event bandwidths' if pairs is not None else ''}, IO excluded)")
-    return {"value": evals / dt, "unit": "evals/s", "cores": th, "kind": "oracle",
-            "sample": sample, "seconds": round(dt, 3), "evals": int(evals)}, err
+    model, ncpu = cpu_info()
+    return ({"value": evals / dt, "unit": "evals/s", "cores": th, "kind": "oracle",
+             "sample": sample, "seconds": round(dt, 3), "evals": int(evals), "cpu_model": model,
+             "host_cpus": ncpu}, ref, k)
 
 
 def cpu_baseline_window(inst, out, budget_s=20.0, kernel=0, corner=False):
@@ -189,8 +187,9 @@ def cpu_baseline_window(inst, out, budget_s=20.0, kernel=0, corner=False):
     sample = (f"window {wx}x{wy}x{inst.gt} voxels at ({x0}, {y0}) around the densest region, "
               f"{len(sub)} of {len(p)} events (those within reach); FP64 PB-SYM with the whole n, "
               f"IO excluded")
+    model, ncpu = cpu_info()
     return {"value": evals / dt, "unit": "evals/s", "cores": th, "kind": "oracle", "sample": sample,
-            "seconds": round(dt, 3), "evals": int(evals)}, err
+            "seconds": round(dt, 3), "evals": int(evals), "cpu_model": model, "host_cpus": ncpu}, err
 
 
 def _median(v):
@@ -283,6 +282,22 @@ def bench_batch(args, dev):
         sc = float(oa.abs().max())
         if sc > 0:
             diff = max(diff, float((oa - ob).abs().max()) / sc)
+    # every grid of both forms against the FP64 oracle on its whole grid
+    import oracle
+    th = _cpu_threads()
+    errs = {"sequential": [], "batched": []}
+    t0 = time.perf_counter()
+    for i, oa, ob in zip(insts, outs_a, outs_b):
+        ref, _ = oracle.pbsym(i.points, oracle.Grid(gx=i.gx, gy=i.gy, gt=i.gt, hs=i.hs, ht=i.ht), nthreads=th)
+        errs["sequential"].append(error_stats(oa.cpu().numpy(), ref))
+        errs["batched"].append(error_stats(ob.cpu().numpy(), ref))
+        del ref
+    odt = time.perf_counter() - t0
+    vs_oracle = {k: {"max_rel_err": max(e["max_rel"] for e in v), "max_rms_rel_err": max(e["rms_rel"] for e in v),
+                     "support_mismatch": sum(e["mismatch"] for e in v), "grids": len(v)}
+                 for k, v in errs.items()}
+    _log(f"oracle on all {len(insts)} grids in {odt:.1f} s: sequential max {vs_oracle['sequential']['max_rel_err']:.3e}, "
+         f"batched max {vs_oracle['batched']['max_rel_err']:.3e}")
     rec = {"metric": "bandwidth-sweep makespan", "value": res["batched"], "unit": "ms",
            "higher_is_better": False, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "dtype": "f32", "data": "synthetic",
@@ -292,7 +307,8 @@ def bench_batch(args, dev):
            "speedup": res["sequential"] / res["batched"],
            "evals_per_s": {"sequential": evals / (res["sequential"] * 1e-3),
                            "batched": evals / (res["batched"] * 1e-3)},
-           "max_rel_diff_batched_vs_sequential": diff}
+           "max_rel_diff_batched_vs_sequential": diff,
+           "vs_oracle": vs_oracle, "oracle_seconds": round(odt, 2)}
     print(json.dumps(rec), flush=True)
 
 
@@ -324,7 +340,9 @@ def bench_serve(args, dev):
     reqs = [mk(r) for r in raw]
     warm, reqs = reqs[:100], reqs[100:]
 
-    def serve(requests, rate, batching):
+    def serve(requests, rate, batching, keep=()):
+        """Serve `requests` (Poisson arrivals at `rate`, or all at once); the
+        outputs of the requests whose positions are in `keep` are returned."""
         srv = Server(executor=ex, max_batch=256 if batching else 1, max_inflight=2 if batching else 1)
         srv.resident = resident
         rng = np.random.default_rng(170509366 + int(rate * 1000))
@@ -332,38 +350,66 @@ def bench_serve(args, dev):
         arr = t0 + (np.cumsum(rng.exponential(1.0 / rate, len(requests))) if rate else np.zeros(len(requests)))
         i = 0
         vox = 0
+        kept, tks = {}, []
         while i < len(requests) or not srv.idle():
             now = time.perf_counter()
             while i < len(requests) and arr[i] <= now:
-                srv.submit(requests[i], t_arrival=float(arr[i]))
+                tks.append(srv.submit(requests[i], t_arrival=float(arr[i])))
                 i += 1
             srv.poll()
             for tk in srv.finished:
-                if tk.out is not None:
+                if tk.charged:
                     vox += tk.out.numel()
-                    tk.out = None
+                    if tk.rid - tks[0].rid in keep:
+                        kept[tk.rid - tks[0].rid] = tk.out
+                    srv.release(tk)
         dt = time.perf_counter() - t0
         st = srv.latency_stats()
-        st.update({"requests_per_s": len(requests) / dt, "voxels_per_s": vox / dt, "seconds": dt})
-        return st
+        st.update({"requests_per_s": len(requests) / dt, "voxels_per_s": vox / dt, "seconds": dt,
+                   "failed": len(srv.failed)})
+        return st, kept
 
     serve(warm, 0, True)
-    sat = serve(reqs, 0, True)
+    # 32 sampled requests of the saturation run are kept for the oracle
+    sample = sorted(int(v) for v in np.random.default_rng(170509366).choice(len(reqs), 32, replace=False))
+    sat, kept = serve(reqs, 0, True, keep=set(sample))
     rate_sat = sat["requests_per_s"]
     _log(f"saturation: {rate_sat:.1f} req/s ({sat['ticks']} ticks)")
     levels = []
     for frac in (0.25, 0.5, 0.75, 0.9):
         lam = frac * rate_sat
-        b = serve(reqs, lam, True)
-        f = serve(reqs, lam, False)
+        b, _ = serve(reqs, lam, True)
+        f, _ = serve(reqs, lam, False)
         _log(f"load {frac:.2f} ({lam:.1f} req/s): batched p50 {b['p50_ms']:.2f} p99 {b['p99_ms']:.2f} ms; "
              f"one-at-a-time p50 {f['p50_ms']:.2f} p99 {f['p99_ms']:.2f} ms")
         levels.append({"load": frac, "rate": lam, "batched": b, "one_at_a_time": f})
+    # the sampled requests against the FP64 oracle on their windows (whole set n)
+    import oracle
+    th = _cpu_threads()
+    t0 = time.perf_counter()
+    worst, worst_rms, mism = 0.0, 0.0, 0
+    for j in sample:
+        r = reqs[j]
+        inst = sets[names.index(r.set)]
+        ref, _ = oracle.pbsym(inst.points, oracle.Grid(gx=r.gx, gy=r.gy, gt=r.gt, hs=r.hs, ht=r.ht,
+                                                       x0=float(r.ox), y0=float(r.oy), t0=float(r.ot)),
+                              nthreads=th)
+        got = kept[j].cpu().numpy()
+        if float(np.max(ref)) > 0.0:
+            e = error_stats(got, ref)
+            worst, worst_rms, mism = max(worst, e["max_rel"]), max(worst_rms, e["rms_rel"]), mism + e["mismatch"]
+        elif np.any(got):
+            worst = float("inf")
+        del ref
+    odt = time.perf_counter() - t0
+    _log(f"oracle on {len(sample)} sampled requests in {odt:.1f} s: max rel err {worst:.3e}")
     rec = {"metric": "serve saturation rate", "value": rate_sat, "unit": "requests/s",
            "higher_is_better": True, "n_gpus": 1, "data": "synthetic", "dtype": "f32",
            "config": {"workload": "serve-4sets-2048x2048x512", "requests": nreq,
                       "resident_bytes": resident},
-           "saturation": sat, "levels": levels}
+           "saturation": sat, "levels": levels,
+           "vs_oracle": {"requests": len(sample), "max_rel_err": worst, "max_rms_rel_err": worst_rms,
+                         "support_mismatch": mism, "seconds": round(odt, 2)}}
     print(json.dumps(rec), flush=True)
 
 
@@ -480,6 +526,9 @@ def main():
     ap.add_argument("--fp32-operands", action="store_true",
                     help="FP32 matrix-core operands in the gather (default: two FP16 terms where it has them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload only: skip the FP32-operand run and the nested "
+                         "uniform-10k and clustered-200k-hs50 records")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--tile-t", type=int, default=0, help="tuning: time rows per tile (16/32)")
     ap.add_argument("--cell-xy", type=int, default=0, help="tuning: bin edge in y (x bins are narrower)")
@@ -542,8 +591,7 @@ def main():
         import workloads
         pairs_np = workloads.adaptive_pairs(inst.points, inst.gx, inst.gy, inst.hs, inst.ht, inst.sres,
                                             inst.x0, inst.y0)
-    desc = m.Desc(gx=inst.gx, gy=inst.gy, gt=inst.gt, hs=inst.hs, ht=inst.ht, sres=inst.sres,
-                  tres=inst.tres, x0=inst.x0, y0=inst.y0, t0=inst.t0, flags=flags)
+    desc = _desc_of(m, inst, flags)
     if args.tile_t or args.cell_xy or args.cell_t:
         tuning, tuning_src = m.Tuning(args.tile_t, args.cell_xy, args.cell_t), "manual"
     elif args.tuning == "auto":
@@ -554,96 +602,22 @@ def main():
     if args.fp32_operands:
         tuning = dataclasses.replace(tuning or m.Tuning(), operand_form=1)
     operands = _operand_form(inst, tuning, kahan, args.adaptive, kern)
-    plan = m.Plan(desc, tuning)
     pts = torch.from_numpy(inst.points).to(dev)
     pairs = torch.from_numpy(pairs_np).to(dev) if args.adaptive else None
-
-    def compute(p, o, st=None, w=None):
-        if args.adaptive:
-            return p.compute_adaptive_into(pts, pairs, o, stats=st, workspace=w)
-        return p.compute_into(pts, o, stats=st, workspace=w)
-    out = torch.empty((inst.gx, inst.gy, inst.gt), dtype=torch.float32, device=dev)
-    stats = torch.zeros(8, dtype=torch.float64, device=dev)
-    ws = plan.workspace(n, dev)
-    stream = torch.cuda.current_stream(dev)
-    _log(f"workload {inst.name}: n={n}, grid {inst.gx}x{inst.gy}x{inst.gt}, "
-         f"workspace {ws.numel() / 2**20:.1f} MiB, kahan={kahan}")
-
-    # exact evaluation count (once, outside the timed region)
-    chk = m.Plan(m.Desc(**{**desc.__dict__, "flags": m.FLAG_POINT_STATS | m.FLAG_MASS
-                           | (flags & m.FLAG_ADAPTIVE)}), tuning)
-    cstats = torch.zeros(8, dtype=torch.float64, device=dev)
-    compute(chk, out, cstats, ws)
-    torch.cuda.synchronize()
-    cs = cstats.cpu().numpy()
-    evals = int(cs[2])
-    chk.close()
-    _log(f"evals {evals}, point mass {cs[1]:.9f}, grid mass {cs[0]:.9f}")
-
-    for _ in range(args.warmup):
-        compute(plan, out, stats, ws)
-    torch.cuda.synchronize()
-    _log(f"warmup {args.warmup} done")
-
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    plan.profile(args.steps)  # HIP events around each step's gather kernel
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        ev[k][0].record(stream)
-        compute(plan, out, stats, ws)
-        ev[k][1].record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    step_ms = sorted(a.elapsed_time(b) for a, b in ev)
-    kern_ms = plan.profile_read()
-    plan.profile(0)
-    if len(kern_ms) != args.steps:
-        raise SystemExit(f"expected {args.steps} gather timings, got {len(kern_ms)}")
-    gather_ms = sum(kern_ms) / len(kern_ms)
-    _log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step wall, median event "
-         f"{step_ms[len(step_ms) // 2]:.3f} ms, gather kernel {gather_ms:.3f} ms")
-    st = stats.cpu().numpy()
-
-    # stage timing outside the timed region: binning, and the whole
-    # accumulation pass (work list, gather, split reduction, mass)
-    reps = max(5, args.steps)
-    bev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-    gev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-    for k in range(reps):
-        bev[k][0].record(stream)
-        if args.adaptive:
-            plan.bin_adaptive(pts, pairs, ws)
-        else:
-            plan.bin(pts, ws)
-        bev[k][1].record(stream)
-        gev[k][0].record(stream)
-        plan.accumulate(n, out, ws)
-        gev[k][1].record(stream)
-    torch.cuda.synchronize()
-    bin_ms = sum(a.elapsed_time(b) for a, b in bev) / reps
-    pass_ms = sum(a.elapsed_time(b) for a, b in gev) / reps
-    _log(f"stage times: bin {bin_ms:.3f} ms, accumulation pass {pass_ms:.3f} ms")
-
+    _log(f"workload {inst.name}: n={n}, grid {inst.gx}x{inst.gy}x{inst.gt}, kahan={kahan}")
+    run = time_compute(m, desc, tuning, pts, pairs, args.steps, args.warmup, stages=True)
+    evals, out = run["evals"], run["out"]
     grid_bytes = inst.gx * inst.gy * inst.gt * 4
     alg_bytes = grid_bytes + n * (40 if args.adaptive else 24)  # points (and pairs) read once
-    alg_flops = 2.0 * evals  # one multiply and one add per (voxel, point) pair
-    # the binding roofline: HBM below the ridge point, FP32 matrix cores above it
-    if alg_flops / alg_bytes < MFMA_F32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9):
-        bound, unit, peak = "hbm", "GB/s", HBM_PEAK_GBS
-        achieved = alg_bytes / (gather_ms * 1e-3) / 1e9
-    else:
-        bound, unit, peak = "mfma", "TFLOP/s", MFMA_F32_PEAK_TFLOPS
-        achieved = alg_flops / (gather_ms * 1e-3) / 1e12
+    roof = _roofline(alg_bytes, 2.0 * evals, run["gather_ms"])
     # the counters hold for the sources and tunings they were taken on, and
     # for the workload they were taken on (the default run)
     profiled = (args.workload == "clustered-1M" and kahan and not args.adaptive and kern == 0 and not args.corner
                 and tuning_src.startswith("autotune") and not args.fp32_operands)
     traffic = _traffic_from_profile(profiled_sources_hash()) if profiled else None
-
-    value = evals / (ms_per_step * 1e-3)
+    if roof["bound"] == "hbm":
+        roof["traffic"] = traffic
+    value = evals / (run["ms_per_step"] * 1e-3)
     rec = {
         "metric": "voxel-point kernel evals/s",
         "value": value,
@@ -651,7 +625,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": run["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -665,12 +639,12 @@ def main():
                    "tuning": ([tuning.tile_t, tuning.cell_xy, tuning.cell_t, tuning.split_share]
                               if tuning else [0, 0, 0, 0]),
                    "tuning_source": tuning_src},
-        "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                     "frac": achieved / peak, "traffic": traffic if bound == "hbm" else None,
-                     "algorithmic": {"bytes": alg_bytes, "flops": alg_flops}},
-        "stage_ms": {"bin": bin_ms, "pass": pass_ms, "gather_kernel": gather_ms},
-        "mass": {"grid": float(st[0]), "points": float(cs[1])},
+        "roofline": roof,
+        "stage_ms": {"bin": run["bin_ms"], "pass": run["pass_ms"], "gather_kernel": run["gather_ms"],
+                     "median_step_event": run["median_step_ms"]},
+        "mass": {"grid": run["grid_mass"], "points": run["point_mass"]},
     }
+    headline_default = (args.workload == "clustered-1M" and not args.adaptive and kern == 0 and not args.corner)
 
     if not args.no_cpu_baseline and args.workload.startswith("world-"):
         cb, err = cpu_baseline_window(inst, out, args.cpu_budget, kern, args.corner)
@@ -678,8 +652,8 @@ def main():
         rec["max_rel_err_vs_oracle"] = err
         _log(f"gpu vs oracle on the window: max rel err {err:.3e}")
     elif not args.no_cpu_baseline:
-        def gpu_sample(k):
-            sp = m.Plan(m.Desc(**{**desc.__dict__, "flags": flags & ~m.FLAG_MASS}), tuning)
+        def gpu_sample(k, tun=tuning):
+            sp = m.Plan(m.Desc(**{**desc.__dict__, "flags": flags & ~m.FLAG_MASS}), tun)
             xs = torch.from_numpy(np.ascontiguousarray(inst.points[:k])).to(dev)
             if args.adaptive:
                 o = sp.compute_adaptive(xs, torch.from_numpy(np.ascontiguousarray(pairs_np[:k])).to(dev))
@@ -689,11 +663,233 @@ def main():
             r = o.cpu().numpy()
             sp.close()
             return r
-        cb, err = cpu_baseline(inst, gpu_sample, args.cpu_budget, pairs_np, kern, args.corner)
+        cb, ref, k = cpu_baseline(inst, args.cpu_budget, pairs_np, kern, args.corner)
+        est = error_stats(gpu_sample(k), ref)
         rec["cpu_baseline"] = cb
-        rec["max_rel_err_vs_oracle"] = err
-        _log(f"gpu vs oracle on the cpu sample: max rel err {err:.3e}")
+        rec["max_rel_err_vs_oracle"] = est["max_rel"]
+        rec["rms_rel_err_vs_oracle"] = est["rms_rel"]
+        rec["support_mismatch"] = est["mismatch"]
+        _log(f"gpu vs oracle on the cpu sample: max rel err {est['max_rel']:.3e}, rms {est['rms_rel']:.3e}, "
+             f"support mismatch {est['mismatch']}")
+        if headline_default and not args.no_extras:
+            rec["precision"] = precision_record(m, inst, desc, tuning, pts, operands, est, ref, k, gpu_sample,
+                                                args)
+        del ref
+        if headline_default:
+            cb["single_thread"] = cpu_single_thread(inst, min(n, 62_500))
+    if headline_default and not args.no_extras:
+        del out
+        run = None
+        torch.cuda.empty_cache()
+        rec["configs"] = other_configs(m, dev, args)
     print(json.dumps(rec), flush=True)
+
+
+def _desc_of(m, inst, flags):
+    return m.Desc(gx=inst.gx, gy=inst.gy, gt=inst.gt, hs=inst.hs, ht=inst.ht, sres=inst.sres,
+                  tres=inst.tres, x0=inst.x0, y0=inst.y0, t0=inst.t0, flags=flags)
+
+
+def _roofline(alg_bytes, alg_flops, gather_ms):
+    """The binding roofline of a workload for the gather kernel: HBM below the
+    ridge point, FP32 matrix cores above it."""
+    if alg_flops / alg_bytes < MFMA_F32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9):
+        achieved = alg_bytes / (gather_ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "algorithmic": {"bytes": alg_bytes, "flops": alg_flops}}
+    achieved = alg_flops / (gather_ms * 1e-3) / 1e12
+    return {"bound": "mfma", "achieved": achieved, "peak": MFMA_F32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / MFMA_F32_PEAK_TFLOPS, "traffic": None,
+            "algorithmic": {"bytes": alg_bytes, "flops": alg_flops}}
+
+
+def time_compute(m, desc, tuning, pts, pairs, steps, warmup, stages=False):
+    """Time `steps` full computations (after `warmup`) with the points resident:
+    wall time per step between two synchronisations, the median of per-step
+    events, and the gather kernel's duration from the events the library
+    records around that launch on its stream.  Also the exact evaluation count
+    and the per-point mass (a separate computation outside the timed region),
+    and, with `stages`, the binning and accumulation stages timed apart."""
+    import torch
+    dev = pts.device
+    stream = torch.cuda.current_stream(dev)
+    n = int(pts.shape[0])
+    adaptive = pairs is not None
+    plan = m.Plan(desc, tuning)
+
+    def compute(p, o, st=None, w=None):
+        if adaptive:
+            return p.compute_adaptive_into(pts, pairs, o, stats=st, workspace=w)
+        return p.compute_into(pts, o, stats=st, workspace=w)
+    out = torch.empty((desc.gx, desc.gy, desc.gt), dtype=torch.float32, device=dev)
+    stats = torch.zeros(8, dtype=torch.float64, device=dev)
+    ws = plan.workspace(n, dev)
+    chk = m.Plan(m.Desc(**{**desc.__dict__, "flags": desc.flags | m.FLAG_POINT_STATS | m.FLAG_MASS}), tuning)
+    cstats = torch.zeros(8, dtype=torch.float64, device=dev)
+    compute(chk, out, cstats, ws)
+    torch.cuda.synchronize()
+    cs = cstats.cpu().numpy()
+    chk.close()
+    for _ in range(warmup):
+        compute(plan, out, stats, ws)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    plan.profile(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record(stream)
+        compute(plan, out, stats, ws)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern_ms = plan.profile_read()
+    plan.profile(0)
+    if len(kern_ms) != steps:
+        raise SystemExit(f"expected {steps} gather timings, got {len(kern_ms)}")
+    res = {"ms_per_step": (t1 - t0) * 1e3 / steps,
+           "median_step_ms": _median([a.elapsed_time(b) for a, b in ev]),
+           "gather_ms": sum(kern_ms) / len(kern_ms), "evals": int(cs[2]),
+           "point_mass": float(cs[1]), "grid_mass": float(stats[0].item()), "out": out}
+    _log(f"{desc.gx}x{desc.gy}x{desc.gt} hs={desc.hs:g} ht={desc.ht:g} flags={desc.flags}: "
+         f"{res['ms_per_step']:.4f} ms/step wall, median event {res['median_step_ms']:.4f} ms, "
+         f"gather {res['gather_ms']:.4f} ms, {res['evals']} evals")
+    if stages:
+        reps = max(5, steps)
+        bev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        gev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for k in range(reps):
+            bev[k][0].record(stream)
+            if adaptive:
+                plan.bin_adaptive(pts, pairs, ws)
+            else:
+                plan.bin(pts, ws)
+            bev[k][1].record(stream)
+            gev[k][0].record(stream)
+            plan.accumulate(n, out, ws)
+            gev[k][1].record(stream)
+        torch.cuda.synchronize()
+        res["bin_ms"] = sum(a.elapsed_time(b) for a, b in bev) / reps
+        res["pass_ms"] = sum(a.elapsed_time(b) for a, b in gev) / reps
+        _log(f"stage times: bin {res['bin_ms']:.3f} ms, accumulation pass {res['pass_ms']:.3f} ms")
+    plan.close()
+    return res
+
+
+def error_stats(gpu, ref):
+    """Max and RMS error of a GPU grid against the oracle's, relative to the
+    oracle's peak (RMS over voxels where either side is nonzero), and the
+    support mismatch: voxels where exactly one side is nonzero."""
+    import numpy as np
+    g = np.asarray(gpu, dtype=np.float64)
+    peak = max(float(np.max(np.abs(ref))), 1e-300)
+    d = np.abs(g - ref)
+    supp = (g != 0.0) | (ref != 0.0)
+    ns = int(np.count_nonzero(supp))
+    return {"max_rel": float(np.max(d)) / peak,
+            "rms_rel": (float(np.sqrt(np.mean(d[supp] ** 2))) / peak) if ns else 0.0,
+            "mismatch": int(np.count_nonzero((g != 0.0) != (ref != 0.0)))}
+
+
+def cpu_info():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_single_thread(inst, k):
+    """The oracle on one thread over the first k events (the paper's
+    sequential times are single-threaded, Sec. 6.2)."""
+    import oracle
+    g = oracle.Grid(gx=inst.gx, gy=inst.gy, gt=inst.gt, hs=inst.hs, ht=inst.ht, sres=inst.sres,
+                    tres=inst.tres, x0=inst.x0, y0=inst.y0, t0=inst.t0)
+    t0 = time.perf_counter()
+    _, evals = oracle.pbsym(inst.points[:k], g, nthreads=1)
+    dt = time.perf_counter() - t0
+    _log(f"cpu oracle, one thread: {k} events of {inst.name}, {evals} evals, {dt:.2f} s")
+    return {"value": evals / dt, "unit": "evals/s", "cores": 1, "seconds": round(dt, 3),
+            "sample": f"first {k} of {inst.points.shape[0]} events on the full grid"}
+
+
+def precision_record(m, inst, desc, tuning, pts, operands, est, ref, k, gpu_sample, args):
+    """What the headline's arithmetic is and what it costs in accuracy: the
+    two-term operand form and its stated bias bound, and the FP32-operand
+    gather timed and checked on the same oracle sample."""
+    from paper_1705_09366_amd import autotune
+    rec = {"operands": operands,
+           "per_product_relative_bias_bound": 2.0 ** -19 if operands.startswith("fp16") else 0.0,
+           "bias_note": "two-term FP16 operands keep 22 significant bits each and drop the lo*lo term, "
+                        "so each product is low by less than 2^-19 of itself (all products are "
+                        "non-negative); accumulation is FP32 on the matrix cores",
+           "max_rel_err_vs_oracle": est["max_rel"], "rms_rel_err_vs_oracle": est["rms_rel"],
+           "support_mismatch": est["mismatch"], "oracle_sample_events": k}
+    t32, src32 = autotune.resolve(desc, inst.points.shape[0], fp32=True)
+    t32 = dataclasses.replace(t32 or m.Tuning(), operand_form=1)
+    r32 = time_compute(m, desc, t32, pts, None, max(5, args.steps // 2), 2)
+    e32 = error_stats(gpu_sample(k, t32), ref)
+    alg_bytes = inst.gx * inst.gy * inst.gt * 4 + inst.points.shape[0] * 24
+    rec["fp32_operands"] = {"ms_per_step": r32["ms_per_step"], "gather_ms": r32["gather_ms"],
+                            "roofline_frac": _roofline(alg_bytes, 2.0 * r32["evals"], r32["gather_ms"])["frac"],
+                            "tuning_source": src32, "max_rel_err_vs_oracle": e32["max_rel"],
+                            "rms_rel_err_vs_oracle": e32["rms_rel"], "support_mismatch": e32["mismatch"]}
+    del r32
+    return rec
+
+
+def other_configs(m, dev, args):
+    """The latency-bound small case and the large-bandwidth case, each timed
+    and checked against the FP64 oracle on the whole grid (the large-bandwidth
+    case twice: compensated and plain FP32 accumulation)."""
+    import numpy as np
+    import torch
+    import oracle
+    import workloads
+    from paper_1705_09366_amd import autotune
+    out = {}
+    th = _cpu_threads()
+    for name, inst, modes in (("uniform-10k", workloads.config0(), ("kahan",)),
+                              ("clustered-200k-hs50", workloads.config2(), ("kahan", "plain"))):
+        n = inst.points.shape[0]
+        pts = torch.from_numpy(inst.points).to(dev)
+        g = oracle.Grid(gx=inst.gx, gy=inst.gy, gt=inst.gt, hs=inst.hs, ht=inst.ht)
+        t0 = time.perf_counter()
+        ref, evals = oracle.pbsym(inst.points, g, nthreads=th)
+        dt = time.perf_counter() - t0
+        _log(f"cpu oracle: {name} whole grid, {evals} evals, {dt:.2f} s on {th} threads")
+        rec = {"workload": inst.name, "n": n, "grid": [inst.gx, inst.gy, inst.gt], "hs": inst.hs,
+               "ht": inst.ht, "evals": int(evals),
+               "cpu_oracle": {"value": evals / dt, "unit": "evals/s", "cores": th, "seconds": round(dt, 3),
+                              "sample": "whole workload"}}
+        if name == "uniform-10k":
+            rec["cpu_oracle"]["single_thread"] = cpu_single_thread(inst, n)
+        for mode in modes:
+            flags = m.FLAG_MASS | (m.FLAG_KAHAN if mode == "kahan" else 0)
+            desc = _desc_of(m, inst, flags)
+            tun, src = autotune.resolve(desc, n)
+            r = time_compute(m, desc, tun, pts, None, 50 if name == "uniform-10k" else args.steps, 3)
+            est = error_stats(r["out"].cpu().numpy(), ref)
+            alg_bytes = inst.gx * inst.gy * inst.gt * 4 + n * 24
+            roof = _roofline(alg_bytes, 2.0 * r["evals"], r["gather_ms"])
+            rec[mode] = {"ms_per_step": r["ms_per_step"], "median_step_ms": r["median_step_ms"],
+                         "evals_per_s": r["evals"] / (r["ms_per_step"] * 1e-3), "gather_ms": r["gather_ms"],
+                         "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac")},
+                         "operands": _operand_form(inst, tun, mode == "kahan", False, 0),
+                         "tuning_source": src, "max_rel_err_vs_oracle": est["max_rel"],
+                         "rms_rel_err_vs_oracle": est["rms_rel"], "support_mismatch": est["mismatch"]}
+            _log(f"{name} {mode}: {r['ms_per_step']:.4f} ms/step, max rel err {est['max_rel']:.3e}, "
+                 f"rms {est['rms_rel']:.3e}, mismatch {est['mismatch']}")
+            del r
+        del ref, pts
+        torch.cuda.empty_cache()
+        out[name] = rec
+    return out
 
 
 if __name__ == "__main__":

@@ -154,7 +154,8 @@ typedef struct stkde_plan_s* stkde_plan_t;
  * TOO_LARGE (gx*gy*gt*4 bytes overflows, or a dimension above 65535). */
 stkde_status stkde_plan(const stkde_desc* desc, const stkde_tuning* tuning, stkde_plan_t* out);
 
-/* Release a plan.  NULL is accepted. */
+/* Release a plan (and its recorded graph).  NULL is accepted.  The caller
+ * makes sure no replay of its graph is still running. */
 stkde_status stkde_plan_destroy(stkde_plan_t plan);
 
 /* Gather timing.  stkde_plan_profile(plan, k) makes the next k calls of
@@ -224,6 +225,27 @@ stkde_status stkde_bin(stkde_plan_t plan, const double* d_xyt, int64_t n, void* 
                        size_t ws_bytes, void* stream);
 stkde_status stkde_accumulate(stkde_plan_t plan, int64_t n, float* d_out, void* d_ws,
                               size_t ws_bytes, double* d_stats, void* stream);
+
+/* One stkde_compute as a HIP graph, for callers that repeat the same
+ * computation on new point values at fixed addresses (the interactive
+ * re-estimation of Sec. 1 at one grid and bandwidth pair): the whole launch
+ * sequence is replayed by one graph launch, without the host work and launch
+ * gaps of the individual kernels.
+ *
+ * stkde_plan_capture records stkde_compute(plan, d_xyt, n, d_out, d_ws,
+ * ws_bytes, d_stats) -- the same arguments and checks -- into a graph held
+ * by the plan (replacing an earlier one); nothing runs.  The graph keeps the
+ * pointers and n it was recorded with: d_xyt, d_out, d_ws and d_stats must
+ * stay allocated while it is replayed, and a replay reads the point values
+ * d_xyt holds when it runs.  No profiling events are recorded into it.
+ * stkde_plan_replay launches the graph on `stream`; its result is bitwise
+ * that of stkde_compute with the same arguments.  Recording changes the
+ * plan: it must not run concurrently with other calls on the same plan.
+ * Not for plans with STKDE_FLAG_ADAPTIVE (INVALID_ARG).
+ * Errors: as stkde_compute; replay: UNSUPPORTED (nothing recorded), HIP. */
+stkde_status stkde_plan_capture(stkde_plan_t plan, const double* d_xyt, int64_t n, float* d_out,
+                                void* d_ws, size_t ws_bytes, double* d_stats);
+stkde_status stkde_plan_replay(stkde_plan_t plan, void* stream);
 
 /* Per-point bandwidths (plans with STKDE_FLAG_ADAPTIVE; the estimator is
  * given at that flag).  Arguments as stkde_compute / stkde_bin, plus

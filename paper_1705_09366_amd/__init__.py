@@ -49,7 +49,7 @@ EXPORTED = ("stkde_plan", "stkde_plan_destroy", "stkde_workspace_bytes", "stkde_
             "stkde_batch_capture", "stkde_batch_replay", "stkde_batch_destroy",
             "stkde_plan_profile", "stkde_plan_profile_read",
             "stkde_ablation_accumulate", "stkde_ablation_compute",
-            "stkde_compute_adaptive", "stkde_bin_adaptive")
+            "stkde_compute_adaptive", "stkde_bin_adaptive", "stkde_plan_capture", "stkde_plan_replay")
 
 # Baselines of include/stkde_ablation.h (benchmarks and tests only).
 ABLATION_SCATTER = 1
@@ -132,6 +132,9 @@ def lib():
                                              ctypes.c_size_t, ctypes.c_void_p]
         L.stkde_plan_profile_read.argtypes = [ctypes.c_void_p, P(ctypes.c_float), ctypes.c_int32,
                                               P(ctypes.c_int32)]
+        L.stkde_plan_capture.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        L.stkde_plan_replay.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         for name in EXPORTED:
             if name not in ("stkde_status_string", "stkde_version"):
                 getattr(L, name).restype = ctypes.c_int
@@ -280,6 +283,41 @@ class Plan:
         if st != STKDE_OK:
             raise StkdeError(st, "stkde_compute")
         return out
+
+    def capture(self, points, out, stats=None, workspace=None):
+        """Record one :meth:`compute_into` with these tensors as a HIP graph
+        (``stkde_plan_capture``); :meth:`replay` launches it.  The tensors
+        must stay alive while the graph is replayed; a replay reads the
+        values ``points`` holds when it runs."""
+        import torch
+        n = int(points.shape[0])
+        if points.dtype != torch.float64 or not points.is_cuda or points.dim() != 2 or points.shape[1] != 3 \
+                or not points.is_contiguous():
+            raise ValueError("points must be a contiguous [n, 3] float64 CUDA tensor")
+        d = self.desc
+        if out.dtype != torch.float32 or not out.is_cuda or out.numel() != d.gx * d.gy * d.gt \
+                or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 CUDA tensor of gx*gy*gt elements")
+        if stats is not None and (stats.dtype != torch.float64 or stats.numel() < 8 or not stats.is_cuda):
+            raise ValueError("stats must be a float64 CUDA tensor of 8 elements")
+        ws = workspace if workspace is not None else self.workspace(n, points.device)
+        p, nb = self._ws_args(ws)
+        st = lib().stkde_plan_capture(self._h, ctypes.c_void_p(points.data_ptr()), n,
+                                      ctypes.c_void_p(out.data_ptr()), p, nb,
+                                      ctypes.c_void_p(stats.data_ptr()) if stats is not None else None)
+        if st != STKDE_OK:
+            raise StkdeError(st, "stkde_plan_capture")
+        self._graph_refs = (points, out, stats, ws)  # kept alive for the replays
+        return out
+
+    def replay(self, stream=None):
+        """Launch the recorded graph on ``stream`` (default: the current one)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        st = lib().stkde_plan_replay(self._h, ctypes.c_void_p(stream.cuda_stream))
+        if st != STKDE_OK:
+            raise StkdeError(st, "stkde_plan_replay")
 
     def _ws_args(self, ws):
         base = ws.data_ptr()

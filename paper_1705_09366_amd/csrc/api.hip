@@ -27,6 +27,10 @@ struct stkde_plan_s {
     // gather timing (stkde_plan_profile): event pairs, filled in order
     std::vector<hipEvent_t> ev;
     int32_t ev_used = 0;
+    // one stkde_compute recorded as a HIP graph (stkde_plan_capture)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool capturing = false;  // no profiling events while recording
 };
 
 namespace {
@@ -35,6 +39,12 @@ void release_events(stkde_plan_s* p) {
         if (e) (void)hipEventDestroy(e);
     p->ev.clear();
     p->ev_used = 0;
+}
+void release_graph(stkde_plan_s* p) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
 }
 }  // namespace
 
@@ -403,7 +413,10 @@ stkde_status stkde_plan(const stkde_desc* d, const stkde_tuning* tun, stkde_plan
 }
 
 stkde_status stkde_plan_destroy(stkde_plan_t p) {
-    if (p) release_events(p);
+    if (p) {
+        release_events(p);
+        release_graph(p);
+    }
     delete p;
     return STKDE_OK;
 }
@@ -481,7 +494,7 @@ stkde_status stkde_accumulate(stkde_plan_t p, int64_t n, float* d_out, void* d_w
     stkde::InstDev d = make_dev(p->ig, p->sg, c.ws, c.L.sl, n, 0, 0, 0, d_out, d_stats,
                                 (fl & STKDE_FLAG_MASS) != 0, p->split_share, adapt);
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (p->ev_used + 2 <= (int32_t)p->ev.size()) {
+    if (!p->capturing && p->ev_used + 2 <= (int32_t)p->ev.size()) {
         e0 = p->ev[(size_t)p->ev_used];
         e1 = p->ev[(size_t)p->ev_used + 1];
         p->ev_used += 2;
@@ -530,6 +543,59 @@ stkde_status stkde_compute_adaptive(stkde_plan_t p, const double* d_xyt, const d
                                     void* stream) {
     if (!p || !d_xyt || !d_hst || !d_out || !is_adaptive(p)) return STKDE_ERR_INVALID_ARG;
     return compute_impl(p, d_xyt, d_hst, n, d_out, d_ws, ws_bytes, d_stats, stream);
+}
+
+// ---- one computation as a HIP graph ------------------------------------------
+
+stkde_status stkde_plan_capture(stkde_plan_t p, const double* d_xyt, int64_t n, float* d_out, void* d_ws,
+                                size_t ws_bytes, double* d_stats) {
+    if (!p || !d_xyt || !d_out || is_adaptive(p)) return STKDE_ERR_INVALID_ARG;
+    Call c;
+    stkde_status st = check_common(p, n, d_ws, ws_bytes, nullptr, &c);
+    if (st != STKDE_OK) return st;
+    {
+        // the gather's launch size is a host query: make it before recording
+        const uint32_t fl = p->desc.flags;
+        const int kf = p->ig.kernel;
+        int mode = acc_mode((fl & STKDE_FLAG_KAHAN) != 0, p->kahan_mode, n, p->desc, p->ig.Hs, p->ig.Ht,
+                            p->ig.tile_t);
+        if (kf != stkde::kKernelEpan && mode == stkde::kAccKahanReg) mode = stkde::kAccKahanMem;
+        const bool full = kf == stkde::kKernelEpan && use_full(p->ig.hv, p->ig.tile_t);
+        const bool h16 = use_h16(kf, false, full, p->ig.tile_t, p->operand_form);
+        if (h16 && mode == stkde::kAccKahanReg) mode = stkde::kAccKahanMem;
+        stkde::prepare_gather(p->ig.tile_t, mode, full, false, kf, h16);
+    }
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return STKDE_ERR_HIP;
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        st = STKDE_ERR_HIP;
+    } else {
+        p->capturing = true;
+        st = compute_impl(p, d_xyt, nullptr, n, d_out, d_ws, ws_bytes, d_stats, cs);
+        p->capturing = false;
+        // always end the capture, also after a failed launch
+        if (hipStreamEndCapture(cs, &graph) != hipSuccess && st == STKDE_OK) st = STKDE_ERR_HIP;
+    }
+    hipGraphExec_t exec = nullptr;
+    if (st == STKDE_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+        st = STKDE_ERR_HIP;
+    (void)hipStreamDestroy(cs);
+    if (st != STKDE_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    release_graph(p);
+    p->graph = graph;
+    p->exec = exec;
+    return STKDE_OK;
+}
+
+stkde_status stkde_plan_replay(stkde_plan_t p, void* stream) {
+    if (!p) return STKDE_ERR_INVALID_ARG;
+    if (!p->exec) return STKDE_ERR_UNSUPPORTED;
+    if (hipGraphLaunch(p->exec, reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return STKDE_ERR_HIP;
+    return STKDE_OK;
 }
 
 // ---- binned sets ------------------------------------------------------------

@@ -14,11 +14,15 @@ enqueues it on the next of the executor's streams, so that a new tick's
 work starts while the previous one drains; while ``max_inflight`` ticks are
 on the device, the next tick collects whatever arrived meanwhile, so
 batches grow with the load.  Admission is first come, first served, against a byte
-budget: the outputs of admitted, unfinished requests plus the ticks'
-workspaces must fit in the device memory left after the resident sets and
-a reserve.  A request completes when its tick's completion event has been
-reached; its latency is measured on the host clock from submission (or a
-given arrival time) to the poll that observes completion.
+budget: the outputs of admitted requests that the caller has not released
+(:meth:`Server.release`) plus the workspaces of the ticks on the device must
+fit in the device memory left after the resident sets and a reserve.  A
+tick's workspace is known from its plan before anything is launched, so a
+tick is cut back (its last requests return to the head of the queue) until
+outputs and workspace fit; the budget is never exceeded.  A request completes
+when its tick's completion event has been reached; its latency is measured
+on the host clock from submission (or a given arrival time) to the poll that
+observes completion.
 
 The device side sits behind a small executor interface, so the scheduling
 logic is testable without a GPU.
@@ -63,6 +67,8 @@ class Ticket:
     stats: object = None
     tick: int = -1
     done: bool = False
+    error: Optional[str] = None
+    charged: int = 0  # output bytes held against the budget until released
 
     @property
     def latency(self) -> float:
@@ -130,13 +136,28 @@ class GpuExecutor:
         tk.out, tk.stats = out, stats
         return item
 
-    def launch(self, items: List[Item]):
+    def plan_tick(self, items: List[Item]):
+        """Plan one tick (validation and workspace size, no device memory)."""
+        return Batch(items, allocate=False)
+
+    def planned_workspace_bytes(self, planned) -> int:
+        return planned.workspace_bytes
+
+    def discard_plan(self, planned):
+        planned.close()
+
+    def discard(self, item: Item, tk: Ticket):
+        """Undo prepare() for a request that goes back to the queue."""
+        item.plan.close()
+        tk.out, tk.stats = None, None
+
+    def launch(self, items: List[Item], planned=None):
         """Enqueue one tick on the next stream (its outputs were allocated on
         that stream by prepare)."""
         torch = self.torch
         st = self.streams[self._next_stream]
         self._next_stream = (self._next_stream + 1) % len(self.streams)
-        b = Batch(items, allocate=False)
+        b = planned if planned is not None else Batch(items, allocate=False)
         with torch.cuda.stream(st):
             b.allocate(self.device)
             b.run(stream=st)
@@ -175,6 +196,8 @@ class Server:
         self.active_bytes = 0
         self.high_water = 0
         self.finished: List[Ticket] = []
+        self.failed: List[Ticket] = []
+        self.max_inflight_seen = 0
         self._next_id = 0
         self._ticks = 0
 
@@ -199,7 +222,7 @@ class Server:
     def _retire(self):
         now = None
         keep = []
-        for token, tickets, items, nbytes in self.inflight:
+        for token, tickets, items, ws in self.inflight:
             if self.ex.done(token):
                 now = self.clock() if now is None else now
                 for tk in tickets:
@@ -207,35 +230,85 @@ class Server:
                     tk.done = True
                     self.finished.append(tk)
                 self.ex.release(token, items)
-                self.active_bytes -= nbytes
+                self.active_bytes -= ws  # outputs stay charged until released
             else:
-                keep.append((token, tickets, items, nbytes))
+                keep.append((token, tickets, items, ws))
         self.inflight = keep
+
+    def release(self, tk: Ticket):
+        """The caller is done with a finished request's output: its bytes
+        return to the budget (the tensors are dropped here)."""
+        if not tk.done:
+            raise ValueError("release() of a request that has not finished")
+        tk.out, tk.stats = None, None
+        self.active_bytes -= tk.charged
+        tk.charged = 0
 
     def _admit(self):
         if len(self.inflight) >= self.max_inflight or not self.waiting:
             return
-        tickets, items, nbytes = [], [], 0
-        while self.waiting and len(tickets) < self.max_batch:
-            tk = self.waiting[0]
-            need = tk.req.nbytes() + 64
-            # first come, first served: the head waits until it fits
-            if self.active_bytes + nbytes + need > self.budget:
+        # the longest first-come-first-served prefix whose outputs fit
+        tickets, nbytes = [], 0
+        for tk in self.waiting:
+            if len(tickets) >= self.max_batch:
                 break
-            self.waiting.popleft()
-            tk.t_admit = self.clock()
-            tk.tick = self._ticks
-            items.append(self.ex.prepare(tk))
+            need = tk.req.nbytes() + 64
+            if self.active_bytes + nbytes + need > self.budget:
+                break  # the head waits until it fits
             tickets.append(tk)
             nbytes += need
         if not tickets:
             return
-        token = self.ex.launch(items)
-        nbytes += self.ex.workspace_bytes(token)
+        for _ in tickets:
+            self.waiting.popleft()
+        items = []
+        try:
+            for tk in tickets:
+                items.append(self.ex.prepare(tk))
+        except Exception as e:
+            # the bad request fails; the others go back to the queue in order
+            k = len(items)
+            for it, tk in zip(items, tickets):
+                self.ex.discard(it, tk)
+            for tk in reversed(tickets[:k] + tickets[k + 1:]):
+                self.waiting.appendleft(tk)
+            bad = tickets[k]
+            bad.error, bad.done, bad.t_done = str(e), True, self.clock()
+            self.failed.append(bad)
+            raise
+        # cut the tick back until outputs plus its workspace fit
+        while True:
+            planned = self.ex.plan_tick(items)
+            ws = self.ex.planned_workspace_bytes(planned)
+            if self.active_bytes + nbytes + ws <= self.budget:
+                break
+            self.ex.discard_plan(planned)
+            tk, it = tickets.pop(), items.pop()
+            self.ex.discard(it, tk)
+            nbytes -= tk.req.nbytes() + 64
+            if not tickets:
+                if not self.inflight and self.active_bytes == 0:
+                    # alone on an idle device it still does not fit: refuse it
+                    tk.error = (f"request needs {tk.req.nbytes() + 64 + ws} bytes with its "
+                                f"workspace; the budget is {self.budget}")
+                    tk.done = True
+                    tk.t_done = self.clock()
+                    self.failed.append(tk)
+                else:
+                    self.waiting.appendleft(tk)
+                return
+            self.waiting.appendleft(tk)
+        now = self.clock()
+        for tk in tickets:
+            tk.t_admit = now
+            tk.tick = self._ticks
+            tk.charged = tk.req.nbytes() + 64
+        token = self.ex.launch(items, planned)
         self._ticks += 1
-        self.active_bytes += nbytes
+        self.active_bytes += nbytes + ws
         self.high_water = max(self.high_water, self.active_bytes)
-        self.inflight.append((token, tickets, items, nbytes))
+        self.max_inflight_seen = max(self.max_inflight_seen, len(self.inflight) + 1)
+        self.inflight.append((token, tickets, items, ws))
 
     def poll(self):
         """Retire finished ticks, then launch a tick of admitted requests."""
@@ -262,4 +335,4 @@ class Server:
             return lat[min(len(lat) - 1, int(round(p / 100.0 * (len(lat) - 1))))]
         return {"count": len(lat), "p50_ms": pct(50) * 1e3, "p99_ms": pct(99) * 1e3,
                 "mean_ms": sum(lat) / len(lat) * 1e3, "ticks": self._ticks,
-                "high_water_bytes": self.high_water}
+                "high_water_bytes": self.high_water, "max_inflight_seen": self.max_inflight_seen}
