@@ -198,7 +198,12 @@ stkde_status stkde_workspace_bytes(stkde_plan_t plan, int64_t n, size_t* bytes);
  *          [5] (STKDE_FLAG_ADAPTIVE) number of points with finite coordinates
  *              whose bandwidth pair is not finite and positive or exceeds
  *              the plan's hs / ht: they contribute nothing, count in n,
- *          [6..7] reserved (0).
+ *          [6] number of the grid's tiles computed in parts: a tile
+ *              that must examine far more points than its grid's share is
+ *              cut into contiguous ranges of its points, computed by several
+ *              workgroups and added in range order (the grid then differs
+ *              from the uncut computation in its last bits),
+ *          [7] reserved (0).
  *  stream  hipStream_t as void*.
  *
  * Errors: INVALID_ARG (also for a plan with STKDE_FLAG_ADAPTIVE), TOO_LARGE,
@@ -343,7 +348,10 @@ stkde_status stkde_batch_workspace_bytes(stkde_batch_t batch, size_t* bytes);
 /* Compute every item's grid on `stream` (d_ws: >= the workspace bytes,
  * 256-byte aligned; scratch).  Each grid is the one stkde_compute would give
  * for the set's points, within the tolerance of their rounding; it is
- * bitwise the same as the item run alone when none of its tiles is split.
+ * bitwise the same as the item run alone (in a batch of one) when neither
+ * run computes one of its tiles in parts (d_stats[6] = 0 in both).  Which
+ * tiles are cut depends on the batch: the costliest tiles of the whole
+ * batch (at most 1024) are candidates, within 1024 partial tiles.
  * Errors: WORKSPACE, HIP. */
 stkde_status stkde_batch_run(stkde_batch_t batch, void* d_ws, size_t ws_bytes, void* stream);
 

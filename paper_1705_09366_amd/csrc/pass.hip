@@ -31,12 +31,14 @@ size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 __global__ __launch_bounds__(256) void k_put_desc(DescChunk c, int32_t first, int32_t m,
                                                   InstDev* __restrict__ dst,
                                                   unsigned long long* __restrict__ inst_cost,
+                                                  uint32_t* __restrict__ inst_split,
                                                   uint32_t* __restrict__ hist,
                                                   uint32_t* __restrict__ sc, int32_t clear) {
     const int tid = threadIdx.x;
     if (tid < m) {
         dst[first + tid] = c.d[tid];
         inst_cost[first + tid] = 0ull;
+        inst_split[first + tid] = 0u;
     }
     if (clear) {
         for (int k = tid; k < kCostClasses; k += 256) hist[k] = 0u;
@@ -210,10 +212,12 @@ __global__ __launch_bounds__(256) void k_collect_heavy(uint32_t T, const uint32_
 //     (ties by tile), and flagged in the spatial queue's bitmask;
 //  2. a taken tile whose cost exceeds max(kSplitFloor, its instance's total
 //     cost / its split share) is cut into up to kMaxParts equal candidate
-//     ranges, while partial slots last (costliest first).
+//     ranges, while partial slots last (costliest first); inst_split counts
+//     the tiles of each instance that are cut.
 __global__ __launch_bounds__(1024) void k_plan_items(const InstDev* __restrict__ descs, int32_t count,
                                                      const unsigned long long* __restrict__ heavy,
                                                      const unsigned long long* __restrict__ inst_cost,
+                                                     uint32_t* __restrict__ inst_split,
                                                      WorkItem* __restrict__ items,
                                                      uint32_t* __restrict__ top,
                                                      uint32_t* __restrict__ bits,
@@ -256,11 +260,12 @@ __global__ __launch_bounds__(1024) void k_plan_items(const InstDev* __restrict__
 
     // ---- 2. splitting
     uint32_t tile = 0, c = 0, parts = 1;
+    int32_t inst = 0;
     if ((uint32_t)tid < nh) {
         const unsigned long long k = keys[tid];
         tile = (uint32_t)k;
         c = ~(uint32_t)(k >> 32);
-        const int32_t inst = find_inst(descs, count, tile);
+        inst = find_inst(descs, count, tile);
         const unsigned long long ss = descs[inst].split_share;
         const unsigned long long share = (inst_cost[inst] + ss - 1) / ss;
         const uint32_t thr = share > kSplitFloor ? (share > 0xffffffffull ? 0xffffffffu : (uint32_t)share)
@@ -290,6 +295,7 @@ __global__ __launch_bounds__(1024) void k_plan_items(const InstDev* __restrict__
             items[ipos + p] = WorkItem{tile, b, e, parts > 1 ? slot0 + p : kNoSlot};
         }
         if (parts > 1) {
+            atomicAdd(&inst_split[inst], 1u);
             top[4 * spos + 0] = tile;
             top[4 * spos + 1] = parts;
             top[4 * spos + 2] = slot0;
@@ -329,10 +335,11 @@ __global__ __launch_bounds__(256) void k_mass_chunks(const InstDev* __restrict__
 }
 
 // Per instance: stats[0] = grid mass (sum * sres^2 tres, or 0 without the
-// mass flag), [1], [2], [6], [7] = 0, [3], [4], [5] = the set's non-finite,
-// culled and invalid-bandwidth counts.
+// mass flag), [1], [2], [7] = 0, [3], [4], [5] = the set's non-finite,
+// culled and invalid-bandwidth counts, [6] = tiles computed in parts.
 __global__ __launch_bounds__(64) void k_finalize(const InstDev* __restrict__ descs,
-                                                 const double* __restrict__ mid) {
+                                                 const double* __restrict__ mid,
+                                                 const uint32_t* __restrict__ inst_split) {
     static_assert(kMassChunks == 64, "one wave per instance");
     const InstDev& D = descs[blockIdx.x];
     double* st = D.stats;
@@ -350,7 +357,7 @@ __global__ __launch_bounds__(64) void k_finalize(const InstDev* __restrict__ des
         st[3] = (double)(cs[kKeyNonFinite + 1] - cs[kKeyNonFinite]);
         st[4] = (double)(cs[kKeyCulled + 1] - cs[kKeyCulled]);
         st[5] = (double)(cs[kKeyBadBw + 1] - cs[kKeyBadBw]);
-        st[6] = 0.0;
+        st[6] = (double)inst_split[blockIdx.x];
         st[7] = 0.0;
     }
 }
@@ -368,6 +375,7 @@ PassLayout layout_pass(const InstGeom* inst, int32_t count, int tile_t, bool kah
     l.T = T;
     l.desc = o; o = al256(o + (size_t)count * sizeof(InstDev));
     l.inst_cost = o; o = al256(o + (size_t)count * 8);
+    l.inst_split = o; o = al256(o + (size_t)count * 4);
     l.cost = o; o = al256(o + (size_t)T * 4);
     l.hist = o; o = al256(o + (size_t)kCostClasses * 4);
     l.bits = o; o = al256(o + ((size_t)T + 31) / 32 * 4);
@@ -392,6 +400,7 @@ hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassL
     const bool kahan = mode != kAccPlain;
     InstDev* d_desc = reinterpret_cast<InstDev*>(pass + pl.desc);
     auto* inst_cost = reinterpret_cast<unsigned long long*>(pass + pl.inst_cost);
+    auto* inst_split = reinterpret_cast<uint32_t*>(pass + pl.inst_split);
     auto* cost = reinterpret_cast<uint32_t*>(pass + pl.cost);
     auto* hist = reinterpret_cast<uint32_t*>(pass + pl.hist);
     auto* bits = reinterpret_cast<uint32_t*>(pass + pl.bits);
@@ -415,7 +424,7 @@ hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassL
         const int32_t m = count - first < kDescChunk ? count - first : kDescChunk;
         for (int32_t k = 0; k < m; ++k) c.d[k] = descs[first + k];
         hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(256), 0, s, c, first, m, d_desc, inst_cost,
-                           hist, sc, first == 0 ? 1 : 0);
+                           inst_split, hist, sc, first == 0 ? 1 : 0);
     }
     const uint32_t T = (uint32_t)pl.T;
     hipLaunchKernelGGL(k_tile_cost, dim3((T + 255) / 256), dim3(256), 0, s, (const InstDev*)d_desc,
@@ -424,7 +433,8 @@ hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassL
     hipLaunchKernelGGL(k_collect_heavy, dim3((T + 2047) / 2048), dim3(256), 0, s, T, (const uint32_t*)cost,
                        (const uint32_t*)hist, heavy, sc);
     hipLaunchKernelGGL(k_plan_items, dim3(1), dim3(1024), 0, s, (const InstDev*)d_desc, count,
-                       (const unsigned long long*)heavy, (const unsigned long long*)inst_cost, items, top,
+                       (const unsigned long long*)heavy, (const unsigned long long*)inst_cost, inst_split,
+                       items, top,
                        bits, sc, ctr, (uint32_t)kPartSlots);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -438,7 +448,7 @@ hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassL
     hipLaunchKernelGGL(k_mass_chunks, dim3(kMassChunks, (uint32_t)count), dim3(256), 0, s,
                        (const InstDev*)d_desc, mid);
     hipLaunchKernelGGL(k_finalize, dim3((uint32_t)count), dim3(64), 0, s, (const InstDev*)d_desc,
-                       (const double*)mid);
+                       (const double*)mid, (const uint32_t*)inst_split);
     return hipGetLastError();
 }
 

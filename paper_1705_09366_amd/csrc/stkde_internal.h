@@ -190,6 +190,7 @@ SortLayout layout_sort(int64_t n);
 struct PassLayout {
     size_t desc;         // count InstDev
     size_t inst_cost;    // count u64: candidates summed over the instance's tiles
+    size_t inst_split;   // count u32: tiles of the instance computed in parts
     size_t cost;         // T u32: candidates per tile
     size_t hist;         // kCostClasses u32: tiles per cost class
     size_t bits;         // ceil(T / 32) u32: spatial-queue positions taken by the heavy queue

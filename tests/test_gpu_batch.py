@@ -220,13 +220,17 @@ def test_split_hot_tiles_in_a_batch(torch_cuda):
     b = m.Batch(items)
     b.run()
     torch.cuda.synchronize()
+    cut = []
     for d, it in zip(descs, items):
         ref, _ = oracle.pbsym(pts, _grid_of(d))
         got = it.out.cpu().numpy()
         rel = _check_close(got, ref)
         st = it.stats.cpu().numpy()
         assert st[0] == pytest.approx(float(np.sum(got, dtype=np.float64)), rel=1e-9)
-        _say(f"hs={d['hs']} flags={d['flags']}: rel err {rel:.2e}")
+        _say(f"hs={d['hs']} flags={d['flags']}: rel err {rel:.2e}, {int(st[6])} tiles in parts")
+        cut.append(int(st[6]))
+    # the pile's tiles are cut (their count is reported per grid)
+    assert max(cut) > 0
     b.close()
     s.close()
 

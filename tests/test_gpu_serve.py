@@ -1,8 +1,9 @@
 """GPU: continuous batching over resident sets.  Requests arrive while
 earlier ticks are on the device (two ticks in flight on two streams, a few
-requests per tick); each result equals the same request run alone (bitwise:
-same tuning, same set) and matches the FP64 oracle on the window grid with
-the whole set's points.  The second test does the same at the serving
+requests per tick); each result equals the same request run alone (bitwise
+with the same tuning and set when neither run cut one of its tiles into
+parts, else within tolerance) and matches the FP64 oracle on the window grid
+with the whole set's points.  The second test does the same at the serving
 workload's size: 4 resident sets of 100k..2M clustered points over
 2048 x 2048 x 512, 32 requests for windows of 64..1024 x 64..1024 x 64..128
 voxels at hs, ht in [3, 40], every window compared whole with the oracle."""
@@ -53,11 +54,22 @@ def _serve(torch, srv, ex, reqs):
 
 
 def _check_alone(torch, m, ex, tk):
+    """The request run alone (a batch of one) gives the served grid bit for
+    bit when neither run computed one of its tiles in parts (stats[6] = 0 in
+    both; which tiles are cut depends on the batch), else the two agree
+    within the parity tolerance of the peak."""
     item = ex.prepare(type(tk)(rid=-1, req=tk.req, t_arrival=0.0))
     b = m.Batch([item])
     b.run()
     torch.cuda.synchronize()
-    same = torch.equal(item.out, tk.out)
+    cut = (int(item.stats[6].item()), int(tk.stats[6].item()))
+    if cut == (0, 0):
+        same = torch.equal(item.out, tk.out)
+    else:
+        a, c = item.out.double(), tk.out.double()
+        peak = float(a.abs().max())
+        same = float((a - c).abs().max()) <= 1e-5 * peak
+        _say(f"request {tk.rid}: tiles in parts alone / served {cut}, compared within tolerance")
     b.close()
     item.plan.close()
     return same
