@@ -1063,7 +1063,7 @@ int resident_groups() {
                                                      kThreads, 0) != hipSuccess)
         occ = 0;
     v = (ncu > 0 ? ncu : 256) * (occ > 0 ? occ : 1);
-    if (MODE == kAccKahanMem && v > kMemKahanGroups) v = kMemKahanGroups;
+    if (MODE == kAccKahanMem && v > kMemKahanGroups) v = kMemKahanGroups;  // (and below kahan_slots(T))
     cache[dev].store(v, std::memory_order_relaxed);
     return v;
 }
@@ -1073,7 +1073,7 @@ void launch_items_t(const InstDev* d, int32_t count, const WorkItem* items, cons
                     const uint32_t* sc, uint32_t* ctr, float* partials, float* kscratch, int64_t T,
                     hipStream_t s) {
     int64_t g = resident_groups<TT, MODE, FULL, ADAPT, KF, H16>();
-    const int64_t most = T + kPartSlots;  // items never exceed tiles + partial slots
+    const int64_t most = max_items(T);  // (the Kahan scratch holds kahan_slots(T) workgroups)
     if (g > most) g = most;
     if (g < 1) g = 1;
     hipLaunchKernelGGL((k_gather_items<TT, MODE, FULL, ADAPT, KF, H16>), dim3((uint32_t)g), dim3(kThreads), 0,

@@ -32,16 +32,24 @@ __global__ __launch_bounds__(256) void k_put_desc(DescChunk c, int32_t first, in
                                                   InstDev* __restrict__ dst,
                                                   unsigned long long* __restrict__ inst_cost,
                                                   uint32_t* __restrict__ inst_split,
+                                                  uint32_t* __restrict__ mass_done,
                                                   uint32_t* __restrict__ hist,
+                                                  uint32_t* __restrict__ cursor,
+                                                  uint32_t* __restrict__ demand,
                                                   uint32_t* __restrict__ sc, int32_t clear) {
     const int tid = threadIdx.x;
     if (tid < m) {
         dst[first + tid] = c.d[tid];
         inst_cost[first + tid] = 0ull;
         inst_split[first + tid] = 0u;
+        mass_done[first + tid] = 0u;
     }
     if (clear) {
-        for (int k = tid; k < kCostClasses; k += 256) hist[k] = 0u;
+        for (int k = tid; k < kCostClasses; k += 256) {
+            hist[k] = 0u;
+            cursor[k] = 0u;
+            demand[k] = 0u;
+        }
         if (tid < kScCount) sc[tid] = 0u;
     }
 }
@@ -117,8 +125,8 @@ __global__ __launch_bounds__(256) void k_tile_cost(const InstDev* __restrict__ d
         if (h[k]) atomicAdd(&hist[k], h[k]);
 }
 
-// Exclusive prefix sum over a 1024-thread workgroup; *total gets the sum.
-__device__ inline uint32_t block_scan(uint32_t v, uint32_t* ws, uint32_t* total) {
+// Exclusive prefix sum over a 256-thread workgroup; *total gets the sum.
+__device__ inline uint32_t block_scan256(uint32_t v, uint32_t* ws, uint32_t* total) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t inc = v;
 #pragma unroll
@@ -131,7 +139,7 @@ __device__ inline uint32_t block_scan(uint32_t v, uint32_t* ws, uint32_t* total)
     __syncthreads();
     uint32_t pre = 0, tot = 0;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
+    for (int k = 0; k < 4; ++k) {
         const uint32_t x = ws[k];
         pre += k < w ? x : 0u;
         tot += x;
@@ -140,183 +148,223 @@ __device__ inline uint32_t block_scan(uint32_t v, uint32_t* ws, uint32_t* total)
     return pre + inc - v;
 }
 
-// Threshold class of the heaviest-first queue: the smallest class c >=
-// class(1) whose suffix count (tiles of class >= c) is at most kTopTiles.
-// Every workgroup of k_collect_heavy derives it from the histogram alone.
-__device__ inline uint32_t heavy_class(const uint32_t* __restrict__ hist, uint32_t* ws,
-                                       uint32_t* s_cls) {
-    const int tid = threadIdx.x;
-    constexpr int kPer = kCostClasses / 256;  // classes per thread, highest first
-    static_assert(kPer * 256 == kCostClasses, "whole classes per thread");
-    if (tid == 0) *s_cls = kCostClasses;
-    uint32_t h[kPer], sum = 0;
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        h[u] = hist[kCostClasses - 1 - (kPer * tid + u)];
-        sum += h[u];
-    }
-    // exclusive scan over the 256 threads (classes above this thread's)
-    const int lane = tid & 63, w = tid >> 6;
-    uint32_t inc = sum;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t v = __shfl_up(inc, o, 64);
-        if (lane >= o) inc += v;
-    }
-    if (lane == 63) ws[w] = inc;
-    __syncthreads();
-    uint32_t above = inc - sum;
-    for (int k = 0; k < w; ++k) above += ws[k];
-    const uint32_t cmin = cost_class(1u);
-    uint32_t best = kCostClasses;
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const uint32_t c = kCostClasses - 1 - (kPer * tid + u);
-        above += h[u];
-        if (c >= cmin && above <= (uint32_t)kTopTiles) best = c;
-    }
-    if (best < kCostClasses) atomicMin(s_cls, best);
-    __syncthreads();
-    return *s_cls;
+// Split threshold of a tile of instance D: max(kSplitFloor, total cost /
+// split share); its parts: min(kMaxParts, ceil(cost / threshold)).
+__device__ inline uint32_t split_parts(const InstDev& D, unsigned long long inst_total, uint32_t c) {
+    const unsigned long long ss = D.split_share;
+    const unsigned long long share = (inst_total + ss - 1) / ss;
+    const uint32_t thr = share > kSplitFloor ? (share > 0xffffffffull ? 0xffffffffu : (uint32_t)share)
+                                             : kSplitFloor;
+    if (c <= thr) return 1u;
+    const uint32_t want = (uint32_t)(((unsigned long long)c + thr - 1) / thr);
+    return want < (uint32_t)kMaxParts ? want : (uint32_t)kMaxParts;
 }
 
-// Collect the heavy tiles (those of the threshold class and above) into
-// heavy[] in any order; k_plan_items sorts them.
-__global__ __launch_bounds__(256) void k_collect_heavy(uint32_t T, const uint32_t* __restrict__ cost,
-                                                       const uint32_t* __restrict__ hist,
-                                                       unsigned long long* __restrict__ heavy,
-                                                       uint32_t* __restrict__ sc) {
+// The heaviest-first queue, in one launch.
+//
+// Every workgroup derives from the cost-class histogram the threshold class
+// (the smallest class c >= class(1) whose suffix count, tiles of class >= c,
+// is at most kTopTiles) and the number of heavy tiles in the classes above
+// each class; it places its heavy tiles (those of the threshold class and
+// above) into heavy[] grouped by class, costliest class first (in any order
+// within a class), flags them in the spatial queue's bitmask, and adds the
+// partial slots each would take if split to its class's demand.
+//
+// The last workgroup to finish then plans the queue: tiles are split (into
+// split_parts parts) in the costliest classes whose summed demand fits the
+// partial slots, every tile of a class or none, so that which tiles are cut
+// depends only on the costs, not on the order of heavy[]; it writes the work
+// items and split records in heavy[] order, and clears the queues' counters.
+__global__ __launch_bounds__(256) void k_collect_plan(const InstDev* __restrict__ descs, int32_t count,
+                                                      uint32_t T, const uint32_t* __restrict__ cost,
+                                                      const uint32_t* __restrict__ hist,
+                                                      const unsigned long long* __restrict__ inst_cost,
+                                                      uint32_t* __restrict__ inst_split,
+                                                      uint32_t* __restrict__ cursor,
+                                                      uint32_t* __restrict__ demand,
+                                                      unsigned long long* __restrict__ heavy,
+                                                      WorkItem* __restrict__ items,
+                                                      uint32_t* __restrict__ top,
+                                                      uint32_t* __restrict__ bits,
+                                                      uint32_t* __restrict__ sc,
+                                                      uint32_t* __restrict__ ctr, uint32_t nslots,
+                                                      uint32_t* __restrict__ done) {
+    constexpr int kPer = kCostClasses / 256;  // classes per thread, highest first
+    static_assert(kPer * 256 == kCostClasses, "whole classes per thread");
+    __shared__ uint32_t above[kCostClasses];  // heavy tiles in the classes above c
+    // this workgroup's heavy tiles per class (its base in heavy[] once
+    // reserved) and their slot demand: one global atomic per class present,
+    // not one per tile (same-address atomics serialise)
+    __shared__ uint32_t lcnt[kCostClasses];
+    __shared__ uint32_t ldem[kCostClasses];
     __shared__ uint32_t ws[4];
-    __shared__ uint32_t s_cls;
+    __shared__ uint32_t s_cls, s_last;
+    const int tid = threadIdx.x;
+    for (int k = tid; k < kCostClasses; k += 256) {
+        lcnt[k] = 0u;
+        ldem[k] = 0u;
+    }
     // the costs are loaded first, so that their loads overlap the threshold's
     constexpr int kU = 8;  // loads in flight per thread
-    const uint32_t j0 = blockIdx.x * (256u * kU) + threadIdx.x;
+    const uint32_t j0 = blockIdx.x * (256u * kU) + tid;
     uint32_t cv[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
         const uint32_t j = j0 + 256u * u;
         cv[u] = j < T ? cost[j] : 0u;
     }
-    const uint32_t cls = heavy_class(hist, ws, &s_cls);
+    // suffix counts over the classes, thread tid holding classes
+    // kCostClasses - 1 - (kPer tid + u), highest first
+    if (tid == 0) s_cls = kCostClasses;
+    uint32_t h[kPer], sum = 0;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        h[u] = hist[kCostClasses - 1 - (kPer * tid + u)];
+        sum += h[u];
+    }
+    uint32_t tot;
+    uint32_t run = block_scan256(sum, ws, &tot);  // tiles in the classes above this thread's
+    const uint32_t cmin = cost_class(1u);
+    uint32_t best = kCostClasses;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const uint32_t c = kCostClasses - 1 - (kPer * tid + u);
+        above[c] = run;
+        run += h[u];
+        if (c >= cmin && run <= (uint32_t)kTopTiles) best = c;
+    }
+    if (best < kCostClasses) atomicMin(&s_cls, best);
+    __syncthreads();
+    const uint32_t cls = s_cls;
+    uint32_t rank[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-        if (cv[u] != 0u && cost_class(cv[u]) >= cls) {
-            const uint32_t pos = atomicAdd(&sc[kScHeavyFound], 1u);  // < kTopTiles by the choice of cls
-            heavy[pos] = ((unsigned long long)(~cv[u]) << 32) | (j0 + 256u * u);
-        }
-    }
-}
-
-// The heaviest-first queue (one workgroup of 1024 threads):
-//  1. the heavy tiles (k_collect_heavy) are sorted by cost, descending
-//     (ties by tile), and flagged in the spatial queue's bitmask;
-//  2. a taken tile whose cost exceeds max(kSplitFloor, its instance's total
-//     cost / its split share) is cut into up to kMaxParts equal candidate
-//     ranges, while partial slots last (costliest first); inst_split counts
-//     the tiles of each instance that are cut.
-__global__ __launch_bounds__(1024) void k_plan_items(const InstDev* __restrict__ descs, int32_t count,
-                                                     const unsigned long long* __restrict__ heavy,
-                                                     const unsigned long long* __restrict__ inst_cost,
-                                                     uint32_t* __restrict__ inst_split,
-                                                     WorkItem* __restrict__ items,
-                                                     uint32_t* __restrict__ top,
-                                                     uint32_t* __restrict__ bits,
-                                                     uint32_t* __restrict__ sc,
-                                                     uint32_t* __restrict__ ctr, uint32_t nslots) {
-    __shared__ unsigned long long keys[kTopTiles];
-    __shared__ uint32_t ws[16];
-    const int tid = threadIdx.x;
-    const uint32_t nh = sc[kScHeavyFound];  // <= kTopTiles
-    // bitonic sort of the heavy keys, ascending: cost descending, then tile.
-    // One key per thread; exchanges with partners in the same wave go through
-    // lane shuffles, the others through LDS.
-    unsigned long long key = (uint32_t)tid < nh ? heavy[tid] : ~0ull;
-    if (nh > 1) {
-        for (int k = 2; k <= kTopTiles; k <<= 1) {
-            for (int jj = k >> 1; jj > 0; jj >>= 1) {
-                unsigned long long other;
-                if (jj >= 64) {
-                    __syncthreads();  // every thread has read the previous exchange
-                    keys[tid] = key;
-                    __syncthreads();
-                    other = keys[tid ^ jj];
-                } else {
-                    const uint32_t lo = __shfl_xor((uint32_t)key, jj, 64);
-                    const uint32_t hi = __shfl_xor((uint32_t)(key >> 32), jj, 64);
-                    other = ((unsigned long long)hi << 32) | lo;
-                }
-                // the lower index of a pair keeps the smaller key in an
-                // ascending run, the larger one in a descending run
-                const bool up = (tid & k) == 0;
-                const bool lower = (tid & jj) == 0;
-                const bool keep_small = (up == lower);
-                key = keep_small ? (key < other ? key : other) : (key < other ? other : key);
-            }
+        const uint32_t c = cv[u], j = j0 + 256u * u;
+        rank[u] = 0xffffffffu;
+        if (c != 0u && cost_class(c) >= cls) {
+            const uint32_t k = cost_class(c);
+            rank[u] = atomicAdd(&lcnt[k], 1u);
+            const int32_t inst = find_inst(descs, count, j);
+            const uint32_t parts = split_parts(descs[inst], inst_cost[inst], c);
+            if (parts > 1) atomicAdd(&ldem[k], parts);
+            const uint32_t sp = spatial_pos(descs[inst], j);
+            atomicOr(&bits[sp >> 5], 1u << (sp & 31u));
         }
     }
     __syncthreads();
-    keys[tid] = key;
+    // reserve each class's run in heavy[]; lcnt becomes the run's base
+    for (int k = tid; k < kCostClasses; k += 256) {
+        if (lcnt[k]) lcnt[k] = above[k] + atomicAdd(&cursor[k], lcnt[k]);  // < kTopTiles by the choice of cls
+        if (ldem[k]) atomicAdd(&demand[k], ldem[k]);
+    }
     __syncthreads();
-
-    // ---- 2. splitting
-    uint32_t tile = 0, c = 0, parts = 1;
-    int32_t inst = 0;
-    if ((uint32_t)tid < nh) {
-        const unsigned long long k = keys[tid];
-        tile = (uint32_t)k;
-        c = ~(uint32_t)(k >> 32);
-        inst = find_inst(descs, count, tile);
-        const unsigned long long ss = descs[inst].split_share;
-        const unsigned long long share = (inst_cost[inst] + ss - 1) / ss;
-        const uint32_t thr = share > kSplitFloor ? (share > 0xffffffffull ? 0xffffffffu : (uint32_t)share)
-                                                 : kSplitFloor;
-        if (c > thr) {
-            const uint32_t want = (uint32_t)(((unsigned long long)c + thr - 1) / thr);
-            parts = want < (uint32_t)kMaxParts ? want : (uint32_t)kMaxParts;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const uint32_t c = cv[u], j = j0 + 256u * u;
+        if (rank[u] != 0xffffffffu) heavy[lcnt[cost_class(c)] + rank[u]] = ((unsigned long long)c << 32) | j;
+    }
+    // the last workgroup plans the queue
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) s_last = atomicAdd(done, 1u) == gridDim.x - 1 ? 1u : 0u;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    const uint32_t nh = (cls < (uint32_t)kCostClasses) ? above[cls] + hist[cls] : 0u;
+    // split classes: the costliest classes whose demand fits the slots
+    uint32_t dm[kPer], dsum = 0;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        dm[u] = __hip_atomic_load(&demand[kCostClasses - 1 - (kPer * tid + u)], __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+        dsum += dm[u];
+    }
+    uint32_t dtot;
+    uint32_t drun = block_scan256(dsum, ws, &dtot);
+    uint32_t cut = kCostClasses;  // lowest class that may split
+    if (tid == 0) s_cls = kCostClasses;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        drun += dm[u];
+        if (drun <= nslots) cut = kCostClasses - 1 - (kPer * tid + u);
+    }
+    if (cut < kCostClasses) atomicMin(&s_cls, cut);
+    __syncthreads();
+    const uint32_t split_cls = s_cls;
+    // heavy[] in order, four entries per thread
+    constexpr int kE = kTopTiles / 256;
+    uint32_t tl[kE], cc[kE], np[kE];
+    int32_t ins[kE];
+    uint32_t n_items = 0, n_slots = 0, n_split = 0;
+#pragma unroll
+    for (int e = 0; e < kE; ++e) {
+        const uint32_t k = (uint32_t)(kE * tid + e);
+        tl[e] = cc[e] = 0u;
+        np[e] = 0u;
+        ins[e] = 0;
+        if (k < nh) {
+            const unsigned long long v = __hip_atomic_load(&heavy[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            tl[e] = (uint32_t)v;
+            cc[e] = (uint32_t)(v >> 32);
+            ins[e] = find_inst(descs, count, tl[e]);
+            np[e] = cost_class(cc[e]) >= split_cls ? split_parts(descs[ins[e]], inst_cost[ins[e]], cc[e]) : 1u;
+            n_items += np[e];
+            n_slots += np[e] > 1 ? np[e] : 0u;
+            n_split += np[e] > 1 ? 1u : 0u;
         }
-        const uint32_t pos = spatial_pos(descs[inst], tile);
-        atomicOr(&bits[pos >> 5], 1u << (pos & 31u));
     }
-    uint32_t need = parts > 1 ? parts : 0u;
-    uint32_t tot_need;
-    const uint32_t pre_need = block_scan(need, ws, &tot_need);
-    if (pre_need + need > nslots) {
-        parts = 1;
-        need = 0;
-    }
-    uint32_t nslot_used, nitems_h, nsplit;
-    const uint32_t slot0 = block_scan(need, ws, &nslot_used);
-    const uint32_t ipos = block_scan((uint32_t)tid < nh ? parts : 0u, ws, &nitems_h);
-    const uint32_t spos = block_scan(parts > 1 ? 1u : 0u, ws, &nsplit);
-    if ((uint32_t)tid < nh) {
+    uint32_t tot_items, tot_slots, tot_split;
+    uint32_t ipos = block_scan256(n_items, ws, &tot_items);
+    uint32_t spos0 = block_scan256(n_slots, ws, &tot_slots);
+    uint32_t kpos = block_scan256(n_split, ws, &tot_split);
+#pragma unroll
+    for (int e = 0; e < kE; ++e) {
+        const uint32_t k = (uint32_t)(kE * tid + e);
+        if (k >= nh) continue;
+        const uint32_t parts = np[e], c = cc[e], tile = tl[e];
         for (uint32_t p = 0; p < parts; ++p) {
             const uint32_t b = (uint32_t)(((unsigned long long)c * p) / parts);
-            const uint32_t e = p + 1 == parts ? kAll : (uint32_t)(((unsigned long long)c * (p + 1)) / parts);
-            items[ipos + p] = WorkItem{tile, b, e, parts > 1 ? slot0 + p : kNoSlot};
+            const uint32_t en = p + 1 == parts ? kAll : (uint32_t)(((unsigned long long)c * (p + 1)) / parts);
+            items[ipos + p] = WorkItem{tile, b, en, parts > 1 ? spos0 + p : kNoSlot};
         }
+        ipos += parts;
         if (parts > 1) {
-            atomicAdd(&inst_split[inst], 1u);
-            top[4 * spos + 0] = tile;
-            top[4 * spos + 1] = parts;
-            top[4 * spos + 2] = slot0;
-            top[4 * spos + 3] = c;
+            atomicAdd(&inst_split[ins[e]], 1u);
+            top[4 * kpos + 0] = tile;
+            top[4 * kpos + 1] = parts;
+            top[4 * kpos + 2] = spos0;
+            top[4 * kpos + 3] = c;
+            spos0 += parts;
+            ++kpos;
         }
     }
-    for (int k = tid; k < kCtrWords; k += 1024) ctr[k] = 0u;  // both queues' counters
+    for (int k = tid; k < kCtrWords; k += 256) ctr[k] = 0u;  // both queues' counters
     if (tid == 0) {
-        sc[kScHeavyItems] = nitems_h;
-        sc[kScSplit] = nsplit;
+        sc[kScHeavyItems] = tot_items;
+        sc[kScSplit] = tot_split;
         sc[kScHeavyTiles] = nh;
+        *done = 0u;
     }
 }
 
-// First level of each instance's FP64 grid sum: chunk blockIdx.x of the
-// tile partials of instance blockIdx.y, strided per-thread sums, then a tree.
-__global__ __launch_bounds__(256) void k_mass_chunks(const InstDev* __restrict__ descs,
-                                                     double* __restrict__ mid) {
+// Each instance's FP64 grid sum in a fixed order: workgroup (chunk, inst)
+// sums chunk `chunk` of the instance's tile partials (strided per-thread
+// sums, then a tree) into mid[inst][chunk]; the last of the instance's
+// kMassChunks workgroups to finish adds the chunks (a tree over the 64
+// chunks in a fixed shape) and writes the instance's statistics:
+// stats[0] = grid mass (sum * sres^2 tres, or 0 without the mass flag),
+// [1], [2], [7] = 0, [3], [4], [5] = the set's non-finite, culled and
+// invalid-bandwidth counts, [6] = tiles computed in parts.
+__global__ __launch_bounds__(256) void k_mass(const InstDev* __restrict__ descs, double* __restrict__ mid,
+                                              const uint32_t* __restrict__ inst_split,
+                                              uint32_t* __restrict__ mass_done) {
+    static_assert(kMassChunks == 64, "one wave adds an instance's chunks");
     __shared__ double sh[256];
+    __shared__ uint32_t s_last;
     const int inst = blockIdx.y, ch = blockIdx.x, tid = threadIdx.x;
     const InstDev& D = descs[inst];
+    if (!D.stats) return;  // nothing to report (every workgroup of the instance leaves)
     double s = 0.0;
     if (D.flags & kInstMass) {
         const int64_t cnt = (int64_t)D.ntiles * kWaves;
@@ -331,24 +379,20 @@ __global__ __launch_bounds__(256) void k_mass_chunks(const InstDev* __restrict__
         if (tid < w) sh[tid] += sh[tid + w];
         __syncthreads();
     }
-    if (tid == 0) mid[(size_t)inst * kMassChunks + ch] = sh[0];
-}
-
-// Per instance: stats[0] = grid mass (sum * sres^2 tres, or 0 without the
-// mass flag), [1], [2], [7] = 0, [3], [4], [5] = the set's non-finite,
-// culled and invalid-bandwidth counts, [6] = tiles computed in parts.
-__global__ __launch_bounds__(64) void k_finalize(const InstDev* __restrict__ descs,
-                                                 const double* __restrict__ mid,
-                                                 const uint32_t* __restrict__ inst_split) {
-    static_assert(kMassChunks == 64, "one wave per instance");
-    const InstDev& D = descs[blockIdx.x];
-    double* st = D.stats;
-    if (!st) return;
-    const int lane = threadIdx.x;
-    double v = mid[(size_t)blockIdx.x * kMassChunks + lane];
+    if (tid == 0) {
+        __hip_atomic_store(&mid[(size_t)inst * kMassChunks + ch], sh[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        s_last = atomicAdd(&mass_done[inst], 1u) == (uint32_t)kMassChunks - 1 ? 1u : 0u;
+    }
+    __syncthreads();
+    if (!s_last || tid >= 64) return;
+    __threadfence();
+    const int lane = tid;
+    double v = __hip_atomic_load(&mid[(size_t)inst * kMassChunks + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
     if (lane == 0) {
+        double* st = D.stats;
         st[0] = (D.flags & kInstMass) ? v * D.mass_scale : 0.0;
         st[1] = 0.0;
         st[2] = 0.0;
@@ -357,8 +401,9 @@ __global__ __launch_bounds__(64) void k_finalize(const InstDev* __restrict__ des
         st[3] = (double)(cs[kKeyNonFinite + 1] - cs[kKeyNonFinite]);
         st[4] = (double)(cs[kKeyCulled + 1] - cs[kKeyCulled]);
         st[5] = (double)(cs[kKeyBadBw + 1] - cs[kKeyBadBw]);
-        st[6] = (double)inst_split[blockIdx.x];
+        st[6] = (double)inst_split[inst];
         st[7] = 0.0;
+        mass_done[inst] = 0u;
     }
 }
 
@@ -376,18 +421,21 @@ PassLayout layout_pass(const InstGeom* inst, int32_t count, int tile_t, bool kah
     l.desc = o; o = al256(o + (size_t)count * sizeof(InstDev));
     l.inst_cost = o; o = al256(o + (size_t)count * 8);
     l.inst_split = o; o = al256(o + (size_t)count * 4);
+    l.mass_done = o; o = al256(o + (size_t)count * 4);
     l.cost = o; o = al256(o + (size_t)T * 4);
     l.hist = o; o = al256(o + (size_t)kCostClasses * 4);
+    l.cursor = o; o = al256(o + (size_t)kCostClasses * 4);
+    l.demand = o; o = al256(o + (size_t)kCostClasses * 4);
     l.bits = o; o = al256(o + ((size_t)T + 31) / 32 * 4);
     l.scalars = o; o = al256(o + (size_t)kScCount * 4);
     l.counters = o; o = al256(o + (size_t)kCtrWords * 4);
     l.heavy = o; o = al256(o + (size_t)kTopTiles * 8);
     l.top = o; o = al256(o + (size_t)kTopTiles * 16);
     l.items = o; o = al256(o + (size_t)kTopTiles * kMaxParts * sizeof(WorkItem));
-    l.partials = o; o = al256(o + (size_t)kPartSlots * kTileXY * kTileXY * tile_t * 4);
+    l.partials = o; o = al256(o + (size_t)part_slots(T) * kTileXY * kTileXY * tile_t * 4);
     l.kscratch = o;
     // per thread: (sum, compensation) of 4 column groups x tile_t/16 row blocks, f32x4 each
-    if (kahan) o = al256(o + (size_t)kMemKahanGroups * kThreads * 2 * (4 * (tile_t / 16)) * 16);
+    if (kahan) o = al256(o + (size_t)kahan_slots(T) * kThreads * 2 * (4 * (tile_t / 16)) * 16);
     l.tile_part = o; o = al256(o + (size_t)parts * 8);
     l.mass_mid = o; o = al256(o + (size_t)count * kMassChunks * 8);
     l.total = o;
@@ -401,8 +449,11 @@ hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassL
     InstDev* d_desc = reinterpret_cast<InstDev*>(pass + pl.desc);
     auto* inst_cost = reinterpret_cast<unsigned long long*>(pass + pl.inst_cost);
     auto* inst_split = reinterpret_cast<uint32_t*>(pass + pl.inst_split);
+    auto* mass_done = reinterpret_cast<uint32_t*>(pass + pl.mass_done);
     auto* cost = reinterpret_cast<uint32_t*>(pass + pl.cost);
     auto* hist = reinterpret_cast<uint32_t*>(pass + pl.hist);
+    auto* cursor = reinterpret_cast<uint32_t*>(pass + pl.cursor);
+    auto* demand = reinterpret_cast<uint32_t*>(pass + pl.demand);
     auto* bits = reinterpret_cast<uint32_t*>(pass + pl.bits);
     auto* sc = reinterpret_cast<uint32_t*>(pass + pl.scalars);
     auto* ctr = reinterpret_cast<uint32_t*>(pass + pl.counters);
@@ -412,30 +463,30 @@ hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassL
     auto* kscratch = reinterpret_cast<float*>(pass + pl.kscratch);
     auto* tile_part = reinterpret_cast<double*>(pass + pl.tile_part);
     auto* mid = reinterpret_cast<double*>(pass + pl.mass_mid);
+    auto* heavy = reinterpret_cast<unsigned long long*>(pass + pl.heavy);
 
+    bool any_stats = false;
     int64_t tb = 0;
     for (int32_t i = 0; i < count; ++i) {
         descs[i].tile_base = (int32_t)tb;
         descs[i].tile_part = tile_part + tb * kWaves;
         tb += descs[i].ntiles;
+        any_stats = any_stats || descs[i].stats != nullptr;
     }
     for (int32_t first = 0; first < count; first += kDescChunk) {
         DescChunk c{};
         const int32_t m = count - first < kDescChunk ? count - first : kDescChunk;
         for (int32_t k = 0; k < m; ++k) c.d[k] = descs[first + k];
         hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(256), 0, s, c, first, m, d_desc, inst_cost,
-                           inst_split, hist, sc, first == 0 ? 1 : 0);
+                           inst_split, mass_done, hist, cursor, demand, sc, first == 0 ? 1 : 0);
     }
     const uint32_t T = (uint32_t)pl.T;
     hipLaunchKernelGGL(k_tile_cost, dim3((T + 255) / 256), dim3(256), 0, s, (const InstDev*)d_desc,
                        count, T, tile_t, cost, hist, inst_cost, bits);
-    auto* heavy = reinterpret_cast<unsigned long long*>(pass + pl.heavy);
-    hipLaunchKernelGGL(k_collect_heavy, dim3((T + 2047) / 2048), dim3(256), 0, s, T, (const uint32_t*)cost,
-                       (const uint32_t*)hist, heavy, sc);
-    hipLaunchKernelGGL(k_plan_items, dim3(1), dim3(1024), 0, s, (const InstDev*)d_desc, count,
-                       (const unsigned long long*)heavy, (const unsigned long long*)inst_cost, inst_split,
-                       items, top,
-                       bits, sc, ctr, (uint32_t)kPartSlots);
+    hipLaunchKernelGGL(k_collect_plan, dim3((T + 2047) / 2048), dim3(256), 0, s, (const InstDev*)d_desc, count,
+                       T, (const uint32_t*)cost, (const uint32_t*)hist, (const unsigned long long*)inst_cost,
+                       inst_split, cursor, demand, heavy, items, top, bits, sc, ctr, (uint32_t)part_slots(pl.T),
+                       sc + kScPlanDone);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev_before && (e = hipEventRecord(ev_before, s)) != hipSuccess) return e;
@@ -445,10 +496,9 @@ hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassL
     if (ev_after && (e = hipEventRecord(ev_after, s)) != hipSuccess) return e;
     e = launch_reduce_split(d_desc, count, top, sc, partials, tile_t, kahan, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_mass_chunks, dim3(kMassChunks, (uint32_t)count), dim3(256), 0, s,
-                       (const InstDev*)d_desc, mid);
-    hipLaunchKernelGGL(k_finalize, dim3((uint32_t)count), dim3(64), 0, s, (const InstDev*)d_desc,
-                       (const double*)mid, (const uint32_t*)inst_split);
+    if (any_stats)
+        hipLaunchKernelGGL(k_mass, dim3(kMassChunks, (uint32_t)count), dim3(256), 0, s, (const InstDev*)d_desc,
+                           mid, (const uint32_t*)inst_split, mass_done);
     return hipGetLastError();
 }
 

@@ -135,6 +135,16 @@ constexpr int kAccPlain = 0;
 constexpr int kAccKahanReg = 1;
 constexpr int kAccKahanMem = 2;
 constexpr int kMemKahanGroups = 1536;  // workgroups (scratch slots) in memory mode
+// Work items of a pass over T tiles: every tile once, the heavy ones (at
+// most kTopTiles) in up to kMaxParts parts; the persistent gather never runs
+// more workgroups than that, and a pass never needs more partial slots than
+// its heavy tiles' parts.
+inline int64_t max_items(int64_t T) { return T + (int64_t)(kMaxParts - 1) * (T < kTopTiles ? T : kTopTiles); }
+inline int64_t part_slots(int64_t T) {
+    const int64_t m = (int64_t)kMaxParts * (T < kTopTiles ? T : kTopTiles);
+    return m < kPartSlots ? m : kPartSlots;
+}
+inline int64_t kahan_slots(int64_t T) { return max_items(T) < kMemKahanGroups ? max_items(T) : kMemKahanGroups; }
 // Full-cover path of the gather: a point whose disc covers the whole 16 x 16
 // columns of a tile adds Kt (1 - a(x) - b(y)) there, which two 16 x 16
 // products (sum of Kt (a - 1) over x, sum of Kt b over y) give for all the
@@ -162,7 +172,7 @@ constexpr int kCtrStride = 64;  // u32
 constexpr int kScHeavyItems = 0;  // items in the heaviest-first queue
 constexpr int kScSplit = 1;       // split tiles
 constexpr int kScHeavyTiles = 2;  // tiles in the heaviest-first queue
-constexpr int kScHeavyFound = 3;  // heavy tiles collected (before sorting)
+constexpr int kScPlanDone = 3;    // workgroups of the queue planning that have finished
 constexpr int kScCount = 8;
 // Counters (u32 offsets into PassLayout::counters): queue q, lane k at
 // (q * kFetchLanes + k) * kCtrStride.
@@ -191,16 +201,19 @@ struct PassLayout {
     size_t desc;         // count InstDev
     size_t inst_cost;    // count u64: candidates summed over the instance's tiles
     size_t inst_split;   // count u32: tiles of the instance computed in parts
+    size_t mass_done;    // count u32: mass workgroups of the instance that have finished
     size_t cost;         // T u32: candidates per tile
     size_t hist;         // kCostClasses u32: tiles per cost class
+    size_t cursor;       // kCostClasses u32: heavy tiles placed per class
+    size_t demand;       // kCostClasses u32: partial slots the class's heavy tiles would take
     size_t bits;         // ceil(T / 32) u32: spatial-queue positions taken by the heavy queue
     size_t scalars;      // kScCount u32
     size_t counters;     // kCtrWords u32: the queues' fetch counters
-    size_t heavy;        // kTopTiles u64 keys of the heavy tiles, in collection order
+    size_t heavy;        // kTopTiles u64 (cost << 32 | tile) of the heavy tiles, by class
     size_t top;          // kTopTiles x 4 u32 split tiles: tile, parts, slot0, candidates
     size_t items;        // kTopTiles * kMaxParts WorkItem (the heaviest-first queue)
-    size_t partials;     // kPartSlots x 16 x 16 x tile_t FP32
-    size_t kscratch;     // Kahan plans: kMemKahanGroups x kThreads x 2 x (4 tile_t/16) f32x4
+    size_t partials;     // part_slots(T) x 16 x 16 x tile_t FP32
+    size_t kscratch;     // Kahan plans: kahan_slots(T) x kThreads x 2 x (4 tile_t/16) f32x4
     size_t tile_part;    // sum over instances of ntiles * kWaves FP64
     size_t mass_mid;     // count * kMassChunks FP64
     size_t total;
