@@ -252,6 +252,22 @@ stkde_status stkde_plan_capture(stkde_plan_t plan, const double* d_xyt, int64_t 
                                 void* d_ws, size_t ws_bytes, double* d_stats);
 stkde_status stkde_plan_replay(stkde_plan_t plan, void* stream);
 
+/* One stkde_compute without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the workspace is the library's own
+ * device scratch of STKDE_STATIC_SCRATCH_BYTES (128 MiB), a static array that
+ * each GPU the library runs on holds until the process ends.  Arguments and
+ * results as stkde_compute (same plan and input: the same bits), without
+ * d_ws / ws_bytes; the caller still passes the points, the output and the
+ * optional statistics.  No device memory is allocated or freed.
+ * Every call on a GPU uses that GPU's one scratch: calls that may overlap on
+ * one GPU (other streams, other threads) race and must be ordered by the
+ * caller.  Errors: as stkde_compute; WORKSPACE when
+ * stkde_workspace_bytes(plan, n) exceeds STKDE_STATIC_SCRATCH_BYTES. */
+#define STKDE_STATIC_SCRATCH_BYTES (128u << 20)
+stkde_status stkde_compute_noalloc(stkde_plan_t plan, const double* d_xyt, int64_t n, float* d_out,
+                                   double* d_stats, void* stream);
+
 /* Per-point bandwidths (plans with STKDE_FLAG_ADAPTIVE; the estimator is
  * given at that flag).  Arguments as stkde_compute / stkde_bin, plus
  *

@@ -49,7 +49,11 @@ EXPORTED = ("stkde_plan", "stkde_plan_destroy", "stkde_workspace_bytes", "stkde_
             "stkde_batch_capture", "stkde_batch_replay", "stkde_batch_destroy",
             "stkde_plan_profile", "stkde_plan_profile_read",
             "stkde_ablation_accumulate", "stkde_ablation_compute",
-            "stkde_compute_adaptive", "stkde_bin_adaptive", "stkde_plan_capture", "stkde_plan_replay")
+            "stkde_compute_adaptive", "stkde_bin_adaptive", "stkde_plan_capture", "stkde_plan_replay",
+            "stkde_compute_noalloc")
+
+# Bytes of the library's own device scratch (stkde_compute_noalloc).
+STATIC_SCRATCH_BYTES = 128 << 20
 
 # Baselines of include/stkde_ablation.h (benchmarks and tests only).
 ABLATION_SCATTER = 1
@@ -135,6 +139,8 @@ def lib():
         L.stkde_plan_capture.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
         L.stkde_plan_replay.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.stkde_compute_noalloc.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         for name in EXPORTED:
             if name not in ("stkde_status_string", "stkde_version"):
                 getattr(L, name).restype = ctypes.c_int
@@ -282,6 +288,31 @@ class Plan:
                                  ctypes.c_void_p(stream.cuda_stream))
         if st != STKDE_OK:
             raise StkdeError(st, "stkde_compute")
+        return out
+
+    def compute_noalloc(self, points, out, stats=None, stream=None):
+        """As :meth:`compute_into`, with the library's own device scratch as
+        the workspace (``stkde_compute_noalloc``): nothing is allocated, by
+        the library or here.  Calls that may overlap on one GPU race."""
+        import torch
+        n = int(points.shape[0])
+        if points.dtype != torch.float64 or not points.is_cuda or points.dim() != 2 or points.shape[1] != 3 \
+                or not points.is_contiguous():
+            raise ValueError("points must be a contiguous [n, 3] float64 CUDA tensor")
+        d = self.desc
+        if out.dtype != torch.float32 or not out.is_cuda or out.numel() != d.gx * d.gy * d.gt \
+                or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 CUDA tensor of gx*gy*gt elements")
+        if stats is not None and (stats.dtype != torch.float64 or stats.numel() < 8 or not stats.is_cuda):
+            raise ValueError("stats must be a float64 CUDA tensor of 8 elements")
+        if stream is None:
+            stream = torch.cuda.current_stream(points.device)
+        st = lib().stkde_compute_noalloc(self._h, ctypes.c_void_p(points.data_ptr()), n,
+                                         ctypes.c_void_p(out.data_ptr()),
+                                         ctypes.c_void_p(stats.data_ptr()) if stats is not None else None,
+                                         ctypes.c_void_p(stream.cuda_stream))
+        if st != STKDE_OK:
+            raise StkdeError(st, "stkde_compute_noalloc")
         return out
 
     def capture(self, points, out, stats=None, workspace=None):

@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <new>
 #include <vector>
 
@@ -596,6 +597,45 @@ stkde_status stkde_plan_replay(stkde_plan_t p, void* stream) {
     if (!p->exec) return STKDE_ERR_UNSUPPORTED;
     if (hipGraphLaunch(p->exec, reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return STKDE_ERR_HIP;
     return STKDE_OK;
+}
+
+}  // extern "C"
+
+// ---- one computation in the library's own device scratch -------------------
+//
+// stkde_compute_noalloc runs stkde_compute with the workspace in `scratch`,
+// a file-scope device array that each GPU holds from the library's load
+// until the process ends.  In host code `scratch` names a host-side stand-in,
+// not device memory: its device address on the current GPU comes from
+// hipGetSymbolAddress, taken once per device and kept in scratch_ptr.
+static __device__ __align__(256) uint8_t scratch[STKDE_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::atomic<void*> scratch_ptr[kMaxScratchDevices];
+
+// Device address of the current GPU's copy of `scratch` (null on failure).
+void* static_scratch() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxScratchDevices) return nullptr;
+    void* p = scratch_ptr[dev].load(std::memory_order_acquire);
+    if (p) return p;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    scratch_ptr[dev].store(p, std::memory_order_release);  // every thread finds the same address
+    return p;
+}
+}  // namespace
+
+extern "C" {
+
+stkde_status stkde_compute_noalloc(stkde_plan_t p, const double* d_xyt, int64_t n, float* d_out,
+                                   double* d_stats, void* stream) {
+    if (!p || !d_xyt || !d_out || is_adaptive(p) || n < 1) return STKDE_ERR_INVALID_ARG;
+    if (n > 0x7fffffffLL) return STKDE_ERR_TOO_LARGE;
+    if (layout_compute(p, n).total > (size_t)STKDE_STATIC_SCRATCH_BYTES) return STKDE_ERR_WORKSPACE;
+    void* ws = static_scratch();
+    if (!ws) return STKDE_ERR_HIP;
+    return compute_impl(p, d_xyt, nullptr, n, d_out, ws, (size_t)STKDE_STATIC_SCRATCH_BYTES, d_stats, stream);
 }
 
 // ---- binned sets ------------------------------------------------------------

@@ -106,6 +106,27 @@ def test_compute_rejects_before_launch(L):
     assert lib.stkde_compute(h, fake, 10, fake, ctypes.c_void_p(0x10010), need, None, None) == -3
 
 
+def test_compute_noalloc_rejects_before_launch(L):
+    """The entry point without allocation validates like stkde_compute and
+    refuses a computation whose workspace exceeds the static scratch, all on
+    the host (no HIP call)."""
+    lib = L.lib()
+    p = L.Plan(L.Desc(gx=32, gy=32, gt=32, hs=3.0, ht=3.0))
+    fake = ctypes.c_void_p(0x10000)
+    h = p.handle
+    assert lib.stkde_compute_noalloc(None, fake, 10, fake, None, None) == -1
+    assert lib.stkde_compute_noalloc(h, None, 10, fake, None, None) == -1
+    assert lib.stkde_compute_noalloc(h, fake, 10, None, None, None) == -1
+    assert lib.stkde_compute_noalloc(h, fake, 0, fake, None, None) == -1
+    assert lib.stkde_compute_noalloc(h, fake, 1 << 31, fake, None, None) == -2
+    big = L.Plan(L.Desc(gx=1024, gy=1024, gt=256, hs=10.0, ht=7.0))
+    n = 4_000_000
+    assert big.workspace_bytes(n) > L.STATIC_SCRATCH_BYTES
+    assert lib.stkde_compute_noalloc(big.handle, fake, n, fake, None, None) == -3
+    ad = L.Plan(L.Desc(gx=32, gy=32, gt=32, hs=3.0, ht=3.0, flags=L.FLAG_ADAPTIVE))
+    assert lib.stkde_compute_noalloc(ad.handle, fake, 10, fake, None, None) == -1
+
+
 def test_ablation_rejects_before_launch(L):
     """The baselines validate like stkde_compute, and reject unknown methods."""
     lib = L.lib()
