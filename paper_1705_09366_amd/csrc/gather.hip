@@ -231,13 +231,13 @@ __device__ inline void kahan_fold(f32x4 (&sum)[CG], f32x4 (&comp)[CG], f32x4 (&p
 // written, without contraction).
 __device__ inline bool exact_disc(const double* __restrict__ x64, uint32_t ri, int32_t X, int32_t Y,
                                   double hv) {
-    const double dx = __dadd_rn((double)X + 0.5, -x64[3 * (size_t)ri]);
-    const double dy = __dadd_rn((double)Y + 0.5, -x64[3 * (size_t)ri + 1]);
+    const double dx = __dadd_rn((double)X + 0.5, -as_global(x64)[3 * (size_t)ri]);
+    const double dy = __dadd_rn((double)Y + 0.5, -as_global(x64)[3 * (size_t)ri + 1]);
     return __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)) < __dmul_rn(hv, hv);
 }
 
 __device__ inline bool exact_window(const double* __restrict__ x64, uint32_t ri, int32_t T, double tv) {
-    return fabs(__dadd_rn((double)T + 0.5, -x64[3 * (size_t)ri + 2])) <= tv;
+    return fabs(__dadd_rn((double)T + 0.5, -as_global(x64)[3 * (size_t)ri + 2])) <= tv;
 }
 
 // H16: two-term FP16 operands (see the header).
@@ -392,8 +392,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                     if (lane < nranges) {
                         const int32_t cz = tb.ct0 + lane / nyr, cy = tb.cy0 + lane % nyr;
                         const int32_t row = (cz * D.ncy + cy) * D.ncx;
-                        beg = (int32_t)D.cell_start[row + tb.cx0];
-                        len = (int32_t)D.cell_start[row + tb.cx1 + 1] - beg;
+                        beg = (int32_t)as_global(D.cell_start)[row + tb.cx0];
+                        len = (int32_t)as_global(D.cell_start)[row + tb.cx1 + 1] - beg;
                     }
                     int32_t inc = len;
 #pragma unroll
@@ -619,8 +619,24 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                         }
                         const int32_t ri = sRB[lo] + (c - sRP[lo]);
                         rix = (uint32_t)ri;
-                        r = recs[ri];
-                        if constexpr (ADAPT) pbw = D.bw[ri];
+                        {
+                            const auto* q = reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(
+                                as_global(recs + ri));
+                            const u32x4 a = q[0], b2 = q[1];
+                            r.xh = __uint_as_float(a.x);
+                            r.yh = __uint_as_float(a.y);
+                            r.th = __uint_as_float(a.z);
+                            r.xb = a.w;
+                            r.yb = b2.x;
+                            r.tb = b2.y;
+                            r.xl_yl = b2.z;
+                            r.tl = b2.w;
+                        }
+                        if constexpr (ADAPT) {
+                            const f32x4 v = *reinterpret_cast<const __attribute__((address_space(1))) f32x4*>(
+                                as_global(D.bw + ri));
+                            pbw = make_float4(v.x, v.y, v.z, v.w);
+                        }
                     }
                 };
                 int32_t bb = (int32_t)min(it.cbeg, (uint32_t)cend);
@@ -947,13 +963,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                         const int32_t T = T0 + 16 * b + 4 * (lane >> 4);
                         const f32x4 v = acc[g * NB + b] * cnorm;
                         if (vec && T + 3 < gtI) {
-                            *reinterpret_cast<f32x4*>(col + T) = v;
+                            *reinterpret_cast<__attribute__((address_space(1))) f32x4*>(as_global(col) + T) = v;
                             msum += (double)v[0] + (double)v[1] + (double)v[2] + (double)v[3];
                         } else {
 #pragma unroll
                             for (int e = 0; e < 4; ++e) {
                                 if (T + e < gtI) {
-                                    col[T + e] = v[e];
+                                    as_global(col)[T + e] = v[e];
                                     msum += (double)v[e];
                                 }
                             }
@@ -963,7 +979,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                 if (mass) {
 #pragma unroll
                     for (int d = 32; d >= 1; d >>= 1) msum += __shfl_xor(msum, d, 64);
-                    if (lane == 0) D.tile_part[(size_t)tile * kWaves + wave] = msum;
+                    if (lane == 0) as_global(D.tile_part)[(size_t)tile * kWaves + wave] = msum;
                 }
             }
         }
@@ -1024,14 +1040,14 @@ __global__ __launch_bounds__(kThreads) void k_reduce_split(const InstDev* __rest
             const f32x4 o = s * D.cnorm;
             if (col_ok) {
                 if ((gtI & 3) == 0 && T0 + r + 3 < gtI) {
-                    *reinterpret_cast<f32x4*>(col + T0 + r) = o;
+                    *reinterpret_cast<__attribute__((address_space(1))) f32x4*>(as_global(col) + T0 + r) = o;
 #pragma unroll
                     for (int e = 0; e < 4; ++e) msum += (double)o[e];
                 } else {
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         if (T0 + r + e < gtI) {
-                            col[T0 + r + e] = o[e];
+                            as_global(col)[T0 + r + e] = o[e];
                             msum += (double)o[e];
                         }
                     }
@@ -1041,7 +1057,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce_split(const InstDev* __rest
         if (D.flags & kInstMass) {
 #pragma unroll
             for (int d = 32; d >= 1; d >>= 1) msum += __shfl_xor(msum, d, 64);
-            if (lane == 0) D.tile_part[(size_t)tile * kWaves + wave] = msum;
+            if (lane == 0) as_global(D.tile_part)[(size_t)tile * kWaves + wave] = msum;
         }
     }
 }

@@ -94,8 +94,8 @@ __global__ __launch_bounds__(256) void k_tile_cost(const InstDev* __restrict__ d
                 hi[u] = lo[u] = 0u;
                 if (r0 + u < nrows) {
                     const int32_t row = (ct * D.ncy + cy) * D.ncx;
-                    hi[u] = D.cell_start[row + b.cx1 + 1];
-                    lo[u] = D.cell_start[row + b.cx0];
+                    hi[u] = as_global(D.cell_start)[row + b.cx1 + 1];
+                    lo[u] = as_global(D.cell_start)[row + b.cx0];
                     if (cy == b.cy1) {
                         cy = b.cy0;
                         ++ct;
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(256) void k_mass(const InstDev* __restrict__ descs,
         const int64_t chunk = (cnt + kMassChunks - 1) / kMassChunks;
         const int64_t beg = (int64_t)ch * chunk;
         const int64_t end = beg + chunk < cnt ? beg + chunk : cnt;
-        for (int64_t i = beg + tid; i < end; i += 256) s += D.tile_part[i];
+        for (int64_t i = beg + tid; i < end; i += 256) s += as_global(D.tile_part)[i];
     }
     sh[tid] = s;
     __syncthreads();
@@ -392,12 +392,12 @@ __global__ __launch_bounds__(256) void k_mass(const InstDev* __restrict__ descs,
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
     if (lane == 0) {
-        double* st = D.stats;
+        auto* st = as_global(D.stats);
         st[0] = (D.flags & kInstMass) ? v * D.mass_scale : 0.0;
         st[1] = 0.0;
         st[2] = 0.0;
         // the set's points that are never visited, from the offsets of their keys
-        const uint32_t* cs = D.cell_start + (size_t)D.ncx * D.ncy * D.nct;
+        const auto* cs = as_global(D.cell_start + (size_t)D.ncx * D.ncy * D.nct);
         st[3] = (double)(cs[kKeyNonFinite + 1] - cs[kKeyNonFinite]);
         st[4] = (double)(cs[kKeyCulled + 1] - cs[kKeyCulled]);
         st[5] = (double)(cs[kKeyBadBw + 1] - cs[kKeyBadBw]);

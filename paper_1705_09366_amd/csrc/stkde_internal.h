@@ -221,6 +221,15 @@ struct PassLayout {
 };
 PassLayout layout_pass(const InstGeom* inst, int32_t count, int tile_t, bool kahan);
 
+// Global-memory view of a device pointer.  Pointers the kernels read from
+// descriptors are generic to the compiler, and generic (flat) accesses count
+// against both the vector-memory and the LDS wait counters: every LDS wait
+// would also wait for them (the records in flight, the grid stores).
+template <typename T>
+__device__ inline __attribute__((address_space(1))) T* as_global(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+
 // Instance holding global tile `tile` (descriptors ordered by tile_base).
 __device__ inline int32_t find_inst(const InstDev* __restrict__ d, int32_t count, uint32_t tile) {
     int32_t lo = 0, hi = count - 1;
