@@ -608,16 +608,25 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                     }
                 };
 
-                // record (and bandwidth terms) of candidate c, if any
-                auto fetch = [&](const int32_t c, PointRec& r, uint32_t& rix, float4& pbw) {
+                // the ranges in registers: lane r holds range r's first
+                // candidate (past the last range: larger than any) and the
+                // record index minus candidate index within it
+                const int32_t rpl = lane < nranges ? sRP[lane] : 0x7fffffff;
+                const int32_t rol = lane < nranges ? sRB[lane] - sRP[lane] : 0;
+                // record (and bandwidth terms) of candidate cw + lane, if any
+                // (cw: the wave's first candidate).  Its range is the last one
+                // starting at or before it: the ranges starting at or before
+                // cw form a prefix of the lanes, and the few starting within
+                // the wave's 64 candidates are stepped over in order.
+                auto fetch = [&](const int32_t cw_, PointRec& r, uint32_t& rix, float4& pbw) {
+                    const int32_t cw = __builtin_amdgcn_readfirstlane(cw_);
+                    const int32_t c = cw + lane;
+                    int32_t lo = __popcll(__ballot(rpl <= cw)) - 1;  // sRP[0] = 0 <= cw
+                    for (unsigned long long in = __ballot(rpl > cw && rpl <= cw + 63); in != 0ull; in &= in - 1ull)
+                        lo += c >= __builtin_amdgcn_readlane(rpl, __builtin_ctzll(in)) ? 1 : 0;
+                    const int32_t roff = __shfl(rol, lo, 64);  // every lane takes part
                     if (c < cend) {
-                        int32_t lo = 0, hi = nranges - 1;  // last range with sRP <= c
-                        while (lo < hi) {
-                            const int32_t mid = (lo + hi + 1) >> 1;
-                            if (sRP[mid] <= c) lo = mid;
-                            else hi = mid - 1;
-                        }
-                        const int32_t ri = sRB[lo] + (c - sRP[lo]);
+                        const int32_t ri = roff + c;
                         rix = (uint32_t)ri;
                         {
                             const auto* q = reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(
@@ -647,14 +656,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                     PointRec rn{};
                     float4 pbn{};
                     uint32_t rin = 0;
-                    fetch(bb + tid, rn, rin, pbn);
+                    fetch(bb + 64 * wave, rn, rin, pbn);
                     while (bb < cend && count_s <= kCap - kThreads) {
                         const int32_t c = bb + tid;
                         bool surv = false;
                         const PointRec r = rn;
                         const float4 pbw = pbn;
                         const uint32_t rix = rin;
-                        fetch(bb + kThreads + tid, rn, rin, pbn);
+                        fetch(bb + kThreads + 64 * wave, rn, rin, pbn);
                         uint32_t qm = 0;
                         if (c < cend) {
                             const int32_t xlo = (int32_t)(r.xb & 0xffffu) - BX0, xhi = (int32_t)(r.xb >> 16) - BX0;
