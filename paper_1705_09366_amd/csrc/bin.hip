@@ -98,32 +98,60 @@ __device__ inline bool point_bandwidths(const SetGeom& g, const double* __restri
     return isfinite(hs) && isfinite(ht) && hs > 0.0 && ht > 0.0 && *hv <= g.hv && *tv <= g.tv;
 }
 
+constexpr int kMaxDigitBits = 11;
+constexpr int kMaxBuckets = 1 << kMaxDigitBits;
+
+// Keys of one radix block's points (kSortItems per thread, index order
+// within the block as in the scatter) and the block's histogram of the first
+// digit (the low dbits bits), hist[d * nblk + block].
 __global__ __launch_bounds__(kThreads) void k_transform(SetGeom g, const double* __restrict__ xyt,
                                                         const double* __restrict__ hst, int32_t n,
                                                         uint32_t* __restrict__ keys,
-                                                        uint32_t* __restrict__ vals) {
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i < n) {
-        double hv, tv;
-        const bool bw_ok = point_bandwidths(g, hst, i, &hv, &tv);
-        const Footprint f = footprint(g, xyt[3 * (size_t)i], xyt[3 * (size_t)i + 1],
-                                      xyt[3 * (size_t)i + 2], bw_ok ? hv : g.hv, bw_ok ? tv : g.tv);
-        uint32_t key;
-        if (!f.finite) key = (uint32_t)(g.ncell + kKeyNonFinite);
-        else if (!bw_ok) key = (uint32_t)(g.ncell + kKeyBadBw);
-        else if (!f.inside) key = (uint32_t)(g.ncell + kKeyCulled);
-        else key = bin_key(g, f);
-        keys[i] = key;
-        vals[i] = (uint32_t)i;
+                                                        uint32_t* __restrict__ vals, int nbuck,
+                                                        uint32_t* __restrict__ hist, int32_t nblk) {
+    __shared__ uint32_t cnt[kMaxBuckets];
+    const int tid = threadIdx.x;
+    const int32_t base = blockIdx.x * kSortTile;
+    // every coordinate of this thread is loaded before the first footprint,
+    // so that the loads are in flight together
+    double px[kSortItems], py[kSortItems], pt[kSortItems];
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        const int32_t i = base + it * kThreads + tid;
+        const int32_t ic = i < n ? i : n - 1;
+        px[it] = xyt[3 * (size_t)ic];
+        py[it] = xyt[3 * (size_t)ic + 1];
+        pt[it] = xyt[3 * (size_t)ic + 2];
     }
+    for (int d = tid; d < nbuck; d += kThreads) cnt[d] = 0;
+    __syncthreads();
+    const uint32_t mask = (uint32_t)nbuck - 1u;
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        const int32_t i = base + it * kThreads + tid;
+        if (i < n) {
+            double hv, tv;
+            const bool bw_ok = point_bandwidths(g, hst, i, &hv, &tv);
+            const Footprint f = footprint(g, px[it], py[it], pt[it], bw_ok ? hv : g.hv, bw_ok ? tv : g.tv);
+            uint32_t key;
+            if (!f.finite) key = (uint32_t)(g.ncell + kKeyNonFinite);
+            else if (!bw_ok) key = (uint32_t)(g.ncell + kKeyBadBw);
+            else if (!f.inside) key = (uint32_t)(g.ncell + kKeyCulled);
+            else key = bin_key(g, f);
+            keys[i] = key;
+            vals[i] = (uint32_t)i;
+            atomicAdd(&cnt[key & mask], 1u);
+        }
+    }
+    __syncthreads();
+    for (int d = tid; d < nbuck; d += kThreads) hist[(size_t)d * nblk + blockIdx.x] = cnt[d];
 }
 
-// ---- stable LSD radix sort, digits of 8 to 11 bits --------------------------
+// ---- stable LSD radix sort, digits of 6 to 11 bits --------------------------
 //
 // A key of b bits is sorted in ceil(b / 11) passes of equal digits (18-bit
-// keys: two 9-bit passes).
-constexpr int kMaxDigitBits = 11;
-constexpr int kMaxBuckets = 1 << kMaxDigitBits;
+// keys: two 9-bit passes; 12- to 14-bit keys: two passes of 6 or 7 bits, fewer
+// buckets than threads).  The first pass's histogram comes with the keys.
 
 // Per-block digit histogram.  hist is digit-major: hist[d * nblk + b].
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
@@ -152,36 +180,15 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restr
     for (int d = threadIdx.x; d < nbuck; d += kThreads) hist[(size_t)d * nblk + blockIdx.x] = cnt[d];
 }
 
-// totals[d] = sum over blocks of hist[d][b]; one workgroup per digit.
-__global__ __launch_bounds__(kThreads) void k_radix_rowsum(const uint32_t* __restrict__ hist,
-                                                           int32_t nblk, uint32_t* __restrict__ totals) {
-    __shared__ uint32_t wsum[kWaves];
-    const uint32_t* row = hist + (size_t)blockIdx.x * nblk;
-    uint32_t v = 0;
-    for (int32_t i = threadIdx.x; i < nblk; i += kThreads) v += row[i];
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) totals[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-}
-
-// One workgroup per digit d: hist[d][b] <- (keys with a smaller digit) +
-// (keys with digit d in blocks before b), i.e. the scatter base of block b.
-__global__ __launch_bounds__(kThreads) void k_radix_scan(uint32_t* __restrict__ hist, int32_t nblk,
-                                                         const uint32_t* __restrict__ totals) {
+// One workgroup per digit d: hist[d][b] <- keys with digit d in blocks before
+// b (an exclusive scan of the row), totals[d] <- the row's sum.  The keys of
+// smaller digits are added by the scatter.
+__global__ __launch_bounds__(kThreads) void k_radix_rowscan(uint32_t* __restrict__ hist, int32_t nblk,
+                                                            uint32_t* __restrict__ totals) {
     __shared__ uint32_t wsum[kWaves];
     __shared__ uint32_t carry_s;
     const int d = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    // keys of smaller digits
-    uint32_t lower = 0;
-    for (int e = tid; e < d; e += kThreads) lower += totals[e];
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) lower += __shfl_xor(lower, o, 64);
-    if (lane == 0) wsum[wv] = lower;
-    __syncthreads();
-    if (tid == 0) carry_s = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-    __syncthreads();
+    if (tid == 0) carry_s = 0u;
     uint32_t* row = hist + (size_t)d * nblk;
     for (int32_t base = 0; base < nblk; base += kThreads) {
         const int32_t i = base + tid;
@@ -201,6 +208,8 @@ __global__ __launch_bounds__(kThreads) void k_radix_scan(uint32_t* __restrict__ 
         __syncthreads();
         if (tid == 0) carry_s += wsum[0] + wsum[1] + wsum[2] + wsum[3];
     }
+    __syncthreads();
+    if (tid == 0) totals[d] = carry_s;
 }
 
 // Stable scatter.  Keys of a block are processed in index order: round r
@@ -209,8 +218,8 @@ __global__ __launch_bounds__(kThreads) void k_radix_scan(uint32_t* __restrict__ 
 // rounds) + (in earlier waves of this round) + (in earlier lanes).
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, int32_t n, int shift,
-    int dbits, const uint32_t* __restrict__ hist, int32_t nblk, uint32_t* __restrict__ kout,
-    uint32_t* __restrict__ vout) {
+    int dbits, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ totals, int32_t nblk,
+    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
     __shared__ uint32_t off[kMaxBuckets];
     __shared__ uint32_t wcnt[kWaves][kMaxBuckets];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -226,8 +235,40 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
         kr[r] = i < n ? kin[i] : 0u;
         vr[r] = i < n ? vin[i] : 0u;
     }
+    // off[d] = keys of the smaller digits (an exclusive scan of the digit
+    // totals; thread tid holds digits per * tid + [0, per) below nbuck, per
+    // >= 1 also for digits of fewer than 8 bits) + this block's offset within
+    // digit d
+    {
+        const int per = (nbuck + kThreads - 1) / kThreads;
+        uint32_t tv[kMaxBuckets / kThreads], ts = 0;
+#pragma unroll
+        for (int k = 0; k < kMaxBuckets / kThreads; ++k) {
+            const int d = per * tid + k;
+            tv[k] = (k < per && d < nbuck) ? totals[d] : 0u;
+            ts += tv[k];
+        }
+        uint32_t inc = ts;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t u = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += u;
+        }
+        if (lane == 63) wcnt[0][wv] = inc;
+        __syncthreads();
+        uint32_t run = inc - ts;
+        for (int w = 0; w < wv; ++w) run += wcnt[0][w];
+#pragma unroll
+        for (int k = 0; k < kMaxBuckets / kThreads; ++k) {
+            const int d = per * tid + k;
+            if (k < per && d < nbuck) {
+                off[d] = run + hist[(size_t)d * nblk + blockIdx.x];
+                run += tv[k];
+            }
+        }
+        __syncthreads();  // wcnt[0] is cleared next
+    }
     for (int d = tid; d < nbuck; d += kThreads) {
-        off[d] = hist[(size_t)d * nblk + blockIdx.x];
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) wcnt[w][d] = 0;
     }
@@ -391,24 +432,22 @@ hipError_t launch_bin(const SetGeom& g, const double* d_xyt, int32_t n, uint8_t*
     uint32_t* hist = reinterpret_cast<uint32_t*>(sort + so.hist);
     uint32_t* totals = reinterpret_cast<uint32_t*>(sort + so.totals);
     uint32_t* cs = reinterpret_cast<uint32_t*>(set + sl.cell_start);
-    const int nb = (n + kThreads - 1) / kThreads;
-
-    hipLaunchKernelGGL(k_transform, dim3(nb), dim3(kThreads), 0, s, g, d_xyt, d_hst, n, k0, v0);
 
     // keys are at most ncell + 2 (non-finite points): ceil(bits / 11) passes of equal digits
     const int bits = bits_for((uint32_t)(g.ncell + kKeySentinels - 1));
     const int passes = bits <= 8 ? 1 : (bits + kMaxDigitBits - 1) / kMaxDigitBits;
     const int dbits = bits <= 8 ? 8 : (bits + passes - 1) / passes;
     const int nbuck = 1 << dbits;
+    hipLaunchKernelGGL(k_transform, dim3(so.nblk), dim3(kThreads), 0, s, g, d_xyt, d_hst, n, k0, v0, nbuck,
+                       hist, so.nblk);
     for (int p = 0; p < passes; ++p) {
-        hipLaunchKernelGGL(k_radix_hist, dim3(so.nblk), dim3(kThreads), 0, s, k0, n, dbits * p, nbuck,
-                           hist, so.nblk);
-        hipLaunchKernelGGL(k_radix_rowsum, dim3(nbuck), dim3(kThreads), 0, s, hist, so.nblk,
-                           totals + kMaxBuckets * p);
-        hipLaunchKernelGGL(k_radix_scan, dim3(nbuck), dim3(kThreads), 0, s, hist, so.nblk,
-                           totals + kMaxBuckets * p);
+        if (p > 0)
+            hipLaunchKernelGGL(k_radix_hist, dim3(so.nblk), dim3(kThreads), 0, s, k0, n, dbits * p, nbuck,
+                               hist, so.nblk);
+        uint32_t* tot = totals + kMaxBuckets * p;
+        hipLaunchKernelGGL(k_radix_rowscan, dim3(nbuck), dim3(kThreads), 0, s, hist, so.nblk, tot);
         hipLaunchKernelGGL(k_radix_scatter, dim3(so.nblk), dim3(kThreads), 0, s, k0, v0, n, dbits * p,
-                           dbits, hist, so.nblk, k1, v1);
+                           dbits, hist, tot, so.nblk, k1, v1);
         std::swap(k0, k1);
         std::swap(v0, v1);
     }

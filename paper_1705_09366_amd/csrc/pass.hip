@@ -199,6 +199,10 @@ __global__ __launch_bounds__(256) void k_collect_plan(const InstDev* __restrict_
     __shared__ uint32_t ldem[kCostClasses];
     __shared__ uint32_t ws[4];
     __shared__ uint32_t s_cls, s_last;
+    // one workgroup (up to 2048 tiles): heavy[] and the demand stay in LDS,
+    // without the global atomics and the hand-over to a last workgroup
+    __shared__ unsigned long long sheavy[kTopTiles];
+    const bool one = gridDim.x == 1;
     const int tid = threadIdx.x;
     for (int k = tid; k < kCostClasses; k += 256) {
         lcnt[k] = 0u;
@@ -254,29 +258,42 @@ __global__ __launch_bounds__(256) void k_collect_plan(const InstDev* __restrict_
     __syncthreads();
     // reserve each class's run in heavy[]; lcnt becomes the run's base
     for (int k = tid; k < kCostClasses; k += 256) {
-        if (lcnt[k]) lcnt[k] = above[k] + atomicAdd(&cursor[k], lcnt[k]);  // < kTopTiles by the choice of cls
-        if (ldem[k]) atomicAdd(&demand[k], ldem[k]);
+        if (one) {
+            lcnt[k] = above[k];
+        } else {
+            if (lcnt[k]) lcnt[k] = above[k] + atomicAdd(&cursor[k], lcnt[k]);  // < kTopTiles by the choice of cls
+            if (ldem[k]) atomicAdd(&demand[k], ldem[k]);
+        }
     }
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
         const uint32_t c = cv[u], j = j0 + 256u * u;
-        if (rank[u] != 0xffffffffu) heavy[lcnt[cost_class(c)] + rank[u]] = ((unsigned long long)c << 32) | j;
+        if (rank[u] != 0xffffffffu) {
+            const uint32_t at = lcnt[cost_class(c)] + rank[u];
+            const unsigned long long v = ((unsigned long long)c << 32) | j;
+            if (one) sheavy[at] = v;
+            else heavy[at] = v;
+        }
     }
     // the last workgroup plans the queue
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) s_last = atomicAdd(done, 1u) == gridDim.x - 1 ? 1u : 0u;
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
+    if (!one) {
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) s_last = atomicAdd(done, 1u) == gridDim.x - 1 ? 1u : 0u;
+        __syncthreads();
+        if (!s_last) return;
+        __threadfence();
+    } else {
+        __syncthreads();
+    }
     const uint32_t nh = (cls < (uint32_t)kCostClasses) ? above[cls] + hist[cls] : 0u;
     // split classes: the costliest classes whose demand fits the slots
     uint32_t dm[kPer], dsum = 0;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
-        dm[u] = __hip_atomic_load(&demand[kCostClasses - 1 - (kPer * tid + u)], __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t k = kCostClasses - 1 - (kPer * tid + u);
+        dm[u] = one ? ldem[k] : __hip_atomic_load(&demand[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         dsum += dm[u];
     }
     uint32_t dtot;
@@ -304,7 +321,8 @@ __global__ __launch_bounds__(256) void k_collect_plan(const InstDev* __restrict_
         np[e] = 0u;
         ins[e] = 0;
         if (k < nh) {
-            const unsigned long long v = __hip_atomic_load(&heavy[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned long long v =
+                one ? sheavy[k] : __hip_atomic_load(&heavy[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             tl[e] = (uint32_t)v;
             cc[e] = (uint32_t)(v >> 32);
             ins[e] = find_inst(descs, count, tl[e]);
@@ -344,7 +362,7 @@ __global__ __launch_bounds__(256) void k_collect_plan(const InstDev* __restrict_
         sc[kScHeavyItems] = tot_items;
         sc[kScSplit] = tot_split;
         sc[kScHeavyTiles] = nh;
-        *done = 0u;
+        if (!one) *done = 0u;
     }
 }
 
