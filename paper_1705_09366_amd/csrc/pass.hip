@@ -56,8 +56,44 @@ __global__ __launch_bounds__(256) void k_put_desc(DescChunk c, int32_t first, in
 
 __device__ inline uint32_t cost_class(uint32_t c) { return __float_as_uint((float)c) >> 20; }
 
-// Candidates per tile (the points of the bins the gather reads), the cost
-// class histogram, and per-instance totals.
+// Candidates of global tile j of instance D (the points of the bins the
+// gather reads for it): bin rows (t, y) in batches of 16, each batch's 32
+// offsets loaded together; (ct, cy) walks the rows with y fastest.
+__device__ inline uint32_t tile_candidates(const InstDev& D, uint32_t j, int32_t rows) {
+    const int32_t tile = (int32_t)(j - (uint32_t)D.tile_base);
+    const int32_t tx = tile % D.ntx;
+    const int32_t rest = tile / D.ntx;
+    const int32_t ty = rest % D.nty;
+    const int32_t tt = rest / D.nty;
+    const TileBins b = tile_bins(D, tx * kTileXY + D.ox, ty * kTileXY + D.oy, tt * rows + D.ot, rows);
+    const int32_t nyr = b.cy1 - b.cy0 + 1;
+    const int32_t nrows = nyr * (b.ct1 - b.ct0 + 1);
+    int32_t ct = b.ct0, cy = b.cy0;
+    uint32_t c = 0;
+    for (int32_t r0 = 0; r0 < nrows; r0 += 16) {
+        uint32_t hi[16], lo[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            hi[u] = lo[u] = 0u;
+            if (r0 + u < nrows) {
+                const int32_t row = (ct * D.ncy + cy) * D.ncx;
+                hi[u] = as_global(D.cell_start)[row + b.cx1 + 1];
+                lo[u] = as_global(D.cell_start)[row + b.cx0];
+                if (cy == b.cy1) {
+                    cy = b.cy0;
+                    ++ct;
+                } else {
+                    ++cy;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) c += hi[u] - lo[u];
+    }
+    return c;
+}
+
+// Candidates per tile, the cost class histogram, and per-instance totals.
 __global__ __launch_bounds__(256) void k_tile_cost(const InstDev* __restrict__ descs, int32_t count,
                                                    uint32_t T, int32_t rows,
                                                    uint32_t* __restrict__ cost,
@@ -75,38 +111,7 @@ __global__ __launch_bounds__(256) void k_tile_cost(const InstDev* __restrict__ d
     int32_t inst = 0;
     if (valid) {
         inst = find_inst(descs, count, j);
-        const InstDev& D = descs[inst];
-        const int32_t tile = (int32_t)(j - (uint32_t)D.tile_base);
-        const int32_t tx = tile % D.ntx;
-        const int32_t rest = tile / D.ntx;
-        const int32_t ty = rest % D.nty;
-        const int32_t tt = rest / D.nty;
-        const TileBins b = tile_bins(D, tx * kTileXY + D.ox, ty * kTileXY + D.oy, tt * rows + D.ot, rows);
-        // bin rows (t, y) in batches of 16, each batch's 32 offsets loaded
-        // together; (ct, cy) walks the rows with y fastest
-        const int32_t nyr = b.cy1 - b.cy0 + 1;
-        const int32_t nrows = nyr * (b.ct1 - b.ct0 + 1);
-        int32_t ct = b.ct0, cy = b.cy0;
-        for (int32_t r0 = 0; r0 < nrows; r0 += 16) {
-            uint32_t hi[16], lo[16];
-#pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                hi[u] = lo[u] = 0u;
-                if (r0 + u < nrows) {
-                    const int32_t row = (ct * D.ncy + cy) * D.ncx;
-                    hi[u] = as_global(D.cell_start)[row + b.cx1 + 1];
-                    lo[u] = as_global(D.cell_start)[row + b.cx0];
-                    if (cy == b.cy1) {
-                        cy = b.cy0;
-                        ++ct;
-                    } else {
-                        ++cy;
-                    }
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 16; ++u) c += hi[u] - lo[u];
-        }
+        c = tile_candidates(descs[inst], j, rows);
         cost[j] = c;
         atomicAdd(&h[cost_class(c)], 1u);
     }
@@ -175,11 +180,18 @@ __device__ inline uint32_t split_parts(const InstDev& D, unsigned long long inst
 // partial slots, every tile of a class or none, so that which tiles are cut
 // depends only on the costs, not on the order of heavy[]; it writes the work
 // items and split records in heavy[] order, and clears the queues' counters.
-__global__ __launch_bounds__(256) void k_collect_plan(const InstDev* __restrict__ descs, int32_t count,
+//
+// Fused (one workgroup, at most 256 tiles and kDescChunk instances): the
+// descriptors arrive as arguments, and the workgroup also does the work of
+// k_put_desc and k_tile_cost, with the cost histogram, the per-instance
+// totals and the taken-tile mask in LDS -- one launch plans the pass.
+__global__ __launch_bounds__(256) void k_collect_plan(DescChunk dc, int32_t fused, int32_t rows,
+                                                      InstDev* __restrict__ gdesc, int32_t count,
                                                       uint32_t T, const uint32_t* __restrict__ cost,
-                                                      const uint32_t* __restrict__ hist,
-                                                      const unsigned long long* __restrict__ inst_cost,
+                                                      const uint32_t* __restrict__ ghist,
+                                                      const unsigned long long* __restrict__ ginst_cost,
                                                       uint32_t* __restrict__ inst_split,
+                                                      uint32_t* __restrict__ mass_done,
                                                       uint32_t* __restrict__ cursor,
                                                       uint32_t* __restrict__ demand,
                                                       unsigned long long* __restrict__ heavy,
@@ -202,20 +214,54 @@ __global__ __launch_bounds__(256) void k_collect_plan(const InstDev* __restrict_
     // one workgroup (up to 2048 tiles): heavy[] and the demand stay in LDS,
     // without the global atomics and the hand-over to a last workgroup
     __shared__ unsigned long long sheavy[kTopTiles];
+    // fused: descriptors, cost histogram, per-instance totals, taken tiles
+    __shared__ InstDev sdesc[kDescChunk];
+    __shared__ uint32_t shist[kCostClasses];
+    __shared__ unsigned long long sicost[kDescChunk];
+    __shared__ uint32_t sbits[256 / 32];
     const bool one = gridDim.x == 1;
     const int tid = threadIdx.x;
     for (int k = tid; k < kCostClasses; k += 256) {
         lcnt[k] = 0u;
         ldem[k] = 0u;
+        if (fused) shist[k] = 0u;
     }
+    if (fused) {
+        if (tid < count) {
+            sdesc[tid] = dc.d[tid];
+            gdesc[tid] = dc.d[tid];
+            sicost[tid] = 0ull;
+            inst_split[tid] = 0u;
+            mass_done[tid] = 0u;
+        }
+        if (tid < 256 / 32) sbits[tid] = 0u;
+        if (tid < kScCount) sc[tid] = 0u;
+        __syncthreads();
+    }
+    const InstDev* const descs = fused ? sdesc : gdesc;
+    const uint32_t* const hist = fused ? shist : ghist;
+    const unsigned long long* const inst_cost = fused ? sicost : ginst_cost;
     // the costs are loaded first, so that their loads overlap the threshold's
+    // (fused: computed here, one tile per thread)
     constexpr int kU = 8;  // loads in flight per thread
     const uint32_t j0 = blockIdx.x * (256u * kU) + tid;
     uint32_t cv[kU];
+    if (fused) {
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-        const uint32_t j = j0 + 256u * u;
-        cv[u] = j < T ? cost[j] : 0u;
+        for (int u = 0; u < kU; ++u) cv[u] = 0u;
+        if (j0 < T) {
+            const int32_t inst = find_inst(descs, count, j0);
+            cv[0] = tile_candidates(descs[inst], j0, rows);
+            atomicAdd(&shist[cost_class(cv[0])], 1u);
+            if (cv[0]) atomicAdd(&sicost[inst], (unsigned long long)cv[0]);
+        }
+        __syncthreads();
+    } else {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const uint32_t j = j0 + 256u * u;
+            cv[u] = j < T ? cost[j] : 0u;
+        }
     }
     // suffix counts over the classes, thread tid holding classes
     // kCostClasses - 1 - (kPer tid + u), highest first
@@ -252,7 +298,8 @@ __global__ __launch_bounds__(256) void k_collect_plan(const InstDev* __restrict_
             const uint32_t parts = split_parts(descs[inst], inst_cost[inst], c);
             if (parts > 1) atomicAdd(&ldem[k], parts);
             const uint32_t sp = spatial_pos(descs[inst], j);
-            atomicOr(&bits[sp >> 5], 1u << (sp & 31u));
+            if (fused) atomicOr(&sbits[sp >> 5], 1u << (sp & 31u));
+            else atomicOr(&bits[sp >> 5], 1u << (sp & 31u));
         }
     }
     __syncthreads();
@@ -358,6 +405,7 @@ __global__ __launch_bounds__(256) void k_collect_plan(const InstDev* __restrict_
         }
     }
     for (int k = tid; k < kCtrWords; k += 256) ctr[k] = 0u;  // both queues' counters
+    if (fused && tid < (int)((T + 31) / 32)) bits[tid] = sbits[tid];  // complete since the heavy selection
     if (tid == 0) {
         sc[kScHeavyItems] = tot_items;
         sc[kScSplit] = tot_split;
@@ -369,11 +417,8 @@ __global__ __launch_bounds__(256) void k_collect_plan(const InstDev* __restrict_
 // Each instance's FP64 grid sum in a fixed order: workgroup (chunk, inst)
 // sums chunk `chunk` of the instance's tile partials (strided per-thread
 // sums, then a tree) into mid[inst][chunk]; the last of the instance's
-// kMassChunks workgroups to finish adds the chunks (a tree over the 64
-// chunks in a fixed shape) and writes the instance's statistics:
-// stats[0] = grid mass (sum * sres^2 tres, or 0 without the mass flag),
-// [1], [2], [7] = 0, [3], [4], [5] = the set's non-finite, culled and
-// invalid-bandwidth counts, [6] = tiles computed in parts.
+// kMassChunks workgroups to finish adds the chunks (a butterfly over the 64
+// chunks) and writes the instance's statistics (write_stats).
 __global__ __launch_bounds__(256) void k_mass(const InstDev* __restrict__ descs, double* __restrict__ mid,
                                               const uint32_t* __restrict__ inst_split,
                                               uint32_t* __restrict__ mass_done) {
@@ -410,17 +455,7 @@ __global__ __launch_bounds__(256) void k_mass(const InstDev* __restrict__ descs,
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
     if (lane == 0) {
-        auto* st = as_global(D.stats);
-        st[0] = (D.flags & kInstMass) ? v * D.mass_scale : 0.0;
-        st[1] = 0.0;
-        st[2] = 0.0;
-        // the set's points that are never visited, from the offsets of their keys
-        const auto* cs = as_global(D.cell_start + (size_t)D.ncx * D.ncy * D.nct);
-        st[3] = (double)(cs[kKeyNonFinite + 1] - cs[kKeyNonFinite]);
-        st[4] = (double)(cs[kKeyCulled + 1] - cs[kKeyCulled]);
-        st[5] = (double)(cs[kKeyBadBw + 1] - cs[kKeyBadBw]);
-        st[6] = (double)inst_split[inst];
-        st[7] = 0.0;
+        write_stats(D, v, inst_split[inst]);
         mass_done[inst] = 0u;
     }
 }
@@ -491,20 +526,27 @@ hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassL
         tb += descs[i].ntiles;
         any_stats = any_stats || descs[i].stats != nullptr;
     }
-    for (int32_t first = 0; first < count; first += kDescChunk) {
-        DescChunk c{};
-        const int32_t m = count - first < kDescChunk ? count - first : kDescChunk;
-        for (int32_t k = 0; k < m; ++k) c.d[k] = descs[first + k];
-        hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(256), 0, s, c, first, m, d_desc, inst_cost,
-                           inst_split, mass_done, hist, cursor, demand, sc, first == 0 ? 1 : 0);
-    }
     const uint32_t T = (uint32_t)pl.T;
-    hipLaunchKernelGGL(k_tile_cost, dim3((T + 255) / 256), dim3(256), 0, s, (const InstDev*)d_desc,
-                       count, T, tile_t, cost, hist, inst_cost, bits);
-    hipLaunchKernelGGL(k_collect_plan, dim3((T + 2047) / 2048), dim3(256), 0, s, (const InstDev*)d_desc, count,
-                       T, (const uint32_t*)cost, (const uint32_t*)hist, (const unsigned long long*)inst_cost,
-                       inst_split, cursor, demand, heavy, items, top, bits, sc, ctr, (uint32_t)part_slots(pl.T),
-                       sc + kScPlanDone);
+    // a pass of at most 256 tiles is planned by one workgroup in one launch
+    const bool fused = T <= 256u && count <= kDescChunk;
+    DescChunk dc0{};
+    if (fused) {
+        for (int32_t k = 0; k < count; ++k) dc0.d[k] = descs[k];
+    } else {
+        for (int32_t first = 0; first < count; first += kDescChunk) {
+            DescChunk c{};
+            const int32_t m = count - first < kDescChunk ? count - first : kDescChunk;
+            for (int32_t k = 0; k < m; ++k) c.d[k] = descs[first + k];
+            hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(256), 0, s, c, first, m, d_desc, inst_cost,
+                               inst_split, mass_done, hist, cursor, demand, sc, first == 0 ? 1 : 0);
+        }
+        hipLaunchKernelGGL(k_tile_cost, dim3((T + 255) / 256), dim3(256), 0, s, (const InstDev*)d_desc,
+                           count, T, tile_t, cost, hist, inst_cost, bits);
+    }
+    hipLaunchKernelGGL(k_collect_plan, dim3(fused ? 1u : (T + 2047) / 2048), dim3(256), 0, s, dc0,
+                       fused ? 1 : 0, tile_t, d_desc, count, T, (const uint32_t*)cost, (const uint32_t*)hist,
+                       (const unsigned long long*)inst_cost, inst_split, mass_done, cursor, demand, heavy, items,
+                       top, bits, sc, ctr, (uint32_t)part_slots(pl.T), sc + kScPlanDone);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev_before && (e = hipEventRecord(ev_before, s)) != hipSuccess) return e;

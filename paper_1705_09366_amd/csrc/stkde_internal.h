@@ -289,6 +289,24 @@ __device__ inline uint32_t spatial_pos(const InstDev& D, uint32_t j) {
     return (uint32_t)D.tile_base + (tx * (uint32_t)D.nty + ty) * ntt + tt;
 }
 
+// ---- an instance's statistics ------------------------------------------------
+// d_stats of instance D from its grid sum v and its count of split tiles:
+// [0] grid mass (v * sres^2 tres, or 0 without the mass flag), [1], [2], [7]
+// = 0, [3], [4], [5] = the set's non-finite, culled and invalid-bandwidth
+// counts (the offsets of their keys), [6] = tiles computed in parts.
+__device__ inline void write_stats(const InstDev& D, double v, uint32_t nsplit) {
+    auto* st = as_global(D.stats);
+    st[0] = (D.flags & kInstMass) ? v * D.mass_scale : 0.0;
+    st[1] = 0.0;
+    st[2] = 0.0;
+    const auto* cs = as_global(D.cell_start + (size_t)D.ncx * D.ncy * D.nct);
+    st[3] = (double)(cs[kKeyNonFinite + 1] - cs[kKeyNonFinite]);
+    st[4] = (double)(cs[kKeyCulled + 1] - cs[kKeyCulled]);
+    st[5] = (double)(cs[kKeyBadBw + 1] - cs[kKeyBadBw]);
+    st[6] = (double)nsplit;
+    st[7] = 0.0;
+}
+
 // ---- launchers (asynchronous on s; return the launch error) ---------------
 // Bin n points into set memory `set` using radix scratch `sort`.  d_hst
 // (n x 2 FP64 per-point bandwidths in domain units, or null) makes each
