@@ -777,6 +777,32 @@ def time_compute(m, desc, tuning, pts, pairs, steps, warmup, stages=False):
     return res
 
 
+def time_graph(m, desc, tuning, pts, eager_out, steps, warmup):
+    """Wall time per step of the same computation recorded once as a HIP graph
+    (stkde_plan_capture) and replayed `steps` times after `warmup` replays,
+    and whether a replay's grid is bitwise the eager one."""
+    import torch
+    n = int(pts.shape[0])
+    plan = m.Plan(desc, tuning)
+    out = torch.empty_like(eager_out)
+    stats = torch.zeros(8, dtype=torch.float64, device=pts.device)
+    ws = plan.workspace(n, pts.device)
+    plan.capture(pts, out, stats=stats, workspace=ws)
+    for _ in range(warmup):
+        plan.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.replay()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    same = bool(torch.equal(out, eager_out))
+    plan.close()
+    ms = (t1 - t0) * 1e3 / steps
+    _log(f"{desc.gx}x{desc.gy}x{desc.gt} graph replay: {ms:.4f} ms/step, bitwise equal to eager: {same}")
+    return {"ms_per_step": ms, "bitwise_equal_eager": same}
+
+
 def error_stats(gpu, ref):
     """Max and RMS error of a GPU grid against the oracle's, relative to the
     oracle's peak (RMS over voxels where either side is nonzero), and the
@@ -883,6 +909,8 @@ def other_configs(m, dev, args):
                          "operands": _operand_form(inst, tun, mode == "kahan", False, 0),
                          "tuning_source": src, "max_rel_err_vs_oracle": est["max_rel"],
                          "rms_rel_err_vs_oracle": est["rms_rel"], "support_mismatch": est["mismatch"]}
+            if name == "uniform-10k":
+                rec[mode]["graph_replay"] = time_graph(m, desc, tun, pts, r["out"], 200, 10)
             _log(f"{name} {mode}: {r['ms_per_step']:.4f} ms/step, max rel err {est['max_rel']:.3e}, "
                  f"rms {est['rms_rel']:.3e}, mismatch {est['mismatch']}")
             del r

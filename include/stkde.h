@@ -361,6 +361,14 @@ stkde_status stkde_batch_plan(const stkde_item* items, int32_t count, stkde_batc
 /* Bytes of device workspace stkde_batch_run needs. */
 stkde_status stkde_batch_workspace_bytes(stkde_batch_t batch, size_t* bytes);
 
+/* Number of passes (one gather launch each) stkde_batch_run enqueues (host
+ * only).  A batch whose grids are all plain or all compensated, with 16- or
+ * 32-row tiles, runs as one pass whatever their operand forms and
+ * full-cover paths: one launch of a gather that runs each tile with the
+ * code of its grid's own kernel.  Other batches take one pass per (tile
+ * rows, accumulation, operand form).  Errors: INVALID_ARG. */
+stkde_status stkde_batch_passes(stkde_batch_t batch, int32_t* passes);
+
 /* Compute every item's grid on `stream` (d_ws: >= the workspace bytes,
  * 256-byte aligned; scratch).  Each grid is the one stkde_compute would give
  * for the set's points, within the tolerance of their rounding; it is

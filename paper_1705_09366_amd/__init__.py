@@ -50,7 +50,7 @@ EXPORTED = ("stkde_plan", "stkde_plan_destroy", "stkde_workspace_bytes", "stkde_
             "stkde_plan_profile", "stkde_plan_profile_read",
             "stkde_ablation_accumulate", "stkde_ablation_compute",
             "stkde_compute_adaptive", "stkde_bin_adaptive", "stkde_plan_capture", "stkde_plan_replay",
-            "stkde_compute_noalloc")
+            "stkde_compute_noalloc", "stkde_batch_passes")
 
 # Bytes of the library's own device scratch (stkde_compute_noalloc).
 STATIC_SCRATCH_BYTES = 128 << 20
@@ -122,6 +122,7 @@ def lib():
         L.stkde_set_destroy.argtypes = [ctypes.c_void_p]
         L.stkde_batch_plan.argtypes = [P(_Item), ctypes.c_int32, P(ctypes.c_void_p)]
         L.stkde_batch_workspace_bytes.argtypes = [ctypes.c_void_p, P(ctypes.c_size_t)]
+        L.stkde_batch_passes.argtypes = [ctypes.c_void_p, P(ctypes.c_int32)]
         L.stkde_batch_run.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                       ctypes.c_void_p]
         L.stkde_batch_capture.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]
@@ -590,8 +591,9 @@ class Item:
 
 
 class Batch:
-    """Many grids in one work list and one persistent gather launch per
-    (tile_t, Kahan) group (``stkde_batch_*``); optionally recorded once as a
+    """Many grids in one work list and one persistent gather launch (per
+    (tile_t, Kahan, operand form) group when the grids do not fit one
+    multi-variant launch; ``stkde_batch_*``); optionally recorded once as a
     HIP graph and replayed.  ``allocate=False`` plans (and validates) only;
     :meth:`allocate` then provides the workspace."""
 
@@ -623,6 +625,14 @@ class Batch:
         self.ws = None
         if allocate:
             self.allocate(self.items[0].out.device)
+
+    def passes(self) -> int:
+        """Passes (gather launches) a run enqueues (``stkde_batch_passes``)."""
+        v = ctypes.c_int32(0)
+        st = lib().stkde_batch_passes(self._h, ctypes.byref(v))
+        if st != STKDE_OK:
+            raise StkdeError(st, "stkde_batch_passes")
+        return int(v.value)
 
     def allocate(self, device=None):
         import torch

@@ -4,7 +4,8 @@
 //   compute = bin (transform, radix sort, bin offsets, records) into the
 //             workspace's set region -> one pass (work list, gather, split
 //             reduction, mass) -> optional point statistics;
-//   batch   = one pass per (tile_t, Kahan) group over the items' sets.
+//   batch   = one pass per (tile_t, Kahan) group over the items' sets, or one
+//             pass with one multi-variant gather when they allow it.
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -64,8 +65,10 @@ struct stkde_batch_s {
         int mode;  // accumulation mode of the gather (kAcc*)
         bool full; // full-cover path
         bool h16;  // two-term FP16 operands
+        bool multi = false;  // grids of several gather variants in one launch
         std::vector<int32_t> idx;
         std::vector<stkde::InstGeom> geo;
+        std::vector<int32_t> variant;  // multi: each grid's gather variant
         stkde::PassLayout pl;
     };
     std::vector<stkde_item> items;
@@ -305,6 +308,8 @@ stkde::InstDev make_dev(const stkde::InstGeom& ig, const stkde::SetGeom& sg, con
     d.nty = ig.nty;
     d.ntiles = ig.ntiles;
     d.tile_base = 0;
+    d.tile_t = ig.tile_t;
+    d.variant = 0;
     d.flags = (mass && stats) ? stkde::kInstMass : 0u;
     if (!adaptive && ig.kernel == stkde::kKernelEpan && use_full(ig.hv, ig.tile_t)) d.flags |= stkde::kInstFull;
     d.inv_hv2 = ig.inv_hv2;
@@ -765,6 +770,43 @@ stkde_status stkde_batch_plan(const stkde_item* items, int32_t count, stkde_batc
             }
         }
     }
+    // The passes of a batch that is all plain or all compensated, with 16- and
+    // 32-row tiles, run as one pass with one gather launch (the multi-variant
+    // gather): each grid keeps its kernel's code -- the full-cover FP32 kernel
+    // for the FP32 passes (the path is switched per grid; the register form
+    // of Kahan gives the bits of the scratch form), the two-term FP16 kernel
+    // for the others -- so each keeps the bits of its own pass.
+    if (bt->groups.size() > 1) {
+        bool one = true;
+        for (const auto& g : bt->groups)
+            one = one && g.kahan == bt->groups[0].kahan && (g.tile_t == 16 || g.tile_t == 32);
+        if (one) {
+            stkde_batch_s::Group m;
+            m.kahan = bt->groups[0].kahan;
+            m.mode = m.kahan ? stkde::kAccKahanReg : stkde::kAccPlain;
+            m.full = false;
+            m.h16 = false;
+            m.multi = true;
+            // the multi-variant gather spaces its Kahan and partial slots for
+            // 32-row tiles whatever rows the batch's grids have: so does the layout
+            m.tile_t = 32;
+            for (const auto& g : bt->groups) {
+                for (size_t k = 0; k < g.idx.size(); ++k) {
+                    m.idx.push_back(g.idx[k]);
+                    m.geo.push_back(g.geo[k]);
+                    m.variant.push_back(stkde::multi_variant(g.tile_t, g.h16));
+                }
+            }
+            m.pl = stkde::layout_pass(m.geo.data(), (int32_t)m.geo.size(), m.tile_t, m.kahan);
+            if (m.pl.T > 0x7fffffffLL) {
+                delete bt;
+                return STKDE_ERR_TOO_LARGE;
+            }
+            bt->groups.clear();
+            bt->ws_bytes = m.pl.total;
+            bt->groups.push_back(std::move(m));
+        }
+    }
     *out = bt;
     return STKDE_OK;
 }
@@ -772,6 +814,12 @@ stkde_status stkde_batch_plan(const stkde_item* items, int32_t count, stkde_batc
 stkde_status stkde_batch_workspace_bytes(stkde_batch_t b, size_t* bytes) {
     if (!b || !bytes) return STKDE_ERR_INVALID_ARG;
     *bytes = b->ws_bytes;
+    return STKDE_OK;
+}
+
+stkde_status stkde_batch_passes(stkde_batch_t b, int32_t* passes) {
+    if (!b || !passes) return STKDE_ERR_INVALID_ARG;
+    *passes = (int32_t)b->groups.size();
     return STKDE_OK;
 }
 
@@ -788,9 +836,10 @@ stkde_status batch_enqueue(stkde_batch_t b, uint8_t* ws, hipStream_t s) {
                                     (int32_t)it.ot, it.d_out, it.d_stats,
                                     (it.plan->desc.flags & STKDE_FLAG_MASS) != 0,
                                     it.plan->split_share));
+            if (g.multi) devs.back().variant = g.variant[k];
         }
         if (stkde::launch_pass(devs.data(), (int32_t)devs.size(), ws, g.pl, g.tile_t, g.mode, g.full, false,
-                               stkde::kKernelEpan, g.h16, s) != hipSuccess)
+                               stkde::kKernelEpan, g.h16, s, nullptr, nullptr, g.multi) != hipSuccess)
             return STKDE_ERR_HIP;
     }
     return STKDE_OK;
@@ -807,8 +856,10 @@ stkde_status stkde_batch_run(stkde_batch_t b, void* d_ws, size_t ws_bytes, void*
 stkde_status stkde_batch_capture(stkde_batch_t b, void* d_ws, size_t ws_bytes) {
     if (!b) return STKDE_ERR_INVALID_ARG;
     if (!d_ws || ws_bytes < b->ws_bytes || ((uintptr_t)d_ws & 255u)) return STKDE_ERR_WORKSPACE;
-    for (const auto& g : b->groups)
-        stkde::prepare_gather(g.tile_t, g.mode, g.full, false, stkde::kKernelEpan, g.h16);
+    for (const auto& g : b->groups) {
+        if (g.multi) stkde::prepare_gather_multi(g.kahan);
+        else stkde::prepare_gather(g.tile_t, g.mode, g.full, false, stkde::kKernelEpan, g.h16);
+    }
     hipStream_t cs = nullptr;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return STKDE_ERR_HIP;
     hipGraph_t graph = nullptr;

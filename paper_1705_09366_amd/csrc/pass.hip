@@ -95,8 +95,7 @@ __device__ inline uint32_t tile_candidates(const InstDev& D, uint32_t j, int32_t
 
 // Candidates per tile, the cost class histogram, and per-instance totals.
 __global__ __launch_bounds__(256) void k_tile_cost(const InstDev* __restrict__ descs, int32_t count,
-                                                   uint32_t T, int32_t rows,
-                                                   uint32_t* __restrict__ cost,
+                                                   uint32_t T, uint32_t* __restrict__ cost,
                                                    uint32_t* __restrict__ hist,
                                                    unsigned long long* __restrict__ inst_cost,
                                                    uint32_t* __restrict__ bits) {
@@ -111,7 +110,7 @@ __global__ __launch_bounds__(256) void k_tile_cost(const InstDev* __restrict__ d
     int32_t inst = 0;
     if (valid) {
         inst = find_inst(descs, count, j);
-        c = tile_candidates(descs[inst], j, rows);
+        c = tile_candidates(descs[inst], j, descs[inst].tile_t);
         cost[j] = c;
         atomicAdd(&h[cost_class(c)], 1u);
     }
@@ -185,7 +184,7 @@ __device__ inline uint32_t split_parts(const InstDev& D, unsigned long long inst
 // descriptors arrive as arguments, and the workgroup also does the work of
 // k_put_desc and k_tile_cost, with the cost histogram, the per-instance
 // totals and the taken-tile mask in LDS -- one launch plans the pass.
-__global__ __launch_bounds__(256) void k_collect_plan(DescChunk dc, int32_t fused, int32_t rows,
+__global__ __launch_bounds__(256) void k_collect_plan(DescChunk dc, int32_t fused,
                                                       InstDev* __restrict__ gdesc, int32_t count,
                                                       uint32_t T, const uint32_t* __restrict__ cost,
                                                       const uint32_t* __restrict__ ghist,
@@ -251,7 +250,7 @@ __global__ __launch_bounds__(256) void k_collect_plan(DescChunk dc, int32_t fuse
         for (int u = 0; u < kU; ++u) cv[u] = 0u;
         if (j0 < T) {
             const int32_t inst = find_inst(descs, count, j0);
-            cv[0] = tile_candidates(descs[inst], j0, rows);
+            cv[0] = tile_candidates(descs[inst], j0, descs[inst].tile_t);
             atomicAdd(&shist[cost_class(cv[0])], 1u);
             if (cv[0]) atomicAdd(&sicost[inst], (unsigned long long)cv[0]);
         }
@@ -497,7 +496,7 @@ PassLayout layout_pass(const InstGeom* inst, int32_t count, int tile_t, bool kah
 
 hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassLayout& pl,
                        int tile_t, int mode, bool full, bool adapt, int kf, bool h16, hipStream_t s,
-                       hipEvent_t ev_before, hipEvent_t ev_after) {
+                       hipEvent_t ev_before, hipEvent_t ev_after, bool multi) {
     const bool kahan = mode != kAccPlain;
     InstDev* d_desc = reinterpret_cast<InstDev*>(pass + pl.desc);
     auto* inst_cost = reinterpret_cast<unsigned long long*>(pass + pl.inst_cost);
@@ -541,20 +540,22 @@ hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassL
                                inst_split, mass_done, hist, cursor, demand, sc, first == 0 ? 1 : 0);
         }
         hipLaunchKernelGGL(k_tile_cost, dim3((T + 255) / 256), dim3(256), 0, s, (const InstDev*)d_desc,
-                           count, T, tile_t, cost, hist, inst_cost, bits);
+                           count, T, cost, hist, inst_cost, bits);
     }
     hipLaunchKernelGGL(k_collect_plan, dim3(fused ? 1u : (T + 2047) / 2048), dim3(256), 0, s, dc0,
-                       fused ? 1 : 0, tile_t, d_desc, count, T, (const uint32_t*)cost, (const uint32_t*)hist,
+                       fused ? 1 : 0, d_desc, count, T, (const uint32_t*)cost, (const uint32_t*)hist,
                        (const unsigned long long*)inst_cost, inst_split, mass_done, cursor, demand, heavy, items,
                        top, bits, sc, ctr, (uint32_t)part_slots(pl.T), sc + kScPlanDone);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev_before && (e = hipEventRecord(ev_before, s)) != hipSuccess) return e;
-    e = launch_gather_items(d_desc, count, items, bits, sc, ctr, partials, kscratch, pl.T, tile_t, mode,
-                            full, adapt, kf, h16, s);
+    e = multi ? launch_gather_multi(d_desc, count, items, bits, sc, ctr, partials, kscratch, pl.T, kahan, s)
+              : launch_gather_items(d_desc, count, items, bits, sc, ctr, partials, kscratch, pl.T, tile_t, mode,
+                                    full, adapt, kf, h16, s);
     if (e != hipSuccess) return e;
     if (ev_after && (e = hipEventRecord(ev_after, s)) != hipSuccess) return e;
-    e = launch_reduce_split(d_desc, count, top, sc, partials, tile_t, kahan, s);
+    e = multi ? launch_reduce_split_multi(d_desc, count, top, sc, partials, kahan, s)
+              : launch_reduce_split(d_desc, count, top, sc, partials, tile_t, kahan, s);
     if (e != hipSuccess) return e;
     if (any_stats)
         hipLaunchKernelGGL(k_mass, dim3(kMassChunks, (uint32_t)count), dim3(256), 0, s, (const InstDev*)d_desc,

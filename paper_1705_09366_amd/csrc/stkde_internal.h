@@ -98,6 +98,8 @@ struct alignas(16) InstDev {
     float inv_hv, inv_tv;                // 1/hv, 1/tv (the pair as printed is odd in u, v, w)
     double hv64, tv64;                   // hv, tv in FP64 (exact support tests)
     uint32_t split_share;                // split tiles above total cost / split_share
+    int32_t tile_t;                      // rows per tile
+    int32_t variant;                     // gather variant (index in a multi-variant pass), else 0
 };
 // Kernel pairs (the public STKDE_KERNEL_* values).
 constexpr int kKernelEpan = 0;
@@ -325,9 +327,13 @@ hipError_t launch_bin(const SetGeom& g, const double* d_xyt, int32_t n, uint8_t*
 // kernel pair (other than Epanechnikov: neither full nor adapt, tile_t <= 32);
 // h16: two-term FP16 matrix-core operands (Epanechnikov, neither full nor
 // adapt, tile_t <= 32, mode not kAccKahanReg; ignored elsewhere).
+// multi: a pass over grids of several gather variants in one launch
+// (launch_gather_multi; tile_t and the layout pl are then those of 32-row
+// tiles, the spacing of its slots; mode gives plain or compensated; full,
+// adapt, kf and h16 are per grid, in each descriptor's variant).
 hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassLayout& pl,
                        int tile_t, int mode, bool full, bool adapt, int kf, bool h16, hipStream_t s,
-                       hipEvent_t ev_before = nullptr, hipEvent_t ev_after = nullptr);
+                       hipEvent_t ev_before = nullptr, hipEvent_t ev_after = nullptr, bool multi = false);
 // The gather proper (called by launch_pass).
 hipError_t launch_gather_items(const InstDev* d_desc, int32_t count, const WorkItem* d_items,
                                const uint32_t* d_bits, const uint32_t* d_scalars,
@@ -337,6 +343,20 @@ hipError_t launch_gather_items(const InstDev* d_desc, int32_t count, const WorkI
 // Query (and cache) the gather's launch size for the current device ahead of a
 // stream capture.
 void prepare_gather(int tile_t, int mode, bool full, bool adapt, int kf, bool h16);
+// The multi-variant gather of a batch (Epanechnikov pair, one bandwidth pair
+// per grid): plain or compensated; each grid's InstDev::variant is
+// multi_variant(its tile rows, its operand form) -- the full-cover FP32
+// kernel (register-form Kahan when compensated) or the two-term FP16 kernel
+// (scratch-form Kahan), 16 or 32 rows; those variants give every grid the
+// bits of its own pass.  Split-tile partial slots are 16 x 16 x 32 floats.
+inline int32_t multi_variant(int tile_t, bool h16) { return (h16 ? 2 : 0) + (tile_t == 32 ? 1 : 0); }
+hipError_t launch_gather_multi(const InstDev* d_desc, int32_t count, const WorkItem* d_items,
+                               const uint32_t* d_bits, const uint32_t* d_scalars, uint32_t* d_counters,
+                               float* d_partials, float* d_kscratch, int64_t T, bool kahan, hipStream_t s);
+void prepare_gather_multi(bool kahan);
+hipError_t launch_reduce_split_multi(const InstDev* d_desc, int32_t count, const uint32_t* d_top,
+                                     const uint32_t* d_scalars, const float* d_partials, bool kahan,
+                                     hipStream_t s);
 hipError_t launch_reduce_split(const InstDev* d_desc, int32_t count, const uint32_t* d_top,
                                const uint32_t* d_scalars, const float* d_partials, int tile_t,
                                bool kahan, hipStream_t s);

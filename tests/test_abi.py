@@ -263,6 +263,48 @@ def test_batch_plan_refuses_too_many_bin_rows(L):
     s.close()
 
 
+def _passes(L, s, plans):
+    arr = (L._Item * len(plans))()
+    for k, plan in enumerate(plans):
+        arr[k] = L._Item(plan.handle.value, s.handle.value, 0x10000, 0, 0, 0, 0x20000 + 0x100000 * k, None)
+    h = ctypes.c_void_p()
+    assert L.lib().stkde_batch_plan(arr, len(plans), ctypes.byref(h)) == 0
+    v = ctypes.c_int32(0)
+    assert L.lib().stkde_batch_passes(h, ctypes.byref(v)) == 0
+    assert L.lib().stkde_batch_passes(h, None) == L.STKDE_ERR_INVALID_ARG
+    L.lib().stkde_batch_destroy(h)
+    return v.value
+
+
+def test_batch_passes(L):
+    """Grids that are all compensated (or all plain) with 16- and 32-row
+    tiles, two-term and FP32 operands, small and full-cover bandwidths share
+    one pass; mixing plain and compensated grids, or 64-row tiles, does not."""
+    base = dict(gx=192, gy=160, gt=96, hs=20.0, ht=6.0)
+    s = L.BinnedSet(L.Desc(**base), 100, L.Tuning(tile_t=32))
+
+    def plan(hs, tt, flags, form=0):
+        return L.Plan(L.Desc(**{**base, "hs": hs, "flags": flags}), L.Tuning(tile_t=tt, operand_form=form))
+    for flags in (1, 0):
+        mixed = [plan(4.0, 16, flags), plan(4.0, 32, flags), plan(18.0, 16, flags), plan(18.0, 32, flags),
+                 plan(6.0, 32, flags, form=1)]
+        assert _passes(L, s, mixed) == 1
+        assert _passes(L, s, mixed[:1]) == 1
+        for p in mixed:
+            p.close()
+    two = [plan(4.0, 16, 1), plan(4.0, 16, 0)]
+    assert _passes(L, s, two) == 2
+    rows64 = [plan(4.0, 64, 0), plan(4.0, 16, 0)]
+    assert _passes(L, s, rows64) == 2
+    with pytest.raises(L.StkdeError):
+        b = L.Batch.__new__(L.Batch)
+        b._h = ctypes.c_void_p()
+        b.passes()
+    for p in two + rows64:
+        p.close()
+    s.close()
+
+
 def test_profile_api_host_checks(L):
     plan = L.Plan(L.Desc(gx=16, gy=16, gt=16, hs=2.0, ht=2.0))
     assert L.lib().stkde_plan_profile(plan.handle, -1) == L.STKDE_ERR_INVALID_ARG

@@ -1,6 +1,8 @@
 """GPU parity of binned sets and batches, through the C ABI.
 
-A batch computes many grids in one work list per (tile_t, Kahan) group:
+A batch computes many grids in one work list (one gather launch when its
+grids are all plain or all compensated with 16- or 32-row tiles, else one per
+(tile_t, Kahan, operand form) group):
 bandwidth sweeps over one binned set, voxel-aligned windows of a base grid,
 mixed tile shapes, split hot tiles.  Every grid is compared with the FP64
 oracle on the same points (bar: max |gpu - oracle| <= 1e-5 max(oracle));
@@ -232,6 +234,67 @@ def test_split_hot_tiles_in_a_batch(torch_cuda):
     # the pile's tiles are cut (their count is reported per grid)
     assert max(cut) > 0
     b.close()
+    s.close()
+
+
+def test_one_gather_launch_for_mixed_variants(torch_cuda):
+    """Grids with 16- and 32-row tiles, two-term FP16 and full-cover FP32
+    kernels (and an FP32 grid below the full-cover bandwidth), all
+    compensated, then all plain, run as one pass: one gather launch.  Every
+    grid matches the FP64 oracle; a grid is bitwise the same item run alone
+    when neither run cuts one of its tiles; a dense pile makes hot tiles that
+    are cut and reduced with their grid's tile height; a graph replay is
+    bitwise the eager run."""
+    import paper_1705_09366_amd as m
+    torch = torch_cuda
+    rng = np.random.default_rng(21)
+    base = dict(gx=80, gy=72, gt=72, hs=18.0, ht=6.0)
+    pile = np.array([40.0, 36.0, 36.0]) + rng.uniform(0, 1, (30_000, 3))
+    pts = np.concatenate([pile, _points(rng, 3000, 80, 72, 72)])
+    s = _set(torch, m, pts, base, m.Tuning(tile_t=32))
+    mixed = [(4.0, 16, 0), (4.0, 32, 0), (16.0, 16, 0), (16.0, 32, 0), (6.0, 32, 1)]  # hs, rows, operand form
+    rows16 = [(4.0, 16, 0), (16.0, 16, 0)]  # 16-row grids only: slots still spaced for 32 rows
+    for flags, specs in ((1 | 4, mixed), (4, mixed), (1 | 4, rows16)):
+        items, descs = [], []
+        for hs, tt, form in specs:
+            d = dict(gx=80, gy=72, gt=72, hs=hs, ht=5.0, flags=flags)
+            descs.append(d)
+            items.append(m.Item(plan=m.Plan(m.Desc(**d), m.Tuning(tile_t=tt, operand_form=form)), set=s,
+                                out=_out(torch, d), stats=torch.zeros(8, dtype=torch.float64, device="cuda")))
+        _say(f"one-launch batch flags={flags}")
+        b = m.Batch(items)
+        assert b.passes() == 1
+        b.run()
+        torch.cuda.synchronize()
+        cut = []
+        for d, it in zip(descs, items):
+            ref, _ = oracle.pbsym(pts, _grid_of(d))
+            got = it.out.cpu().numpy()
+            rel = _check_close(got, ref)
+            st = it.stats.cpu().numpy()
+            assert st[0] == pytest.approx(float(np.sum(got, dtype=np.float64)), rel=1e-9)
+            cut.append(int(st[6]))
+            _say(f"hs={d['hs']}: rel err {rel:.2e}, {int(st[6])} tiles in parts")
+        assert max(cut) > 0
+        for it, d, c in zip(items, descs, cut):
+            alone = m.Item(plan=it.plan, set=s, out=_out(torch, d),
+                           stats=torch.zeros(8, dtype=torch.float64, device="cuda"))
+            ba = m.Batch([alone])
+            ba.run()
+            torch.cuda.synchronize()
+            if c == 0 and int(alone.stats[6].item()) == 0:
+                assert torch.equal(alone.out, it.out)
+            ba.close()
+        ref = [it.out.clone() for it in items]
+        b.capture()
+        for it in items:
+            it.out.fill_(float("nan"))
+        torch.cuda.synchronize()
+        b.replay()
+        torch.cuda.synchronize()
+        for it, o in zip(items, ref):
+            assert torch.equal(it.out, o)
+        b.close()
     s.close()
 
 
