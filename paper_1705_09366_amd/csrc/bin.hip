@@ -101,34 +101,37 @@ __device__ inline bool point_bandwidths(const SetGeom& g, const double* __restri
 constexpr int kMaxDigitBits = 11;
 constexpr int kMaxBuckets = 1 << kMaxDigitBits;
 
-// Keys of one radix block's points (kSortItems per thread, index order
-// within the block as in the scatter) and the block's histogram of the first
-// digit (the low dbits bits), hist[d * nblk + block].
-__global__ __launch_bounds__(kThreads) void k_transform(SetGeom g, const double* __restrict__ xyt,
-                                                        const double* __restrict__ hst, int32_t n,
-                                                        uint32_t* __restrict__ keys,
-                                                        uint32_t* __restrict__ vals, int nbuck,
-                                                        uint32_t* __restrict__ hist, int32_t nblk) {
+// Keys of one radix block's points and the block's histogram of the first
+// digit (the low dbits bits), hist[d * nblk + block].  kTransformThreads
+// threads, kSortTile / kTransformThreads points each (the histogram does not
+// depend on which thread counts a point).
+constexpr int kTransformThreads = 1024;
+constexpr int kTransformItems = kSortTile / kTransformThreads;
+__global__ __launch_bounds__(kTransformThreads) void k_transform(SetGeom g, const double* __restrict__ xyt,
+                                                                 const double* __restrict__ hst, int32_t n,
+                                                                 uint32_t* __restrict__ keys,
+                                                                 uint32_t* __restrict__ vals, int nbuck,
+                                                                 uint32_t* __restrict__ hist, int32_t nblk) {
     __shared__ uint32_t cnt[kMaxBuckets];
     const int tid = threadIdx.x;
     const int32_t base = blockIdx.x * kSortTile;
     // every coordinate of this thread is loaded before the first footprint,
     // so that the loads are in flight together
-    double px[kSortItems], py[kSortItems], pt[kSortItems];
+    double px[kTransformItems], py[kTransformItems], pt[kTransformItems];
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
-        const int32_t i = base + it * kThreads + tid;
+    for (int it = 0; it < kTransformItems; ++it) {
+        const int32_t i = base + it * kTransformThreads + tid;
         const int32_t ic = i < n ? i : n - 1;
         px[it] = xyt[3 * (size_t)ic];
         py[it] = xyt[3 * (size_t)ic + 1];
         pt[it] = xyt[3 * (size_t)ic + 2];
     }
-    for (int d = tid; d < nbuck; d += kThreads) cnt[d] = 0;
+    for (int d = tid; d < nbuck; d += kTransformThreads) cnt[d] = 0;
     __syncthreads();
     const uint32_t mask = (uint32_t)nbuck - 1u;
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
-        const int32_t i = base + it * kThreads + tid;
+    for (int it = 0; it < kTransformItems; ++it) {
+        const int32_t i = base + it * kTransformThreads + tid;
         if (i < n) {
             double hv, tv;
             const bool bw_ok = point_bandwidths(g, hst, i, &hv, &tv);
@@ -144,7 +147,7 @@ __global__ __launch_bounds__(kThreads) void k_transform(SetGeom g, const double*
         }
     }
     __syncthreads();
-    for (int d = tid; d < nbuck; d += kThreads) hist[(size_t)d * nblk + blockIdx.x] = cnt[d];
+    for (int d = tid; d < nbuck; d += kTransformThreads) hist[(size_t)d * nblk + blockIdx.x] = cnt[d];
 }
 
 // ---- stable LSD radix sort, digits of 6 to 11 bits --------------------------
@@ -438,8 +441,8 @@ hipError_t launch_bin(const SetGeom& g, const double* d_xyt, int32_t n, uint8_t*
     const int passes = bits <= 8 ? 1 : (bits + kMaxDigitBits - 1) / kMaxDigitBits;
     const int dbits = bits <= 8 ? 8 : (bits + passes - 1) / passes;
     const int nbuck = 1 << dbits;
-    hipLaunchKernelGGL(k_transform, dim3(so.nblk), dim3(kThreads), 0, s, g, d_xyt, d_hst, n, k0, v0, nbuck,
-                       hist, so.nblk);
+    hipLaunchKernelGGL(k_transform, dim3(so.nblk), dim3(kTransformThreads), 0, s, g, d_xyt, d_hst, n, k0, v0,
+                       nbuck, hist, so.nblk);
     for (int p = 0; p < passes; ++p) {
         if (p > 0)
             hipLaunchKernelGGL(k_radix_hist, dim3(so.nblk), dim3(kThreads), 0, s, k0, n, dbits * p, nbuck,
