@@ -139,10 +139,11 @@ typedef struct {
                              FP16 terms each (hi + lo, 22 significant bits; the
                              product as hi*hi + hi*lo + lo*hi with FP32
                              accumulation) where the gather has that form -- one
-                             bandwidth pair, no full-cover path (which only the
-                             Epanechnikov pair takes, from hs / sres >= 14), 16-
-                             or 32-row tiles -- and FP32 elsewhere; 1 FP32
-                             everywhere */
+                             bandwidth pair, 16- or 32-row tiles; with the
+                             full-cover path (which only the Epanechnikov pair
+                             takes, from hs / sres >= 14) at 16 rows outside
+                             batches, for the points that reach a tile in part
+                             -- and FP32 elsewhere; 1 FP32 everywhere */
 } stkde_tuning;
 
 typedef struct stkde_plan_s* stkde_plan_t;

@@ -270,12 +270,16 @@ float norm_const(double hs, double ht, int64_t n, int kernel = 0) {
 // The gather's full-cover path pays off when discs are large against a tile.
 bool use_full(double hv, int32_t tile_t) { return tile_t <= 32 && hv >= stkde::kFullMinHv; }
 
-// Two-term FP16 matrix-core operands: the gathers with one bandwidth pair, no
-// full-cover path and 16- or 32-row tiles have them (every kernel pair),
-// unless the plan's tuning asks for FP32 operands.
-bool use_h16(int kf, bool adapt, bool full, int32_t tile_t, int32_t operand_form) {
+// Two-term FP16 matrix-core operands: the gathers with one bandwidth pair and
+// 16- or 32-row tiles have them (every kernel pair), unless the plan's tuning
+// asks for FP32 operands -- with the full-cover path only at 16 rows (that
+// kernel's 32-row form holds too many registers) and only in a computation of
+// its own: a batch keeps FP32 operands on the full-cover path, the kernel its
+// one-launch gather holds (with the two-term full-cover kernel that launch
+// would run at half the occupancy).
+bool use_h16(int kf, bool adapt, bool full, int32_t tile_t, int32_t operand_form, bool batch = false) {
     (void)kf;
-    return !adapt && !full && tile_t <= 32 && operand_form == 0;
+    return !adapt && tile_t <= 32 && operand_form == 0 && (!full || (tile_t == 16 && !batch));
 }
 
 stkde::InstDev make_dev(const stkde::InstGeom& ig, const stkde::SetGeom& sg, const uint8_t* set_mem,
@@ -750,7 +754,7 @@ stkde_status stkde_batch_plan(const stkde_item* items, int32_t count, stkde_batc
                 g.full = false;
                 for (int32_t i = 0; i < count; ++i) {
                     const bool fi = use_full(geo[(size_t)i].hv, tt);
-                    const bool hi = use_h16(stkde::kKernelEpan, false, fi, tt, items[i].plan->operand_form);
+                    const bool hi = use_h16(stkde::kKernelEpan, false, fi, tt, items[i].plan->operand_form, true);
                     if ((mode[(size_t)i] != stkde::kAccPlain) == g.kahan && geo[(size_t)i].tile_t == tt &&
                         hi == g.h16) {
                         g.idx.push_back(i);

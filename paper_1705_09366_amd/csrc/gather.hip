@@ -291,8 +291,8 @@ __device__ __attribute__((always_inline)) inline void gather_item(
     const int32_t pstride) {
     static_assert(!(FULL && ADAPT), "the full-cover path assumes one bandwidth pair");
     static_assert(KF == kKernelEpan || (!FULL && !ADAPT), "other pairs: no full-cover path, one pair");
-    static_assert(!H16 || (!FULL && !ADAPT && TT <= 32 && MODE != kAccKahanReg),
-                  "two-term FP16 operands: one bandwidth pair, no full-cover path, 16/32 rows");
+    static_assert(!H16 || (!ADAPT && TT <= 32 && MODE != kAccKahanReg),
+                  "two-term FP16 operands: one bandwidth pair, 16/32 rows, no register-form Kahan");
     using Lds = GatherLds<TT, MODE, FULL, ADAPT, KF, H16>;
     constexpr int kCap = Lds::kCap;
     constexpr int kLPad = Lds::kLPad;
@@ -364,8 +364,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
     float* __restrict__ kscratch) {
     static_assert(!(FULL && ADAPT), "the full-cover path assumes one bandwidth pair");
     static_assert(KF == kKernelEpan || (!FULL && !ADAPT), "other pairs: no full-cover path, one pair");
-    static_assert(!H16 || (!FULL && !ADAPT && TT <= 32 && MODE != kAccKahanReg),
-                  "two-term FP16 operands: one bandwidth pair, no full-cover path, 16/32 rows");
+    static_assert(!H16 || (!ADAPT && TT <= 32 && MODE != kAccKahanReg),
+                  "two-term FP16 operands: one bandwidth pair, 16/32 rows, no register-form Kahan");
     constexpr int kCap = H16 ? kCapH16 : kCapF32;
     constexpr int kLPad = H16 ? 32 : 8;  // wave lists are padded to this many entries
     constexpr int NB = TT / 16;  // 16-row blocks per tile
@@ -752,8 +752,14 @@ void dispatch_variant(bool full, bool adapt, bool h16, F& f) {
     if (adapt) {
         f.template operator()<TT, MODE, false, true, kKernelEpan, false>();
     } else if constexpr (TT <= 32) {
-        if (full) f.template operator()<TT, MODE, true, false, kKernelEpan, false>();
-        else if constexpr (MODE != kAccKahanReg) {
+        if (full) {
+            if constexpr (MODE != kAccKahanReg) {
+                if (h16) f.template operator()<TT, MODE, true, false, kKernelEpan, true>();
+                else f.template operator()<TT, MODE, true, false, kKernelEpan, false>();
+            } else {
+                f.template operator()<TT, MODE, true, false, kKernelEpan, false>();
+            }
+        } else if constexpr (MODE != kAccKahanReg) {
             if (h16) f.template operator()<TT, MODE, false, false, kKernelEpan, true>();
             else f.template operator()<TT, MODE, false, false, kKernelEpan, false>();
         } else {
