@@ -441,8 +441,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
     const uint32_t T = (uint32_t)ntiles_total;
     const uint32_t home = blockIdx.x % kFetchLanes;
     for (int q = 0; q < 2; ++q) {
-        const uint32_t qlen = q == 0 ? sc[kScHeavyItems] : T;
-        for (uint32_t lane_off = 0; lane_off < (uint32_t)kFetchLanes; ++lane_off) {
+        // an empty queue is skipped without reading its counters (the spatial
+        // queue is empty when the heaviest-first queue took every tile)
+        const uint32_t qlen = q == 0 ? sc[kScHeavyItems] : (sc[kScHeavyTiles] >= T ? 0u : T);
+        for (uint32_t lane_off = 0; qlen > 0 && lane_off < (uint32_t)kFetchLanes; ++lane_off) {
             const uint32_t k = (home + lane_off) % kFetchLanes;
             uint32_t* c = ctr + (q * kFetchLanes + k) * kCtrStride;
             // spatial queue: after the set-up of a tile that takes one phase, the
@@ -536,8 +538,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
     const uint32_t T = (uint32_t)ntiles_total;
     const uint32_t home = blockIdx.x % kFetchLanes;
     for (int q = 0; q < 2; ++q) {
-        const uint32_t qlen = q == 0 ? sc[kScHeavyItems] : T;
-        for (uint32_t lane_off = 0; lane_off < (uint32_t)kFetchLanes; ++lane_off) {
+        // an empty queue is skipped without reading its counters (the spatial
+        // queue is empty when the heaviest-first queue took every tile)
+        const uint32_t qlen = q == 0 ? sc[kScHeavyItems] : (sc[kScHeavyTiles] >= T ? 0u : T);
+        for (uint32_t lane_off = 0; qlen > 0 && lane_off < (uint32_t)kFetchLanes; ++lane_off) {
             const uint32_t k = (home + lane_off) % kFetchLanes;
             uint32_t* c = ctr + (q * kFetchLanes + k) * kCtrStride;
             // spatial queue: after the set-up of a tile that takes one phase, the
