@@ -101,20 +101,21 @@ __device__ inline bool point_bandwidths(const SetGeom& g, const double* __restri
 constexpr int kMaxDigitBits = 11;
 constexpr int kMaxBuckets = 1 << kMaxDigitBits;
 
-// Keys of one radix block's points and the block's histogram of the first
-// digit (the low dbits bits), hist[d * nblk + block].  kTransformThreads
-// threads, kSortTile / kTransformThreads points each (the histogram does not
-// depend on which thread counts a point).
-constexpr int kTransformThreads = 1024;
-constexpr int kTransformItems = kSortTile / kTransformThreads;
-__global__ __launch_bounds__(kTransformThreads) void k_transform(SetGeom g, const double* __restrict__ xyt,
-                                                                 const double* __restrict__ hst, int32_t n,
-                                                                 uint32_t* __restrict__ keys,
-                                                                 uint32_t* __restrict__ vals, int nbuck,
-                                                                 uint32_t* __restrict__ hist, int32_t nblk) {
+// Keys of one radix block's points (kThreads * ITEMS of them) and the block's
+// histogram of the first digit (the low dbits bits), hist[d * nblk + block]:
+// two points per thread (the histogram does not depend on which thread counts
+// a point).
+template <int ITEMS>
+__global__ __launch_bounds__(kThreads * ITEMS / 2) void k_transform(SetGeom g, const double* __restrict__ xyt,
+                                                                    const double* __restrict__ hst, int32_t n,
+                                                                    uint32_t* __restrict__ keys,
+                                                                    uint32_t* __restrict__ vals, int nbuck,
+                                                                    uint32_t* __restrict__ hist, int32_t nblk) {
+    constexpr int kTransformThreads = kThreads * ITEMS / 2;
+    constexpr int kTransformItems = 2;
     __shared__ uint32_t cnt[kMaxBuckets];
     const int tid = threadIdx.x;
-    const int32_t base = blockIdx.x * kSortTile;
+    const int32_t base = blockIdx.x * (kThreads * ITEMS);
     // every coordinate of this thread is loaded before the first footprint,
     // so that the loads are in flight together
     double px[kTransformItems], py[kTransformItems], pt[kTransformItems];
@@ -157,6 +158,7 @@ __global__ __launch_bounds__(kTransformThreads) void k_transform(SetGeom g, cons
 // buckets than threads).  The first pass's histogram comes with the keys.
 
 // Per-block digit histogram.  hist is digit-major: hist[d * nblk + b].
+template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                          int32_t n, int shift, int nbuck,
                                                          uint32_t* __restrict__ hist,
@@ -164,10 +166,10 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restr
     __shared__ uint32_t cnt[kMaxBuckets];
     // every key of this thread is loaded before the first count, so that the
     // loads are in flight together
-    const int32_t base = blockIdx.x * kSortTile;
-    uint32_t kr[kSortItems];
+    const int32_t base = blockIdx.x * (kThreads * ITEMS);
+    uint32_t kr[ITEMS];
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
+    for (int it = 0; it < ITEMS; ++it) {
         const int32_t i = base + it * kThreads + threadIdx.x;
         kr[it] = i < n ? keys[i] : 0u;
     }
@@ -175,7 +177,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restr
     __syncthreads();
     const uint32_t mask = (uint32_t)nbuck - 1u;
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
+    for (int it = 0; it < ITEMS; ++it) {
         const int32_t i = base + it * kThreads + threadIdx.x;
         if (i < n) atomicAdd(&cnt[(kr[it] >> shift) & mask], 1u);
     }
@@ -219,6 +221,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_rowscan(uint32_t* __restrict
 // covers indices base + r*256 + [0, 256), waves in order, lanes in order.
 // The rank of a key among equal digits is (keys of that digit in earlier
 // rounds) + (in earlier waves of this round) + (in earlier lanes).
+template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, int32_t n, int shift,
     int dbits, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ totals, int32_t nblk,
@@ -230,10 +233,10 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     const uint32_t mask = (uint32_t)nbuck - 1u;
     // every key and value of this thread is loaded up front, so that the
     // loads are in flight together rather than one round at a time
-    const int32_t base = blockIdx.x * kSortTile;
-    uint32_t kr[kSortItems], vr[kSortItems];
+    const int32_t base = blockIdx.x * (kThreads * ITEMS);
+    uint32_t kr[ITEMS], vr[ITEMS];
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
+    for (int r = 0; r < ITEMS; ++r) {
         const int32_t i = base + r * kThreads + tid;
         kr[r] = i < n ? kin[i] : 0u;
         vr[r] = i < n ? vin[i] : 0u;
@@ -278,7 +281,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     __syncthreads();
     const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
+    for (int r = 0; r < ITEMS; ++r) {
         const int32_t i = base + r * kThreads + tid;
         const bool valid = i < n;
         const uint32_t key = kr[r], val = vr[r];
@@ -414,7 +417,9 @@ SortLayout layout_sort(int64_t n) {
     SortLayout l{};
     size_t o = 0;
     const size_t nn = (size_t)n;
-    l.nblk = (int32_t)((n + kSortTile - 1) / kSortTile);
+    l.items = sort_items(n);
+    const int64_t tile = (int64_t)kThreads * l.items;
+    l.nblk = (int32_t)((n + tile - 1) / tile);
     l.keys0 = o; o = al256(o + nn * 4);
     l.vals0 = o; o = al256(o + nn * 4);
     l.keys1 = o; o = al256(o + nn * 4);
@@ -441,19 +446,23 @@ hipError_t launch_bin(const SetGeom& g, const double* d_xyt, int32_t n, uint8_t*
     const int passes = bits <= 8 ? 1 : (bits + kMaxDigitBits - 1) / kMaxDigitBits;
     const int dbits = bits <= 8 ? 8 : (bits + passes - 1) / passes;
     const int nbuck = 1 << dbits;
-    hipLaunchKernelGGL(k_transform, dim3(so.nblk), dim3(kTransformThreads), 0, s, g, d_xyt, d_hst, n, k0, v0,
-                       nbuck, hist, so.nblk);
-    for (int p = 0; p < passes; ++p) {
-        if (p > 0)
-            hipLaunchKernelGGL(k_radix_hist, dim3(so.nblk), dim3(kThreads), 0, s, k0, n, dbits * p, nbuck,
-                               hist, so.nblk);
-        uint32_t* tot = totals + kMaxBuckets * p;
-        hipLaunchKernelGGL(k_radix_rowscan, dim3(nbuck), dim3(kThreads), 0, s, hist, so.nblk, tot);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(so.nblk), dim3(kThreads), 0, s, k0, v0, n, dbits * p,
-                           dbits, hist, tot, so.nblk, k1, v1);
-        std::swap(k0, k1);
-        std::swap(v0, v1);
-    }
+    auto run_sort = [&]<int ITEMS>() {
+        hipLaunchKernelGGL((k_transform<ITEMS>), dim3(so.nblk), dim3(kThreads * ITEMS / 2), 0, s, g, d_xyt, d_hst,
+                           n, k0, v0, nbuck, hist, so.nblk);
+        for (int p = 0; p < passes; ++p) {
+            if (p > 0)
+                hipLaunchKernelGGL((k_radix_hist<ITEMS>), dim3(so.nblk), dim3(kThreads), 0, s, k0, n, dbits * p,
+                                   nbuck, hist, so.nblk);
+            uint32_t* tot = totals + kMaxBuckets * p;
+            hipLaunchKernelGGL(k_radix_rowscan, dim3(nbuck), dim3(kThreads), 0, s, hist, so.nblk, tot);
+            hipLaunchKernelGGL((k_radix_scatter<ITEMS>), dim3(so.nblk), dim3(kThreads), 0, s, k0, v0, n,
+                               dbits * p, dbits, hist, tot, so.nblk, k1, v1);
+            std::swap(k0, k1);
+            std::swap(v0, v1);
+        }
+    };
+    if (so.items == kSortItemsSmall) run_sort.template operator()<kSortItemsSmall>();
+    else run_sort.template operator()<kSortItems>();
     hipLaunchKernelGGL(k_offsets_records, dim3((uint32_t)(((int64_t)n + kThreads) / kThreads)), dim3(kThreads), 0,
                        s, g, d_xyt, d_hst, k0, v0, n, cs, reinterpret_cast<PointRec*>(set + sl.recs),
                        d_hst ? reinterpret_cast<float4*>(set + sl.bw) : nullptr,

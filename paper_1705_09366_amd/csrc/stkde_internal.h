@@ -119,8 +119,13 @@ struct alignas(16) WorkItem {
 constexpr uint32_t kAll = 0xffffffffu;
 constexpr uint32_t kNoSlot = 0xffffffffu;
 
-constexpr int kSortItems = 8;                         // keys per thread per radix block
-constexpr int kSortTile = kThreads * kSortItems;      // keys per radix block
+// Keys per thread of a radix block: 8 (blocks of 2048 keys), or 2 (512) for
+// sets of at most kSmallSort points, whose few blocks would otherwise each
+// take eight dependent rounds.
+constexpr int kSortItems = 8;
+constexpr int kSortItemsSmall = 2;
+constexpr int64_t kSmallSort = 65536;
+inline int sort_items(int64_t n) { return n <= kSmallSort ? kSortItemsSmall : kSortItems; }
 constexpr int kStatBlock = 256;                       // points per statistics block
 constexpr int kTopTiles = 1024;                       // most tiles in the heaviest-first queue
 constexpr int kMaxParts = 8;                          // parts of one split tile
@@ -194,7 +199,8 @@ SetLayout layout_set(const SetGeom& s, int64_t n, bool adaptive = false, bool ex
 struct SortLayout {
     size_t keys0, vals0, keys1, vals1, hist, totals;
     size_t total;
-    int32_t nblk;
+    int32_t nblk;   // radix blocks of kThreads * items keys
+    int32_t items;  // sort_items(n)
 };
 SortLayout layout_sort(int64_t n);
 
