@@ -179,18 +179,11 @@ __device__ inline uint32_t split_parts(const InstDev& D, unsigned long long inst
 // partial slots, every tile of a class or none, so that which tiles are cut
 // depends only on the costs, not on the order of heavy[]; it writes the work
 // items and split records in heavy[] order, and clears the queues' counters.
-//
-// Fused (one workgroup, at most 256 tiles and kDescChunk instances): the
-// descriptors arrive as arguments, and the workgroup also does the work of
-// k_put_desc and k_tile_cost, with the cost histogram, the per-instance
-// totals and the taken-tile mask in LDS -- one launch plans the pass.
-__global__ __launch_bounds__(256) void k_collect_plan(DescChunk dc, int32_t fused,
-                                                      InstDev* __restrict__ gdesc, int32_t count,
+__global__ __launch_bounds__(256) void k_collect_plan(const InstDev* __restrict__ descs, int32_t count,
                                                       uint32_t T, const uint32_t* __restrict__ cost,
-                                                      const uint32_t* __restrict__ ghist,
-                                                      const unsigned long long* __restrict__ ginst_cost,
+                                                      const uint32_t* __restrict__ hist,
+                                                      const unsigned long long* __restrict__ inst_cost,
                                                       uint32_t* __restrict__ inst_split,
-                                                      uint32_t* __restrict__ mass_done,
                                                       uint32_t* __restrict__ cursor,
                                                       uint32_t* __restrict__ demand,
                                                       unsigned long long* __restrict__ heavy,
@@ -213,54 +206,20 @@ __global__ __launch_bounds__(256) void k_collect_plan(DescChunk dc, int32_t fuse
     // one workgroup (up to 2048 tiles): heavy[] and the demand stay in LDS,
     // without the global atomics and the hand-over to a last workgroup
     __shared__ unsigned long long sheavy[kTopTiles];
-    // fused: descriptors, cost histogram, per-instance totals, taken tiles
-    __shared__ InstDev sdesc[kDescChunk];
-    __shared__ uint32_t shist[kCostClasses];
-    __shared__ unsigned long long sicost[kDescChunk];
-    __shared__ uint32_t sbits[256 / 32];
     const bool one = gridDim.x == 1;
     const int tid = threadIdx.x;
     for (int k = tid; k < kCostClasses; k += 256) {
         lcnt[k] = 0u;
         ldem[k] = 0u;
-        if (fused) shist[k] = 0u;
     }
-    if (fused) {
-        if (tid < count) {
-            sdesc[tid] = dc.d[tid];
-            gdesc[tid] = dc.d[tid];
-            sicost[tid] = 0ull;
-            inst_split[tid] = 0u;
-            mass_done[tid] = 0u;
-        }
-        if (tid < 256 / 32) sbits[tid] = 0u;
-        if (tid < kScCount) sc[tid] = 0u;
-        __syncthreads();
-    }
-    const InstDev* const descs = fused ? sdesc : gdesc;
-    const uint32_t* const hist = fused ? shist : ghist;
-    const unsigned long long* const inst_cost = fused ? sicost : ginst_cost;
     // the costs are loaded first, so that their loads overlap the threshold's
-    // (fused: computed here, one tile per thread)
     constexpr int kU = 8;  // loads in flight per thread
     const uint32_t j0 = blockIdx.x * (256u * kU) + tid;
     uint32_t cv[kU];
-    if (fused) {
 #pragma unroll
-        for (int u = 0; u < kU; ++u) cv[u] = 0u;
-        if (j0 < T) {
-            const int32_t inst = find_inst(descs, count, j0);
-            cv[0] = tile_candidates(descs[inst], j0, descs[inst].tile_t);
-            atomicAdd(&shist[cost_class(cv[0])], 1u);
-            if (cv[0]) atomicAdd(&sicost[inst], (unsigned long long)cv[0]);
-        }
-        __syncthreads();
-    } else {
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const uint32_t j = j0 + 256u * u;
-            cv[u] = j < T ? cost[j] : 0u;
-        }
+    for (int u = 0; u < kU; ++u) {
+        const uint32_t j = j0 + 256u * u;
+        cv[u] = j < T ? cost[j] : 0u;
     }
     // suffix counts over the classes, thread tid holding classes
     // kCostClasses - 1 - (kPer tid + u), highest first
@@ -297,8 +256,7 @@ __global__ __launch_bounds__(256) void k_collect_plan(DescChunk dc, int32_t fuse
             const uint32_t parts = split_parts(descs[inst], inst_cost[inst], c);
             if (parts > 1) atomicAdd(&ldem[k], parts);
             const uint32_t sp = spatial_pos(descs[inst], j);
-            if (fused) atomicOr(&sbits[sp >> 5], 1u << (sp & 31u));
-            else atomicOr(&bits[sp >> 5], 1u << (sp & 31u));
+            atomicOr(&bits[sp >> 5], 1u << (sp & 31u));
         }
     }
     __syncthreads();
@@ -404,13 +362,106 @@ __global__ __launch_bounds__(256) void k_collect_plan(DescChunk dc, int32_t fuse
         }
     }
     for (int k = tid; k < kCtrWords; k += 256) ctr[k] = 0u;  // both queues' counters
-    if (fused && tid < (int)((T + 31) / 32)) bits[tid] = sbits[tid];  // complete since the heavy selection
     if (tid == 0) {
         sc[kScHeavyItems] = tot_items;
         sc[kScSplit] = tot_split;
         sc[kScHeavyTiles] = nh;
         if (!one) *done = 0u;
     }
+}
+
+// The whole planning of a pass of at most 256 tiles and kDescChunk grids, in
+// one workgroup, tile j on thread j: the descriptors arrive as arguments (this
+// kernel stores them for the later ones and clears the pass counters), the
+// tile costs as k_tile_cost counts them.  With so few tiles the work list of
+// k_collect_plan reduces to: every tile with candidates is heavy (at most
+// 256 <= kTopTiles of them), and it is cut into split_parts parts when the
+// costliest classes' slot demand fits the partial slots -- every candidate
+// of a class whose suffix demand (over the classes at and above it) is at
+// most nslots -- the same tiles and parts; the items follow in tile order,
+// which changes only which workgroup computes an item.
+__global__ __launch_bounds__(256) void k_plan_small(DescChunk dc, int32_t count, uint32_t T,
+                                                    InstDev* __restrict__ gdesc,
+                                                    uint32_t* __restrict__ inst_split,
+                                                    uint32_t* __restrict__ mass_done,
+                                                    WorkItem* __restrict__ items,
+                                                    uint32_t* __restrict__ top,
+                                                    uint32_t* __restrict__ bits,
+                                                    uint32_t* __restrict__ sc,
+                                                    uint32_t* __restrict__ ctr, uint32_t nslots) {
+    __shared__ InstDev sdesc[kDescChunk];
+    __shared__ unsigned long long sic[kDescChunk];
+    __shared__ uint32_t ssplit[kDescChunk];
+    __shared__ uint32_t sbits[256 / 32];
+    __shared__ uint32_t scls[256], sdem[256];
+    __shared__ uint32_t ws[4];
+    const int tid = threadIdx.x;
+    if (tid < count) {
+        sdesc[tid] = dc.d[tid];
+        gdesc[tid] = dc.d[tid];
+        sic[tid] = 0ull;
+        ssplit[tid] = 0u;
+        mass_done[tid] = 0u;
+    }
+    if (tid < 256 / 32) sbits[tid] = 0u;
+    __syncthreads();
+    const uint32_t j = (uint32_t)tid;
+    const bool valid = j < T;
+    int32_t inst = 0;
+    uint32_t c = 0;
+    if (valid) {
+        inst = find_inst(sdesc, count, j);
+        c = tile_candidates(sdesc[inst], j, sdesc[inst].tile_t);
+        if (c) atomicAdd(&sic[inst], (unsigned long long)c);
+    }
+    __syncthreads();
+    const bool heavy = valid && c != 0u;
+    uint32_t parts = heavy ? split_parts(sdesc[inst], sic[inst], c) : 0u;
+    if (heavy) {
+        const uint32_t sp = spatial_pos(sdesc[inst], j);
+        atomicOr(&sbits[sp >> 5], 1u << (sp & 31u));
+    }
+    // the cut: a tile that would split does when the demand of its class and
+    // the costlier ones fits the slots (computed tile by tile only when the
+    // whole demand does not fit)
+    const uint32_t dem = parts > 1 ? parts : 0u;
+    uint32_t dtot;
+    (void)block_scan256(dem, ws, &dtot);
+    if (dtot > nslots) {
+        const uint32_t k = heavy ? cost_class(c) : 0u;
+        scls[tid] = k;
+        sdem[tid] = dem;
+        __syncthreads();
+        uint32_t suffix = 0;
+        for (int u = 0; u < 256; ++u) suffix += scls[u] >= k ? sdem[u] : 0u;
+        if (dem && suffix > nslots) parts = 1u;
+    }
+    uint32_t tot_items, tot_slots, tot_split, tot_heavy;
+    const uint32_t ipos = block_scan256(parts, ws, &tot_items);
+    const uint32_t spos = block_scan256(parts > 1 ? parts : 0u, ws, &tot_slots);
+    const uint32_t kpos = block_scan256(parts > 1 ? 1u : 0u, ws, &tot_split);
+    (void)block_scan256(heavy ? 1u : 0u, ws, &tot_heavy);
+    for (uint32_t p = 0; p < parts; ++p) {
+        const uint32_t b = (uint32_t)(((unsigned long long)c * p) / parts);
+        const uint32_t en = p + 1 == parts ? kAll : (uint32_t)(((unsigned long long)c * (p + 1)) / parts);
+        items[ipos + p] = WorkItem{j, b, en, parts > 1 ? spos + p : kNoSlot};
+    }
+    if (parts > 1) {
+        atomicAdd(&ssplit[inst], 1u);
+        top[4 * kpos + 0] = j;
+        top[4 * kpos + 1] = parts;
+        top[4 * kpos + 2] = spos;
+        top[4 * kpos + 3] = c;
+    }
+    for (int k = tid; k < kCtrWords; k += 256) ctr[k] = 0u;  // both queues' counters
+    __syncthreads();
+    if (tid < (int)((T + 31) / 32)) bits[tid] = sbits[tid];
+    if (tid < count) inst_split[tid] = ssplit[tid];
+    if (tid < kScCount)
+        sc[tid] = tid == kScHeavyItems ? tot_items
+                : tid == kScSplit     ? tot_split
+                : tid == kScHeavyTiles ? tot_heavy
+                                       : 0u;
 }
 
 // Each instance's FP64 grid sum in a fixed order: workgroup (chunk, inst)
@@ -526,11 +577,12 @@ hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassL
         any_stats = any_stats || descs[i].stats != nullptr;
     }
     const uint32_t T = (uint32_t)pl.T;
-    // a pass of at most 256 tiles is planned by one workgroup in one launch
-    const bool fused = T <= 256u && count <= kDescChunk;
-    DescChunk dc0{};
-    if (fused) {
-        for (int32_t k = 0; k < count; ++k) dc0.d[k] = descs[k];
+    if (T <= 256u && count <= kDescChunk) {
+        // a pass of at most 256 tiles is planned by one workgroup in one launch
+        DescChunk dc{};
+        for (int32_t k = 0; k < count; ++k) dc.d[k] = descs[k];
+        hipLaunchKernelGGL(k_plan_small, dim3(1), dim3(256), 0, s, dc, count, T, d_desc, inst_split, mass_done,
+                           items, top, bits, sc, ctr, (uint32_t)part_slots(pl.T));
     } else {
         for (int32_t first = 0; first < count; first += kDescChunk) {
             DescChunk c{};
@@ -541,11 +593,11 @@ hipError_t launch_pass(InstDev* descs, int32_t count, uint8_t* pass, const PassL
         }
         hipLaunchKernelGGL(k_tile_cost, dim3((T + 255) / 256), dim3(256), 0, s, (const InstDev*)d_desc,
                            count, T, cost, hist, inst_cost, bits);
+        hipLaunchKernelGGL(k_collect_plan, dim3((T + 2047) / 2048), dim3(256), 0, s, (const InstDev*)d_desc,
+                           count, T, (const uint32_t*)cost, (const uint32_t*)hist,
+                           (const unsigned long long*)inst_cost, inst_split, cursor, demand, heavy, items, top,
+                           bits, sc, ctr, (uint32_t)part_slots(pl.T), sc + kScPlanDone);
     }
-    hipLaunchKernelGGL(k_collect_plan, dim3(fused ? 1u : (T + 2047) / 2048), dim3(256), 0, s, dc0,
-                       fused ? 1 : 0, d_desc, count, T, (const uint32_t*)cost, (const uint32_t*)hist,
-                       (const unsigned long long*)inst_cost, inst_split, mass_done, cursor, demand, heavy, items,
-                       top, bits, sc, ctr, (uint32_t)part_slots(pl.T), sc + kScPlanDone);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev_before && (e = hipEventRecord(ev_before, s)) != hipSuccess) return e;
