@@ -92,7 +92,7 @@ def profiled_sources_hash():
     csrc = os.path.join(ROOT, "paper_1705_09366_amd", "csrc")
     h = hashlib.sha256()
     for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
+        if f.endswith((".hip", ".h", ".inc")):
             h.update(open(os.path.join(csrc, f), "rb").read())
     h.update(open(os.path.join(ROOT, "paper_1705_09366_amd", "tuned_gfx950.json"), "rb").read())
     return h.hexdigest()
