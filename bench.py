@@ -49,16 +49,21 @@ def _log(msg):
 
 def _operand_form(inst, tuning, kahan, adaptive, kern):
     """Matrix-core operands of the gather, by the library's rule: two FP16
-    terms with one bandwidth pair, no full-cover path (Epanechnikov pair with
-    hs / sres >= 14) and 16- or 32-row tiles, unless the tuning asks for
-    FP32."""
+    terms with one bandwidth pair and 16- or 32-row tiles, unless the tuning
+    asks for FP32; with the full-cover path (Epanechnikov pair with
+    hs / sres >= 14) only at 16 rows and only for the points that reach a
+    tile in part (the covering points keep FP32 separable sums)."""
     import math
     tt = tuning.tile_t if tuning and tuning.tile_t else (32 if math.ceil(inst.ht / inst.tres) <= 12 else 16)
     if kahan or kern != 0:
         tt = min(tt, 32)
-    fp32 = (tuning is not None and tuning.operand_form == 1) or adaptive or tt > 32 \
-        or (kern == 0 and inst.hs / inst.sres >= 14.0)
-    return "fp32" if fp32 else "fp16 hi+lo, fp32 accumulate"
+    full = kern == 0 and inst.hs / inst.sres >= 14.0
+    fp32 = (tuning is not None and tuning.operand_form == 1) or adaptive or tt > 32 or (full and tt != 16)
+    if fp32:
+        return "fp32"
+    if full:
+        return "fp16 hi+lo (points reaching a tile in part), fp32 (tile- and quadrant-cover sums), fp32 accumulate"
+    return "fp16 hi+lo, fp32 accumulate"
 
 
 def _instance(name):
