@@ -711,11 +711,14 @@ def _roofline(alg_bytes, alg_flops, gather_ms):
 
 def time_compute(m, desc, tuning, pts, pairs, steps, warmup, stages=False):
     """Time `steps` full computations (after `warmup`) with the points resident:
-    wall time per step between two synchronisations, the median of per-step
-    events, and the gather kernel's duration from the events the library
-    records around that launch on its stream.  Also the exact evaluation count
-    and the per-point mass (a separate computation outside the timed region),
-    and, with `stages`, the binning and accumulation stages timed apart."""
+    wall time per step between two synchronisations, with nothing else on the
+    stream; then, in a second run of `steps` computations, the median of
+    per-step events and the gather kernel's duration from the events the
+    library records around that launch on its stream (event records between
+    launches cost a few microseconds per step, which the wall time leaves
+    out).  Also the exact evaluation count and the per-point mass (a separate
+    computation outside the timed region), and, with `stages`, the binning and
+    accumulation stages timed apart."""
     import torch
     dev = pts.device
     stream = torch.cuda.current_stream(dev)
@@ -739,16 +742,19 @@ def time_compute(m, desc, tuning, pts, pairs, steps, warmup, stages=False):
     for _ in range(warmup):
         compute(plan, out, stats, ws)
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        compute(plan, out, stats, ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     plan.profile(steps)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     for k in range(steps):
         ev[k][0].record(stream)
         compute(plan, out, stats, ws)
         ev[k][1].record(stream)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
     kern_ms = plan.profile_read()
     plan.profile(0)
     if len(kern_ms) != steps:
@@ -904,7 +910,7 @@ def other_configs(m, dev, args):
             flags = m.FLAG_MASS | (m.FLAG_KAHAN if mode == "kahan" else 0)
             desc = _desc_of(m, inst, flags)
             tun, src = autotune.resolve(desc, n)
-            r = time_compute(m, desc, tun, pts, None, 50 if name == "uniform-10k" else args.steps, 3)
+            r = time_compute(m, desc, tun, pts, None, 200 if name == "uniform-10k" else args.steps, 3)
             est = error_stats(r["out"].cpu().numpy(), ref)
             alg_bytes = inst.gx * inst.gy * inst.gt * 4 + n * 24
             roof = _roofline(alg_bytes, 2.0 * r["evals"], r["gather_ms"])

@@ -346,7 +346,7 @@ struct ComputeLayout {
 ComputeLayout layout_compute(const stkde_plan_s* p, int64_t n) {
     ComputeLayout c{};
     c.sl = stkde::layout_set(p->sg, n, (p->desc.flags & STKDE_FLAG_ADAPTIVE) != 0, exact_support(p->desc));
-    c.so = stkde::layout_sort(n);
+    c.so = stkde::layout_sort(p->sg, n, (p->desc.flags & STKDE_FLAG_ADAPTIVE) != 0, exact_support(p->desc));
     c.pl = stkde::layout_pass(&p->ig, 1, p->ig.tile_t, (p->desc.flags & STKDE_FLAG_KAHAN) != 0);
     c.nblk_pts = (int32_t)((n + stkde::kStatBlock - 1) / stkde::kStatBlock);
     c.pstats = al256((size_t)c.nblk_pts * 4 * 8);
@@ -664,7 +664,7 @@ stkde_status stkde_set_plan(const stkde_desc* base, const stkde_tuning* tun, int
     tmp.n = n;
     make_set_geom(*base, tun ? tun->cell_xy : 0, tun ? tun->cell_t : 0, rows, &tmp.sg);
     tmp.sl = stkde::layout_set(tmp.sg, n);
-    tmp.so = stkde::layout_sort(n);
+    tmp.so = stkde::layout_sort(tmp.sg, n);
     stkde_set_s* s = new (std::nothrow) stkde_set_s(tmp);
     if (!s) return STKDE_ERR_TOO_LARGE;
     *out = s;

@@ -464,11 +464,13 @@ __global__ __launch_bounds__(256) void k_plan_small(DescChunk dc, int32_t count,
                                        : 0u;
 }
 
-// Each instance's FP64 grid sum in a fixed order: workgroup (chunk, inst)
-// sums chunk `chunk` of the instance's tile partials (strided per-thread
-// sums, then a tree) into mid[inst][chunk]; the last of the instance's
-// kMassChunks workgroups to finish adds the chunks (a butterfly over the 64
-// chunks) and writes the instance's statistics (write_stats).
+// Each instance's FP64 grid sum in a fixed order: the instance's tile
+// partials are cut into nch = min(kMassChunks, ceil(partials / 2048))
+// chunks; workgroup (chunk, inst) sums its chunk (strided per-thread sums,
+// then a tree) into mid[inst][chunk], and the last of the instance's nch
+// workgroups to finish adds the chunks (a butterfly over 64 lanes, zero past
+// nch) and writes the instance's statistics (write_stats).  An instance of
+// one chunk (at most 512 tiles) writes them at once, without the hand-over.
 __global__ __launch_bounds__(256) void k_mass(const InstDev* __restrict__ descs, double* __restrict__ mid,
                                               const uint32_t* __restrict__ inst_split,
                                               uint32_t* __restrict__ mass_done) {
@@ -478,10 +480,13 @@ __global__ __launch_bounds__(256) void k_mass(const InstDev* __restrict__ descs,
     const int inst = blockIdx.y, ch = blockIdx.x, tid = threadIdx.x;
     const InstDev& D = descs[inst];
     if (!D.stats) return;  // nothing to report (every workgroup of the instance leaves)
+    const int64_t cnt = (D.flags & kInstMass) ? (int64_t)D.ntiles * kWaves : 0;
+    const int64_t nch64 = (cnt + kMassChunkMin - 1) / kMassChunkMin;
+    const int nch = nch64 < 1 ? 1 : (nch64 > kMassChunks ? kMassChunks : (int)nch64);
+    if (ch >= nch) return;
     double s = 0.0;
-    if (D.flags & kInstMass) {
-        const int64_t cnt = (int64_t)D.ntiles * kWaves;
-        const int64_t chunk = (cnt + kMassChunks - 1) / kMassChunks;
+    {
+        const int64_t chunk = (cnt + nch - 1) / nch;
         const int64_t beg = (int64_t)ch * chunk;
         const int64_t end = beg + chunk < cnt ? beg + chunk : cnt;
         for (int64_t i = beg + tid; i < end; i += 256) s += as_global(D.tile_part)[i];
@@ -492,16 +497,22 @@ __global__ __launch_bounds__(256) void k_mass(const InstDev* __restrict__ descs,
         if (tid < w) sh[tid] += sh[tid + w];
         __syncthreads();
     }
+    if (nch == 1) {
+        if (tid == 0) write_stats(D, sh[0], inst_split[inst]);
+        return;
+    }
     if (tid == 0) {
         __hip_atomic_store(&mid[(size_t)inst * kMassChunks + ch], sh[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __threadfence();
-        s_last = atomicAdd(&mass_done[inst], 1u) == (uint32_t)kMassChunks - 1 ? 1u : 0u;
+        s_last = atomicAdd(&mass_done[inst], 1u) == (uint32_t)nch - 1 ? 1u : 0u;
     }
     __syncthreads();
     if (!s_last || tid >= 64) return;
     __threadfence();
     const int lane = tid;
-    double v = __hip_atomic_load(&mid[(size_t)inst * kMassChunks + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    double v = lane < nch ? __hip_atomic_load(&mid[(size_t)inst * kMassChunks + lane], __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT)
+                          : 0.0;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
     if (lane == 0) {

@@ -133,6 +133,7 @@ constexpr int kPartSlots = 1024;                      // partial tiles of one pa
 constexpr uint32_t kSplitFloor = 2048;                // never split below this many candidates
 constexpr uint32_t kBalanceItems = 2048;              // default split share of an instance's cost
 constexpr int kMassChunks = 64;
+constexpr int64_t kMassChunkMin = 2048;  // tile partials per mass chunk, at least
 // Accumulation modes of the gather: plain FP32; Kahan with the running
 // (sum, compensation) pair in registers; the same pair kept in a per-workgroup
 // scratch slot, touched only when a tile takes more than one phase (fewer
@@ -198,11 +199,18 @@ SetLayout layout_set(const SetGeom& s, int64_t n, bool adaptive = false, bool ex
 // ---- scratch of the binning radix sort --------------------------------------
 struct SortLayout {
     size_t keys0, vals0, keys1, vals1, hist, totals;
+    // a sort of one pass (keys of at most 11 bits): keys0, then the records,
+    // bandwidth terms and FP64 voxel coordinates of the valid points in input
+    // order (no value or second key array)
+    size_t prec, pbw, px64;
     size_t total;
-    int32_t nblk;   // radix blocks of kThreads * items keys
-    int32_t items;  // sort_items(n)
+    int32_t nblk;    // radix blocks of kThreads * items keys
+    int32_t items;   // sort_items(n)
+    bool one_pass;   // the geometry's keys take one pass
+    bool adaptive;   // room for per-point bandwidth terms
+    bool exact;      // room for FP64 voxel coordinates
 };
-SortLayout layout_sort(int64_t n);
+SortLayout layout_sort(const SetGeom& g, int64_t n, bool adaptive = false, bool exact = false);
 
 // ---- scratch of one gather pass over `count` instances ---------------------
 struct PassLayout {
