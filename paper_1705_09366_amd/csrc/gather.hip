@@ -444,19 +444,26 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
         // an empty queue is skipped without reading its counters (the spatial
         // queue is empty when the heaviest-first queue took every tile)
         const uint32_t qlen = q == 0 ? sc[kScHeavyItems] : (sc[kScHeavyTiles] >= T ? 0u : T);
-        for (uint32_t lane_off = 0; qlen > 0 && lane_off < (uint32_t)kFetchLanes; ++lane_off) {
+        // a queue of at most one item per workgroup is not fetched from:
+        // workgroup b takes item b (every workgroup is resident, so each item
+        // starts at once, as with the counters, and no workgroup walks them)
+        const bool dyn = qlen > gridDim.x;
+        for (uint32_t lane_off = 0; qlen > 0 && lane_off < (dyn ? (uint32_t)kFetchLanes : 1u); ++lane_off) {
             const uint32_t k = (home + lane_off) % kFetchLanes;
             uint32_t* c = ctr + (q * kFetchLanes + k) * kCtrStride;
             // spatial queue: after the set-up of a tile that takes one phase, the
             // next position of this counter is taken at once, so that the
             // atomic's latency is hidden behind the tile's work (taking it
-            // early for longer tiles costs more in balance than it saves)
-            bool pend = false;
+            // early for longer tiles costs more in balance than it saves; a
+            // queue not fetched from ignores that position)
+            bool pend = false, first = true;
             uint32_t pnext = 0;
             for (;;) {
                 if (tid == 0) {
                     uint32_t v;
-                    if (pend) {
+                    if (!dyn) {
+                        v = first && blockIdx.x < qlen ? blockIdx.x : 0xffffffffu;
+                    } else if (pend) {
                         v = pnext;
                         pend = false;
                     } else {
@@ -470,6 +477,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                 __syncthreads();
                 const uint32_t idx = __builtin_amdgcn_readfirstlane(sIdx);
                 __syncthreads();  // sIdx is rewritten by the next fetch
+                first = false;
                 if (idx >= qlen) break;
                 WorkItem it;
                 // spatial queue: every tile in spatial order, minus those the
@@ -541,19 +549,26 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
         // an empty queue is skipped without reading its counters (the spatial
         // queue is empty when the heaviest-first queue took every tile)
         const uint32_t qlen = q == 0 ? sc[kScHeavyItems] : (sc[kScHeavyTiles] >= T ? 0u : T);
-        for (uint32_t lane_off = 0; qlen > 0 && lane_off < (uint32_t)kFetchLanes; ++lane_off) {
+        // a queue of at most one item per workgroup is not fetched from:
+        // workgroup b takes item b (every workgroup is resident, so each item
+        // starts at once, as with the counters, and no workgroup walks them)
+        const bool dyn = qlen > gridDim.x;
+        for (uint32_t lane_off = 0; qlen > 0 && lane_off < (dyn ? (uint32_t)kFetchLanes : 1u); ++lane_off) {
             const uint32_t k = (home + lane_off) % kFetchLanes;
             uint32_t* c = ctr + (q * kFetchLanes + k) * kCtrStride;
             // spatial queue: after the set-up of a tile that takes one phase, the
             // next position of this counter is taken at once, so that the
             // atomic's latency is hidden behind the tile's work (taking it
-            // early for longer tiles costs more in balance than it saves)
-            bool pend = false;
+            // early for longer tiles costs more in balance than it saves; a
+            // queue not fetched from ignores that position)
+            bool pend = false, first = true;
             uint32_t pnext = 0;
             for (;;) {
                 if (tid == 0) {
                     uint32_t v;
-                    if (pend) {
+                    if (!dyn) {
+                        v = first && blockIdx.x < qlen ? blockIdx.x : 0xffffffffu;
+                    } else if (pend) {
                         v = pnext;
                         pend = false;
                     } else {
@@ -567,6 +582,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                 __syncthreads();
                 const uint32_t idx = __builtin_amdgcn_readfirstlane(sIdx);
                 __syncthreads();  // sIdx is rewritten by the next fetch
+                first = false;
                 if (idx >= qlen) break;
                 WorkItem it;
                 // spatial queue: every tile in spatial order, minus those the
