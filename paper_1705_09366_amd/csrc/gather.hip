@@ -349,7 +349,9 @@ __device__ __attribute__((always_inline)) inline void gather_item(
     uint16_t* myL = sL[wave];
 
 #define GATHER_NEXT_ITEM return
+#define GATHER_STORE_NT false
 #include "gather_item.inc"
+#undef GATHER_STORE_NT
 #undef GATHER_NEXT_ITEM
 }
 
@@ -444,10 +446,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
         // an empty queue is skipped without reading its counters (the spatial
         // queue is empty when the heaviest-first queue took every tile)
         const uint32_t qlen = q == 0 ? sc[kScHeavyItems] : (sc[kScHeavyTiles] >= T ? 0u : T);
-        // a queue of at most one item per workgroup is not fetched from:
-        // workgroup b takes item b (every workgroup is resident, so each item
-        // starts at once, as with the counters, and no workgroup walks them)
-        const bool dyn = qlen > gridDim.x;
+        // queues of at most one item per workgroup are not fetched from: the
+        // heaviest-first queue's item b goes to workgroup b, and when both
+        // queues together fit the grid, the spatial queue's item j to
+        // workgroup (heavy items) + j, one that holds no heavy item (every
+        // workgroup is resident, so each item starts at once, as with the
+        // counters, and no workgroup walks them)
+        const uint32_t sbase = q == 0 ? 0u : sc[kScHeavyItems];
+        const bool dyn = sbase + qlen > gridDim.x;
         for (uint32_t lane_off = 0; qlen > 0 && lane_off < (dyn ? (uint32_t)kFetchLanes : 1u); ++lane_off) {
             const uint32_t k = (home + lane_off) % kFetchLanes;
             uint32_t* c = ctr + (q * kFetchLanes + k) * kCtrStride;
@@ -462,7 +468,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                 if (tid == 0) {
                     uint32_t v;
                     if (!dyn) {
-                        v = first && blockIdx.x < qlen ? blockIdx.x : 0xffffffffu;
+                        v = first && blockIdx.x >= sbase ? blockIdx.x - sbase : 0xffffffffu;
                     } else if (pend) {
                         v = pnext;
                         pend = false;
@@ -495,7 +501,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                 }
                 constexpr int32_t pstride = kTileXY * kTileXY * TT;  // floats per partial slot
 #define GATHER_NEXT_ITEM continue
+#define GATHER_STORE_NT true
 #include "gather_item.inc"
+#undef GATHER_STORE_NT
 #undef GATHER_NEXT_ITEM
             }
         }
@@ -549,26 +557,22 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
         // an empty queue is skipped without reading its counters (the spatial
         // queue is empty when the heaviest-first queue took every tile)
         const uint32_t qlen = q == 0 ? sc[kScHeavyItems] : (sc[kScHeavyTiles] >= T ? 0u : T);
-        // a queue of at most one item per workgroup is not fetched from:
-        // workgroup b takes item b (every workgroup is resident, so each item
-        // starts at once, as with the counters, and no workgroup walks them)
-        const bool dyn = qlen > gridDim.x;
-        for (uint32_t lane_off = 0; qlen > 0 && lane_off < (dyn ? (uint32_t)kFetchLanes : 1u); ++lane_off) {
+        // (every queue is fetched from here: the static hand-out of short
+        // queues, as in k_gather_items, measured 20 % slower in this kernel,
+        // whose register allocation spills)
+        for (uint32_t lane_off = 0; qlen > 0 && lane_off < (uint32_t)kFetchLanes; ++lane_off) {
             const uint32_t k = (home + lane_off) % kFetchLanes;
             uint32_t* c = ctr + (q * kFetchLanes + k) * kCtrStride;
             // spatial queue: after the set-up of a tile that takes one phase, the
             // next position of this counter is taken at once, so that the
             // atomic's latency is hidden behind the tile's work (taking it
-            // early for longer tiles costs more in balance than it saves; a
-            // queue not fetched from ignores that position)
-            bool pend = false, first = true;
+            // early for longer tiles costs more in balance than it saves)
+            bool pend = false;
             uint32_t pnext = 0;
             for (;;) {
                 if (tid == 0) {
                     uint32_t v;
-                    if (!dyn) {
-                        v = first && blockIdx.x < qlen ? blockIdx.x : 0xffffffffu;
-                    } else if (pend) {
+                    if (pend) {
                         v = pnext;
                         pend = false;
                     } else {
@@ -582,7 +586,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
                 __syncthreads();
                 const uint32_t idx = __builtin_amdgcn_readfirstlane(sIdx);
                 __syncthreads();  // sIdx is rewritten by the next fetch
-                first = false;
                 if (idx >= qlen) break;
                 WorkItem it;
                 // spatial queue: every tile in spatial order, minus those the
