@@ -518,8 +518,8 @@ def bench_ablation(args, dev):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="clustered-1M", choices=WORKLOADS)
     ap.add_argument("--plain", action="store_true", help="plain FP32 accumulation (no Kahan)")
     ap.add_argument("--kernel", default="epanechnikov", choices=KERNELS,
