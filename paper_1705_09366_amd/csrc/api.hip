@@ -777,9 +777,10 @@ stkde_status stkde_batch_plan(const stkde_item* items, int32_t count, stkde_batc
     // The passes of a batch that is all plain or all compensated, with 16- and
     // 32-row tiles, run as one pass with one gather launch (the multi-variant
     // gather): each grid keeps its kernel's code -- the full-cover FP32 kernel
-    // for the FP32 passes (the path is switched per grid; the register form
-    // of Kahan gives the bits of the scratch form), the two-term FP16 kernel
-    // for the others -- so each keeps the bits of its own pass.
+    // for the FP32 passes (the path is switched per grid; compensated sums in
+    // the scratch form, which gives the bits of the register form), the
+    // two-term FP16 kernel for the others -- so each keeps the bits of its own
+    // pass.
     if (bt->groups.size() > 1) {
         bool one = true;
         for (const auto& g : bt->groups)
@@ -787,7 +788,7 @@ stkde_status stkde_batch_plan(const stkde_item* items, int32_t count, stkde_batc
         if (one) {
             stkde_batch_s::Group m;
             m.kahan = bt->groups[0].kahan;
-            m.mode = m.kahan ? stkde::kAccKahanReg : stkde::kAccPlain;
+            m.mode = m.kahan ? stkde::kAccKahanMem : stkde::kAccPlain;
             m.full = false;
             m.h16 = false;
             m.multi = true;

@@ -834,8 +834,12 @@ void dispatch(int tile_t, int mode, bool full, bool adapt, int kf, bool h16, F&&
 
 // The variant lists of the multi-variant gather, in multi_variant order:
 // full-cover FP32 operands 16, 32 rows; two-term FP16 operands 16, 32 rows.
-using MultiKahan = k_gather_multi_t<GVar<16, kAccKahanReg, true, false, kKernelEpan, false>,
-                                    GVar<32, kAccKahanReg, true, false, kKernelEpan, false>,
+// Compensated sums keep their pair in scratch in every variant here: the
+// register form of the full-cover variants (the form a grid of theirs takes
+// alone; the same operations, the same bits) made the kernel spill about 127
+// VGPRs at its 128-register bound (batch sweep 3.73 -> 3.52 ms without).
+using MultiKahan = k_gather_multi_t<GVar<16, kAccKahanMem, true, false, kKernelEpan, false>,
+                                    GVar<32, kAccKahanMem, true, false, kKernelEpan, false>,
                                     GVar<16, kAccKahanMem, false, false, kKernelEpan, true>,
                                     GVar<32, kAccKahanMem, false, false, kKernelEpan, true>>;
 using MultiPlain = k_gather_multi_t<GVar<16, kAccPlain, true, false, kKernelEpan, false>,
