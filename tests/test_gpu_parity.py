@@ -135,6 +135,35 @@ def test_repeatable_bitwise(torch_cuda):
     assert np.array_equal(a, b) and np.array_equal(c, d)
 
 
+@pytest.mark.parametrize("case", ["corner", "dense", "wide"])
+def test_queues_handed_out_without_counters(torch_cuda, case):
+    """The gather hands out a queue that fits the grid of workgroups without
+    counters (heavy item b to workgroup b; spatial item j after the heavy
+    items).  corner: a 96x96x64 grid whose points sit in one corner, so most
+    tiles hold no candidate and go through the spatial queue (zeros written);
+    dense: every tile of a 128x128x32 grid is heavy (empty spatial queue);
+    wide: 2048 tiles, more than the grid of workgroups, so the heavy queue is
+    handed out directly and the spatial queue from the counters.  Each is
+    compared voxel by voxel with the oracle and repeated bitwise."""
+    rng = np.random.default_rng(53)
+    if case == "corner":
+        g = dict(gx=96, gy=96, gt=64, hs=3.0, ht=2.0)
+        pts = rng.uniform(0, 1, (3000, 3)) * [20, 20, 12]
+    elif case == "dense":
+        g = dict(gx=128, gy=128, gt=32, hs=4.0, ht=3.0)
+        pts = rng.uniform(0, 1, (20000, 3)) * [128, 128, 32]
+    else:
+        g = dict(gx=512, gy=512, gt=64, hs=2.0, ht=2.0)
+        pts = np.concatenate([rng.uniform(0, 1, (15000, 3)) * [512, 512, 64],
+                              rng.normal([256, 256, 32], [20, 20, 6], (15000, 3)).clip(0, [511, 511, 63])])
+    _say(f"queue hand-out case {case}")
+    a, st = _run(torch_cuda, pts, g, flags=1 | 4)
+    b, _ = _run(torch_cuda, pts, g, flags=1 | 4)
+    ref, _ = oracle.pbsym(pts, _grid(g))
+    _check_close(a, ref)
+    assert np.array_equal(a, b)
+
+
 # ------------------------------------------------------------- edge cases
 def test_single_point_closed_form(torch_cuda):
     g = dict(gx=21, gy=21, gt=15, hs=5.0, ht=4.0)
