@@ -22,9 +22,10 @@
 // tile of every instance with t fastest, minus those the first queue took,
 // so that the tiles in flight at any time are neighbours that read the same
 // bins.  Each queue is served by interleaved counters that only grow, so
-// every workgroup leaves after one failed fetch per counter.  One launch serves any number of
-// instances (grids with their own bandwidths and windows over their own
-// binned sets).
+// every workgroup leaves after one failed fetch per counter; in the
+// single-variant kernel a queue that fits the grid of workgroups is handed
+// out without counters.  One launch serves any number of instances (grids
+// with their own bandwidths and windows over their own binned sets).
 //
 // Per work item (256 threads, 16 x 16 x TT tile):
 //   setup   the bin rows (t, y) whose bins can hold points reaching the tile
@@ -49,9 +50,11 @@
 //           block).  The loop has no branches; the next group's coordinates
 //           are fetched while the current group's instructions run;
 //   store   each lane writes 4 consecutive rows of one column per block,
-//           scaled by the normalisation (2/pi)(3/4)/(n hs^2 ht); a part of a
-//           split tile writes its unscaled sums to a partial slot instead,
-//           and the split reduction adds the parts in part order.
+//           scaled by the normalisation (2/pi)(3/4)/(n hs^2 ht) (32-row tiles
+//           of the single-variant kernel without the full-cover path:
+//           non-temporal stores); a part of a split tile writes its unscaled
+//           sums to a partial slot instead, and the split reduction adds the
+//           parts in part order.
 // With compensated accumulation each matrix-core phase (up to kCap points)
 // accumulates into a fresh pass accumulator that is then added into
 // (sum, compensation) by Kahan's rule; within a pass the sum is plain FP32.
